@@ -1,0 +1,202 @@
+"""Benchmark: forward propagation at scale on one MI355X.
+
+Workload: 512^3 cells, h = 10 m, seeded layered medium (20 layers, 1500-4500 m/s, Gaussian-smoothed
+with sigma = 3 cells, seed 2), radius-4 star stencil with leapfrog, dt at half the stability limit,
+15 Hz Ricker point source at the centre, 16-cell sponge, and the halo-first step schedule with all
+six 4-wide faces packed and unpacked on the device (one subdomain's share; zero-receive exchange).
+A step is one pass of the whole per-step sequence: halo stencil, source injection, pack, exchange,
+unpack, interior stencil, receiver recording.
+
+Prints one JSON line: G point-updates/s over the timed steps, the interior kernel's achieved HBM
+bandwidth against the 8 TB/s peak (algorithmic bytes / HIP-event kernel time), and the FP64 CPU
+oracle timed on the host on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_POINT = 16          # read u^n, u^{n-1}, kappa; write u^{n+1} (FP32)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_interior_512.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=512, help="cells per axis")
+    ap.add_argument("--schedule", default="overlap", choices=["overlap", "serial"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--phases", action="store_true", help="also time each phase separately (serial)")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    with open(os.path.join(ROOT, "paper_1603_03971_amd", "csrc", "rtm.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def host_threads() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_baseline(n: int, h: float, v_prof, target_s: float):
+    """FP64 oracle steps on the same 512^3 layered model, on the host cores, for about target_s."""
+    import numpy as np
+
+    import oracle
+
+    threads = host_threads()
+    v = np.broadcast_to(v_prof[:, None, None], (n, n, n))
+    dt = oracle.stable_dt(4, h, float(v_prof.max()))
+    kap = oracle.kappa_field(v, dt, h)
+    sp = oracle.sponge_profile(n, 16, 0.015)
+    rng = np.random.default_rng(0)
+    u = rng.standard_normal((n, n, n))
+    up = rng.standard_normal((n, n, n))
+    out = np.empty_like(u)
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        oracle.step(u, up, kap, (sp, sp, sp), 4, False, threads, out=out)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= target_s or steps >= 200:
+            break
+    return {"value": n ** 3 * steps / el / 1e9, "unit": "Gpts/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} FP64 oracle steps of the {n}^3 layered workload (random wavefield), "
+                      f"{threads} OpenMP threads, {el:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1603_03971_amd import _abi, synth
+    from paper_1603_03971_amd.grid import Grid
+    from paper_1603_03971_amd.propagator import Propagator, Sources
+
+    assert torch.cuda.is_available(), "needs a GPU"
+    n, h = args.n, 10.0
+    shape = (n, n, n)
+    prof = synth.layered_profile(n, h, seed=2)
+    vmax = float(prof.max())
+    dt = Grid.stable_dt(4, h, vmax)
+    g = Grid(n, n, n, h, dt)
+    v_dev = torch.from_numpy(np.ascontiguousarray(np.broadcast_to(prof[:, None, None], shape), dtype=np.float32))
+    kap = g.kappa_from_velocity(v_dev.cuda())
+    del v_dev
+    total_steps = args.warmup + args.steps
+    c = n // 2
+    src = Sources(g, [(c, c, c)], g.injection_weights([prof[c]]), g.ricker(total_steps, 15.0)[:, None])
+    rec = synth.surface_receivers(n, n, k=20, stride=16)           # a sparse 32 x 32 surface spread
+    prop = Propagator(g, kap, sources=src, receivers=rec, schedule=args.schedule)
+    traces = prop.new_traces(total_steps)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        prop.step(traces)
+    prop.sync()
+    torch.cuda.synchronize()
+
+    prop.interior_events = [] if args.schedule == "overlap" else None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        prop.step(traces)
+    prop.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    finite = bool(torch.isfinite(traces).all().item())
+    pts = g.points
+    value = pts * args.steps / wall / 1e9
+    result = {
+        "metric": "Gpoint-updates/s", "value": round(value, 3), "unit": "Gpts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"forward {n}^3 layered (20 layers 1500-4500 m/s, sigma 3, seed 2), radius-4 "
+                               f"8th-order star, leapfrog, dt at half the stability limit, 15 Hz Ricker at the "
+                               f"centre, 16-cell sponge, halo-first with 6 x 4-wide faces packed/unpacked",
+                   "grid": [n, n, n], "h_m": h, "dt_s": dt, "schedule": args.schedule,
+                   "receivers": int(len(rec))},
+        "finite": finite,
+    }
+    # roofline of the dominant kernel (interior stencil), timed with HIP events on its own stream
+    if prop.interior_events:
+        ms = [a.elapsed_time(b) for a, b in prop.interior_events]
+        avg_s = sum(ms) / len(ms) / 1e3
+        wx, hy, R = _abi.rtm_halo_region(g.c)
+        interior_pts = (n - 2 * wx) * (n - 2 * hy) * (n - 2 * R)
+        achieved = BYTES_PER_POINT * interior_pts / avg_s / 1e9
+        traffic = None
+        if os.path.exists(TRAFFIC_FILE):
+            with open(TRAFFIC_FILE) as f:
+                t = json.load(f)
+            if t.get("kernel_source_sha256_16") == kernel_source_hash() and t.get("n") == n:
+                traffic = t.get("hbm_bytes_per_launch")
+        result["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                              "kernel": "rtm_step_interior", "avg_us": round(avg_s * 1e6, 2),
+                              "algorithmic_bytes_per_launch": BYTES_PER_POINT * interior_pts}
+        # whole-step roofline with the halo phases: stencil 16 B/pt + pack/unpack 16 B per face cell
+        face_cells = 6 * 4 * n * n
+        step_bytes = BYTES_PER_POINT * pts + 16 * face_cells
+        result["step_hbm_frac"] = round(step_bytes / (wall / args.steps) / 1e9 / HBM_PEAK_GBS, 4)
+    if args.phases:
+        result["phases_us"] = time_phases(g, prop, traces)
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(n, h, prof, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+def time_phases(g, prop, traces, reps: int = 20):
+    """Per-phase kernel time (the analogue of the paper's per-phase breakdown), one stream."""
+    import torch
+
+    from paper_1603_03971_amd import _abi
+
+    st = torch.cuda.current_stream()
+    c = g.c
+    u_nxt, u_cur, u_prv = prop.u_prv, prop.u_cur, prop.u_prv
+    phases = {
+        "halo": lambda: _abi.rtm_step_halo(c, u_nxt, u_cur, u_prv, prop.kappa, st),
+        "pack": lambda: _abi.rtm_pack_halo(c, u_nxt, prop.send, st),
+        "unpack": lambda: _abi.rtm_unpack_halo(c, u_nxt, prop.recv, st),
+        "interior": lambda: _abi.rtm_step_interior(c, u_nxt, u_cur, u_prv, prop.kappa, st),
+        "record": lambda: _abi.rtm_record(c, u_nxt, prop.rec_idx, traces, prop.nrec, st),
+    }
+    out = {}
+    for name, fn in phases.items():
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        out[name] = round(e0.elapsed_time(e1) / reps * 1e3, 2)
+    return out
+
+
+if __name__ == "__main__":
+    main()

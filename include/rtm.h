@@ -1,0 +1,179 @@
+/*
+ * rtm.h -- C ABI of librtm.so: the per-time-step phases of an acoustic reverse-time-migration
+ * propagator on one MI355X (gfx950).
+ *
+ * The paper (section II, "Structure of the Application") describes a PDE solver that applies a
+ * high-order stencil to a 3-D block of pressure data every time step, and splits each step into
+ * phases: stencil on the halo region, pack of the halo points into messages, non-blocking
+ * exchange, stencil on the rest of the block while the messages are in flight, wait, unpack.  The
+ * calls below are those phases for one subdomain, plus the source injection, receiver recording
+ * and zero-lag imaging that reverse time migration wraps around them.
+ *
+ * Scheme (3-D isotropic acoustic wave equation, radius-R star stencil, second-order leapfrog,
+ * Cerjan sponge on both time levels):
+ *
+ *     L u     = sum over x, y, z of [ c0 u + sum_{m=1..R} c_m (u(+m) + u(-m)) ]        (dimensionless)
+ *     u^{n+1} = g (2 u^n - g u^{n-1} + kappa L u^n),    kappa = (v dt / h)^2,  g = gx[i] gy[j] gz[k].
+ *
+ * Geometry.  Every field (wavefield time levels, kappa, snapshots, image) is FP32 in the same padded
+ * layout: owned cell (i, j, k), 0 <= i < nx etc., lives at element
+ *     (k + R) * pitch_z + (j + R) * pitch_y + (i + R)
+ * of the base pointer, where R = radius is also the ghost width.  Ghost cells hold what the last
+ * rtm_unpack_halo wrote (zero for a physical boundary).  pitch_y >= nx + 2R and
+ * pitch_z >= pitch_y * (ny + 2R).  A base pointer that is 16-byte aligned with pitch_y and pitch_z
+ * multiples of 4 selects the vectorised kernels; other layouts are accepted and take a scalar path.
+ *
+ * Ownership and ordering.  All field, index and weight arguments are DEVICE pointers owned by the
+ * caller; the library never allocates, frees, copies to the host or synchronises.  Each compute call
+ * only enqueues work on `stream` (NULL = the null stream) and returns at once; ordering across
+ * streams is the caller's.  The library keeps no pointer after a call returns.  Calls are
+ * thread-safe and re-entrant.
+ *
+ * Errors.  Every call returns RTM_OK or a negative status and enqueues nothing on error.  No C++
+ * exception crosses this boundary.
+ */
+#ifndef RTM_H
+#define RTM_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RTM_ABI_VERSION 1
+
+enum {
+    RTM_OK = 0,
+    RTM_EINVAL = -1,   /* null pointer, dimension < 2R, radius not 2 or 4, pitch too small, n < 0 */
+    RTM_EALIAS = -2,   /* an output overlaps an input it must not overlap (e.g. u_nxt == u_cur) */
+    RTM_ELAUNCH = -3,  /* the HIP runtime reported an error when the kernel was launched */
+    RTM_EDEVICE = -4,  /* no HIP device, or the current device is not gfx950 */
+};
+
+typedef struct rtm_grid {
+    int32_t nx, ny, nz;        /* owned cells per axis, each >= 2 * radius */
+    int32_t radius;            /* stencil radius R: 4 (8th order) or 2 (4th order); ghost width = R */
+    int64_t pitch_y;           /* elements between consecutive y rows, >= nx + 2R */
+    int64_t pitch_z;           /* elements between consecutive z planes, >= pitch_y * (ny + 2R) */
+    float c[5];                /* c0..cR, second-derivative weights on unit spacing (1/h^2 lives in kappa) */
+    const float *gx, *gy, *gz; /* device sponge profiles of length nx, ny, nz (all ones = no sponge) */
+} rtm_grid;
+
+/* ---- host-only helpers (no device work) ---------------------------------------------------- */
+
+/* Fill grid->c with the centred Taylor weights of the second derivative for `radius` (Fornberg
+ * 1988; R = 4: -205/72, 8/5, -1/5, 8/315, -1/560; R = 2: -5/2, 4/3, -1/12), zero the rest, and set
+ * the other fields.  Returns RTM_EINVAL for a bad radius, dims or pitches. */
+int rtm_grid_init(rtm_grid *grid, int32_t nx, int32_t ny, int32_t nz, int32_t radius,
+                  int64_t pitch_y, int64_t pitch_z, const float *gx, const float *gy, const float *gz);
+
+/* Largest Courant number v dt / h for which this leapfrog scheme is stable in 3-D:
+ * 2 / sqrt(3 S) with S = |c0| + 2 sum |c_m| (the checkerboard mode).  0 for a bad radius. */
+double rtm_stability_limit(int32_t radius);
+
+/* Cerjan taper along one axis into host memory `out[n]`: exp(-(alpha d)^2), with d = the number
+ * of cells into a `width`-cell sponge at either end (d = max(0, width - i, i - (n - 1 - width))). */
+int rtm_sponge_profile(int32_t n, int32_t width, double alpha, float *out);
+
+/* Ricker wavelet samples into host memory `out[nsteps]`: f(t_n), t_n = n dt,
+ * f(t) = (1 - 2 (pi fp tau)^2) exp(-(pi fp tau)^2), tau = t - t0. */
+int rtm_ricker(int32_t nsteps, double dt, double fpeak, double t0, float *out);
+
+/* Offsets (in elements) of the six face slots -X, +X, -Y, +Y, -Z, +Z inside one contiguous face
+ * buffer; offsets[6] is the total size.  Slot sizes are R*ny*nz, R*ny*nz, nx*R*nz, nx*R*nz,
+ * nx*ny*R, nx*ny*R.  Inside a slot the face's R-thick sub-block is stored x fastest, then y, then z. */
+int rtm_face_layout(const rtm_grid *grid, int64_t offsets[7]);
+
+/* Padded-layout element index of owned cell (i, j, k) (no bounds check beyond the grid's own). */
+int64_t rtm_index(const rtm_grid *grid, int32_t i, int32_t j, int32_t k);
+
+int rtm_abi_version(void);
+const char *rtm_strerror(int status);
+
+/* Process-wide performance options.  They never change results (every variant evaluates the same
+ * per-point expression), but the halo and interior calls of one step must see the same options, so
+ * change them only between steps.
+ *   RTM_OPT_INTERIOR_VARIANT  workgroup shape of the interior call's tiled kernel: 0 = 16x16 threads
+ *                             (64x16 cells), 1 = 32x8 (128x8 cells, default), 2 = 16x8 (64x8 cells),
+ *                             3 = scalar per-cell kernels for both calls.
+ *   RTM_OPT_ZCHUNK            z planes per workgroup of the tiled kernels; 0 = automatic (one wave of
+ *                             resident workgroups over the whole chip).
+ *   RTM_OPT_XCD_REMAP         1 = give each XCD a contiguous range of tiles (default), 0 = hardware order.
+ *   RTM_OPT_HALO_X_WIDTH      width of the halo region's x strips (default 64 = one tile);
+ *   RTM_OPT_HALO_Y_WIDTH      height of its y strips (default 16); see rtm_halo_region.
+ * Returns RTM_EINVAL for an unknown option or value. */
+enum {
+    RTM_OPT_INTERIOR_VARIANT = 1,
+    RTM_OPT_ZCHUNK = 2,
+    RTM_OPT_XCD_REMAP = 3,
+    RTM_OPT_HALO_X_WIDTH = 4,
+    RTM_OPT_HALO_Y_WIDTH = 5,
+};
+int rtm_set_option(int32_t option, int32_t value);
+
+/* The halo region of a grid under the current options: widths = {wx, hy, R} with
+ * wx = max(R, min(RTM_OPT_HALO_X_WIDTH, nx / 2)) and hy = max(R, min(RTM_OPT_HALO_Y_WIDTH, ny / 2)).
+ * rtm_step_halo updates exactly the owned cells with k < R or k >= nz - R or j < hy or j >= ny - hy
+ * or i < wx or i >= nx - wx (a superset of the R-shell that neighbours need, widened so that the
+ * tiled kernel reads whole cache lines); rtm_step_interior updates the rest.  The region depends
+ * only on the grid and the options, never on pointers, so a caller can route each source to the
+ * call that owns its cell.  RTM_EINVAL for a bad grid or NULL widths. */
+int rtm_halo_region(const rtm_grid *grid, int32_t widths[3]);
+
+/* ---- the per-time-step phases (device work, enqueued on `stream`) -------------------------- */
+
+/* Phase 1 (section II): the update of u_nxt on the halo region (rtm_halo_region): every owned cell
+ * within R of a face, which is what the neighbours need, widened in x and y to whole tiles.  Reads u_cur on owned and ghost cells (ghosts from the previous
+ * unpack), u_prv and kappa at the cell.  u_nxt may equal u_prv (two-buffer in-place update);
+ * u_nxt == u_cur is RTM_EALIAS. */
+int rtm_step_halo(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv,
+                  const float *kappa, hipStream_t stream);
+
+/* Phase 4 (section II): the same update on every owned cell not in the halo region; it reads no
+ * ghost cell, so it may run while the halo exchange is in flight.  Halo and interior evaluate the same
+ * per-point expression, so any split of one step gives bitwise identical results. */
+int rtm_step_interior(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv,
+                      const float *kappa, hipStream_t stream);
+
+/* Phase 2 (section II): copy the R outermost owned layers of u on each face into `faces` (one
+ * buffer of rtm_face_layout()[6] elements, slots as described there).  Bitwise copy.  Each slot must
+ * hold fewer than 2^31 elements (RTM_EINVAL otherwise); the same limit applies to unpack. */
+int rtm_pack_halo(const rtm_grid *grid, const float *u, float *faces, hipStream_t stream);
+
+/* Phase 6 (section II): write slot f of the received faces into the R-wide ghost layer of u on face
+ * f (face f of u receives what the neighbour across face f packed from its opposite face).
+ * faces[f] is a device pointer to that slot's data (slot size as in rtm_face_layout), or NULL for a
+ * physical boundary (zero ghosts).  Passing per-slot pointers lets a periodic self-exchange be a
+ * pointer swap.  Edge and corner ghosts are not touched (a star stencil never reads them). */
+int rtm_unpack_halo(const rtm_grid *grid, float *u, const float *const faces[6], hipStream_t stream);
+
+/* Source injection: u[idx[s]] += w[s] * amp[s] for s < n (duplicate indices add up).  idx are
+ * padded-layout element indices (rtm_index); an index outside the padded block is skipped.  For a
+ * point source w = (v_s dt)^2 / h^3 and amp = the wavelet at t_n; in back-propagation amp is the
+ * time-reversed trace sample of each receiver. */
+int rtm_inject(const rtm_grid *grid, float *u, const int64_t *idx, const float *w, const float *amp,
+               int32_t n, hipStream_t stream);
+
+/* Receiver recording: out[r] = u[idx[r]] for r < n (an index outside the padded block gives 0). */
+int rtm_record(const rtm_grid *grid, const float *u, const int64_t *idx, float *out, int32_t n,
+               hipStream_t stream);
+
+/* Material coefficient on the device: kappa = (v * dt_over_h)^2 in FP32 on the owned cells of the
+ * padded `kappa`; `v` is a compact x-fastest nz*ny*nx FP32 velocity array.  Ghost cells of kappa are
+ * not written (the stencil never reads them). */
+int rtm_kappa_from_velocity(const rtm_grid *grid, float *kappa, const float *v, float dt_over_h,
+                            hipStream_t stream);
+
+/* Zero-lag cross-correlation imaging condition (Claerbout 1971): image += weight * src * rcv on
+ * owned cells; src is the source wavefield at a time level and rcv the receiver wavefield at the
+ * same level.  image may not overlap src or rcv. */
+int rtm_image_accumulate(const rtm_grid *grid, float *image, const float *src, const float *rcv,
+                         float weight, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTM_H */

@@ -1,0 +1,186 @@
+"""ctypes binding of librtm.so: the same names and arguments as include/rtm.h.
+
+Argument marshalling only.  Field arguments accept a torch tensor (its data_ptr is passed), a raw
+integer device address, or None (NULL).  Streams accept a torch.cuda.Stream, a raw hipStream_t
+integer, or None (the null stream).  A nonzero status raises RTMError.  If the library has not been
+built, importing the binding fails loudly: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librtm.so")
+
+RTM_OK, RTM_EINVAL, RTM_EALIAS, RTM_ELAUNCH, RTM_EDEVICE = 0, -1, -2, -3, -4
+RTM_OPT_INTERIOR_VARIANT, RTM_OPT_ZCHUNK, RTM_OPT_XCD_REMAP, RTM_OPT_HALO_X_WIDTH, RTM_OPT_HALO_Y_WIDTH = 1, 2, 3, 4, 5
+
+
+class RTMError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {_lib.rtm_strerror(status).decode()} (status {status})")
+
+
+class rtm_grid(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("radius", ctypes.c_int32),
+        ("pitch_y", ctypes.c_int64), ("pitch_z", ctypes.c_int64),
+        ("c", ctypes.c_float * 5),
+        ("gx", ctypes.c_void_p), ("gy", ctypes.c_void_p), ("gz", ctypes.c_void_p),
+    ]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
+                          "or `python paper_1603_03971_amd/build.py` (no CPU fallback exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, f32, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_double
+    gp = ctypes.POINTER(rtm_grid)
+    sig = {
+        "rtm_abi_version": ([], ctypes.c_int),
+        "rtm_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "rtm_grid_init": ([gp, i32, i32, i32, i32, i64, i64, vp, vp, vp], ctypes.c_int),
+        "rtm_stability_limit": ([i32], f64),
+        "rtm_sponge_profile": ([i32, i32, f64, vp], ctypes.c_int),
+        "rtm_ricker": ([i32, f64, f64, f64, vp], ctypes.c_int),
+        "rtm_face_layout": ([gp, ctypes.POINTER(i64)], ctypes.c_int),
+        "rtm_index": ([gp, i32, i32, i32], i64),
+        "rtm_set_option": ([i32, i32], ctypes.c_int),
+        "rtm_halo_region": ([gp, ctypes.POINTER(i32)], ctypes.c_int),
+        "rtm_step_halo": ([gp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "rtm_step_interior": ([gp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "rtm_pack_halo": ([gp, vp, vp, vp], ctypes.c_int),
+        "rtm_unpack_halo": ([gp, vp, ctypes.POINTER(vp), vp], ctypes.c_int),
+        "rtm_inject": ([gp, vp, vp, vp, vp, i32, vp], ctypes.c_int),
+        "rtm_record": ([gp, vp, vp, vp, i32, vp], ctypes.c_int),
+        "rtm_kappa_from_velocity": ([gp, vp, vp, f32, vp], ctypes.c_int),
+        "rtm_image_accumulate": ([gp, vp, vp, vp, f32, vp], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = _load()
+lib = _lib
+
+
+def _p(x) -> int | None:
+    """Device address of a tensor / int / None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _s(stream) -> int | None:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check(status: int, where: str):
+    if status != RTM_OK:
+        raise RTMError(status, where)
+
+
+def rtm_abi_version() -> int:
+    return _lib.rtm_abi_version()
+
+
+def rtm_strerror(status: int) -> str:
+    return _lib.rtm_strerror(status).decode()
+
+
+def rtm_grid_init(nx, ny, nz, radius, pitch_y, pitch_z, gx, gy, gz) -> rtm_grid:
+    g = rtm_grid()
+    _check(_lib.rtm_grid_init(ctypes.byref(g), nx, ny, nz, radius, pitch_y, pitch_z, _p(gx), _p(gy), _p(gz)),
+           "rtm_grid_init")
+    return g
+
+
+def rtm_stability_limit(radius: int) -> float:
+    return _lib.rtm_stability_limit(radius)
+
+
+def rtm_sponge_profile(n: int, width: int, alpha: float):
+    import numpy as np
+
+    out = np.empty(n, dtype=np.float32)
+    _check(_lib.rtm_sponge_profile(n, width, alpha, out.ctypes.data), "rtm_sponge_profile")
+    return out
+
+
+def rtm_ricker(nsteps: int, dt: float, fpeak: float, t0: float):
+    import numpy as np
+
+    out = np.empty(nsteps, dtype=np.float32)
+    _check(_lib.rtm_ricker(nsteps, dt, fpeak, t0, out.ctypes.data), "rtm_ricker")
+    return out
+
+
+def rtm_face_layout(grid: rtm_grid):
+    off = (ctypes.c_int64 * 7)()
+    _check(_lib.rtm_face_layout(ctypes.byref(grid), off), "rtm_face_layout")
+    return list(off)
+
+
+def rtm_index(grid: rtm_grid, i: int, j: int, k: int) -> int:
+    return _lib.rtm_index(ctypes.byref(grid), i, j, k)
+
+
+def rtm_set_option(option: int, value: int):
+    _check(_lib.rtm_set_option(option, value), "rtm_set_option")
+
+
+def rtm_halo_region(grid):
+    """(wx, hy, R): widths of the halo region's x strips, y strips and z slabs."""
+    w = (ctypes.c_int32 * 3)()
+    _check(_lib.rtm_halo_region(ctypes.byref(grid), w), "rtm_halo_region")
+    return tuple(w)
+
+
+def rtm_step_halo(grid, u_nxt, u_cur, u_prv, kappa, stream=None):
+    _check(_lib.rtm_step_halo(ctypes.byref(grid), _p(u_nxt), _p(u_cur), _p(u_prv), _p(kappa), _s(stream)),
+           "rtm_step_halo")
+
+
+def rtm_step_interior(grid, u_nxt, u_cur, u_prv, kappa, stream=None):
+    _check(_lib.rtm_step_interior(ctypes.byref(grid), _p(u_nxt), _p(u_cur), _p(u_prv), _p(kappa), _s(stream)),
+           "rtm_step_interior")
+
+
+def rtm_pack_halo(grid, u, faces, stream=None):
+    _check(_lib.rtm_pack_halo(ctypes.byref(grid), _p(u), _p(faces), _s(stream)), "rtm_pack_halo")
+
+
+def rtm_unpack_halo(grid, u, faces, stream=None):
+    """`faces`: six slot addresses (tensor, int or None for a zero/physical boundary)."""
+    arr = (ctypes.c_void_p * 6)(*[_p(f) for f in faces])
+    _check(_lib.rtm_unpack_halo(ctypes.byref(grid), _p(u), arr, _s(stream)), "rtm_unpack_halo")
+
+
+def rtm_inject(grid, u, idx, w, amp, n, stream=None):
+    _check(_lib.rtm_inject(ctypes.byref(grid), _p(u), _p(idx), _p(w), _p(amp), n, _s(stream)), "rtm_inject")
+
+
+def rtm_record(grid, u, idx, out, n, stream=None):
+    _check(_lib.rtm_record(ctypes.byref(grid), _p(u), _p(idx), _p(out), n, _s(stream)), "rtm_record")
+
+
+def rtm_kappa_from_velocity(grid, kappa, v, dt_over_h, stream=None):
+    _check(_lib.rtm_kappa_from_velocity(ctypes.byref(grid), _p(kappa), _p(v), dt_over_h, _s(stream)),
+           "rtm_kappa_from_velocity")
+
+
+def rtm_image_accumulate(grid, image, src, rcv, weight=1.0, stream=None):
+    _check(_lib.rtm_image_accumulate(ctypes.byref(grid), _p(image), _p(src), _p(rcv), weight, _s(stream)),
+           "rtm_image_accumulate")

@@ -1,0 +1,1033 @@
+// rtm.hip -- HIP kernels for gfx950 and the extern "C" entry points of librtm.so.
+//
+// The per-time-step phases follow the paper's section II (halo stencil, pack, exchange, interior
+// stencil, unpack); the scheme is the radius-R star stencil with second-order leapfrog and a
+// Cerjan sponge:  u^{n+1} = g (2 u^n - g u^{n-1} + kappa L u^n).
+//
+// Every stencil kernel evaluates the same per-point expression (point_update) on the same operands
+// in the same order, with explicit FMAs and FP contraction disabled at compile time, so any split of
+// a step between the halo and interior calls produces bitwise identical wavefields.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <type_traits>
+#include <utility>
+
+#include "rtm.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+
+// ---------------------------------------------------------------------------------------------
+// Device-side geometry (passed by value to every kernel)
+// ---------------------------------------------------------------------------------------------
+struct Geo {
+    int nx, ny, nz, R;
+    long long py, pz;
+    float c[5];
+    const float *gx, *gy, *gz;
+};
+
+__device__ __forceinline__ long long pidx(const Geo &g, int i, int j, int k)
+{
+    return (long long)(k + g.R) * g.pz + (long long)(j + g.R) * g.py + (long long)(i + g.R);
+}
+
+// Sum of the six neighbours at distance m: ((x- + x+) + (y- + y+)) + (z- + z+).
+__device__ __forceinline__ float axis_sum(float xm, float xp, float ym, float yp, float zm, float zp)
+{
+    return ((xm + xp) + (ym + yp)) + (zm + zp);
+}
+
+// The per-point update.  s[m-1] = axis_sum at distance m.  The centre weight is 3 c0 (one c0 per axis).
+template <int R>
+__device__ __forceinline__ float point_update(float u0, const float (&s)[R], float up, float kap, float g,
+                                              const float (&c)[5])
+{
+    float lap = (3.0f * c[0]) * u0;
+#pragma unroll
+    for (int m = 1; m <= R; ++m)
+        lap = __builtin_fmaf(c[m], s[m - 1], lap);
+    float t = __builtin_fmaf(-g, up, 2.0f * u0);
+    t = __builtin_fmaf(kap, lap, t);
+    return g * t;
+}
+
+__device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
+__device__ __forceinline__ void st4(float *p, float4 v) { *reinterpret_cast<float4 *>(p) = v; }
+__device__ __forceinline__ float el(const float4 &v, int e)
+{
+    return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
+}
+
+__device__ __forceinline__ float sponge(const Geo &g, int i, int j, int k)
+{
+    return (g.gx[i] * g.gy[j]) * g.gz[k];
+}
+
+// Scalar update of one owned cell, reading every operand from global memory.
+template <int R>
+__device__ __forceinline__ void update_cell(const Geo &g, float *un, const float *uc, const float *up,
+                                            const float *kap, int i, int j, int k)
+{
+    const long long p = pidx(g, i, j, k);
+    const float u0 = uc[p];
+    float s[R];
+#pragma unroll
+    for (int m = 1; m <= R; ++m)
+        s[m - 1] = axis_sum(uc[p - m], uc[p + m], uc[p - m * g.py], uc[p + m * g.py], uc[p - m * g.pz],
+                            uc[p + m * g.pz]);
+    float c[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) c[m] = g.c[m];
+    un[p] = point_update<R>(u0, s, up[p], kap[p], sponge(g, i, j, k), c);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Halo shell: the owned cells within R of a face, as six slabs (-Z, +Z, -Y, +Y, -X, +X) that do
+// not overlap.  blockIdx.y selects the slab; x is fastest inside a slab.
+// ---------------------------------------------------------------------------------------------
+struct Slab {
+    int ox, oy, oz;   // origin (owned coordinates)
+    int wx, wy, wz;   // extent
+};
+
+// Scalar update over one box [x0,x1) x [y0,y1) x [z0,z1) (fallback for layouts the vectorised
+// kernel cannot take).
+template <int R>
+__global__ __launch_bounds__(kThreads) void k_box(Geo g, float *un, const float *__restrict__ uc, const float *up,
+                                                  const float *__restrict__ kap, int x0, int x1, int y0, int y1,
+                                                  int z0, int z1)
+{
+    const long long wx = x1 - x0, wy = y1 - y0, wz = z1 - z0;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= wx * wy * wz) return;
+    const int i = x0 + (int)(t % wx);
+    const int j = y0 + (int)((t / wx) % wy);
+    const int k = z0 + (int)(t / (wx * wy));
+    update_cell<R>(g, un, uc, up, kap, i, j, k);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Interior: 2.5-D blocking (Micikevicius 2009) for CDNA4.
+//
+// A workgroup of BX x BY threads owns an XY tile of TX = 4 BX columns by TY = BY rows and marches
+// through a chunk of z planes.  Each thread owns four consecutive x cells (one float4) of one row:
+//   * z neighbours come from a register queue of 2R+1 float4 planes that shifts by one each step;
+//   * x and y neighbours come from the current plane, staged with a 4-column / R-row halo in LDS
+//     (double-buffered, so one barrier per plane);
+//   * the next plane's loads are issued before the current plane is computed.
+// Workgroup ids are remapped so that each of the 8 XCDs (round-robin dispatch) receives a
+// contiguous range of tiles, keeping the halo re-reads of neighbouring tiles in the same L2.
+// ---------------------------------------------------------------------------------------------
+
+// Calls f(integral_constant<int, I>) for I = 0, 1, ... in order while it returns true, with I a
+// compile-time constant in every call (so arrays indexed by it stay in registers).
+template <typename F, int... I>
+__device__ __forceinline__ void unroll_seq(F &&f, std::integer_sequence<int, I...>)
+{
+    (void)(f(std::integral_constant<int, I>{}) && ...);
+}
+
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int xcd = b & 7, q = nb >> 3, r = nb & 7;
+    return xcd * q + (xcd < r ? xcd : r) + (b >> 3);
+}
+
+struct Box {
+    int x0, x1, y0, y1, z0, z1;   // owned-cell bounds of the box
+    int X0;                       // first tile column: x0 aligned down so that X0 + R is a multiple of 4
+    int zchunk, ntx, nty, nzc;
+    int nblk;                     // ntx * nty * nzc
+};
+
+constexpr int kMaxBoxes = 6;
+
+struct BoxList {
+    Box b[kMaxBoxes];
+    int nbox;
+    int nblk;     // sum of the boxes' nblk
+    int remap;
+};
+
+template <int R, int BX, int BY>
+__global__ __launch_bounds__(BX *BY) void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up,
+                                                  const float *__restrict__ kap, BoxList bl)
+{
+    constexpr int NT = BX * BY;
+    constexpr int TX = 4 * BX;
+    constexpr int TY = BY;
+    constexpr int LW4 = BX + 2;            // LDS row in float4: 1 halo, BX centre, 1 halo
+    constexpr int LH = TY + 2 * R;         // LDS rows: R halo rows above and below
+    constexpr int NH = 2 * R * BX + 2 * BY; // halo float4 items per plane
+    constexpr int HPT = (NH + NT - 1) / NT;
+    constexpr int QR = 2 * R + 2;          // register ring: the 2R+1 planes in use plus the one in flight
+    constexpr int S = R + 2;               // LDS ring: planes k-1 .. k+R
+    __shared__ float4 lds[S][LH][LW4];
+
+    int lb = bl.remap ? xcd_remap(blockIdx.x, bl.nblk) : (int)blockIdx.x;
+    Box bx = bl.b[0];
+#pragma unroll
+    for (int i = 1; i < kMaxBoxes; ++i) {
+        if (i < bl.nbox && lb >= bx.nblk) {
+            lb -= bx.nblk;
+            bx = bl.b[i];
+        }
+    }
+    const int tix = lb % bx.ntx;
+    const int tiy = (lb / bx.ntx) % bx.nty;
+    const int tiz = lb / (bx.ntx * bx.nty);
+    const int X = bx.X0 + tix * TX;
+    const int Y = bx.y0 + tiy * TY;
+    const int zs = bx.z0 + tiz * bx.zchunk;
+    const int ze = min(zs + bx.zchunk, bx.z1);
+
+    const int tid = threadIdx.x;
+    const int lx = tid % BX, ly = tid / BX;
+    const int x = X + 4 * lx, y = Y + ly;
+    const int xlim = bx.x1 + R;            // columns >= xlim are never needed
+    const int ylim = bx.y1 + R;
+    const int elo = max(0, bx.x0 - x);     // cells of this float4 before the box
+    const int ehi = min(4, bx.x1 - x);     // cells of this float4 inside the box end here
+    const bool active = (ehi > elo) && (y < bx.y1);
+    const bool full = active && elo == 0 && ehi == 4;
+    const bool cload = (x < xlim) && (y < ylim);
+    const long long pz = g.pz;
+
+    // centre column pointer at plane zs.  Lanes whose column or row is not needed load from the
+    // tile origin instead (always inside the padded block), so every load is unconditional; what
+    // they load is never read.
+    const long long pc = pidx(g, x, y, zs);
+    const long long p0 = pidx(g, X, Y, zs);
+    const long long pcl = cload ? pc : p0;
+    const long long pca = active ? pc : p0;
+
+    // halo items owned by this thread: global offset at plane zs and LDS slot (row, float4 column)
+    long long hoff[HPT];
+    int hrow[HPT], hcol[HPT];
+    bool hok[HPT];
+#pragma unroll
+    for (int h = 0; h < HPT; ++h) {
+        const int t = tid + h * NT;
+        hok[h] = false;
+        hoff[h] = p0;
+        hrow[h] = 0;
+        hcol[h] = 0;
+        if (t < 2 * R * BX) {
+            const int yr = t / BX, col = t % BX;
+            const int row = yr < R ? Y - R + yr : Y + TY + (yr - R);
+            const int xx = X + 4 * col;
+            hrow[h] = yr < R ? yr : TY + yr;
+            hcol[h] = 1 + col;
+            hok[h] = (xx < xlim) && (row < ylim);
+            hoff[h] = hok[h] ? pidx(g, xx, row, zs) : p0;
+        } else if (t < NH) {
+            const int t2 = t - 2 * R * BX;
+            const int side = t2 / BY, r = t2 % BY;
+            const int row = Y + r;
+            const int xx = side == 0 ? X - 4 : X + TX;
+            hrow[h] = R + r;
+            hcol[h] = side == 0 ? 0 : 1 + BX;
+            hok[h] = (side == 0 ? (X - 1 >= bx.x0 - R) : (xx < xlim)) && (row < ylim);
+            hoff[h] = hok[h] ? pidx(g, xx, row, zs) : p0;
+        }
+    }
+
+    float c[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) c[m] = g.c[m];
+    float gxy[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int xi = min(max(x + e, 0), g.nx - 1);
+        const int yi = min(y, g.ny - 1);
+        gxy[e] = g.gx[xi] * g.gy[yi];
+    }
+
+    // Two rings.  (1) Registers: this thread's float4 of plane p of u_cur lives in
+    // q[(p - zs + R) % QR]; the z loop is unrolled by QR so every ring index is a compile-time
+    // constant.  (2) LDS: plane p with its x/y halo lives in lds[(p - zs) % S].  Both are filled at
+    // the leading edge (plane k + R while plane k is computed), so a tile reads its halo rows at the
+    // same time as the neighbouring tiles read them as their own centre rows, while they are in L2.
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 q[QR];
+#pragma unroll
+    for (int m = 0; m < 2 * R + 1; ++m) q[m] = ld4(uc + pcl + (long long)(m - R) * pz);
+    q[QR - 1] = zero4;
+    // LDS planes zs .. zs+R-1 (those that exist)
+    for (int d = 0; d < R && zs + d < ze; ++d) {
+        float4 hv[HPT];
+#pragma unroll
+        for (int h = 0; h < HPT; ++h) hv[h] = ld4(uc + hoff[h] + (long long)d * pz);
+        lds[d][R + ly][1 + lx] = ld4(uc + pcl + (long long)d * pz);
+#pragma unroll
+        for (int h = 0; h < HPT; ++h)
+            if (tid + h * NT < NH) lds[d][hrow[h]][hcol[h]] = hv[h];
+    }
+    // halo of plane zs + R (written in the first iteration)
+    float4 hv[HPT];
+#pragma unroll
+    for (int h = 0; h < HPT; ++h) hv[h] = ld4(uc + hoff[h] + (long long)R * pz);
+    // operands of plane k (u_prv, kappa and the z sponge factor) arrive one plane ahead, in the same
+    // batch of loads, so waiting for them never waits for the loads issued for later planes
+    float4 pv[2], kv[2];
+    float gzv[2];
+    pv[0] = ld4(up + pca);
+    kv[0] = ld4(kap + pca);
+    gzv[0] = g.gz[zs];
+
+    int k0_ = zs;                           // first plane of the current ring revolution
+    int sk = 0;                             // LDS slot of plane k
+    // One plane of the march; `S_` is the compile-time position of plane k in the register ring.
+    auto plane = [&](auto S_) -> bool {
+        constexpr int s = decltype(S_)::value;
+        const int k = k0_ + s;
+        if (k >= ze) return false;
+        const int b = s & 1;               // operand slot of plane k
+        const long long dz = (long long)(k - zs) * pz;
+        const int sw = (sk + R < S) ? sk + R : sk + R - S;   // LDS slot of plane k + R
+        // stage plane k + R (centre from the register ring, halo from the pending loads)
+        if (k + R < ze) {
+            lds[sw][R + ly][1 + lx] = q[(s + 2 * R) % QR];
+#pragma unroll
+            for (int h = 0; h < HPT; ++h)
+                if (tid + h * NT < NH) lds[sw][hrow[h]][hcol[h]] = hv[h];
+        }
+        __syncthreads();
+
+        // issue the loads of plane k + R + 1 (centre into the ring slot of plane k - R - 1, which
+        // is no longer needed; its halo) and of u_prv / kappa at plane k + 1.  They are issued on
+        // every plane, with the plane index clamped to the chunk at its end (those values are never
+        // used), so the number of loads in flight is the same on every path and the waits before
+        // the compute only cover the previous plane's loads.
+        {
+            const long long kn = min(k + 1, ze - 1) - zs;          // plane of u_prv / kappa
+            const long long kh = min(k + R + 1, ze - 1) - zs;      // plane of the halo
+            q[(s + 2 * R + 1) % QR] = ld4(uc + pcl + (kn + R) * pz);
+#pragma unroll
+            for (int h = 0; h < HPT; ++h) hv[h] = ld4(uc + hoff[h] + kh * pz);
+            pv[b ^ 1] = ld4(up + pca + kn * pz);
+            kv[b ^ 1] = ld4(kap + pca + kn * pz);
+            gzv[b ^ 1] = g.gz[zs + kn];
+        }
+
+        if (active) {
+            const float4 xl = lds[sk][R + ly][lx];
+            const float4 xc = q[(s + R) % QR];
+            const float4 xr = lds[sk][R + ly][2 + lx];
+            float4 ym[R], yp[R];
+#pragma unroll
+            for (int m = 1; m <= R; ++m) {
+                ym[m - 1] = lds[sk][R + ly - m][1 + lx];
+                yp[m - 1] = lds[sk][R + ly + m][1 + lx];
+            }
+            const float xs[12] = {xl.x, xl.y, xl.z, xl.w, xc.x, xc.y, xc.z, xc.w, xr.x, xr.y, xr.z, xr.w};
+            const float gz = gzv[b];
+            float out[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float sm[R];
+#pragma unroll
+                for (int m = 1; m <= R; ++m)
+                    sm[m - 1] = axis_sum(xs[4 + e - m], xs[4 + e + m], el(ym[m - 1], e), el(yp[m - 1], e),
+                                         el(q[(s + R - m) % QR], e), el(q[(s + R + m) % QR], e));
+                out[e] = point_update<R>(xs[4 + e], sm, el(pv[b], e), el(kv[b], e), gxy[e] * gz, c);
+            }
+            float *dst = un + pc + dz;
+            if (full) {
+                st4(dst, make_float4(out[0], out[1], out[2], out[3]));
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (e >= elo && e < ehi) dst[e] = out[e];
+            }
+        }
+        sk = (sk + 1 < S) ? sk + 1 : 0;
+        return true;
+    };
+#pragma unroll 1
+    for (k0_ = zs; k0_ < ze; k0_ += QR) unroll_seq(plane, std::make_integer_sequence<int, QR>{});
+}
+
+// ---------------------------------------------------------------------------------------------
+// Pack / unpack of the six R-thick faces (bitwise copies), one launch each; blockIdx.y = slot.
+// ---------------------------------------------------------------------------------------------
+struct FaceOffsets {
+    long long off[7];
+};
+struct FacePtrs {
+    const float *p[6];
+};
+
+__device__ __forceinline__ Slab face_owned(const Geo &g, int f)
+{
+    const int R = g.R, nx = g.nx, ny = g.ny, nz = g.nz;
+    switch (f) {
+    case 0: return {0, 0, 0, R, ny, nz};
+    case 1: return {nx - R, 0, 0, R, ny, nz};
+    case 2: return {0, 0, 0, nx, R, nz};
+    case 3: return {0, ny - R, 0, nx, R, nz};
+    case 4: return {0, 0, 0, nx, ny, R};
+    default: return {0, 0, nz - R, nx, ny, R};
+    }
+}
+
+__device__ __forceinline__ Slab face_ghost(const Geo &g, int f)
+{
+    const int R = g.R, nx = g.nx, ny = g.ny, nz = g.nz;
+    switch (f) {
+    case 0: return {-R, 0, 0, R, ny, nz};
+    case 1: return {nx, 0, 0, R, ny, nz};
+    case 2: return {0, -R, 0, nx, R, nz};
+    case 3: return {0, ny, 0, nx, R, nz};
+    case 4: return {0, 0, -R, nx, ny, R};
+    default: return {0, 0, nz, nx, ny, R};
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_pack(Geo g, const float *__restrict__ u, float *__restrict__ faces,
+                                                   FaceOffsets fo)
+{
+    const int f = blockIdx.y;
+    const Slab s = face_owned(g, f);
+    const unsigned cnt = (unsigned)s.wx * (unsigned)s.wy * (unsigned)s.wz;
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt) return;
+    const unsigned row = t / (unsigned)s.wx;
+    const int i = s.ox + (int)(t - row * (unsigned)s.wx);
+    const int j = s.oy + (int)(row % (unsigned)s.wy);
+    const int k = s.oz + (int)(row / (unsigned)s.wy);
+    faces[fo.off[f] + t] = u[pidx(g, i, j, k)];
+}
+
+__global__ __launch_bounds__(kThreads) void k_unpack(Geo g, float *__restrict__ u, FacePtrs src)
+{
+    const int f = blockIdx.y;
+    const Slab s = face_ghost(g, f);
+    const unsigned cnt = (unsigned)s.wx * (unsigned)s.wy * (unsigned)s.wz;
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt) return;
+    const unsigned row = t / (unsigned)s.wx;
+    const int i = s.ox + (int)(t - row * (unsigned)s.wx);
+    const int j = s.oy + (int)(row % (unsigned)s.wy);
+    const int k = s.oz + (int)(row / (unsigned)s.wy);
+    const float *p = src.p[f];
+    u[pidx(g, i, j, k)] = p ? p[t] : 0.0f;
+}
+
+// float4 forms, used when R = 4, nx % 4 == 0 and every pointer and pitch is 16-byte aligned: then each
+// face row starts on a float4 boundary and one thread moves four consecutive cells.
+__global__ __launch_bounds__(kThreads) void k_pack4(Geo g, const float *__restrict__ u, float *__restrict__ faces,
+                                                    FaceOffsets fo)
+{
+    const int f = blockIdx.y;
+    const Slab s = face_owned(g, f);
+    const unsigned w4 = (unsigned)s.wx >> 2;
+    const unsigned cnt = w4 * (unsigned)s.wy * (unsigned)s.wz;
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt) return;
+    const unsigned row = t / w4;
+    const int i = s.ox + 4 * (int)(t - row * w4);
+    const int j = s.oy + (int)(row % (unsigned)s.wy);
+    const int k = s.oz + (int)(row / (unsigned)s.wy);
+    st4(faces + fo.off[f] + 4 * t, ld4(u + pidx(g, i, j, k)));
+}
+
+__global__ __launch_bounds__(kThreads) void k_unpack4(Geo g, float *__restrict__ u, FacePtrs src)
+{
+    const int f = blockIdx.y;
+    const Slab s = face_ghost(g, f);
+    const unsigned w4 = (unsigned)s.wx >> 2;
+    const unsigned cnt = w4 * (unsigned)s.wy * (unsigned)s.wz;
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt) return;
+    const unsigned row = t / w4;
+    const int i = s.ox + 4 * (int)(t - row * w4);
+    const int j = s.oy + (int)(row % (unsigned)s.wy);
+    const int k = s.oz + (int)(row / (unsigned)s.wy);
+    const float *p = src.p[f];
+    st4(u + pidx(g, i, j, k), p ? ld4(p + 4 * t) : make_float4(0.f, 0.f, 0.f, 0.f));
+}
+
+// ---------------------------------------------------------------------------------------------
+// Injection, recording, imaging
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_inject(float *u, long long total, const int64_t *__restrict__ idx,
+                                                     const float *__restrict__ w, const float *__restrict__ amp, int n)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const long long p = idx[s];
+    if (p < 0 || p >= total) return;
+    atomicAdd(u + p, w[s] * amp[s]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_record(const float *__restrict__ u, long long total,
+                                                     const int64_t *__restrict__ idx, float *__restrict__ out, int n)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const long long p = idx[r];
+    out[r] = (p >= 0 && p < total) ? u[p] : 0.0f;
+}
+
+__global__ __launch_bounds__(kThreads) void k_image(Geo g, float *image, const float *__restrict__ src,
+                                                    const float *__restrict__ rcv, float weight)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nxy = (long long)g.nx * g.ny;
+    if (t >= nxy * g.nz) return;
+    const int i = (int)(t % g.nx);
+    const int j = (int)((t / g.nx) % g.ny);
+    const int k = (int)(t / nxy);
+    const long long p = pidx(g, i, j, k);
+    image[p] = __builtin_fmaf(weight * src[p], rcv[p], image[p]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_kappa(Geo g, float *__restrict__ kappa, const float *__restrict__ v,
+                                                    float s)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nxy = (long long)g.nx * g.ny;
+    if (t >= nxy * g.nz) return;
+    const int i = (int)(t % g.nx);
+    const int j = (int)((t / g.nx) % g.ny);
+    const int k = (int)(t / nxy);
+    const float a = v[t] * s;
+    kappa[pidx(g, i, j, k)] = a * a;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Host side: validation, device check, launch configuration
+// ---------------------------------------------------------------------------------------------
+constexpr int kMaxDevices = 64;
+std::atomic<int> g_dev_ok[kMaxDevices];   // 0 unknown, 1 gfx950, -1 other
+
+struct Options {
+    std::atomic<int> interior_variant{1};  // 0: 16x16 threads (64 x 16 cells), 1: 32x8, 2: 16x8, 3: scalar
+    std::atomic<int> zchunk{0};            // 0: automatic
+    std::atomic<int> xcd_remap{1};
+    std::atomic<int> halo_x_width{64};     // x strips of the halo region
+    std::atomic<int> halo_y_width{16};     // y strips of the halo region
+};
+Options g_opt;
+
+int check_device()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return RTM_EDEVICE;
+    if (dev < 0 || dev >= kMaxDevices) return RTM_EDEVICE;
+    int st = g_dev_ok[dev].load(std::memory_order_relaxed);
+    if (st == 0) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return RTM_EDEVICE;
+        st = (std::strncmp(prop.gcnArchName, "gfx950", 6) == 0) ? 1 : -1;
+        g_dev_ok[dev].store(st, std::memory_order_relaxed);
+    }
+    return st == 1 ? RTM_OK : RTM_EDEVICE;
+}
+
+int check_grid(const rtm_grid *gr)
+{
+    if (!gr) return RTM_EINVAL;
+    const int R = gr->radius;
+    if (R != 2 && R != 4) return RTM_EINVAL;
+    if (gr->nx < 2 * R || gr->ny < 2 * R || gr->nz < 2 * R) return RTM_EINVAL;
+    if (gr->pitch_y < (int64_t)gr->nx + 2 * R) return RTM_EINVAL;
+    if (gr->pitch_z < gr->pitch_y * ((int64_t)gr->ny + 2 * R)) return RTM_EINVAL;
+    if (!gr->gx || !gr->gy || !gr->gz) return RTM_EINVAL;
+    return RTM_OK;
+}
+
+Geo make_geo(const rtm_grid *gr)
+{
+    Geo g;
+    g.nx = gr->nx;
+    g.ny = gr->ny;
+    g.nz = gr->nz;
+    g.R = gr->radius;
+    g.py = gr->pitch_y;
+    g.pz = gr->pitch_z;
+    for (int m = 0; m < 5; ++m) g.c[m] = (m <= gr->radius) ? gr->c[m] : 0.0f;
+    g.gx = gr->gx;
+    g.gy = gr->gy;
+    g.gz = gr->gz;
+    return g;
+}
+
+long long padded_total(const rtm_grid *gr) { return gr->pitch_z * ((long long)gr->nz + 2 * gr->radius); }
+
+int launch_status()
+{
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RTM_OK : RTM_ELAUNCH;
+}
+
+unsigned blocks_for(long long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// Launch the tiled kernel over up to kMaxBoxes boxes {x0, x1, y0, y1, z0, z1} (empty ones skipped).
+template <int R, int BX, int BY>
+int launch_tiled(const Geo &g, float *un, const float *uc, const float *up, const float *kap, const int (*boxes)[6],
+                 int nbox, hipStream_t st)
+{
+    constexpr int TX = 4 * BX;
+    BoxList bl;
+    std::memset(&bl, 0, sizeof(bl));
+    int tiles = 0, wz = 0;
+    for (int i = 0; i < nbox; ++i) {
+        const int *b = boxes[i];
+        if (b[1] <= b[0] || b[3] <= b[2] || b[5] <= b[4]) continue;
+        Box &x = bl.b[bl.nbox++];
+        x.x0 = b[0];
+        x.x1 = b[1];
+        x.y0 = b[2];
+        x.y1 = b[3];
+        x.z0 = b[4];
+        x.z1 = b[5];
+        x.X0 = x.x0 - ((x.x0 + R) & 3);
+        x.ntx = (x.x1 - x.X0 + TX - 1) / TX;
+        x.nty = (x.y1 - x.y0 + BY - 1) / BY;
+        if (x.z1 - x.z0 > 2 * R) {           // deep boxes share the z chunking; thin slabs are one chunk
+            tiles += x.ntx * x.nty;
+            wz = std::max(wz, x.z1 - x.z0);
+        }
+    }
+    if (bl.nbox == 0) return RTM_OK;
+    int zc = g_opt.zchunk.load(std::memory_order_relaxed);
+    if (zc <= 0 && tiles > 0) {
+        // One wave of workgroups: split z so that tiles x chunks is about the number of workgroups the
+        // whole chip holds at once (CUs x resident workgroups per CU), with chunks of >= 16 planes.
+        static std::atomic<int> resident{0};
+        int occ = resident.load(std::memory_order_relaxed);
+        if (occ == 0) {
+            int per_cu = 0, cus = 0, dev = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tiled<R, BX, BY>, BX * BY, 0) !=
+                hipSuccess)
+                per_cu = 2;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+                cus = 256;
+            occ = std::max(1, per_cu) * std::max(1, cus);
+            resident.store(occ, std::memory_order_relaxed);
+        }
+        int nzc = (occ + tiles / 2) / tiles;
+        nzc = std::max(1, std::min(nzc, std::max(1, wz / 16)));
+        zc = (wz + nzc - 1) / nzc;
+    }
+    if (zc <= 0) zc = 1 << 30;
+    long long nb = 0;
+    for (int i = 0; i < bl.nbox; ++i) {
+        Box &x = bl.b[i];
+        x.zchunk = std::min(zc, x.z1 - x.z0);
+        x.nzc = (x.z1 - x.z0 + x.zchunk - 1) / x.zchunk;
+        x.nblk = x.ntx * x.nty * x.nzc;
+        nb += x.nblk;
+    }
+    if (nb >= (1ll << 31)) return RTM_EINVAL;
+    bl.nblk = (int)nb;
+    bl.remap = g_opt.xcd_remap.load(std::memory_order_relaxed);
+    hipLaunchKernelGGL((k_tiled<R, BX, BY>), dim3((unsigned)nb), dim3(BX * BY), 0, st, g, un, uc, up, kap, bl);
+    return launch_status();
+}
+
+template <int R>
+int launch_tiled_variant(int var, const Geo &g, float *un, const float *uc, const float *up, const float *kap,
+                         const int (*boxes)[6], int nbox, hipStream_t st)
+{
+    switch (var) {
+    case 1: return launch_tiled<R, 32, 8>(g, un, uc, up, kap, boxes, nbox, st);
+    case 2: return launch_tiled<R, 16, 8>(g, un, uc, up, kap, boxes, nbox, st);
+    default: return launch_tiled<R, 16, 16>(g, un, uc, up, kap, boxes, nbox, st);
+    }
+}
+
+// The halo region: the two R-thick z slabs, the two hy-row y strips between them and the two wx-wide
+// x strips between those.  The widths depend only on the grid and the options (never on pointers),
+// so callers can tell which call updates a given cell (rtm_halo_region).
+struct Region {
+    int wx, hy, R;
+};
+
+Region halo_region(int nx, int ny, int R)
+{
+    Region r;
+    r.R = R;
+    r.wx = std::max(R, std::min(g_opt.halo_x_width.load(std::memory_order_relaxed), nx / 2));
+    r.hy = std::max(R, std::min(g_opt.halo_y_width.load(std::memory_order_relaxed), ny / 2));
+    return r;
+}
+
+int halo_boxes(const Geo &g, const Region &r, int boxes[6][6])
+{
+    const int nx = g.nx, ny = g.ny, nz = g.nz, R = r.R;
+    const int b[6][6] = {
+        {0, nx, 0, ny, 0, R},                        // -Z slab
+        {0, nx, 0, ny, nz - R, nz},                  // +Z slab
+        {0, nx, 0, r.hy, R, nz - R},                 // -Y strip
+        {0, nx, ny - r.hy, ny, R, nz - R},           // +Y strip
+        {0, r.wx, r.hy, ny - r.hy, R, nz - R},       // -X strip
+        {nx - r.wx, nx, r.hy, ny - r.hy, R, nz - R}, // +X strip
+    };
+    std::memcpy(boxes, b, sizeof(b));
+    return 6;
+}
+
+bool vector_path(const Geo &g, const float *un, const float *uc, const float *up, const float *kap)
+{
+    return g_opt.interior_variant.load(std::memory_order_relaxed) != 3 && aligned16(un) && aligned16(uc) &&
+           aligned16(up) && aligned16(kap) && (g.py % 4 == 0) && (g.pz % 4 == 0);
+}
+
+template <int R>
+int launch_box_scalar(const Geo &g, float *un, const float *uc, const float *up, const float *kap, const int *b,
+                      hipStream_t st)
+{
+    const long long n = (long long)std::max(0, b[1] - b[0]) * std::max(0, b[3] - b[2]) * std::max(0, b[5] - b[4]);
+    if (n <= 0) return RTM_OK;
+    hipLaunchKernelGGL((k_box<R>), dim3(blocks_for(n)), dim3(kThreads), 0, st, g, un, uc, up, kap, b[0], b[1], b[2],
+                       b[3], b[4], b[5]);
+    return launch_status();
+}
+
+template <int R>
+int launch_halo(const Geo &g, float *un, const float *uc, const float *up, const float *kap, hipStream_t st)
+{
+    const Region r = halo_region(g.nx, g.ny, R);
+    int boxes[6][6];
+    const int nb = halo_boxes(g, r, boxes);
+    if (vector_path(g, un, uc, up, kap)) return launch_tiled_variant<R>(0, g, un, uc, up, kap, boxes, nb, st);
+    for (int i = 0; i < nb; ++i) {
+        const int rc = launch_box_scalar<R>(g, un, uc, up, kap, boxes[i], st);
+        if (rc != RTM_OK) return rc;
+    }
+    return RTM_OK;
+}
+
+template <int R>
+int launch_interior(const Geo &g, float *un, const float *uc, const float *up, const float *kap, hipStream_t st)
+{
+    const Region r = halo_region(g.nx, g.ny, R);
+    const int boxes[1][6] = {{r.wx, g.nx - r.wx, r.hy, g.ny - r.hy, R, g.nz - R}};
+    if (vector_path(g, un, uc, up, kap)) {
+        const int var = g_opt.interior_variant.load(std::memory_order_relaxed);
+        return launch_tiled_variant<R>(var, g, un, uc, up, kap, boxes, 1, st);
+    }
+    return launch_box_scalar<R>(g, un, uc, up, kap, boxes[0], st);
+}
+
+bool faces_vec(const Geo &g, const float *u)
+{
+    return g.R == 4 && (g.nx % 4 == 0) && aligned16(u) && (g.py % 4 == 0) && (g.pz % 4 == 0);
+}
+
+int fill_face_offsets(const rtm_grid *gr, long long off[7])
+{
+    const long long R = gr->radius, nx = gr->nx, ny = gr->ny, nz = gr->nz;
+    const long long sz[6] = {R * ny * nz, R * ny * nz, nx * R * nz, nx * R * nz, nx * ny * R, nx * ny * R};
+    off[0] = 0;
+    for (int f = 0; f < 6; ++f) off[f + 1] = off[f] + sz[f];
+    return RTM_OK;
+}
+
+bool ranges_overlap(const void *a, long long na, const void *b, long long nb)
+{
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
+    const uintptr_t a1 = a0 + (uintptr_t)na * sizeof(float), b1 = b0 + (uintptr_t)nb * sizeof(float);
+    return a0 < b1 && b0 < a1;
+}
+
+}  // namespace
+
+// =============================================================================================
+// extern "C" entry points
+// =============================================================================================
+extern "C" {
+
+int rtm_abi_version(void) { return RTM_ABI_VERSION; }
+
+const char *rtm_strerror(int status)
+{
+    switch (status) {
+    case RTM_OK: return "ok";
+    case RTM_EINVAL: return "invalid argument (null pointer, radius, dimensions, pitches or count)";
+    case RTM_EALIAS: return "an output buffer overlaps an input it must not overlap";
+    case RTM_ELAUNCH: return "the HIP runtime reported an error at kernel launch";
+    case RTM_EDEVICE: return "no HIP device, or the current device is not gfx950";
+    default: return "unknown status";
+    }
+}
+
+int rtm_grid_init(rtm_grid *grid, int32_t nx, int32_t ny, int32_t nz, int32_t radius, int64_t pitch_y,
+                  int64_t pitch_z, const float *gx, const float *gy, const float *gz)
+{
+    if (!grid) return RTM_EINVAL;
+    rtm_grid g;
+    std::memset(&g, 0, sizeof(g));
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    g.radius = radius;
+    g.pitch_y = pitch_y;
+    g.pitch_z = pitch_z;
+    g.gx = gx;
+    g.gy = gy;
+    g.gz = gz;
+    // Centred Taylor weights of d2/dx2 on unit spacing (Fornberg 1988), as exact rationals.
+    if (radius == 4) {
+        const double c[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+        for (int m = 0; m < 5; ++m) g.c[m] = (float)c[m];
+    } else if (radius == 2) {
+        const double c[3] = {-5.0 / 2.0, 4.0 / 3.0, -1.0 / 12.0};
+        for (int m = 0; m < 3; ++m) g.c[m] = (float)c[m];
+    } else {
+        return RTM_EINVAL;
+    }
+    const int st = check_grid(&g);
+    if (st != RTM_OK) return st;
+    *grid = g;
+    return RTM_OK;
+}
+
+double rtm_stability_limit(int32_t radius)
+{
+    double s;
+    if (radius == 4)
+        s = 205.0 / 72.0 + 2.0 * (8.0 / 5.0 + 1.0 / 5.0 + 8.0 / 315.0 + 1.0 / 560.0);
+    else if (radius == 2)
+        s = 5.0 / 2.0 + 2.0 * (4.0 / 3.0 + 1.0 / 12.0);
+    else
+        return 0.0;
+    return 2.0 / std::sqrt(3.0 * s);
+}
+
+int rtm_sponge_profile(int32_t n, int32_t width, double alpha, float *out)
+{
+    if (n < 0 || width < 0 || !out) return RTM_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        double d = 0.0;
+        if (width > 0) d = std::max(0.0, std::max((double)(width - i), (double)(i - (n - 1 - width))));
+        out[i] = (float)std::exp(-(alpha * d) * (alpha * d));
+    }
+    return RTM_OK;
+}
+
+int rtm_ricker(int32_t nsteps, double dt, double fpeak, double t0, float *out)
+{
+    if (nsteps < 0 || !out) return RTM_EINVAL;
+    const double pi = 3.14159265358979323846;
+    for (int n = 0; n < nsteps; ++n) {
+        const double tau = n * dt - t0;
+        const double a = (pi * fpeak * tau) * (pi * fpeak * tau);
+        out[n] = (float)((1.0 - 2.0 * a) * std::exp(-a));
+    }
+    return RTM_OK;
+}
+
+int rtm_face_layout(const rtm_grid *grid, int64_t offsets[7])
+{
+    const int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (!offsets) return RTM_EINVAL;
+    long long off[7];
+    fill_face_offsets(grid, off);
+    for (int f = 0; f < 7; ++f) offsets[f] = off[f];
+    return RTM_OK;
+}
+
+int64_t rtm_index(const rtm_grid *grid, int32_t i, int32_t j, int32_t k)
+{
+    if (!grid) return -1;
+    const int R = grid->radius;
+    return (int64_t)(k + R) * grid->pitch_z + (int64_t)(j + R) * grid->pitch_y + (int64_t)(i + R);
+}
+
+static int step_common(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv, const float *kappa)
+{
+    int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (!u_nxt || !u_cur || !u_prv || !kappa) return RTM_EINVAL;
+    const long long tot = padded_total(grid);
+    if (ranges_overlap(u_nxt, tot, u_cur, tot) || ranges_overlap(u_nxt, tot, kappa, tot)) return RTM_EALIAS;
+    if (u_nxt != u_prv && ranges_overlap(u_nxt, tot, u_prv, tot)) return RTM_EALIAS;
+    return check_device();
+}
+
+int rtm_step_halo(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv, const float *kappa,
+                  hipStream_t stream)
+{
+    const int st = step_common(grid, u_nxt, u_cur, u_prv, kappa);
+    if (st != RTM_OK) return st;
+    const Geo g = make_geo(grid);
+    return g.R == 4 ? launch_halo<4>(g, u_nxt, u_cur, u_prv, kappa, stream)
+                    : launch_halo<2>(g, u_nxt, u_cur, u_prv, kappa, stream);
+}
+
+int rtm_step_interior(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv,
+                      const float *kappa, hipStream_t stream)
+{
+    const int st = step_common(grid, u_nxt, u_cur, u_prv, kappa);
+    if (st != RTM_OK) return st;
+    const Geo g = make_geo(grid);
+    return g.R == 4 ? launch_interior<4>(g, u_nxt, u_cur, u_prv, kappa, stream)
+                    : launch_interior<2>(g, u_nxt, u_cur, u_prv, kappa, stream);
+}
+
+int rtm_pack_halo(const rtm_grid *grid, const float *u, float *faces, hipStream_t stream)
+{
+    int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (!u || !faces) return RTM_EINVAL;
+    FaceOffsets fo;
+    fill_face_offsets(grid, fo.off);
+    for (int f = 0; f < 6; ++f)
+        if (fo.off[f + 1] - fo.off[f] >= (1ll << 31)) return RTM_EINVAL;
+    if (ranges_overlap(faces, fo.off[6], u, padded_total(grid))) return RTM_EALIAS;
+    st = check_device();
+    if (st != RTM_OK) return st;
+    const Geo g = make_geo(grid);
+    long long mx = 0;
+    for (int f = 0; f < 6; ++f) mx = std::max(mx, fo.off[f + 1] - fo.off[f]);
+    if (faces_vec(g, u) && aligned16(faces)) {
+        hipLaunchKernelGGL(k_pack4, dim3(blocks_for(mx / 4), 6), dim3(kThreads), 0, stream, g, u, faces, fo);
+    } else {
+        hipLaunchKernelGGL(k_pack, dim3(blocks_for(mx), 6), dim3(kThreads), 0, stream, g, u, faces, fo);
+    }
+    return launch_status();
+}
+
+int rtm_unpack_halo(const rtm_grid *grid, float *u, const float *const faces[6], hipStream_t stream)
+{
+    int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (!u || !faces) return RTM_EINVAL;
+    long long off[7];
+    fill_face_offsets(grid, off);
+    for (int f = 0; f < 6; ++f)
+        if (off[f + 1] - off[f] >= (1ll << 31)) return RTM_EINVAL;
+    FacePtrs fp;
+    const long long tot = padded_total(grid);
+    for (int f = 0; f < 6; ++f) {
+        fp.p[f] = faces[f];
+        if (faces[f] && ranges_overlap(faces[f], off[f + 1] - off[f], u, tot)) return RTM_EALIAS;
+    }
+    st = check_device();
+    if (st != RTM_OK) return st;
+    const Geo g = make_geo(grid);
+    long long mx = 0;
+    for (int f = 0; f < 6; ++f) mx = std::max(mx, off[f + 1] - off[f]);
+    bool vec = faces_vec(g, u);
+    for (int f = 0; f < 6; ++f) vec = vec && (fp.p[f] == nullptr || aligned16(fp.p[f]));
+    if (vec) {
+        hipLaunchKernelGGL(k_unpack4, dim3(blocks_for(mx / 4), 6), dim3(kThreads), 0, stream, g, u, fp);
+    } else {
+        hipLaunchKernelGGL(k_unpack, dim3(blocks_for(mx), 6), dim3(kThreads), 0, stream, g, u, fp);
+    }
+    return launch_status();
+}
+
+int rtm_inject(const rtm_grid *grid, float *u, const int64_t *idx, const float *w, const float *amp, int32_t n,
+               hipStream_t stream)
+{
+    int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (n < 0) return RTM_EINVAL;
+    if (n == 0) return RTM_OK;
+    if (!u || !idx || !w || !amp) return RTM_EINVAL;
+    st = check_device();
+    if (st != RTM_OK) return st;
+    hipLaunchKernelGGL(k_inject, dim3(blocks_for(n)), dim3(kThreads), 0, stream, u, padded_total(grid), idx, w, amp,
+                       (int)n);
+    return launch_status();
+}
+
+int rtm_record(const rtm_grid *grid, const float *u, const int64_t *idx, float *out, int32_t n, hipStream_t stream)
+{
+    int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (n < 0) return RTM_EINVAL;
+    if (n == 0) return RTM_OK;
+    if (!u || !idx || !out) return RTM_EINVAL;
+    st = check_device();
+    if (st != RTM_OK) return st;
+    hipLaunchKernelGGL(k_record, dim3(blocks_for(n)), dim3(kThreads), 0, stream, u, padded_total(grid), idx, out,
+                       (int)n);
+    return launch_status();
+}
+
+int rtm_image_accumulate(const rtm_grid *grid, float *image, const float *src, const float *rcv, float weight,
+                         hipStream_t stream)
+{
+    int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (!image || !src || !rcv) return RTM_EINVAL;
+    const long long tot = padded_total(grid);
+    if (ranges_overlap(image, tot, src, tot) || ranges_overlap(image, tot, rcv, tot)) return RTM_EALIAS;
+    st = check_device();
+    if (st != RTM_OK) return st;
+    const Geo g = make_geo(grid);
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_image, dim3(blocks_for(n)), dim3(kThreads), 0, stream, g, image, src, rcv, weight);
+    return launch_status();
+}
+
+int rtm_kappa_from_velocity(const rtm_grid *grid, float *kappa, const float *v, float dt_over_h, hipStream_t stream)
+{
+    int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (!kappa || !v) return RTM_EINVAL;
+    const long long n = (long long)grid->nx * grid->ny * grid->nz;
+    if (ranges_overlap(kappa, padded_total(grid), v, n)) return RTM_EALIAS;
+    st = check_device();
+    if (st != RTM_OK) return st;
+    const Geo g = make_geo(grid);
+    hipLaunchKernelGGL(k_kappa, dim3(blocks_for(n)), dim3(kThreads), 0, stream, g, kappa, v, dt_over_h);
+    return launch_status();
+}
+
+int rtm_halo_region(const rtm_grid *grid, int32_t widths[3])
+{
+    const int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (!widths) return RTM_EINVAL;
+    const Region r = halo_region(grid->nx, grid->ny, grid->radius);
+    widths[0] = r.wx;
+    widths[1] = r.hy;
+    widths[2] = r.R;
+    return RTM_OK;
+}
+
+int rtm_set_option(int32_t option, int32_t value)
+{
+    switch (option) {
+    case RTM_OPT_INTERIOR_VARIANT:
+        if (value < 0 || value > 3) return RTM_EINVAL;
+        g_opt.interior_variant.store(value);
+        return RTM_OK;
+    case RTM_OPT_ZCHUNK:
+        if (value < 0) return RTM_EINVAL;
+        g_opt.zchunk.store(value);
+        return RTM_OK;
+    case RTM_OPT_XCD_REMAP:
+        g_opt.xcd_remap.store(value ? 1 : 0);
+        return RTM_OK;
+    case RTM_OPT_HALO_X_WIDTH:
+        if (value < 1) return RTM_EINVAL;
+        g_opt.halo_x_width.store(value);
+        return RTM_OK;
+    case RTM_OPT_HALO_Y_WIDTH:
+        if (value < 1) return RTM_EINVAL;
+        g_opt.halo_y_width.store(value);
+        return RTM_OK;
+    default: return RTM_EINVAL;
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,210 @@
+"""Time stepping of one subdomain: the per-step phase sequence of the paper's section II.
+
+One step n (u^{n+1} from u^n and u^{n-1}) runs, in the default "overlap" schedule, on two HIP
+streams like the paper's halo-first schedule with a communication thread:
+
+    halo stream H:      wait(interior n-1) -> rtm_step_halo -> inject shell sources -> [halo done]
+                        -> rtm_pack_halo -> exchange -> rtm_unpack_halo
+    interior stream I:  rtm_step_interior -> inject interior sources -> wait(halo done)
+                        -> rtm_record -> [level n+1 complete]
+
+The exchange is where a multi-GPU run would send the packed faces; one subdomain uses its physical
+boundary (NULL slots: zero ghosts) or a periodic self-exchange (slot f receives the opposite face,
+a pointer swap with no copy).  Time levels rotate by pointer: by default u^{n+1} overwrites
+u^{n-1} in place (two buffers), and a level that must outlive the rotation (an RTM snapshot) is
+"pinned" so that the next write goes to a fresh buffer instead of copying it.
+
+The "serial" schedule runs the same calls on one stream; both give bitwise identical fields.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _abi
+from .grid import Grid
+
+OPPOSITE = [1, 0, 3, 2, 5, 4]
+
+
+class Sources:
+    """Point sources (or receivers re-injecting data): cells, weights and an amplitude table.
+
+    amp has shape (nsteps, n): row n is injected after step n.  On the device the sources are split
+    into the cells the halo call updates and the rest, so that each source is added on the stream
+    that wrote its cell, and halo-region sources before the pack."""
+
+    def __init__(self, grid: Grid, ijk, weights, amp, reverse_time: bool = False):
+        ijk = np.asarray(ijk, dtype=np.int64).reshape(-1, 3)
+        w = np.asarray(weights, dtype=np.float32).reshape(-1)
+        if isinstance(amp, torch.Tensor):
+            amp_t = amp.to(device=grid.device, dtype=torch.float32)
+        else:
+            amp_t = torch.from_numpy(np.ascontiguousarray(amp, dtype=np.float32)).to(grid.device)
+        amp_t = amp_t.reshape(-1, len(w))
+        if reverse_time:
+            amp_t = torch.flip(amp_t, dims=[0])
+        self.nsteps = amp_t.shape[0]
+        shell = grid.in_halo(ijk)
+        self.sets = []
+        for mask in (shell, ~shell):
+            sel = np.nonzero(mask)[0]
+            if len(sel) == 0:
+                self.sets.append(None)
+                continue
+            idx = torch.from_numpy(grid.index(ijk[sel])).to(grid.device)
+            ww = torch.from_numpy(w[sel]).to(grid.device)
+            a = amp_t[:, torch.from_numpy(sel).to(grid.device)].contiguous()
+            self.sets.append((idx, ww, a))
+
+    def inject(self, grid: Grid, u: torch.Tensor, n: int, which: int, stream):
+        s = self.sets[which]
+        if s is None or n >= self.nsteps:
+            return
+        idx, w, a = s
+        cnt = idx.numel()
+        _abi.rtm_inject(grid.c, u, idx, w, a.data_ptr() + 4 * n * cnt, cnt, stream)
+
+
+class Propagator:
+    def __init__(self, grid: Grid, kappa: torch.Tensor, *, sources: Sources | list | None = None,
+                 receivers=None, boundary: str = "zero", schedule: str = "overlap"):
+        self.grid = grid
+        self.kappa = kappa
+        if sources is None:
+            sources = []
+        self.sources = sources if isinstance(sources, list) else [sources]
+        self.rec_idx = None
+        if receivers is not None and len(np.asarray(receivers).reshape(-1, 3)):
+            self.rec_idx = torch.from_numpy(grid.index(receivers)).to(grid.device)
+        self.nrec = 0 if self.rec_idx is None else self.rec_idx.numel()
+        if boundary not in ("zero", "periodic"):
+            raise ValueError(boundary)
+        self.boundary = boundary
+        if schedule not in ("overlap", "serial"):
+            raise ValueError(schedule)
+        self.schedule = schedule
+        self.u_prv = grid.field()
+        self.u_cur = grid.field()
+        self.pinned: set[int] = set()
+        self.pool: list[torch.Tensor] = []
+        self.send = grid.faces()
+        slots = grid.face_slots(self.send)
+        self.recv = [None] * 6 if boundary == "zero" else [slots[OPPOSITE[f]] for f in range(6)]
+        self.n = 0
+        self.sH = torch.cuda.Stream(device=grid.device)
+        self.sI = torch.cuda.Stream(device=grid.device)
+        self._ev_int = None
+        self.interior_events = None   # list of (start, end) timing events around rtm_step_interior
+
+    # ------------------------------------------------------------------------------------------
+    def set_state(self, u_cur_host=None, u_prv_host=None, n: int = 0):
+        """Load (u^n, u^{n-1}) from host arrays (None = zero) and fill the ghosts of u^n."""
+        g = self.grid
+        self.u_cur.zero_()
+        self.u_prv.zero_()
+        if u_cur_host is not None:
+            g.upload(u_cur_host, self.u_cur)
+        if u_prv_host is not None:
+            g.upload(u_prv_host, self.u_prv)
+        self.n = n
+        self.exchange_ghosts(self.u_cur)
+
+    def exchange_ghosts(self, u: torch.Tensor, stream=None):
+        """Pack, exchange and unpack the faces of an existing level (used to prime u^0)."""
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _abi.rtm_pack_halo(self.grid.c, u, self.send, st)
+        _abi.rtm_unpack_halo(self.grid.c, u, self.recv, st)
+
+    def pin_current(self):
+        """Keep the buffer of the newest level: later steps will not write into it."""
+        self.pinned.add(self.u_cur.data_ptr())
+        return self.u_cur
+
+    def unpin(self, t: torch.Tensor, recycle: bool = True):
+        self.pinned.discard(t.data_ptr())
+        if recycle:
+            self.pool.append(t)
+
+    def _next_buffer(self) -> torch.Tensor:
+        if self.u_prv.data_ptr() not in self.pinned:
+            return self.u_prv                       # in-place over u^{n-1}
+        return self.pool.pop() if self.pool else self.grid.field(fill=None)
+
+    # ------------------------------------------------------------------------------------------
+    def step(self, traces: torch.Tensor | None = None):
+        """Advance one step; record into row n of `traces` (device, shape (nsteps, nrec)) if given."""
+        g, c = self.grid, self.grid.c
+        u_nxt = self._next_buffer()
+        u_cur, u_prv, kap = self.u_cur, self.u_prv, self.kappa
+        n = self.n
+        tr_ptr = None if traces is None or self.nrec == 0 else traces.data_ptr() + 4 * n * self.nrec
+        if self.schedule == "serial":
+            st = torch.cuda.current_stream()
+            _abi.rtm_step_halo(c, u_nxt, u_cur, u_prv, kap, st)
+            _abi.rtm_step_interior(c, u_nxt, u_cur, u_prv, kap, st)
+            for s in self.sources:
+                s.inject(g, u_nxt, n, 0, st)
+                s.inject(g, u_nxt, n, 1, st)
+            _abi.rtm_pack_halo(c, u_nxt, self.send, st)
+            _abi.rtm_unpack_halo(c, u_nxt, self.recv, st)
+            if tr_ptr is not None:
+                _abi.rtm_record(c, u_nxt, self.rec_idx, tr_ptr, self.nrec, st)
+        else:
+            sH, sI = self.sH, self.sI
+            if self._ev_int is not None:
+                sH.wait_event(self._ev_int)
+            else:
+                sH.wait_stream(torch.cuda.current_stream())
+                sI.wait_stream(torch.cuda.current_stream())
+            _abi.rtm_step_halo(c, u_nxt, u_cur, u_prv, kap, sH)
+            for s in self.sources:
+                s.inject(g, u_nxt, n, 0, sH)
+            ev_halo = torch.cuda.Event()
+            ev_halo.record(sH)
+            _abi.rtm_pack_halo(c, u_nxt, self.send, sH)
+            _abi.rtm_unpack_halo(c, u_nxt, self.recv, sH)
+            if self.interior_events is not None:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(sI)
+                _abi.rtm_step_interior(c, u_nxt, u_cur, u_prv, kap, sI)
+                e1.record(sI)
+                self.interior_events.append((e0, e1))
+            else:
+                _abi.rtm_step_interior(c, u_nxt, u_cur, u_prv, kap, sI)
+            for s in self.sources:
+                s.inject(g, u_nxt, n, 1, sI)
+            sI.wait_event(ev_halo)
+            if tr_ptr is not None:
+                _abi.rtm_record(c, u_nxt, self.rec_idx, tr_ptr, self.nrec, sI)
+            ev_int = torch.cuda.Event()
+            ev_int.record(sI)
+            self._ev_int = ev_int
+        self.u_prv, self.u_cur = self.u_cur, u_nxt
+        self.n = n + 1
+
+    @property
+    def level_stream(self):
+        """Stream on which the newest level is complete (for work that reads it)."""
+        return torch.cuda.current_stream() if self.schedule == "serial" else self.sI
+
+    def sync(self):
+        """Make the caller's current stream wait for everything enqueued so far."""
+        if self.schedule == "overlap":
+            cur = torch.cuda.current_stream()
+            cur.wait_stream(self.sH)
+            cur.wait_stream(self.sI)
+            self._ev_int = None
+
+    def run(self, nsteps: int, traces: torch.Tensor | None = None, on_level=None):
+        """Run nsteps steps.  on_level(k, prop) is called after the step that produced level k, with
+        prop.level_stream ready for work that reads u^k (prop.u_cur)."""
+        for _ in range(nsteps):
+            self.step(traces)
+            if on_level is not None:
+                on_level(self.n, self)
+        self.sync()
+        return traces
+
+    def new_traces(self, nsteps: int) -> torch.Tensor:
+        return torch.zeros((nsteps, max(self.nrec, 1)), dtype=torch.float32, device=self.grid.device)

@@ -1,0 +1,108 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol, validates arguments
+before touching a device, and its host helpers agree with the oracle's independent definitions."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "rtm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rtm_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def abi():
+    from paper_1603_03971_amd import _abi
+    return _abi
+
+
+def test_exports_every_declared_symbol(abi):
+    names = _declared_functions()
+    assert "rtm_step_halo" in names and "rtm_image_accumulate" in names
+    for name in names:
+        assert hasattr(abi.lib, name), name
+    assert abi.rtm_abi_version() == 1
+
+
+def test_python_binding_has_same_names(abi):
+    for name in _declared_functions():
+        assert callable(getattr(abi, name)), name
+
+
+def test_strerror(abi):
+    for code in (0, -1, -2, -3, -4):
+        assert abi.rtm_strerror(code)
+    assert "unknown" in abi.rtm_strerror(-99)
+
+
+def _grid(abi, nx=16, ny=12, nz=10, radius=4, pitch_y=None, pitch_z=None, sponge=True):
+    py = pitch_y if pitch_y is not None else nx + 2 * radius
+    pz = pitch_z if pitch_z is not None else py * (ny + 2 * radius)
+    fake = 0x1000 if sponge else None  # host-side validation never dereferences the sponge pointers
+    return abi.rtm_grid_init(nx, ny, nz, radius, py, pz, fake, fake, fake)
+
+
+def test_grid_init_coefficients(abi):
+    g = _grid(abi)
+    np.testing.assert_allclose(np.array(g.c), oracle.fd_coefficients(4).astype(np.float32), rtol=0, atol=0)
+    g2 = _grid(abi, radius=2)
+    np.testing.assert_allclose(np.array(g2.c)[:3], oracle.fd_coefficients(2).astype(np.float32), rtol=0, atol=0)
+
+
+@pytest.mark.parametrize("kw", [dict(radius=3), dict(nx=7), dict(nz=3, radius=2), dict(pitch_y=20),
+                                dict(pitch_z=100), dict(sponge=False)])
+def test_grid_init_rejects(abi, kw):
+    with pytest.raises(abi.RTMError) as e:
+        _grid(abi, **kw)
+    assert e.value.status == abi.RTM_EINVAL
+
+
+def test_validation_before_device(abi):
+    """Argument errors are reported without any device call (these run on a machine with no GPU)."""
+    g = _grid(abi)
+    L = abi.lib
+    gp = ctypes.byref(g)
+    assert L.rtm_step_halo(None, 16, 32, 48, 64, None) == abi.RTM_EINVAL
+    assert L.rtm_step_halo(gp, None, 32, 48, 64, None) == abi.RTM_EINVAL
+    assert L.rtm_step_interior(gp, 16, 16, 48, 64, None) == abi.RTM_EALIAS          # u_nxt == u_cur
+    total = g.pitch_z * (g.nz + 8)
+    assert L.rtm_step_interior(gp, 4096, 4096 + 8, 4096 * 1000, 4096 * 2000, None) == abi.RTM_EALIAS
+    assert L.rtm_pack_halo(gp, None, 4096, None) == abi.RTM_EINVAL
+    assert L.rtm_pack_halo(gp, 4096, 4096 + 4 * total - 64, None) == abi.RTM_EALIAS
+    assert L.rtm_inject(gp, 4096, 64, 64, 64, -1, None) == abi.RTM_EINVAL
+    assert L.rtm_inject(gp, 4096, 64, 64, 64, 0, None) == abi.RTM_OK                # nothing to do
+    assert L.rtm_record(gp, 4096, 64, 64, -5, None) == abi.RTM_EINVAL
+    assert L.rtm_image_accumulate(gp, 4096, 4096, 1 << 40, 1.0, None) == abi.RTM_EALIAS
+    assert L.rtm_set_option(99, 0) == abi.RTM_EINVAL
+    assert L.rtm_set_option(abi.RTM_OPT_INTERIOR_VARIANT, 7) == abi.RTM_EINVAL
+
+
+def test_face_layout_and_index(abi):
+    g = _grid(abi, nx=16, ny=12, nz=10)
+    off = abi.rtm_face_layout(g)
+    R = 4
+    sizes = [R * 12 * 10, R * 12 * 10, 16 * R * 10, 16 * R * 10, 16 * 12 * R, 16 * 12 * R]
+    assert off == list(np.concatenate([[0], np.cumsum(sizes)]))
+    assert abi.rtm_index(g, 0, 0, 0) == R * g.pitch_z + R * g.pitch_y + R
+    assert abi.rtm_index(g, 3, 2, 1) - abi.rtm_index(g, 0, 0, 0) == 3 + 2 * g.pitch_y + g.pitch_z
+
+
+def test_host_helpers_match_oracle(abi):
+    for r in (2, 4):
+        assert abs(abi.rtm_stability_limit(r) - oracle.stability_limit(r)) < 1e-15
+    assert abi.rtm_stability_limit(3) == 0.0
+    for n, w, a in ((64, 16, 0.015), (40, 0, 0.015), (100, 30, 0.02)):
+        np.testing.assert_allclose(abi.rtm_sponge_profile(n, w, a), oracle.sponge_profile(n, w, a).astype(np.float32),
+                                   rtol=0, atol=0)
+    dt = 1.1321388e-3
+    t = np.arange(300) * dt
+    np.testing.assert_allclose(abi.rtm_ricker(300, dt, 15.0, 0.1), oracle.ricker(t, 15.0, 0.1).astype(np.float32),
+                               rtol=0, atol=2e-7)

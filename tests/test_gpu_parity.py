@@ -1,0 +1,246 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the same seeded inputs.
+
+Bars: FP32 wavefields within 1e-4 relative L2 of the oracle, images within 1e-3; copies (pack,
+unpack, record) and schedule/variant comparisons bitwise.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import problems
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1603_03971_amd import _abi  # noqa: F401  (fails loudly if the library is not built)
+    return torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def test_c1_point_source_parity(torch_cuda):
+    """64^3 constant-velocity point source, 200 steps: final wavefield and traces vs the oracle."""
+    v, h, nsteps, src = problems.c1_inputs()
+    rec = [(32, 32, 8), (40, 32, 32), (32, 20, 32), (12, 50, 33)]
+    _say("c1: gpu")
+    gpu = problems.gpu_forward_problem(v, h, nsteps, src, rec_ijk=rec)
+    _say("c1: oracle")
+    ref = problems.oracle_forward_problem(v, h, nsteps, src, rec_ijk=rec)
+    e_u = problems.rel_l2(gpu["u_cur"], ref["u_cur"])
+    e_p = problems.rel_l2(gpu["u_prv"], ref["u_prv"])
+    e_t = problems.rel_l2(gpu["traces"], ref["traces"])
+    _say(f"c1 rel-L2: u^N {e_u:.3e}  u^N-1 {e_p:.3e}  traces {e_t:.3e}")
+    assert e_u <= 1e-4 and e_p <= 1e-4 and e_t <= 1e-4
+
+
+@pytest.mark.parametrize("schedule", ["overlap", "serial"])
+def test_ragged_layered_parity(torch_cuda, schedule):
+    """150 x 41 x 70 (ragged against every tile size), layered medium, sources inside and in the shell."""
+    v, h, nsteps, src = problems.ragged_inputs()
+    rec = [(1, 1, 1), (149, 40, 69), (75, 20, 35), (3, 39, 66)]
+    _say(f"ragged {schedule}: gpu")
+    gpu = problems.gpu_forward_problem(v, h, nsteps, src, rec_ijk=rec, schedule=schedule)
+    ref = problems.oracle_forward_problem(v, h, nsteps, src, rec_ijk=rec)
+    e_u = problems.rel_l2(gpu["u_cur"], ref["u_cur"])
+    e_t = problems.rel_l2(gpu["traces"], ref["traces"])
+    _say(f"ragged {schedule} rel-L2: u {e_u:.3e} traces {e_t:.3e}")
+    assert e_u <= 1e-4 and e_t <= 1e-4
+
+
+def test_schedules_and_variants_bitwise(torch_cuda):
+    """Halo-first on two streams, single stream, every interior kernel variant and z chunking, and
+    unaligned pitches (scalar path) all give the same bits."""
+    from paper_1603_03971_amd import _abi
+
+    v, h, nsteps, src = problems.ragged_inputs(seed=9)
+    nsteps = 30
+    base = problems.gpu_forward_problem(v, h, nsteps, src, schedule="serial")["u_cur"]
+    runs = {}
+    try:
+        runs["overlap"] = problems.gpu_forward_problem(v, h, nsteps, src, schedule="overlap")["u_cur"]
+        for var in (1, 2, 3):
+            _abi.rtm_set_option(_abi.RTM_OPT_INTERIOR_VARIANT, var)
+            runs[f"variant{var}"] = problems.gpu_forward_problem(v, h, nsteps, src)["u_cur"]
+        _abi.rtm_set_option(_abi.RTM_OPT_INTERIOR_VARIANT, 0)
+        for zc in (1, 7, 1000):
+            _abi.rtm_set_option(_abi.RTM_OPT_ZCHUNK, zc)
+            runs[f"zchunk{zc}"] = problems.gpu_forward_problem(v, h, nsteps, src)["u_cur"]
+        _abi.rtm_set_option(_abi.RTM_OPT_ZCHUNK, 0)
+        _abi.rtm_set_option(_abi.RTM_OPT_XCD_REMAP, 0)
+        runs["noremap"] = problems.gpu_forward_problem(v, h, nsteps, src)["u_cur"]
+        _abi.rtm_set_option(_abi.RTM_OPT_XCD_REMAP, 1)
+        runs["x_align4"] = problems.gpu_forward_problem(v, h, nsteps, src, x_align=4)["u_cur"]
+        runs["unaligned_pitch"] = problems.gpu_forward_problem(v, h, nsteps, src, x_align=1)["u_cur"]
+    finally:
+        _abi.rtm_set_option(_abi.RTM_OPT_INTERIOR_VARIANT, 0)
+        _abi.rtm_set_option(_abi.RTM_OPT_ZCHUNK, 0)
+        _abi.rtm_set_option(_abi.RTM_OPT_XCD_REMAP, 1)
+    assert np.any(base != 0)
+    for name, u in runs.items():
+        assert np.array_equal(u, base), name
+
+
+def test_halo_and_interior_partition_owned_cells(torch_cuda):
+    """NaN-poisoned output: halo then interior write every owned cell exactly once (all finite), and
+    neither touches a ghost cell."""
+    torch = torch_cuda
+    from paper_1603_03971_amd import _abi
+    from paper_1603_03971_amd.grid import Grid
+
+    for (nx, ny, nz) in ((150, 41, 70), (8, 8, 8), (9, 21, 13), (64, 64, 64), (200, 19, 12)):
+        g = Grid(nx, ny, nz, 10.0, 1e-3)
+        rng = np.random.default_rng(nx)
+        u = g.upload(rng.standard_normal((nz, ny, nx)))
+        up = g.upload(rng.standard_normal((nz, ny, nx)))
+        kap = g.upload(rng.uniform(0.01, 0.05, (nz, ny, nx)))
+        out = g.field(fill=float("nan"))
+        s = torch.cuda.current_stream()
+        _abi.rtm_step_halo(g.c, out, u, up, kap, s)
+        halo_only = g.owned(out).clone()
+        _abi.rtm_step_interior(g.c, out, u, up, kap, s)
+        torch.cuda.synchronize()
+        own = g.owned(out)
+        assert torch.isfinite(own).all(), (nx, ny, nz)
+        # the halo call wrote the R-shell widened to x strips of min(64, nx // 2) cells and y strips
+        # of min(16, ny // 2) rows
+        R, wx, hy = 4, max(4, min(64, nx // 2)), max(4, min(16, ny // 2))
+        assert _abi.rtm_halo_region(g.c) == (wx, hy, R)
+        shell = torch.zeros((nz, ny, nx), dtype=torch.bool, device=out.device)
+        shell[:R] = True
+        shell[-R:] = True
+        shell[:, :hy] = True
+        shell[:, -hy:] = True
+        shell[:, :, :wx] = True
+        shell[:, :, nx - wx:] = True
+        assert torch.equal(torch.isfinite(halo_only), shell)
+        pad = g.padded(out)
+        ghost = torch.ones_like(pad, dtype=torch.bool)
+        ghost[R:R + nz, R:R + ny, R:R + nx] = False
+        assert torch.isnan(pad[ghost]).all()
+
+
+def test_pack_unpack_bitwise(torch_cuda):
+    torch = torch_cuda
+    from paper_1603_03971_amd import _abi
+    from paper_1603_03971_amd.grid import Grid
+
+    nx, ny, nz = 37, 22, 19
+    g = Grid(nx, ny, nz, 10.0, 1e-3)
+    host = np.random.default_rng(3).standard_normal((nz, ny, nx)).astype(np.float32)
+    u = g.upload(host)
+    faces = g.faces()
+    s = torch.cuda.current_stream()
+    _abi.rtm_pack_halo(g.c, u, faces, s)
+    torch.cuda.synchronize()
+    got = g.face_slots(faces)
+    want = oracle.pack_faces(host.astype(np.float64))
+    for f in range(6):
+        assert np.array_equal(got[f].cpu().numpy(), want[f].astype(np.float32)), f
+    # unpack random slots into the ghosts; NULL slots give zeros
+    slots = [torch.from_numpy(np.random.default_rng(10 + f).standard_normal(g.face_sizes[f]).astype(np.float32)).cuda()
+             for f in range(6)]
+    w = g.field(fill=7.0)
+    _abi.rtm_unpack_halo(g.c, w, slots, s)
+    z = g.field(fill=7.0)
+    _abi.rtm_unpack_halo(g.c, z, [None] * 6, s)
+    torch.cuda.synchronize()
+    pad = g.padded(w).cpu().numpy()
+    padz = g.padded(z).cpu().numpy()
+    R = 4
+    sl = [s_.cpu().numpy() for s_ in slots]
+    ghost_blocks = [
+        pad[R:R + nz, R:R + ny, 0:R], pad[R:R + nz, R:R + ny, R + nx:],
+        pad[R:R + nz, 0:R, R:R + nx], pad[R:R + nz, R + ny:, R:R + nx],
+        pad[0:R, R:R + ny, R:R + nx], pad[R + nz:, R:R + ny, R:R + nx],
+    ]
+    for f in range(6):
+        assert np.array_equal(ghost_blocks[f].ravel(), sl[f]), f
+    assert np.all(pad[R:R + nz, R:R + ny, R:R + nx] == 7.0)     # owned untouched
+    assert pad[0, 0, 0] == 7.0                                    # corners untouched
+    assert np.all(padz[R:R + nz, R:R + ny, 0:R] == 0.0)
+
+
+def test_periodic_standing_wave(torch_cuda):
+    """Periodic self-exchange (slot swap): the discrete dispersion relation's closed form and the
+    oracle's periodic mode."""
+    torch = torch_cuda
+    from paper_1603_03971_amd.grid import Grid
+    from paper_1603_03971_amd.propagator import Propagator
+
+    nx, ny, nz, h, v = 48, 24, 40, 10.0, 2000.0
+    p0, (kx, ky, kz) = problems.plane_standing_wave(nx, ny, nz, h, v, (3, 2, 5))
+    dt = Grid.stable_dt(4, h, v)
+    c = [-205 / 72, 8 / 5, -1 / 5, 8 / 315, -1 / 560]
+    sym = lambda t: c[0] + 2 * sum(c[m] * math.cos(m * t) for m in range(1, 5))
+    lam = sym(kx * h) + sym(ky * h) + sym(kz * h)
+    w = 2 / dt * math.asin(v * dt / (2 * h) * math.sqrt(-lam))
+    g = Grid(nx, ny, nz, h, dt, sponge_width=0)
+    kap = g.kappa_from_velocity(np.full((nz, ny, nx), v))
+    nsteps = 200
+    for schedule in ("overlap", "serial"):
+        prop = Propagator(g, kap, boundary="periodic", schedule=schedule)
+        prop.set_state(p0, p0 * math.cos(w * dt))
+        prop.run(nsteps)
+        torch.cuda.synchronize()
+        u = g.download(prop.u_cur).astype(np.float64)
+        exact = p0 * math.cos(w * nsteps * dt)
+        err = np.max(np.abs(u - exact))
+        _say(f"periodic {schedule}: max err vs closed form {err:.3e}")
+        assert err < 2e-5
+    ref = oracle.forward(oracle.kappa_field(np.full((nz, ny, nx), v), dt, h), None, nsteps, u_cur=p0,
+                         u_prv=p0 * math.cos(w * dt), periodic=True, nthreads=8)
+    assert problems.rel_l2(u, ref["u_cur"]) < 1e-4
+
+
+def test_inject_and_record_exact(torch_cuda):
+    torch = torch_cuda
+    from paper_1603_03971_amd import _abi
+    from paper_1603_03971_amd.grid import Grid
+
+    g = Grid(20, 18, 16, 10.0, 1e-3)
+    u = g.field()
+    cells = np.array([[1, 2, 3], [19, 17, 15], [1, 2, 3], [10, 9, 8]])
+    idx = torch.from_numpy(g.index(cells)).cuda()
+    w = torch.tensor([0.5, 2.0, 0.25, -1.0], device="cuda")
+    amp = torch.tensor([2.0, 3.0, 4.0, 5.0], device="cuda")
+    s = torch.cuda.current_stream()
+    _abi.rtm_inject(g.c, u, idx, w, amp, 4, s)
+    out = torch.zeros(4, device="cuda")
+    _abi.rtm_record(g.c, u, idx, out, 4, s)
+    bad = torch.tensor([-5, g.total + 10], dtype=torch.int64, device="cuda")
+    out2 = torch.full((2,), 9.0, device="cuda")
+    _abi.rtm_inject(g.c, u, bad, w[:2], amp[:2], 2, s)       # out-of-range indices are skipped
+    _abi.rtm_record(g.c, u, bad, out2, 2, s)
+    torch.cuda.synchronize()
+    assert out.cpu().tolist() == [2.0, 6.0, 2.0, -5.0]      # duplicate cell sums 1.0 + 1.0
+    assert out2.cpu().tolist() == [0.0, 0.0]
+    host = g.download(u)
+    assert np.count_nonzero(host) == 3
+
+
+def test_image_and_kappa_kernels(torch_cuda):
+    torch = torch_cuda
+    from paper_1603_03971_amd import _abi
+    from paper_1603_03971_amd.grid import Grid
+
+    nx, ny, nz = 45, 30, 21
+    g = Grid(nx, ny, nz, 10.0, 7e-4)
+    rng = np.random.default_rng(4)
+    a, b, i0 = rng.standard_normal((3, nz, ny, nx))
+    img = g.upload(i0)
+    _abi.rtm_image_accumulate(g.c, img, g.upload(a), g.upload(b), 0.75, torch.cuda.current_stream())
+    vel = rng.uniform(1500, 4500, (nz, ny, nx))
+    kap = g.kappa_from_velocity(vel)
+    torch.cuda.synchronize()
+    a32, b32, i32 = (x.astype(np.float32).astype(np.float64) for x in (a, b, i0))
+    np.testing.assert_allclose(g.download(img), i32 + 0.75 * a32 * b32, rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(g.download(kap), (vel * 7e-4 / 10.0) ** 2, rtol=5e-7)

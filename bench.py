@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_POINT = 16          # read u^n, u^{n-1}, kappa; write u^{n+1} (FP32)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_interior_512.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "forward_512_layered_traffic.txt")
 
 
 def parse():
@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=512, help="cells per axis")
-    ap.add_argument("--schedule", default="overlap", choices=["overlap", "serial"])
+    ap.add_argument("--schedule", default="serial", choices=["overlap", "serial"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--phases", action="store_true", help="also time each phase separately (serial)")
@@ -119,7 +119,7 @@ def main():
     prop.sync()
     torch.cuda.synchronize()
 
-    prop.interior_events = [] if args.schedule == "overlap" else None
+    prop.interior_events = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         prop.step(traces)
@@ -136,7 +136,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"forward {n}^3 layered (20 layers 1500-4500 m/s, sigma 3, seed 2), radius-4 "
                                f"8th-order star, leapfrog, dt at half the stability limit, 15 Hz Ricker at the "
-                               f"centre, 16-cell sponge, halo-first with 6 x 4-wide faces packed/unpacked",
+                               f"centre, 16-cell sponge, halo-first with 6 x 4-wide faces packed/unpacked, "
+                               f"{args.steps} timed steps",
                    "grid": [n, n, n], "h_m": h, "dt_s": dt, "schedule": args.schedule,
                    "receivers": int(len(rec))},
         "finite": finite,

@@ -172,6 +172,48 @@ int rtm_kappa_from_velocity(const rtm_grid *grid, float *kappa, const float *v, 
 int rtm_image_accumulate(const rtm_grid *grid, float *image, const float *src, const float *rcv,
                          float weight, hipStream_t stream);
 
+/* ---- exact adjoint and adjoint-state gradient (Tarantola 1984) ------------------------------ */
+
+/* One step of the transposed recursion of the forward update u^{n+1} = G (2 + K L) u^n - G^2 u^{n-1}
+ * (G = diag(g), K = diag(kappa), L symmetric with the zero ghosts of a physical boundary):
+ *     mu_out = 2 g mu_a + L(kappa g mu_a) - g^2 mu_b,
+ * with mu_a the adjoint state one level later and mu_b two levels later.  `work` is a caller-owned
+ * padded field whose ghost cells are zero; it receives kappa g mu_a on the owned cells.  mu_out may
+ * equal mu_b (in-place two-buffer recursion).  Adjoint sources (the residual traces, R^T y) are added
+ * with rtm_inject afterwards.  Every owned cell is updated. */
+int rtm_adjoint_step(const rtm_grid *grid, float *mu_out, const float *mu_a, const float *mu_b, const float *kappa,
+                     float *work, hipStream_t stream);
+
+/* Gradient of the least-squares misfit with respect to kappa, one term per step:
+ * grad += g * mu^{n+1} * L u^n on owned cells (u's ghosts are read, zero for a physical boundary). */
+int rtm_gradient_accumulate(const rtm_grid *grid, float *grad, const float *u, const float *mu, hipStream_t stream);
+
+/* resid[i] = d[i] - obs[i] for i < n, and *misfit += 1/2 sum resid^2 accumulated in FP64 in a fixed
+ * order (bitwise reproducible; misfit is a device double the caller zeroes).  resid may equal d or
+ * obs. */
+int rtm_misfit_residual(const float *d, const float *obs, float *resid, int64_t n, double *misfit, hipStream_t stream);
+
+/* Chain rule through kappa = (v dt / h)^2: grad_v = 2 v (dt/h)^2 grad_kappa, with grad_v and v compact
+ * x-fastest nz*ny*nx arrays and grad_kappa a padded field. */
+int rtm_velocity_gradient(const rtm_grid *grid, float *grad_v, const float *grad_kappa, const float *v,
+                          float dt_over_h, hipStream_t stream);
+
+/* ---- reduced-precision source-wavefield snapshots ------------------------------------------- */
+
+enum { RTM_SNAP_BF16 = 1, RTM_SNAP_F16 = 2 };
+
+/* Encode the owned cells of u into a compact snapshot: scales[k] = max |u| over plane k (one FP32
+ * scale per z slab, nz values) and codes[(k ny + j) nx + i] = RNE(u / scales[k]) as BF16 or FP16 bits
+ * (nx*ny*nz 16-bit values, x fastest); a zero scale gives zero codes.  The division is an IEEE FP32
+ * division.  Two kernels on `stream` (a per-plane max, then the quantisation). */
+int rtm_snapshot_encode(const rtm_grid *grid, const float *u, uint16_t *codes, float *scales, int32_t format,
+                        hipStream_t stream);
+
+/* Imaging with a coded source snapshot: image += weight * (decode(code) * scale) * rcv on owned cells;
+ * the decoded value and the accumulation are FP32. */
+int rtm_image_accumulate_coded(const rtm_grid *grid, float *image, const uint16_t *codes, const float *scales,
+                               int32_t format, const float *rcv, float weight, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

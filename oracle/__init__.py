@@ -20,5 +20,9 @@ from .rtm import (  # noqa: F401
     gradient_kappa,
     misfit,
     pack_faces,
+    snapshot_encode,
+    snapshot_decode,
+    bf16_rne,
+    bf16_to_f32,
     rel_l2,
 )

@@ -227,17 +227,22 @@ def forward(kappa, sponge, nsteps: int, *, radius: int = 4, src_ijk=None, src_w=
 
 
 def migrate(kappa, sponge, nsteps: int, *, radius: int = 4, src_ijk, src_w, src_amp, rec_ijk, rec_w,
-            data, image_every: int = 1, nthreads: int = 1) -> np.ndarray:
+            data, image_every: int = 1, nthreads: int = 1, snapshot_format: str | None = None) -> np.ndarray:
     """Zero-lag cross-correlation image of one shot.
 
     Forward: the source wavefield u^k, kept at the imaging levels k in T = {k in 1..N : k % s == 0}.
     Backward: the receiver wavefield r with r^0 = r^{-1} = 0 and, for m = 0..N-1,
     r^{m+1} = update(r^m, r^{m-1}) + sum_r w_r data[N-1-m, r]; r^{m+1} is the receiver
-    wavefield at forward level k = N - m.  Image: I = sum_{k in T} u^k r^{N+1-k}.
+    wavefield at forward level k = N - m.  Image: I = sum_{k in T} u^k r^{N+1-k}.  With
+    snapshot_format, u^k is stored as 16-bit codes with a per-slab scale and decoded before imaging.
     """
     fwd = forward(kappa, sponge, nsteps, radius=radius, src_ijk=src_ijk, src_w=src_w, src_amp=src_amp,
                   snap_every=image_every, nthreads=nthreads)
     snaps = fwd["snaps"]
+    if snapshot_format is not None:
+        # snapshots kept in a 16-bit code with one scale per z slab (FP32 decisions), decoded for imaging
+        snaps = [snapshot_decode(*snapshot_encode(sn, snapshot_format), snapshot_format).astype(np.float64)
+                 for sn in snaps]
     data = _f64(data).reshape(nsteps, -1)
     rec_w = _f64(rec_w).reshape(-1)
     ri, rj, rk = _ijk(rec_ijk)
@@ -309,6 +314,42 @@ def gradient_kappa(kappa, sponge, nsteps: int, *, radius: int = 4, src_ijk, src_
     for n in range(nsteps):
         grad += g * states[n + 1] * laplacian(fwd["levels"][n], radius, False, nthreads)
     return 0.5 * float(np.sum(resid * resid)), grad
+
+
+# ----------------------------------------------------------------------------------------------
+# Reduced-precision snapshots (per-slab scale, 16-bit codes)
+# ----------------------------------------------------------------------------------------------
+def bf16_rne(x32: np.ndarray) -> np.ndarray:
+    """FP32 -> BF16 bit patterns, round to nearest, ties to even (finite inputs): keep the upper 16
+    bits after adding half an ulp of the kept part (0x7FFF plus the lowest kept bit)."""
+    b = np.ascontiguousarray(x32, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    return ((b + 0x7FFF + ((b >> 16) & 1)) >> 16).astype(np.uint16)
+
+
+def bf16_to_f32(codes: np.ndarray) -> np.ndarray:
+    return (np.asarray(codes, dtype=np.uint32) << 16).astype(np.uint32).view(np.float32)
+
+
+def snapshot_encode(u, fmt: str):
+    """Per-slab (z plane) scale s_k = max |u| over the plane and codes RNE(u / s_k) in BF16 or FP16.
+    The quotient and the rounding decision are taken in FP32.  Returns (codes uint16, scales f32)."""
+    u32 = np.asarray(u, dtype=np.float32)
+    scales = np.max(np.abs(u32), axis=(1, 2)).astype(np.float32)
+    safe = np.where(scales > 0, scales, np.float32(1.0)).astype(np.float32)
+    q = (u32 / safe[:, None, None]).astype(np.float32)
+    q[scales == 0] = 0.0
+    if fmt == "bf16":
+        codes = bf16_rne(q)
+    elif fmt == "f16":
+        codes = q.astype(np.float16).view(np.uint16)
+    else:
+        raise ValueError(fmt)
+    return codes, scales
+
+
+def snapshot_decode(codes, scales, fmt: str) -> np.ndarray:
+    vals = bf16_to_f32(codes) if fmt == "bf16" else np.asarray(codes, dtype=np.uint16).view(np.float16).astype(np.float32)
+    return vals.astype(np.float32) * np.asarray(scales, dtype=np.float32)[:, None, None]
 
 
 # ----------------------------------------------------------------------------------------------

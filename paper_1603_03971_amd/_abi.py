@@ -14,6 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librtm.so")
 
 RTM_OK, RTM_EINVAL, RTM_EALIAS, RTM_ELAUNCH, RTM_EDEVICE = 0, -1, -2, -3, -4
+RTM_SNAP_BF16, RTM_SNAP_F16 = 1, 2
 RTM_OPT_INTERIOR_VARIANT, RTM_OPT_ZCHUNK, RTM_OPT_XCD_REMAP, RTM_OPT_HALO_X_WIDTH, RTM_OPT_HALO_Y_WIDTH = 1, 2, 3, 4, 5
 
 
@@ -58,6 +59,12 @@ def _load():
         "rtm_record": ([gp, vp, vp, vp, i32, vp], ctypes.c_int),
         "rtm_kappa_from_velocity": ([gp, vp, vp, f32, vp], ctypes.c_int),
         "rtm_image_accumulate": ([gp, vp, vp, vp, f32, vp], ctypes.c_int),
+        "rtm_snapshot_encode": ([gp, vp, vp, vp, i32, vp], ctypes.c_int),
+        "rtm_adjoint_step": ([gp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "rtm_gradient_accumulate": ([gp, vp, vp, vp, vp], ctypes.c_int),
+        "rtm_misfit_residual": ([vp, vp, vp, i64, vp, vp], ctypes.c_int),
+        "rtm_velocity_gradient": ([gp, vp, vp, vp, f32, vp], ctypes.c_int),
+        "rtm_image_accumulate_coded": ([gp, vp, vp, vp, i32, vp, f32, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -184,3 +191,32 @@ def rtm_kappa_from_velocity(grid, kappa, v, dt_over_h, stream=None):
 def rtm_image_accumulate(grid, image, src, rcv, weight=1.0, stream=None):
     _check(_lib.rtm_image_accumulate(ctypes.byref(grid), _p(image), _p(src), _p(rcv), weight, _s(stream)),
            "rtm_image_accumulate")
+
+
+def rtm_snapshot_encode(grid, u, codes, scales, fmt, stream=None):
+    _check(_lib.rtm_snapshot_encode(ctypes.byref(grid), _p(u), _p(codes), _p(scales), fmt, _s(stream)),
+           "rtm_snapshot_encode")
+
+
+def rtm_image_accumulate_coded(grid, image, codes, scales, fmt, rcv, weight=1.0, stream=None):
+    _check(_lib.rtm_image_accumulate_coded(ctypes.byref(grid), _p(image), _p(codes), _p(scales), fmt, _p(rcv),
+                                           weight, _s(stream)), "rtm_image_accumulate_coded")
+
+
+def rtm_adjoint_step(grid, mu_out, mu_a, mu_b, kappa, work, stream=None):
+    _check(_lib.rtm_adjoint_step(ctypes.byref(grid), _p(mu_out), _p(mu_a), _p(mu_b), _p(kappa), _p(work), _s(stream)),
+           "rtm_adjoint_step")
+
+
+def rtm_gradient_accumulate(grid, grad, u, mu, stream=None):
+    _check(_lib.rtm_gradient_accumulate(ctypes.byref(grid), _p(grad), _p(u), _p(mu), _s(stream)),
+           "rtm_gradient_accumulate")
+
+
+def rtm_misfit_residual(d, obs, resid, n, misfit, stream=None):
+    _check(_lib.rtm_misfit_residual(_p(d), _p(obs), _p(resid), n, _p(misfit), _s(stream)), "rtm_misfit_residual")
+
+
+def rtm_velocity_gradient(grid, grad_v, grad_kappa, v, dt_over_h, stream=None):
+    _check(_lib.rtm_velocity_gradient(ctypes.byref(grid), _p(grad_v), _p(grad_kappa), _p(v), dt_over_h, _s(stream)),
+           "rtm_velocity_gradient")

@@ -44,18 +44,33 @@ __device__ __forceinline__ float axis_sum(float xm, float xp, float ym, float yp
     return ((xm + xp) + (ym + yp)) + (zm + zp);
 }
 
-// The per-point update.  s[m-1] = axis_sum at distance m.  The centre weight is 3 c0 (one c0 per axis).
-template <int R>
-__device__ __forceinline__ float point_update(float u0, const float (&s)[R], float up, float kap, float g,
-                                              const float (&c)[5])
+// What a stencil kernel computes at a cell from the stencil field u (its Laplacian lap), two
+// centre operands a, b and the sponge factor g:
+//   OP_FORWARD   u = u^n,            a = u^{n-1}, b = kappa:   g (2 u^n - g u^{n-1} + kappa L u^n)
+//   OP_ADJOINT   u = kappa g mu_a,   a = mu_a,    b = mu_b:    2 g mu_a + L(kappa g mu_a) - g^2 mu_b
+//   OP_GRADIENT  u = u^n,            a = mu,      b = grad:    grad + g mu L u^n
+enum { OP_FORWARD = 0, OP_ADJOINT = 1, OP_GRADIENT = 2 };
+
+// The per-point operation.  s[m-1] = axis_sum at distance m.  The centre weight is 3 c0 (one c0 per
+// axis).
+template <int R, int OP>
+__device__ __forceinline__ float point_op(float u0, const float (&s)[R], float a, float b, float g,
+                                          const float (&c)[5])
 {
     float lap = (3.0f * c[0]) * u0;
 #pragma unroll
     for (int m = 1; m <= R; ++m)
         lap = __builtin_fmaf(c[m], s[m - 1], lap);
-    float t = __builtin_fmaf(-g, up, 2.0f * u0);
-    t = __builtin_fmaf(kap, lap, t);
-    return g * t;
+    if constexpr (OP == OP_FORWARD) {
+        float t = __builtin_fmaf(-g, a, 2.0f * u0);
+        t = __builtin_fmaf(b, lap, t);
+        return g * t;
+    } else if constexpr (OP == OP_ADJOINT) {
+        const float t = __builtin_fmaf(2.0f * g, a, lap);
+        return __builtin_fmaf(-(g * g), b, t);
+    } else {
+        return __builtin_fmaf(g * a, lap, b);
+    }
 }
 
 __device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
@@ -71,7 +86,7 @@ __device__ __forceinline__ float sponge(const Geo &g, int i, int j, int k)
 }
 
 // Scalar update of one owned cell, reading every operand from global memory.
-template <int R>
+template <int R, int OP>
 __device__ __forceinline__ void update_cell(const Geo &g, float *un, const float *uc, const float *up,
                                             const float *kap, int i, int j, int k)
 {
@@ -85,7 +100,7 @@ __device__ __forceinline__ void update_cell(const Geo &g, float *un, const float
     float c[5];
 #pragma unroll
     for (int m = 0; m < 5; ++m) c[m] = g.c[m];
-    un[p] = point_update<R>(u0, s, up[p], kap[p], sponge(g, i, j, k), c);
+    un[p] = point_op<R, OP>(u0, s, up[p], kap[p], sponge(g, i, j, k), c);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -99,10 +114,9 @@ struct Slab {
 
 // Scalar update over one box [x0,x1) x [y0,y1) x [z0,z1) (fallback for layouts the vectorised
 // kernel cannot take).
-template <int R>
+template <int R, int OP>
 __global__ __launch_bounds__(kThreads) void k_box(Geo g, float *un, const float *__restrict__ uc, const float *up,
-                                                  const float *__restrict__ kap, int x0, int x1, int y0, int y1,
-                                                  int z0, int z1)
+                                                  const float *kap, int x0, int x1, int y0, int y1, int z0, int z1)
 {
     const long long wx = x1 - x0, wy = y1 - y0, wz = z1 - z0;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -110,7 +124,7 @@ __global__ __launch_bounds__(kThreads) void k_box(Geo g, float *un, const float 
     const int i = x0 + (int)(t % wx);
     const int j = y0 + (int)((t / wx) % wy);
     const int k = z0 + (int)(t / (wx * wy));
-    update_cell<R>(g, un, uc, up, kap, i, j, k);
+    update_cell<R, OP>(g, un, uc, up, kap, i, j, k);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -156,9 +170,9 @@ struct BoxList {
     int remap;
 };
 
-template <int R, int BX, int BY>
+template <int R, int BX, int BY, int OP>
 __global__ __launch_bounds__(BX *BY) void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up,
-                                                  const float *__restrict__ kap, BoxList bl)
+                                                  const float *kap, BoxList bl)
 {
     constexpr int NT = BX * BY;
     constexpr int TX = 4 * BX;
@@ -337,7 +351,7 @@ __global__ __launch_bounds__(BX *BY) void k_tiled(Geo g, float *un, const float 
                 for (int m = 1; m <= R; ++m)
                     sm[m - 1] = axis_sum(xs[4 + e - m], xs[4 + e + m], el(ym[m - 1], e), el(yp[m - 1], e),
                                          el(q[(s + R - m) % QR], e), el(q[(s + R + m) % QR], e));
-                out[e] = point_update<R>(xs[4 + e], sm, el(pv[b], e), el(kv[b], e), gxy[e] * gz, c);
+                out[e] = point_op<R, OP>(xs[4 + e], sm, el(pv[b], e), el(kv[b], e), gxy[e] * gz, c);
             }
             float *dst = un + pc + dz;
             if (full) {
@@ -504,6 +518,129 @@ __global__ __launch_bounds__(kThreads) void k_kappa(Geo g, float *__restrict__ k
 }
 
 // ---------------------------------------------------------------------------------------------
+// Adjoint-state gradient helpers
+// ---------------------------------------------------------------------------------------------
+// w = kappa g mu on owned cells (the field the adjoint stencil differentiates).
+__global__ __launch_bounds__(kThreads) void k_adjoint_weight(Geo g, float *__restrict__ w, const float *__restrict__ mu,
+                                                             const float *__restrict__ kap)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nxy = (long long)g.nx * g.ny;
+    if (t >= nxy * g.nz) return;
+    const int i = (int)(t % g.nx);
+    const int j = (int)((t / g.nx) % g.ny);
+    const int k = (int)(t / nxy);
+    const long long p = pidx(g, i, j, k);
+    w[p] = (kap[p] * sponge(g, i, j, k)) * mu[p];
+}
+
+// resid = d - obs and misfit += 1/2 sum resid^2, summed in FP64 by one workgroup: each thread adds a
+// fixed strided subset in order and the partial sums meet in a fixed tree, so the result does not
+// depend on scheduling (bitwise reproducible).
+constexpr int kReduceThreads = 1024;
+__global__ __launch_bounds__(kReduceThreads) void k_residual(const float *__restrict__ d, const float *__restrict__ obs,
+                                                             float *__restrict__ resid, long long n, double *misfit)
+{
+    double acc = 0.0;
+    for (long long t = threadIdx.x; t < n; t += kReduceThreads) {
+        const float r = d[t] - obs[t];
+        resid[t] = r;
+        acc += (double)r * (double)r;
+    }
+    __shared__ double red[kReduceThreads];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kReduceThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *misfit += 0.5 * red[0];
+}
+
+// grad_v (compact, x fastest) = 2 v (dt/h)^2 grad_kappa (the chain rule through kappa = (v dt/h)^2).
+__global__ __launch_bounds__(kThreads) void k_velocity_gradient(Geo g, float *__restrict__ gv,
+                                                                const float *__restrict__ gk,
+                                                                const float *__restrict__ v, float s2)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nxy = (long long)g.nx * g.ny;
+    if (t >= nxy * g.nz) return;
+    const int i = (int)(t % g.nx);
+    const int j = (int)((t / g.nx) % g.ny);
+    const int k = (int)(t / nxy);
+    gv[t] = (2.0f * s2) * v[t] * gk[pidx(g, i, j, k)];
+}
+
+// ---------------------------------------------------------------------------------------------
+// Reduced-precision snapshots: one FP32 scale per z plane (slab) and 16-bit codes
+// ---------------------------------------------------------------------------------------------
+// FP32 -> BF16 with round-to-nearest-even on the bit pattern (finite inputs).
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x)
+{
+    const uint32_t b = __float_as_uint(x);
+    return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t c) { return __uint_as_float((uint32_t)c << 16); }
+__device__ __forceinline__ uint16_t f32_to_f16_rne(float x)
+{
+    const _Float16 h = (_Float16)x;    // hardware conversion, round to nearest even
+    return __builtin_bit_cast(uint16_t, h);
+}
+__device__ __forceinline__ float f16_to_f32(uint16_t c) { return (float)__builtin_bit_cast(_Float16, c); }
+
+// scales[k] = max |u| over the owned cells of plane k (one workgroup per plane).
+__global__ __launch_bounds__(kThreads) void k_plane_absmax(Geo g, const float *__restrict__ u, float *__restrict__ scales)
+{
+    const int k = blockIdx.x;
+    const int nxy = g.nx * g.ny;
+    float m = 0.0f;
+    for (int t = threadIdx.x; t < nxy; t += blockDim.x) {
+        const int j = t / g.nx, i = t - j * g.nx;
+        m = fmaxf(m, fabsf(u[pidx(g, i, j, k)]));
+    }
+    __shared__ float red[kThreads];
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) scales[k] = red[0];
+}
+
+// codes[(k ny + j) nx + i] = RNE(u / scales[k]) in the 16-bit format; a zero scale gives zero codes.
+__global__ __launch_bounds__(kThreads) void k_encode(Geo g, const float *__restrict__ u, const float *__restrict__ scales,
+                                                     uint16_t *__restrict__ codes, int fmt)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nxy = (long long)g.nx * g.ny;
+    if (t >= nxy * g.nz) return;
+    const int i = (int)(t % g.nx);
+    const int j = (int)((t / g.nx) % g.ny);
+    const int k = (int)(t / nxy);
+    const float sc = scales[k];
+    const float x = sc > 0.0f ? u[pidx(g, i, j, k)] / sc : 0.0f;
+    codes[t] = fmt == RTM_SNAP_BF16 ? f32_to_bf16_rne(x) : f32_to_f16_rne(x);
+}
+
+// image += weight * (decode(code) * scale) * rcv on owned cells.
+__global__ __launch_bounds__(kThreads) void k_image_coded(Geo g, float *image, const uint16_t *__restrict__ codes,
+                                                          const float *__restrict__ scales, int fmt,
+                                                          const float *__restrict__ rcv, float weight)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nxy = (long long)g.nx * g.ny;
+    if (t >= nxy * g.nz) return;
+    const int i = (int)(t % g.nx);
+    const int j = (int)((t / g.nx) % g.ny);
+    const int k = (int)(t / nxy);
+    const uint16_t c = codes[t];
+    const float s = (fmt == RTM_SNAP_BF16 ? bf16_to_f32(c) : f16_to_f32(c)) * scales[k];
+    const long long p = pidx(g, i, j, k);
+    image[p] = __builtin_fmaf(weight * s, rcv[p], image[p]);
+}
+
+// ---------------------------------------------------------------------------------------------
 // Host side: validation, device check, launch configuration
 // ---------------------------------------------------------------------------------------------
 constexpr int kMaxDevices = 64;
@@ -574,7 +711,7 @@ unsigned blocks_for(long long n) { return (unsigned)((n + kThreads - 1) / kThrea
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 // Launch the tiled kernel over up to kMaxBoxes boxes {x0, x1, y0, y1, z0, z1} (empty ones skipped).
-template <int R, int BX, int BY>
+template <int R, int BX, int BY, int OP>
 int launch_tiled(const Geo &g, float *un, const float *uc, const float *up, const float *kap, const int (*boxes)[6],
                  int nbox, hipStream_t st)
 {
@@ -609,7 +746,7 @@ int launch_tiled(const Geo &g, float *un, const float *uc, const float *up, cons
         int occ = resident.load(std::memory_order_relaxed);
         if (occ == 0) {
             int per_cu = 0, cus = 0, dev = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tiled<R, BX, BY>, BX * BY, 0) !=
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tiled<R, BX, BY, OP>, BX * BY, 0) !=
                 hipSuccess)
                 per_cu = 2;
             if (hipGetDevice(&dev) != hipSuccess ||
@@ -634,18 +771,18 @@ int launch_tiled(const Geo &g, float *un, const float *uc, const float *up, cons
     if (nb >= (1ll << 31)) return RTM_EINVAL;
     bl.nblk = (int)nb;
     bl.remap = g_opt.xcd_remap.load(std::memory_order_relaxed);
-    hipLaunchKernelGGL((k_tiled<R, BX, BY>), dim3((unsigned)nb), dim3(BX * BY), 0, st, g, un, uc, up, kap, bl);
+    hipLaunchKernelGGL((k_tiled<R, BX, BY, OP>), dim3((unsigned)nb), dim3(BX * BY), 0, st, g, un, uc, up, kap, bl);
     return launch_status();
 }
 
-template <int R>
+template <int R, int OP>
 int launch_tiled_variant(int var, const Geo &g, float *un, const float *uc, const float *up, const float *kap,
                          const int (*boxes)[6], int nbox, hipStream_t st)
 {
     switch (var) {
-    case 1: return launch_tiled<R, 32, 8>(g, un, uc, up, kap, boxes, nbox, st);
-    case 2: return launch_tiled<R, 16, 8>(g, un, uc, up, kap, boxes, nbox, st);
-    default: return launch_tiled<R, 16, 16>(g, un, uc, up, kap, boxes, nbox, st);
+    case 1: return launch_tiled<R, 32, 8, OP>(g, un, uc, up, kap, boxes, nbox, st);
+    case 2: return launch_tiled<R, 16, 8, OP>(g, un, uc, up, kap, boxes, nbox, st);
+    default: return launch_tiled<R, 16, 16, OP>(g, un, uc, up, kap, boxes, nbox, st);
     }
 }
 
@@ -686,41 +823,50 @@ bool vector_path(const Geo &g, const float *un, const float *uc, const float *up
            aligned16(up) && aligned16(kap) && (g.py % 4 == 0) && (g.pz % 4 == 0);
 }
 
-template <int R>
+template <int R, int OP>
 int launch_box_scalar(const Geo &g, float *un, const float *uc, const float *up, const float *kap, const int *b,
                       hipStream_t st)
 {
     const long long n = (long long)std::max(0, b[1] - b[0]) * std::max(0, b[3] - b[2]) * std::max(0, b[5] - b[4]);
     if (n <= 0) return RTM_OK;
-    hipLaunchKernelGGL((k_box<R>), dim3(blocks_for(n)), dim3(kThreads), 0, st, g, un, uc, up, kap, b[0], b[1], b[2],
+    hipLaunchKernelGGL((k_box<R, OP>), dim3(blocks_for(n)), dim3(kThreads), 0, st, g, un, uc, up, kap, b[0], b[1], b[2],
                        b[3], b[4], b[5]);
     return launch_status();
 }
 
-template <int R>
+template <int R, int OP = OP_FORWARD>
 int launch_halo(const Geo &g, float *un, const float *uc, const float *up, const float *kap, hipStream_t st)
 {
     const Region r = halo_region(g.nx, g.ny, R);
     int boxes[6][6];
     const int nb = halo_boxes(g, r, boxes);
-    if (vector_path(g, un, uc, up, kap)) return launch_tiled_variant<R>(0, g, un, uc, up, kap, boxes, nb, st);
+    if (vector_path(g, un, uc, up, kap)) return launch_tiled_variant<R, OP>(0, g, un, uc, up, kap, boxes, nb, st);
     for (int i = 0; i < nb; ++i) {
-        const int rc = launch_box_scalar<R>(g, un, uc, up, kap, boxes[i], st);
+        const int rc = launch_box_scalar<R, OP>(g, un, uc, up, kap, boxes[i], st);
         if (rc != RTM_OK) return rc;
     }
     return RTM_OK;
 }
 
-template <int R>
+template <int R, int OP = OP_FORWARD>
 int launch_interior(const Geo &g, float *un, const float *uc, const float *up, const float *kap, hipStream_t st)
 {
     const Region r = halo_region(g.nx, g.ny, R);
     const int boxes[1][6] = {{r.wx, g.nx - r.wx, r.hy, g.ny - r.hy, R, g.nz - R}};
     if (vector_path(g, un, uc, up, kap)) {
         const int var = g_opt.interior_variant.load(std::memory_order_relaxed);
-        return launch_tiled_variant<R>(var, g, un, uc, up, kap, boxes, 1, st);
+        return launch_tiled_variant<R, OP>(var, g, un, uc, up, kap, boxes, 1, st);
     }
-    return launch_box_scalar<R>(g, un, uc, up, kap, boxes[0], st);
+    return launch_box_scalar<R, OP>(g, un, uc, up, kap, boxes[0], st);
+}
+
+// Every owned cell (halo region, then the rest) with one of the stencil operations.
+template <int OP>
+int launch_whole(const Geo &g, float *un, const float *uc, const float *up, const float *kap, hipStream_t st)
+{
+    int rc = g.R == 4 ? launch_halo<4, OP>(g, un, uc, up, kap, st) : launch_halo<2, OP>(g, un, uc, up, kap, st);
+    if (rc != RTM_OK) return rc;
+    return g.R == 4 ? launch_interior<4, OP>(g, un, uc, up, kap, st) : launch_interior<2, OP>(g, un, uc, up, kap, st);
 }
 
 bool faces_vec(const Geo &g, const float *u)
@@ -1002,6 +1148,113 @@ int rtm_halo_region(const rtm_grid *grid, int32_t widths[3])
     widths[1] = r.hy;
     widths[2] = r.R;
     return RTM_OK;
+}
+
+int rtm_adjoint_step(const rtm_grid *grid, float *mu_out, const float *mu_a, const float *mu_b, const float *kappa,
+                     float *work, hipStream_t stream)
+{
+    int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (!mu_out || !mu_a || !mu_b || !kappa || !work) return RTM_EINVAL;
+    const long long tot = padded_total(grid);
+    if (ranges_overlap(mu_out, tot, mu_a, tot) || ranges_overlap(mu_out, tot, kappa, tot) ||
+        ranges_overlap(mu_out, tot, work, tot) || ranges_overlap(work, tot, mu_a, tot) ||
+        ranges_overlap(work, tot, mu_b, tot) || ranges_overlap(work, tot, kappa, tot))
+        return RTM_EALIAS;
+    if (mu_out != mu_b && ranges_overlap(mu_out, tot, mu_b, tot)) return RTM_EALIAS;
+    st = check_device();
+    if (st != RTM_OK) return st;
+    const Geo g = make_geo(grid);
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_adjoint_weight, dim3(blocks_for(n)), dim3(kThreads), 0, stream, g, work, mu_a, kappa);
+    st = launch_status();
+    if (st != RTM_OK) return st;
+    return launch_whole<OP_ADJOINT>(g, mu_out, work, mu_a, mu_b, stream);
+}
+
+int rtm_gradient_accumulate(const rtm_grid *grid, float *grad, const float *u, const float *mu, hipStream_t stream)
+{
+    int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (!grad || !u || !mu) return RTM_EINVAL;
+    const long long tot = padded_total(grid);
+    if (ranges_overlap(grad, tot, u, tot) || ranges_overlap(grad, tot, mu, tot)) return RTM_EALIAS;
+    st = check_device();
+    if (st != RTM_OK) return st;
+    const Geo g = make_geo(grid);
+    return launch_whole<OP_GRADIENT>(g, grad, u, mu, grad, stream);
+}
+
+int rtm_misfit_residual(const float *d, const float *obs, float *resid, int64_t n, double *misfit, hipStream_t stream)
+{
+    if (n < 0) return RTM_EINVAL;
+    if (n == 0) return RTM_OK;
+    if (!d || !obs || !resid || !misfit) return RTM_EINVAL;
+    if ((resid != d && ranges_overlap(resid, n, d, n)) || (resid != obs && ranges_overlap(resid, n, obs, n)))
+        return RTM_EALIAS;
+    const int st = check_device();
+    if (st != RTM_OK) return st;
+    hipLaunchKernelGGL(k_residual, dim3(1), dim3(kReduceThreads), 0, stream, d, obs, resid, (long long)n, misfit);
+    return launch_status();
+}
+
+int rtm_velocity_gradient(const rtm_grid *grid, float *grad_v, const float *grad_kappa, const float *v,
+                          float dt_over_h, hipStream_t stream)
+{
+    int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (!grad_v || !grad_kappa || !v) return RTM_EINVAL;
+    const long long n = (long long)grid->nx * grid->ny * grid->nz;
+    if (ranges_overlap(grad_v, n, grad_kappa, padded_total(grid)) || ranges_overlap(grad_v, n, v, n))
+        return RTM_EALIAS;
+    st = check_device();
+    if (st != RTM_OK) return st;
+    const Geo g = make_geo(grid);
+    hipLaunchKernelGGL(k_velocity_gradient, dim3(blocks_for(n)), dim3(kThreads), 0, stream, g, grad_v, grad_kappa, v,
+                       dt_over_h * dt_over_h);
+    return launch_status();
+}
+
+int rtm_snapshot_encode(const rtm_grid *grid, const float *u, uint16_t *codes, float *scales, int32_t format,
+                        hipStream_t stream)
+{
+    int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (!u || !codes || !scales) return RTM_EINVAL;
+    if (format != RTM_SNAP_BF16 && format != RTM_SNAP_F16) return RTM_EINVAL;
+    const long long n = (long long)grid->nx * grid->ny * grid->nz;
+    const long long tot = padded_total(grid);
+    if (ranges_overlap(codes, (n + 1) / 2, u, tot) || ranges_overlap(scales, grid->nz, u, tot) ||
+        ranges_overlap(scales, grid->nz, codes, (n + 1) / 2))
+        return RTM_EALIAS;
+    st = check_device();
+    if (st != RTM_OK) return st;
+    const Geo g = make_geo(grid);
+    hipLaunchKernelGGL(k_plane_absmax, dim3(g.nz), dim3(kThreads), 0, stream, g, u, scales);
+    st = launch_status();
+    if (st != RTM_OK) return st;
+    hipLaunchKernelGGL(k_encode, dim3(blocks_for(n)), dim3(kThreads), 0, stream, g, u, scales, codes, (int)format);
+    return launch_status();
+}
+
+int rtm_image_accumulate_coded(const rtm_grid *grid, float *image, const uint16_t *codes, const float *scales,
+                               int32_t format, const float *rcv, float weight, hipStream_t stream)
+{
+    int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (!image || !codes || !scales || !rcv) return RTM_EINVAL;
+    if (format != RTM_SNAP_BF16 && format != RTM_SNAP_F16) return RTM_EINVAL;
+    const long long tot = padded_total(grid);
+    const long long n = (long long)grid->nx * grid->ny * grid->nz;
+    if (ranges_overlap(image, tot, rcv, tot) || ranges_overlap(image, tot, codes, (n + 1) / 2) ||
+        ranges_overlap(image, tot, scales, grid->nz))
+        return RTM_EALIAS;
+    st = check_device();
+    if (st != RTM_OK) return st;
+    const Geo g = make_geo(grid);
+    hipLaunchKernelGGL(k_image_coded, dim3(blocks_for(n)), dim3(kThreads), 0, stream, g, image, codes, scales,
+                       (int)format, rcv, weight);
+    return launch_status();
 }
 
 int rtm_set_option(int32_t option, int32_t value)

@@ -1,0 +1,135 @@
+"""Profiling driver for rocprofv3 and the summary of its output.
+
+  python3 -m paper_1603_03971_amd.profile interior [--n 512] [--launches 10]
+      runs the 512^3 layered workload's interior stencil launches (the benchmark's configuration)
+      and, for counter calibration, a plain device copy of 1 GiB (reads and writes exactly 1 GiB).
+      Run it under `rocprofv3 --pmc FETCH_SIZE` and, separately, `rocprofv3 --pmc WRITE_SIZE`.
+
+  python3 -m paper_1603_03971_amd.profile summarize --stats DIR --fetch DIR --write DIR --out FILE
+      reads rocprofv3 CSV output (kernel stats of a benchmark run, counter collections of the two
+      runs above) and writes a short text summary plus the traffic record that bench.py reports
+      (keyed by a hash of the kernel source, so stale counters are never reported).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+COPY_BYTES = 1 << 30
+
+
+def run_interior(n: int, launches: int):
+    import numpy as np
+    import torch
+
+    from . import _abi, synth
+    from .grid import Grid
+
+    h = 10.0
+    prof = synth.layered_profile(n, h, seed=2)
+    g = Grid(n, n, n, h, Grid.stable_dt(4, h, float(prof.max())))
+    v = torch.from_numpy(np.ascontiguousarray(np.broadcast_to(prof[:, None, None], (n, n, n)), dtype=np.float32))
+    kap = g.kappa_from_velocity(v.cuda())
+    u, up = g.field(), g.field()
+    g.owned(u).normal_()
+    g.owned(up).normal_()
+    s = torch.cuda.current_stream()
+    for _ in range(launches):
+        _abi.rtm_step_interior(g.c, up, u, up, kap, s)
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    wx, hy, R = _abi.rtm_halo_region(g.c)
+    print(json.dumps({"interior_points": (n - 2 * wx) * (n - 2 * hy) * (n - 2 * R), "copy_bytes": COPY_BYTES}))
+
+
+def _csv(d: str, name: str):
+    files = glob.glob(os.path.join(d, "**", name), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no {name} under {d}")
+    with open(files[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def _counter(rows, kernel_substr: str, counter: str, largest: bool = False):
+    vals = [float(r["Counter_Value"]) for r in rows if kernel_substr in r["Kernel_Name"] and r["Counter_Name"] == counter]
+    if not vals:
+        return None, 0
+    return (max(vals) if largest else sum(vals) / len(vals)), len(vals)
+
+
+def kernel_source_hash() -> str:
+    with open(os.path.join(ROOT, "paper_1603_03971_amd", "csrc", "rtm.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def summarize(stats_dir, fetch_dir, write_dir, out, n, commands):
+    stats = _csv(stats_dir, "*kernel_stats.csv")
+    lines = ["# rocprofv3 summary: 512^3 layered forward workload", ""]
+    lines += ["Commands:"] + [f"    {c}" for c in commands] + [""]
+    lines.append("Kernel statistics (kernel trace of the benchmark run):")
+    lines.append(f"    {'kernel':60s} {'calls':>6s} {'avg us':>10s} {'share %':>8s}")
+    interior_avg_us = None
+    for r in stats[:12]:
+        name = r["Name"].replace("(anonymous namespace)::", "")[:60]
+        avg = float(r["AverageNs"]) / 1e3
+        lines.append(f"    {name:60s} {r['Calls']:>6s} {avg:10.2f} {float(r['Percentage']):8.2f}")
+        if "k_tiled<4, 32, 8, 0>" in r["Name"] and interior_avg_us is None:
+            interior_avg_us = avg
+    record = {"n": n, "kernel_source_sha256_16": kernel_source_hash(), "interior_avg_us_kernel_trace": interior_avg_us}
+    if fetch_dir and write_dir:
+        fr, wr = _csv(fetch_dir, "*counter_collection.csv"), _csv(write_dir, "*counter_collection.csv")
+        f_int, nf = _counter(fr, "k_tiled<4, 32, 8, 0>", "FETCH_SIZE")
+        w_int, nw = _counter(wr, "k_tiled<4, 32, 8, 0>", "WRITE_SIZE")
+        # the 1 GiB copy is the largest copy dispatch of the run
+        f_cp, _ = _counter(fr, "opy", "FETCH_SIZE", largest=True)
+        w_cp, _ = _counter(wr, "opy", "WRITE_SIZE", largest=True)
+        kf = COPY_BYTES / (f_cp * 1024.0)
+        kw = COPY_BYTES / (w_cp * 1024.0)
+        traffic = f_int * 1024.0 * kf + w_int * 1024.0 * kw
+        pts = (n - 128) * (n - 32) * (n - 8)
+        lines += ["", "HBM traffic of the interior stencil launch (counters, KiB per dispatch):",
+                  f"    FETCH_SIZE {f_int:.0f} KiB ({nf} dispatches), WRITE_SIZE {w_int:.0f} KiB ({nw} dispatches)",
+                  f"    calibration with a plain 1 GiB device copy: FETCH x {kf:.3f}, WRITE x {kw:.3f}",
+                  f"    traffic per launch {traffic / 1e6:.1f} MB; algorithmic 16 B x {pts} cells = {16 * pts / 1e6:.1f} MB"
+                  f" (ratio {traffic / (16 * pts):.3f})"]
+        record.update({"fetch_kib": f_int, "write_kib": w_int, "fetch_factor": kf, "write_factor": kw,
+                       "hbm_bytes_per_launch": traffic, "algorithmic_bytes_per_launch": 16 * pts})
+    text = "\n".join(lines) + "\n"
+    with open(out, "w") as f:
+        f.write(text)
+    with open(os.path.splitext(out)[0] + "_traffic.txt", "w") as f:
+        json.dump(record, f)
+        f.write("\n")
+    print(text)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("interior")
+    a.add_argument("--n", type=int, default=512)
+    a.add_argument("--launches", type=int, default=10)
+    b = sub.add_parser("summarize")
+    b.add_argument("--stats", required=True)
+    b.add_argument("--fetch")
+    b.add_argument("--write")
+    b.add_argument("--out", required=True)
+    b.add_argument("--n", type=int, default=512)
+    b.add_argument("--command", action="append", default=[])
+    args = ap.parse_args(argv)
+    if args.cmd == "interior":
+        run_interior(args.n, args.launches)
+    else:
+        summarize(args.stats, args.fetch, args.write, args.out, args.n, args.command)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

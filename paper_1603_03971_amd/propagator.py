@@ -121,6 +121,17 @@ class Propagator:
         self.pinned.add(self.u_cur.data_ptr())
         return self.u_cur
 
+    def pin_previous(self):
+        """Keep the buffer of the level before the newest one."""
+        self.pinned.add(self.u_prv.data_ptr())
+        return self.u_prv
+
+    def set_levels(self, u_cur: torch.Tensor, u_prv: torch.Tensor, n: int):
+        """Continue from existing device levels (u^n, u^{n-1}) without copying them; u_prv may be
+        overwritten by the next step unless it is pinned.  u_cur's ghosts must be current."""
+        self.sync()
+        self.u_cur, self.u_prv, self.n = u_cur, u_prv, n
+
     def unpin(self, t: torch.Tensor, recycle: bool = True):
         self.pinned.discard(t.data_ptr())
         if recycle:
@@ -142,7 +153,14 @@ class Propagator:
         if self.schedule == "serial":
             st = torch.cuda.current_stream()
             _abi.rtm_step_halo(c, u_nxt, u_cur, u_prv, kap, st)
-            _abi.rtm_step_interior(c, u_nxt, u_cur, u_prv, kap, st)
+            if self.interior_events is not None:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(st)
+                _abi.rtm_step_interior(c, u_nxt, u_cur, u_prv, kap, st)
+                e1.record(st)
+                self.interior_events.append((e0, e1))
+            else:
+                _abi.rtm_step_interior(c, u_nxt, u_cur, u_prv, kap, st)
             for s in self.sources:
                 s.inject(g, u_nxt, n, 0, st)
                 s.inject(g, u_nxt, n, 1, st)

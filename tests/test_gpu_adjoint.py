@@ -1,0 +1,214 @@
+"""GPU exact adjoint and adjoint-state gradient against the FP64 oracle and finite differences."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1603_03971_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _grid(shape, h=10.0, vmax=3000.0, sponge=6):
+    from paper_1603_03971_amd.grid import Grid
+
+    nz, ny, nx = shape
+    return Grid(nx, ny, nz, h, Grid.stable_dt(4, h, vmax), sponge_width=sponge)
+
+
+def test_adjoint_step_matches_oracle():
+    import torch
+
+    from paper_1603_03971_amd import _abi
+
+    shape = (29, 34, 41)
+    g = _grid(shape)
+    v = synth.random_smooth_velocity(shape, seed=71, vmin=1500, vmax=3000)
+    ma, mb = synth.random_field(shape, 72), synth.random_field(shape, 73)
+    kap = g.kappa_from_velocity(v)
+    out, work = g.field(), g.field()
+    _abi.rtm_adjoint_step(g.c, out, g.upload(ma), g.upload(mb), kap, work, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    sp = tuple(oracle.sponge_profile(n, 6) for n in (shape[2], shape[1], shape[0]))
+    k64 = oracle.kappa_field(v.astype(np.float32), g.dt, g.h)
+    ref = oracle.adjoint_step(ma.astype(np.float32), mb.astype(np.float32), k64, sp)
+    e = oracle.rel_l2(g.download(out), ref)
+    _say(f"adjoint step rel-L2 {e:.2e}")
+    assert e <= 1e-6
+
+
+def test_gradient_kernel_matches_oracle():
+    import torch
+
+    from paper_1603_03971_amd import _abi
+
+    shape = (21, 30, 37)
+    g = _grid(shape)
+    u, mu, g0 = (synth.random_field(shape, s) for s in (81, 82, 83))
+    grad = g.upload(g0)
+    _abi.rtm_gradient_accumulate(g.c, grad, g.upload(u), g.upload(mu), torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    sp = [oracle.sponge_profile(n, 6) for n in (shape[2], shape[1], shape[0])]
+    gg = sp[2][:, None, None] * sp[1][None, :, None] * sp[0][None, None, :]
+    u32, mu32 = u.astype(np.float32).astype(np.float64), mu.astype(np.float32).astype(np.float64)
+    ref = g0.astype(np.float32) + gg * mu32 * oracle.laplacian(u32, 4)
+    assert oracle.rel_l2(g.download(grad), ref) <= 1e-6
+
+
+def _problem(shape, nsteps, nshots, seed, C=50, nrec_stride=3, true_model=None):
+    """Shots at seeded surface positions with receivers every `nrec_stride` cells at depth 4."""
+    import torch
+
+    from paper_1603_03971_amd.adjoint import MisfitProblem, Shot
+
+    nz, ny, nx = shape
+    g = _grid(shape)
+    src = synth.random_positions(nshots, nx, ny, k=5, seed=seed, margin=8)
+    rec = synth.surface_receivers(nx, ny, k=4, stride=nrec_stride)
+    wav = g.ricker(nsteps, 20.0)
+    v_true = true_model if true_model is not None else synth.random_smooth_velocity(shape, seed + 1, 1800, 2800)
+    shots = []
+    for s in src:
+        w = g.injection_weights([v_true[s[2], s[1], s[0]]])
+        shots.append(Shot([s], w, rec))
+    prob = MisfitProblem(g, nsteps, wav, shots, checkpoint_every=C)
+    kt = g.kappa_from_velocity(v_true)
+    for sh in shots:
+        sh.observed = prob.model(kt, sh)
+    torch.cuda.synchronize()
+    return prob, v_true, src, rec, wav
+
+
+def test_dot_product_fp32():
+    """<F x, y> = <x, F^T y> for the GPU forward map (source series -> traces) and its transpose."""
+    import torch
+
+    shape = (40, 36, 44)
+    nsteps = 90
+    prob, v, src, rec, _ = _problem(shape, nsteps, 1, seed=90, C=25)
+    g = prob.g
+    kap = prob.kappa(torch.from_numpy(v.astype(np.float32)).cuda())
+    shot = prob.shots[0]
+    rng = np.random.default_rng(91)
+    x = rng.standard_normal((nsteps, 1)).astype(np.float32)
+    y = torch.from_numpy(rng.standard_normal((nsteps, len(rec))).astype(np.float32)).cuda()
+    fx = prob.model(kap, shot, amp=x)
+    misfit = torch.zeros(1, dtype=torch.float64, device="cuda")
+    shot.observed = torch.zeros_like(fx)
+    ckpt, _ = prob.forward(kap, shot, misfit)
+    ysrc = torch.zeros((nsteps, 1), dtype=torch.float32, device="cuda")
+    grad = g.field()
+    prob.backward(kap, shot, ckpt, y, grad, y_src=ysrc)
+    torch.cuda.synchronize()
+    fty = ysrc.cpu().numpy().astype(np.float64) * shot.src_w.astype(np.float64)
+    lhs = float(np.sum(fx.cpu().numpy().astype(np.float64) * y.cpu().numpy()))
+    rhs = float(np.sum(x.astype(np.float64) * fty))
+    rel = abs(lhs - rhs) / max(abs(lhs), abs(rhs))
+    _say(f"dot product: <Fx,y> {lhs:.9e} <x,F^T y> {rhs:.9e} rel {rel:.2e}")
+    assert rel <= 1e-5
+
+
+@pytest.fixture(scope="module")
+def grad64():
+    import torch
+
+    shape = (64, 64, 64)
+    nsteps, nshots = 200, 2
+    prob, v_true, src, rec, wav = _problem(shape, nsteps, nshots, seed=100, C=50)
+    v0 = synth.smooth(v_true, 6.0)
+    _say("grad64: gpu gradient")
+    J, gv = prob.misfit_and_gradient(torch.from_numpy(v0.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    return prob, v_true, v0, src, rec, wav, J, gv.cpu().numpy()
+
+
+def test_gradient_matches_oracle_64(grad64):
+    prob, v_true, v0, src, rec, wav, J, gv = grad64
+    g = prob.g
+    h, dt = g.h, g.dt
+    shape = v0.shape
+    sp = tuple(oracle.sponge_profile(n, 6) for n in (shape[2], shape[1], shape[0]))
+    dto = oracle.stable_dt(4, h, 3000.0)
+    assert abs(dto - dt) < 1e-15
+    kt = oracle.kappa_field(v_true.astype(np.float32), dt, h)
+    k0 = oracle.kappa_field(v0.astype(np.float32), dt, h)
+    amp = oracle.ricker(np.arange(prob.nsteps) * dt, 20.0)[:, None]
+    Jo, gk = 0.0, np.zeros(shape)
+    for s in src:
+        w = oracle.injection_weight([v_true[s[2], s[1], s[0]]], dt, h)
+        obs = oracle.forward(kt, sp, prob.nsteps, src_ijk=[s], src_w=w, src_amp=amp, rec_ijk=rec, nthreads=16)["traces"]
+        j, gks = oracle.gradient_kappa(k0, sp, prob.nsteps, src_ijk=[s], src_w=w, src_amp=amp, rec_ijk=rec,
+                                       observed=obs, nthreads=16)
+        Jo += j
+        gk += gks
+    gvo = 2.0 * v0.astype(np.float32) * (dt / h) ** 2 * gk
+    e = oracle.rel_l2(gv, gvo)
+    _say(f"grad64: J gpu {J:.9e} oracle {Jo:.9e}; dJ/dv rel-L2 {e:.2e}")
+    assert abs(J - Jo) <= 1e-3 * Jo
+    assert e <= 1e-3
+
+
+def test_gradient_matches_finite_differences(grad64):
+    """Central differences of the GPU misfit for a 1e-3 relative velocity perturbation on 64 seeded
+    cells of the illuminated zone (between the surface shots and depth 30).  The difference is formed
+    from the traces in FP64, J+ - J- = 1/2 <d+ - d-, d+ + d- - 2 d_obs>, so the two large misfits
+    never cancel in floating point; what remains is the FP32 noise of the traces.  Each cell is
+    perturbed with the sign of its gradient so that the 64 contributions add up instead of partly
+    cancelling (any direction is a valid finite-difference direction)."""
+    import torch
+
+    prob, v_true, v0, src, rec, wav, J, gv = grad64
+    rng = np.random.default_rng(110)
+    cells = np.stack([rng.integers(8, 56, 64), rng.integers(8, 56, 64), rng.integers(6, 30, 64)], axis=1)
+    sign = np.sign(gv[cells[:, 2], cells[:, 1], cells[:, 0]]).astype(np.float64)
+    sign[sign == 0] = 1.0
+    e = np.zeros_like(v0)
+    e[cells[:, 2], cells[:, 1], cells[:, 0]] = sign * 1e-3 * v0[cells[:, 2], cells[:, 1], cells[:, 0]]
+    fd = 0.0
+    kp = prob.kappa(torch.from_numpy((v0 + e).astype(np.float32)).cuda())
+    km = prob.kappa(torch.from_numpy((v0 - e).astype(np.float32)).cuda())
+    for sh in prob.shots:
+        dp = prob.model(kp, sh).cpu().numpy().astype(np.float64)
+        dm = prob.model(km, sh).cpu().numpy().astype(np.float64)
+        obs = sh.observed.cpu().numpy().astype(np.float64)
+        fd += 0.5 * float(np.sum((dp - dm) * (dp + dm - 2.0 * obs)))
+    fd /= 2.0
+    an = float(np.sum(gv.astype(np.float64) * e))
+    rel = abs(fd - an) / abs(an)
+    _say(f"FD: {fd:.6e} adjoint {an:.6e} rel {rel:.2e}")
+    assert rel <= 1e-2
+
+
+def test_checkpoint_interval_invariance():
+    """The recomputation schedule does not change the result: the gradient is bitwise the same for
+    any checkpoint interval."""
+    import torch
+
+    shape = (30, 28, 33)
+    a = _problem(shape, 70, 1, seed=120, C=7)
+    b = _problem(shape, 70, 1, seed=120, C=1000)
+    v0 = synth.smooth(a[1], 4.0)
+    va = torch.from_numpy(v0.astype(np.float32)).cuda()
+    Ja, ga = a[0].misfit_and_gradient(va)
+    Jb, gb = b[0].misfit_and_gradient(va)
+    assert Ja == Jb
+    assert torch.equal(ga, gb)
+
+
+def test_autograd_function():
+    import torch
+
+    from paper_1603_03971_amd.adjoint import velocity_misfit
+
+    shape = (30, 28, 33)
+    prob, v_true, *_ = _problem(shape, 60, 2, seed=130, C=20)
+    v = torch.from_numpy(synth.smooth(v_true, 4.0).astype(np.float32)).cuda().requires_grad_(True)
+    J = velocity_misfit(v, prob)
+    J.backward()
+    J2, gv = prob.misfit_and_gradient(v.detach())
+    assert abs(float(J) - J2) <= 1e-12 * J2
+    assert torch.equal(v.grad, gv)
+    assert float(J) > 0 and float(v.grad.abs().max()) > 0

@@ -418,3 +418,43 @@ def test_pack_faces_layout():
     assert list(f[0][:4]) == [u[0, 0, 0], u[0, 0, 1], u[0, 1, 0], u[0, 1, 1]]
     assert list(f[1][:2]) == [u[0, 0, 5], u[0, 0, 6]]
     assert f[5][0] == u[3, 0, 0]
+
+
+def test_bf16_rounding_is_nearest_even():
+    """Brute force: the oracle's BF16 code is the nearest BF16 value, ties to the even pattern."""
+    rng = np.random.default_rng(51)
+    x = np.concatenate([rng.standard_normal(20000).astype(np.float32),
+                        np.array([1.0, -1.0, 1.00390625, 1.01171875, 0.0, 3.0e-39], dtype=np.float32)])
+    codes = oracle.bf16_rne(x)
+    for xi, c in zip(x, codes):
+        sign, mag = int(c) & 0x8000, int(c) & 0x7FFF
+        cands = [sign | m for m in (max(mag - 1, 0), mag, mag + 1)]      # neighbours of the same sign
+        vals = [oracle.bf16_to_f32(np.array([cc], dtype=np.uint16))[0].astype(np.float64) for cc in cands]
+        d = [abs(v - float(xi)) for v in vals]
+        assert d[1] <= d[0] and d[1] <= d[2], (xi, c)
+        if (d[1] == d[0] and cands[0] != cands[1]) or d[1] == d[2]:
+            assert mag % 2 == 0, (xi, c)
+    # 1 + 2^-8 lies halfway between 1 and 1 + 2^-7: ties go to the even pattern 0x3F80
+    assert oracle.bf16_rne(np.array([1.00390625], dtype=np.float32))[0] == 0x3F80
+    assert oracle.bf16_rne(np.array([1.01171875], dtype=np.float32))[0] == 0x3F82
+
+
+def test_snapshot_codec_roundtrip_bounds():
+    """Per-slab scaling: |decode(encode(u)) - u| <= unit roundoff x slab max (BF16 2^-9, FP16 2^-11
+    in the normal range); all-zero slabs stay zero; FP16 codes equal numpy's RNE conversion."""
+    rng = np.random.default_rng(52)
+    u = rng.standard_normal((6, 9, 11)).astype(np.float32) * np.array([1e-3, 1.0, 50.0, 0.0, 1e-20, 7.0],
+                                                                      dtype=np.float32)[:, None, None]
+    for fmt, ur in (("bf16", 2.0 ** -9), ("f16", 2.0 ** -11)):
+        codes, scales = oracle.snapshot_encode(u, fmt)
+        np.testing.assert_array_equal(scales, np.max(np.abs(u), axis=(1, 2)))
+        rec = oracle.snapshot_decode(codes, scales, fmt)
+        err = np.abs(rec.astype(np.float64) - u.astype(np.float64))
+        tol = scales.astype(np.float64)[:, None, None] * (ur * 1.0001 if fmt == "bf16" else 2.0 ** -14)
+        tol = np.maximum(tol, np.abs(u) * ur * 1.0001)
+        assert np.all(err <= tol + 1e-45), fmt
+        assert np.all(rec[3] == 0)
+    codes, scales = oracle.snapshot_encode(u, "f16")
+    q = (u / np.where(scales > 0, scales, np.float32(1))[:, None, None]).astype(np.float32)
+    q[scales == 0] = 0.0                         # a zero slab is coded as +0
+    np.testing.assert_array_equal(codes, q.astype(np.float16).view(np.uint16))

@@ -458,3 +458,55 @@ def test_snapshot_codec_roundtrip_bounds():
     q = (u / np.where(scales > 0, scales, np.float32(1))[:, None, None]).astype(np.float32)
     q[scales == 0] = 0.0                         # a zero slab is coded as +0
     np.testing.assert_array_equal(codes, q.astype(np.float16).view(np.uint16))
+
+
+def test_cnn_conv3d_matches_direct_definition():
+    """The oracle's convolution equals the definition written as explicit loops (tiny volume)."""
+    from oracle import cnn
+
+    rng = np.random.default_rng(61)
+    x = rng.standard_normal((3, 4, 5, 2))
+    w = rng.standard_normal((27, 3, 2))
+    b = rng.standard_normal(3)
+    y = cnn.conv3d(x, w, b)
+    nz, ny, nx = x.shape[:3]
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                for co in range(3):
+                    s = b[co]
+                    for dz in (-1, 0, 1):
+                        for dy in (-1, 0, 1):
+                            for dx in (-1, 0, 1):
+                                kk, jj, ii = k + dz, j + dy, i + dx
+                                if 0 <= kk < nz and 0 <= jj < ny and 0 <= ii < nx:
+                                    t = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1)
+                                    s += sum(w[t, co, ci] * x[kk, jj, ii, ci] for ci in range(2))
+                    assert abs(y[k, j, i, co] - s) < 1e-12
+
+
+def test_cnn_gradients_match_finite_differences():
+    from oracle import cnn
+
+    rng = np.random.default_rng(62)
+    x = rng.standard_normal((4, 5, 6, 3))
+    tgt = rng.standard_normal((4, 5, 6, 2))
+    params = [(rng.standard_normal((27, 4, 3)) * 0.3, rng.standard_normal(4) * 0.1),
+              (rng.standard_normal((27, 4, 4)) * 0.3, rng.standard_normal(4) * 0.1),
+              (rng.standard_normal((27, 2, 4)) * 0.3, rng.standard_normal(2) * 0.1)]
+    loss, grads = cnn.loss_and_grads(x, tgt, params)
+    eps = 1e-6
+    for li in range(3):
+        for which in (0, 1):
+            p = params[li][which]
+            for _ in range(4):
+                idx = tuple(int(rng.integers(0, s)) for s in p.shape)
+                old = p[idx]
+                p[idx] = old + eps
+                lp = cnn.loss_and_grads(x, tgt, params)[0]
+                p[idx] = old - eps
+                lm = cnn.loss_and_grads(x, tgt, params)[0]
+                p[idx] = old
+                fd = (lp - lm) / (2 * eps)
+                an = grads[li][which][idx]
+                assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (li, which, idx, fd, an)

@@ -214,6 +214,86 @@ int rtm_snapshot_encode(const rtm_grid *grid, const float *u, uint16_t *codes, f
 int rtm_image_accumulate_coded(const rtm_grid *grid, float *image, const uint16_t *codes, const float *scales,
                                int32_t format, const float *rcv, float weight, hipStream_t stream);
 
+/* ---- learned dispersion corrector: a 3-D CNN on BF16 MFMA (FP32 accumulation) --------------- */
+/* Activations are channel-last BF16 volumes of 16 channels with a one-voxel zero halo: channel c of
+ * voxel (i, j, k) of an nx*ny*nz volume is element (((k+1)(ny+2) + (j+1))(nx+2) + (i+1)) * 16 + c.
+ * "Compact" FP32 channel-last volumes have no halo: element ((k ny + j) nx + i) * 16 + c.  nx must
+ * be a multiple of 16.  Weights of a 3x3x3 layer are BF16 [27 taps][16 out][16 in], tap
+ * t = 9 (dz+1) + 3 (dy+1) + (dx+1).  The caller zeroes halos once; the kernels write owned voxels only. */
+
+/* y = conv3x3x3(x, w) + bias (bias may be NULL; relu != 0: max(y, 0)), written as compact FP32
+ * (y32, [voxel][y32_channels]: only the first y32_channels of the 16 output channels, 1..16) and/or
+ * as a BF16 volume with halo (y16, all 16 channels); either may be NULL but not both.  Alignment:
+ * x and y32 16 bytes, w and y16 8 bytes; y16 must not alias x. */
+int rtm_cnn_conv3d(int32_t nx, int32_t ny, int32_t nz, const uint16_t *x, const uint16_t *w, const float *bias,
+                   int32_t relu, float *y32, int32_t y32_channels, uint16_t *y16, hipStream_t stream);
+
+/* dw[t][co][ci] += sum over voxels of dz[voxel][co] x[voxel + t][ci] and db[co] += sum dz[voxel][co]
+ * (x: BF16 with halo, dz: compact FP32, rounded to BF16 for the MFMA; FP32 accumulation, the
+ * per-workgroup partial sums added with FP32 atomics, so the summation order is not fixed). */
+int rtm_cnn_conv3d_wgrad(int32_t nx, int32_t ny, int32_t nz, const uint16_t *x, const float *dz, float *dw, float *db,
+                         hipStream_t stream);
+
+/* dz = dy for channels < channels (0 elsewhere), times the ReLU derivative (y > 0) when relu != 0;
+ * written compact FP32 (dz32) and BF16 with halo (dz16). */
+int rtm_cnn_relu_backward(int32_t nx, int32_t ny, int32_t nz, const float *y, const float *dy, int32_t relu,
+                          int32_t channels, float *dz32, uint16_t *dz16, hipStream_t stream);
+
+/* Gradient of the training loss L = 1/2 sum over voxels and channels < channels of w (out - target)^2,
+ * w = weight * mask[voxel] (mask: NULL, or compact FP32 over the voxels, >= 0), with respect to the
+ * network output: dz = w (out - target) there, 0 on the other channels, compact FP32 (dz32) and BF16
+ * with halo (dz16).  weight >= 0.  When loss is not NULL, L is added into loss[0] (FP64, atomically). */
+int rtm_cnn_loss_grad(int32_t nx, int32_t ny, int32_t nz, const float *out, const float *target, int32_t channels,
+                      float weight, const float *mask, float *dz32, uint16_t *dz16, double *loss, hipStream_t stream);
+
+/* wt[t][ci][co] = w[26 - t][co][ci]: the weights of the data-gradient convolution
+ * dx = rtm_cnn_conv3d(dz, wt). */
+int rtm_cnn_weight_flip(const uint16_t *w, uint16_t *wt, hipStream_t stream);
+
+/* One Adam step (Kingma & Ba 2014) on n FP32 parameters with bias correction for step number `step`
+ * (>= 1); also writes the BF16 copy param_bf16 when it is not NULL. */
+int rtm_cnn_adam(float *param, const float *grad, float *m1, float *m2, int32_t n, float lr, float beta1, float beta2,
+                 float eps, int32_t step, uint16_t *param_bf16, hipStream_t stream);
+
+/* b = BF16(a) (round to nearest even) for n values. */
+int rtm_cnn_to_bf16(const float *a, uint16_t *b, int32_t n, hipStream_t stream);
+
+/* Network input from a coarse-grid state: channel 0 = a = u^n / s, 1 = d = (u^n - u^{n-1}) / s (the
+ * difference formed in FP32), 2 = m a, 3 = m d with m = (velocity[voxel] - v_ref) / v_scale (velocity
+ * compact FP32 over the owned cells), others 0, with s = scale[0] read on the device (s = 0 gives zero
+ * channels).  v_scale > 0.  noise: NULL, or compact FP32 [voxel][2] added to a and d before the
+ * products and the rounding (training-time augmentation; the random numbers are the caller's). */
+int rtm_cnn_pack_input(const rtm_grid *grid, const float *u_cur, const float *u_prv, const float *velocity,
+                       float v_ref, float v_scale, const float *scale, const float *noise, uint16_t *x,
+                       hipStream_t stream);
+
+/* Apply the network's correction, given in the input's level-and-difference form (out compact FP32,
+ * [voxel][out_channels], out_channels 2..16): u^n += c out[.][0] and u^n - u^{n-1} += c out[.][1], i.e.
+ * u^{n-1} += c (out[.][0] - out[.][1]), with c = scale[0] * mask[voxel] (mask: NULL for 1, or compact
+ * FP32 over the owned cells, e.g. 0 near injection points). */
+int rtm_cnn_apply_correction(const rtm_grid *grid, float *u_cur, float *u_prv, const float *out, int32_t out_channels,
+                             const float *mask, const float *scale, hipStream_t stream);
+
+/* Training target in the same form: channel 0 = (ref^n - u^n) / s, channel 1 =
+ * ((ref^n - ref^{n-1}) - (u^n - u^{n-1})) / s, others 0 (compact FP32).  With noise (NULL, or the
+ * [voxel][2] array given to rtm_cnn_pack_input) the noise is subtracted too. */
+int rtm_cnn_target(const rtm_grid *grid, const float *ref_cur, const float *ref_prv, const float *u_cur,
+                   const float *u_prv, const float *scale, const float *noise, float *target, hipStream_t stream);
+
+/* Restriction from a fine grid to one of half the resolution (owned cells of padded fields of the
+ * two grids).  RTM_RESTRICT_INJECT: coarse (i, j, k) takes fine (2i, 2j, 2k).  RTM_RESTRICT_FULL: the
+ * separable (1/4, 1/2, 1/4) full-weighting average of the 27 fine cells around (2i, 2j, 2k), fine
+ * ghost cells included at the boundary; it preserves integrals, so a fine point source maps to the
+ * coarse point source.  Both modes need n_fine >= 2 n_coarse - 1 along every axis (full weighting
+ * then reads at most one ghost layer of the fine field, which must hold its boundary values). */
+#define RTM_RESTRICT_INJECT 0
+#define RTM_RESTRICT_FULL 1
+int rtm_restrict(const rtm_grid *fine, const rtm_grid *coarse, const float *u_fine, float *u_coarse, int32_t mode,
+                 hipStream_t stream);
+
+/* out[0] = max |u| over the owned cells (device; order-independent). */
+int rtm_field_absmax(const rtm_grid *grid, const float *u, float *out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "librtm.so")
 
 RTM_OK, RTM_EINVAL, RTM_EALIAS, RTM_ELAUNCH, RTM_EDEVICE = 0, -1, -2, -3, -4
 RTM_SNAP_BF16, RTM_SNAP_F16 = 1, 2
+RTM_RESTRICT_INJECT, RTM_RESTRICT_FULL = 0, 1
 RTM_OPT_INTERIOR_VARIANT, RTM_OPT_ZCHUNK, RTM_OPT_XCD_REMAP, RTM_OPT_HALO_X_WIDTH, RTM_OPT_HALO_Y_WIDTH = 1, 2, 3, 4, 5
 
 
@@ -65,6 +66,18 @@ def _load():
         "rtm_misfit_residual": ([vp, vp, vp, i64, vp, vp], ctypes.c_int),
         "rtm_velocity_gradient": ([gp, vp, vp, vp, f32, vp], ctypes.c_int),
         "rtm_image_accumulate_coded": ([gp, vp, vp, vp, i32, vp, f32, vp], ctypes.c_int),
+        "rtm_cnn_conv3d": ([i32, i32, i32, vp, vp, vp, i32, vp, i32, vp, vp], ctypes.c_int),
+        "rtm_cnn_conv3d_wgrad": ([i32, i32, i32, vp, vp, vp, vp, vp], ctypes.c_int),
+        "rtm_cnn_relu_backward": ([i32, i32, i32, vp, vp, i32, i32, vp, vp, vp], ctypes.c_int),
+        "rtm_cnn_loss_grad": ([i32, i32, i32, vp, vp, i32, f32, vp, vp, vp, vp, vp], ctypes.c_int),
+        "rtm_cnn_weight_flip": ([vp, vp, vp], ctypes.c_int),
+        "rtm_cnn_adam": ([vp, vp, vp, vp, i32, f32, f32, f32, f32, i32, vp, vp], ctypes.c_int),
+        "rtm_cnn_to_bf16": ([vp, vp, i32, vp], ctypes.c_int),
+        "rtm_cnn_pack_input": ([gp, vp, vp, vp, f32, f32, vp, vp, vp, vp], ctypes.c_int),
+        "rtm_cnn_apply_correction": ([gp, vp, vp, vp, i32, vp, vp, vp], ctypes.c_int),
+        "rtm_cnn_target": ([gp, vp, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "rtm_restrict": ([gp, gp, vp, vp, i32, vp], ctypes.c_int),
+        "rtm_field_absmax": ([gp, vp, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -220,3 +233,60 @@ def rtm_misfit_residual(d, obs, resid, n, misfit, stream=None):
 def rtm_velocity_gradient(grid, grad_v, grad_kappa, v, dt_over_h, stream=None):
     _check(_lib.rtm_velocity_gradient(ctypes.byref(grid), _p(grad_v), _p(grad_kappa), _p(v), dt_over_h, _s(stream)),
            "rtm_velocity_gradient")
+
+
+def rtm_cnn_conv3d(nx, ny, nz, x, w, bias, relu, y32, y16, stream=None, y32_channels=16):
+    _check(_lib.rtm_cnn_conv3d(nx, ny, nz, _p(x), _p(w), _p(bias), int(relu), _p(y32), y32_channels, _p(y16),
+                               _s(stream)), "rtm_cnn_conv3d")
+
+
+def rtm_cnn_conv3d_wgrad(nx, ny, nz, x, dz, dw, db, stream=None):
+    _check(_lib.rtm_cnn_conv3d_wgrad(nx, ny, nz, _p(x), _p(dz), _p(dw), _p(db), _s(stream)), "rtm_cnn_conv3d_wgrad")
+
+
+def rtm_cnn_relu_backward(nx, ny, nz, y, dy, relu, channels, dz32, dz16, stream=None):
+    _check(_lib.rtm_cnn_relu_backward(nx, ny, nz, _p(y), _p(dy), int(relu), channels, _p(dz32), _p(dz16), _s(stream)),
+           "rtm_cnn_relu_backward")
+
+
+def rtm_cnn_loss_grad(nx, ny, nz, out, target, channels, dz32, dz16, loss=None, stream=None, weight=1.0, mask=None):
+    _check(_lib.rtm_cnn_loss_grad(nx, ny, nz, _p(out), _p(target), channels, weight, _p(mask), _p(dz32), _p(dz16),
+                                  _p(loss), _s(stream)), "rtm_cnn_loss_grad")
+
+
+def rtm_cnn_weight_flip(w, wt, stream=None):
+    _check(_lib.rtm_cnn_weight_flip(_p(w), _p(wt), _s(stream)), "rtm_cnn_weight_flip")
+
+
+def rtm_cnn_adam(param, grad, m1, m2, n, lr, beta1, beta2, eps, step, param_bf16=None, stream=None):
+    _check(_lib.rtm_cnn_adam(_p(param), _p(grad), _p(m1), _p(m2), n, lr, beta1, beta2, eps, step, _p(param_bf16),
+                             _s(stream)), "rtm_cnn_adam")
+
+
+def rtm_cnn_to_bf16(a, b, n, stream=None):
+    _check(_lib.rtm_cnn_to_bf16(_p(a), _p(b), n, _s(stream)), "rtm_cnn_to_bf16")
+
+
+def rtm_cnn_pack_input(grid, u_cur, u_prv, velocity, v_ref, v_scale, scale, x, noise=None, stream=None):
+    _check(_lib.rtm_cnn_pack_input(ctypes.byref(grid), _p(u_cur), _p(u_prv), _p(velocity), v_ref, v_scale, _p(scale),
+                                   _p(noise), _p(x), _s(stream)), "rtm_cnn_pack_input")
+
+
+def rtm_cnn_apply_correction(grid, u_cur, u_prv, out, scale, stream=None, out_channels=16, mask=None):
+    _check(_lib.rtm_cnn_apply_correction(ctypes.byref(grid), _p(u_cur), _p(u_prv), _p(out), out_channels, _p(mask),
+                                         _p(scale), _s(stream)), "rtm_cnn_apply_correction")
+
+
+def rtm_cnn_target(grid, ref_cur, ref_prv, u_cur, u_prv, scale, target, noise=None, stream=None):
+    _check(_lib.rtm_cnn_target(ctypes.byref(grid), _p(ref_cur), _p(ref_prv), _p(u_cur), _p(u_prv), _p(scale),
+                               _p(noise), _p(target), _s(stream)), "rtm_cnn_target")
+
+
+def rtm_restrict(fine, coarse, u_fine, u_coarse, stream=None, mode=None):
+    mode = RTM_RESTRICT_INJECT if mode is None else mode
+    _check(_lib.rtm_restrict(ctypes.byref(fine), ctypes.byref(coarse), _p(u_fine), _p(u_coarse), mode, _s(stream)),
+           "rtm_restrict")
+
+
+def rtm_field_absmax(grid, u, out, stream=None):
+    _check(_lib.rtm_field_absmax(ctypes.byref(grid), _p(u), _p(out), _s(stream)), "rtm_field_absmax")

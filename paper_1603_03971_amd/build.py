@@ -9,7 +9,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", "rtm.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "rtm.hip"), os.path.join(HERE, "csrc", "cnn.hip")]
 LIB = os.path.join(HERE, "librtm.so")
 ARCH = os.environ.get("RTM_OFFLOAD_ARCH", "gfx950")
 

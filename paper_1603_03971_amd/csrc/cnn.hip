@@ -1,0 +1,651 @@
+// cnn.hip -- the learned dispersion corrector: a small 3-D CNN on BF16 MFMA with FP32 accumulation,
+// its training kernels, and the glue between the coarse-grid wavefield and the network.
+//
+// Activations are channel-last BF16 volumes with 16 channels and a one-voxel zero halo: element
+// (c, i, j, k) of an nx*ny*nz volume lives at (((k+1)(ny+2) + (j+1))(nx+2) + (i+1)) * 16 + c.  A
+// 3x3x3 convolution with 16 input and 16 output channels is an implicit GEMM: for a block of 16
+// voxels along x, D[voxel][co] = sum over the 27 taps of A_t[voxel][ci] B_t[ci][co], one
+// 16x16x16 MFMA per tap, with A_t read straight from the activation volume (the tap's shifted
+// voxels, four consecutive channels per lane) and B_t the tap's weights kept in registers.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+
+#include "rtm.h"
+
+namespace {
+
+constexpr int kC = 16;          // channels
+constexpr int kTaps = 27;
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float x)
+{
+    const uint32_t b = __float_as_uint(x);
+    return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+
+struct Vol {
+    int nx, ny, nz;
+    __device__ __forceinline__ long long at(int i, int j, int k) const   // padded voxel index
+    {
+        return ((long long)(k + 1) * (ny + 2) + (j + 1)) * (long long)(nx + 2) + (i + 1);
+    }
+    __device__ __forceinline__ long long flat(int i, int j, int k) const // compact voxel index
+    {
+        return ((long long)k * ny + j) * (long long)nx + i;
+    }
+};
+
+// Forward convolution, as MFMAs with M = output channel, N = 16 voxels along x, K = 16 input
+// channels, one per tap: D[co][voxel] += W_t[co][ci] X[voxel + tap][ci].  MFMA lane layout
+// (16x16x16): A[m = l % 16][k = 4(l/16) + i], B[k = 4(l/16) + i][n = l % 16],
+// D[m = 4(l/16) + i][n = l % 16]; so lane l holds W_t[co = l % 16][ci = 4(l/16) ..] (in registers
+// for the whole launch), reads X[voxel = l % 16][ci = 4(l/16) ..] (8 bytes) and ends with four
+// consecutive output channels of one voxel, which makes every store of a wave one contiguous run.
+//
+// A workgroup of TY waves owns a tile of 64 (x) by TY (y) voxels and marches through a chunk of z
+// planes.  The input planes z-1, z, z+1 of the tile (with a one-voxel rim) sit in an LDS ring of
+// three; the next plane is fetched into registers while the current one is computed.  Wave w
+// computes row y0 + w: four 16-voxel segments, 27 MFMAs each per plane.
+template <int TY>
+__global__ __launch_bounds__(64 * TY) void k_conv3d(Vol v, int zc, const uint16_t *__restrict__ x,
+                                                    const uint16_t *__restrict__ w, const float *__restrict__ bias,
+                                                    int relu, float *__restrict__ y32, int y32c,
+                                                    uint16_t *__restrict__ y16)
+{
+    constexpr int TX = 64, PX = TX + 2, PY = TY + 2;
+    constexpr int PLANE = PX * PY * kC;          // BF16 elements of one staged plane
+    constexpr int CHUNKS = PX * PY * 2;          // its 16-byte pieces
+    constexpr int NT = 64 * TY;
+    constexpr int NCH = (CHUNKS + NT - 1) / NT;
+    __shared__ __align__(16) uint16_t lds[3 * PLANE];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int m = lane & 15, q = lane >> 4;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int z0 = blockIdx.z * zc;
+    const int z1 = min(v.nz, z0 + zc);
+    const int y = y0 + wave;
+    const int nseg = min(4, (v.nx - x0) >> 4);
+    const long long sy = (long long)(v.nx + 2) * kC;
+    const long long sz = sy * (v.ny + 2);
+
+    v4s wf[kTaps];
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t)
+        wf[t] = *reinterpret_cast<const v4s *>(w + ((t * kC + m) * kC + 4 * q));
+
+    // piece c of a plane: voxel (row r, column col) of the rim-extended tile, half c & 1 of its channels;
+    // rows and columns past the volume's zero halo are clamped onto it (their values are never used).
+    // Threads past the last piece repeat it (the same bytes to the same place), so that no load or
+    // store is predicated.
+    static_assert(NCH <= 4, "plane pieces per thread");
+    long long g0, g1, g2, g3;
+    int l0, l1, l2, l3;
+    auto piece = [&](int i, long long &go, int &lo) {
+        const int cc = min((int)threadIdx.x + i * NT, CHUNKS - 1);
+        const int vox = cc >> 1, r = vox / PX, col = vox - r * PX;
+        const int py = min(y0 + r, v.ny + 1), px = min(x0 + col, v.nx + 1);
+        go = py * sy + (long long)px * kC + (cc & 1) * 8;
+        lo = cc * 8;
+    };
+    piece(0, g0, l0);
+    piece(1, g1, l1);
+    piece(2, g2, l2);
+    piece(3, g3, l3);
+    int4 p0, p1, p2, p3;
+#define CONV_FETCH(pz)                                                                                 \
+    {                                                                                                  \
+        const uint16_t *src_ = x + (long long)(pz) * sz;                                               \
+        p0 = *reinterpret_cast<const int4 *>(src_ + g0);                                               \
+        if constexpr (NCH > 1) p1 = *reinterpret_cast<const int4 *>(src_ + g1);                        \
+        if constexpr (NCH > 2) p2 = *reinterpret_cast<const int4 *>(src_ + g2);                        \
+        if constexpr (NCH > 3) p3 = *reinterpret_cast<const int4 *>(src_ + g3);                        \
+    }
+#define CONV_STASH(slot)                                                                               \
+    {                                                                                                  \
+        uint16_t *dst_ = lds + (slot) * PLANE;                                                         \
+        *reinterpret_cast<int4 *>(dst_ + l0) = p0;                                                     \
+        if constexpr (NCH > 1) *reinterpret_cast<int4 *>(dst_ + l1) = p1;                              \
+        if constexpr (NCH > 2) *reinterpret_cast<int4 *>(dst_ + l2) = p2;                              \
+        if constexpr (NCH > 3) *reinterpret_cast<int4 *>(dst_ + l3) = p3;                              \
+    }
+
+    // padded plane pz lives in ring slot pz % 3; output plane z needs padded planes z, z + 1, z + 2
+    CONV_FETCH(z0)
+    CONV_STASH(z0 % 3)
+    CONV_FETCH(z0 + 1)
+    CONV_STASH((z0 + 1) % 3)
+    CONV_FETCH(min(z0 + 2, v.nz + 1))
+    for (int z = z0; z < z1; ++z) {
+        __syncthreads();                      // everyone is done with slot (z + 2) % 3 (plane z - 1)
+        CONV_STASH((z + 2) % 3)
+        __syncthreads();
+        CONV_FETCH(min(z + 3, v.nz + 1))      // the plane after next (clamped past the end: unused)
+        // all four segments and rows are computed (rows past ny and segments past nx read clamped
+        // rim data and are not stored), so the MFMA sequence has no branches
+        v4f acc[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc[s] = v4f{0.f, 0.f, 0.f, 0.f};
+        const int b0 = (z % 3) * PLANE, b1 = ((z + 1) % 3) * PLANE, b2 = ((z + 2) % 3) * PLANE;
+        const uint16_t *lane_base = lds + (wave * PX + m) * kC + 4 * q;
+        auto tap_ptr = [&](int t) {
+            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;        // offsets + 1
+            const int bz = dz == 0 ? b0 : (dz == 1 ? b1 : b2);
+            return lane_base + bz + (dy * PX + dx) * kC;
+        };
+        // software pipeline: the four B fragments of tap t + 1 are read from LDS before the four
+        // MFMAs of tap t are issued, so LDS latency overlaps matrix work
+        v4s cur[4], nxt[4];
+        {
+            const uint16_t *r0 = tap_ptr(0);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) cur[s] = *reinterpret_cast<const v4s *>(r0 + s * 16 * kC);
+        }
+#pragma unroll
+        for (int t = 0; t < kTaps; ++t) {
+            if (t + 1 < kTaps) {
+                const uint16_t *r1 = tap_ptr(t + 1);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) nxt[s] = *reinterpret_cast<const v4s *>(r1 + s * 16 * kC);
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                acc[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[t], cur[s], acc[s], 0, 0, 0);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) cur[s] = nxt[s];
+        }
+        if (y >= v.ny) continue;
+        float bi[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bi[i] = bias ? bias[4 * q + i] : 0.0f;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (s >= nseg) break;
+            const int xv = x0 + 16 * s + m;
+            float r[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                r[i] = acc[s][i] + bi[i];
+                if (relu) r[i] = fmaxf(r[i], 0.0f);
+            }
+            if (y16) {
+                uint2 pk;
+                pk.x = (uint32_t)f2bf(r[0]) | ((uint32_t)f2bf(r[1]) << 16);
+                pk.y = (uint32_t)f2bf(r[2]) | ((uint32_t)f2bf(r[3]) << 16);
+                *reinterpret_cast<uint2 *>(y16 + v.at(xv, y, z) * kC + 4 * q) = pk;
+            }
+            if (y32) {
+                const long long o = v.flat(xv, y, z) * y32c;
+                if (y32c == kC) {
+                    *reinterpret_cast<float4 *>(y32 + o + 4 * q) = make_float4(r[0], r[1], r[2], r[3]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (4 * q + i < y32c) y32[o + 4 * q + i] = r[i];
+                }
+            }
+        }
+    }
+#undef CONV_FETCH
+#undef CONV_STASH
+}
+
+// Weight gradient.  dw[t][co][ci] += sum over voxels of dz[voxel][co] x[voxel + tap][ci], as MFMAs
+// with M = output channel, N = input channel and K = 16 voxels along x.  A wave accumulates a row
+// segment for all 27 taps, the workgroup's four waves add their partial sums in LDS, and one atomic
+// add per weight and workgroup goes to global memory.  db[co] += sum of dz[voxel][co].
+__global__ __launch_bounds__(256) void k_conv3d_wgrad(Vol v, const uint16_t *__restrict__ x,
+                                                      const float *__restrict__ dz, float *__restrict__ dw,
+                                                      float *__restrict__ db)
+{
+    __shared__ float red[kTaps * kC * kC];
+    __shared__ float redb[kC];
+    for (int t = threadIdx.x; t < kTaps * kC * kC; t += 256) red[t] = 0.0f;
+    if (threadIdx.x < kC) redb[threadIdx.x] = 0.0f;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int j = blockIdx.y * 4 + wave;
+    const int k = blockIdx.z;
+    const int m = lane & 15, q = lane >> 4;
+    if (j < v.ny) {
+        v4f acc[kTaps];
+#pragma unroll
+        for (int t = 0; t < kTaps; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+        float bsum = 0.0f;
+        for (int x0 = blockIdx.x * 64; x0 < min(v.nx, blockIdx.x * 64 + 64); x0 += 16) {
+            // A[co = m][vox = 4q + i] = dz[x0 + 4q + i][m]
+            v4s a;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float d = dz[v.flat(x0 + 4 * q + i, j, k) * kC + m];
+                bsum += d;
+                a[i] = (short)f2bf(d);
+            }
+#pragma unroll
+            for (int t = 0; t < kTaps; ++t) {
+                const int tz = t / 9 - 1, ty = (t / 3) % 3 - 1, tx = t % 3 - 1;
+                // B[vox = 4q + i][ci = m] = x[(x0 + 4q + i) + tap][m]
+                v4s bb;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    bb[i] = (short)x[v.at(x0 + 4 * q + i + tx, j + ty, k + tz) * kC + m];
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc[t], 0, 0, 0);
+            }
+        }
+        // D[co = 4q + i][ci = m]
+#pragma unroll
+        for (int t = 0; t < kTaps; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) atomicAdd(&red[(t * kC + 4 * q + i) * kC + m], acc[t][i]);
+        atomicAdd(&redb[m], bsum);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kTaps * kC * kC; t += 256) atomicAdd(&dw[t], red[t]);
+    if (threadIdx.x < kC) atomicAdd(&db[threadIdx.x], redb[threadIdx.x]);
+}
+
+// dz = dy * (y > 0) for a ReLU layer (relu = 0: dz = dy), over the channels < cmask (others 0);
+// written as FP32 (compact) and as BF16 with a zero halo for the data-gradient convolution.
+__global__ __launch_bounds__(256) void k_relu_backward(Vol v, const float *__restrict__ y, const float *__restrict__ dy,
+                                                       int relu, int cmask, float *__restrict__ dz32,
+                                                       uint16_t *__restrict__ dz16)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = (long long)v.nx * v.ny * v.nz * kC;
+    if (t >= n) return;
+    const int c = (int)(t % kC);
+    const long long vox = t / kC;
+    const int i = (int)(vox % v.nx);
+    const int jj = (int)((vox / v.nx) % v.ny);
+    const int kk = (int)(vox / ((long long)v.nx * v.ny));
+    float d = c < cmask ? dy[t] : 0.0f;
+    if (relu && !(y[t] > 0.0f)) d = 0.0f;
+    dz32[t] = d;
+    dz16[v.at(i, jj, kk) * kC + c] = f2bf(d);
+}
+
+// Output-layer gradient of L = 1/2 sum over voxels and channels < cmask of w (out - target)^2 with
+// w = weight * mask[voxel] (mask optional): dz = w (out - target) on those channels (others 0), FP32
+// compact and BF16 with a zero halo; L is added into loss[0].
+__global__ __launch_bounds__(256) void k_loss_grad(Vol v, const float *__restrict__ out, const float *__restrict__ tgt,
+                                                   int cmask, float weight, const float *__restrict__ mask,
+                                                   float *__restrict__ dz32, uint16_t *__restrict__ dz16,
+                                                   double *__restrict__ loss)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = (long long)v.nx * v.ny * v.nz * kC;
+    float d = 0.0f;
+    if (t < n) {
+        const int c = (int)(t % kC);
+        const long long vox = t / kC;
+        const int i = (int)(vox % v.nx);
+        const int jj = (int)((vox / v.nx) % v.ny);
+        const int kk = (int)(vox / ((long long)v.nx * v.ny));
+        const float wv = mask ? weight * mask[vox] : weight;
+        if (c < cmask) d = out[t] - tgt[t];
+        dz32[t] = wv * d;
+        dz16[v.at(i, jj, kk) * kC + c] = f2bf(wv * d);
+        d *= sqrtf(wv);                        // the loss term below is wv d^2 / 2
+    }
+    if (!loss) return;
+    __shared__ double red[256];
+    red[threadIdx.x] = 0.5 * (double)d * (double)d;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(loss, red[0]);
+}
+
+// w_t[t'][ci][co] = w[26 - t'][co][ci]: the weights of the data-gradient convolution.
+__global__ void k_weight_flip(const uint16_t *__restrict__ w, uint16_t *__restrict__ wt)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= kTaps * kC * kC) return;
+    const int tap = t / (kC * kC), a = (t / kC) % kC, b = t % kC;
+    wt[t] = w[((kTaps - 1 - tap) * kC + b) * kC + a];
+}
+
+// Adam (Kingma & Ba 2014) on FP32 master weights; also writes the BF16 copy used by the kernels.
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m1,
+                       float *__restrict__ m2, int n, float lr, float b1, float b2, float eps, float c1, float c2,
+                       uint16_t *__restrict__ p16)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const float gt = g[t];
+    const float a = b1 * m1[t] + (1.0f - b1) * gt;
+    const float b = b2 * m2[t] + (1.0f - b2) * gt * gt;
+    m1[t] = a;
+    m2[t] = b;
+    const float val = p[t] - lr * (a / c1) / (sqrtf(b / c2) + eps);
+    p[t] = val;
+    if (p16) p16[t] = f2bf(val);
+}
+
+__global__ void k_to_bf16(const float *__restrict__ a, uint16_t *__restrict__ b, int n)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) b[t] = f2bf(a[t]);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Glue between the coarse-grid wavefield (padded rtm_grid layout) and the network
+// ---------------------------------------------------------------------------------------------
+struct G {
+    int nx, ny, nz, R;
+    long long py, pz;
+    __device__ __forceinline__ long long idx(int i, int j, int k) const
+    {
+        return (long long)(k + R) * pz + (long long)(j + R) * py + (i + R);
+    }
+};
+
+G make_g(const rtm_grid *gr) { return G{gr->nx, gr->ny, gr->nz, gr->radius, gr->pitch_y, gr->pitch_z}; }
+
+// Network input: channel 0 = a = u^n / s, 1 = d = (u^n - u^{n-1}) / s, 2 = m a, 3 = m d with the
+// material m = (v - v_ref) / v_scale, others 0; s is read from the device (scale[0]); BF16,
+// channel-last with a zero halo.  The difference of the two levels, about a tenth of either, is
+// formed in FP32 before the rounding: rounding the levels separately would leave it with a few per
+// cent of error.  Every channel vanishes where the wavefield does, so a bias-free network maps a
+// zero state to a zero correction.  noise (optional, [voxel][2]) is added to a and d
+// (training-time augmentation).
+__global__ __launch_bounds__(256) void k_pack_input(G g, Vol v, const float *__restrict__ u_cur,
+                                                    const float *__restrict__ u_prv, const float *__restrict__ vel,
+                                                    float v_ref, float v_inv, const float *__restrict__ scale,
+                                                    const float *__restrict__ noise, uint16_t *__restrict__ x)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    if (t >= n) return;
+    const int i = (int)(t % g.nx);
+    const int j = (int)((t / g.nx) % g.ny);
+    const int k = (int)(t / ((long long)g.nx * g.ny));
+    const float s = scale[0];
+    const float inv = s > 0.0f ? 1.0f / s : 0.0f;
+    const long long p = g.idx(i, j, k);
+    uint16_t *o = x + v.at(i, j, k) * kC;
+    const float uc = u_cur[p];
+    float a = uc * inv, d = (uc - u_prv[p]) * inv;
+    if (noise) {
+        a += noise[2 * t];
+        d += noise[2 * t + 1];
+    }
+    const float m = (vel[t] - v_ref) * v_inv;
+    o[0] = f2bf(a);
+    o[1] = f2bf(d);
+    o[2] = f2bf(m * a);
+    o[3] = f2bf(m * d);
+#pragma unroll
+    for (int c = 4; c < kC; ++c) o[c] = 0;
+}
+
+// Apply the correction (out: [voxel][oc], in the input's level-and-difference form): u^n += s o0 and
+// u^n - u^{n-1} += s o1, i.e. u^{n-1} += s (o0 - o1), on owned cells; s times mask[voxel] if a mask
+// is given.
+__global__ __launch_bounds__(256) void k_apply_correction(G g, float *u_cur, float *u_prv, const float *__restrict__ out,
+                                                          int oc, const float *__restrict__ mask,
+                                                          const float *__restrict__ scale)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    if (t >= n) return;
+    const int i = (int)(t % g.nx);
+    const int j = (int)((t / g.nx) % g.ny);
+    const int k = (int)(t / ((long long)g.nx * g.ny));
+    const float s = mask ? scale[0] * mask[t] : scale[0];
+    const long long p = g.idx(i, j, k);
+    const float o0 = out[t * oc + 0], o1 = out[t * oc + 1];
+    u_cur[p] = __builtin_fmaf(s, o0, u_cur[p]);
+    u_prv[p] = __builtin_fmaf(s, o0 - o1, u_prv[p]);
+}
+
+// Training target in the input's form: channel 0 = (ref^n - u^n) / s, channel 1 =
+// ((ref^n - ref^{n-1}) - (u^n - u^{n-1})) / s, minus the input noise if any (the network is then asked
+// to remove it); FP32 channel-last, other channels 0.
+__global__ __launch_bounds__(256) void k_target(G g, const float *__restrict__ ref_cur, const float *__restrict__ ref_prv,
+                                                const float *__restrict__ u_cur, const float *__restrict__ u_prv,
+                                                const float *__restrict__ scale, const float *__restrict__ noise,
+                                                float *__restrict__ tgt)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    if (t >= n) return;
+    const int i = (int)(t % g.nx);
+    const int j = (int)((t / g.nx) % g.ny);
+    const int k = (int)(t / ((long long)g.nx * g.ny));
+    const float s = scale[0];
+    const float inv = s > 0.0f ? 1.0f / s : 0.0f;
+    const long long p = g.idx(i, j, k);
+    float *o = tgt + t * kC;
+    const float rc = ref_cur[p], uc = u_cur[p];
+    o[0] = (rc - uc) * inv;
+    o[1] = ((rc - ref_prv[p]) - (uc - u_prv[p])) * inv;
+    if (noise) {
+        o[0] -= noise[2 * t];
+        o[1] -= noise[2 * t + 1];
+    }
+#pragma unroll
+    for (int c = 2; c < kC; ++c) o[c] = 0.0f;
+}
+
+// Fine -> coarse restriction.  Injection: coarse (i, j, k) takes fine (2i, 2j, 2k).  Full weighting:
+// the separable (1/4, 1/2, 1/4) average of the 27 fine cells around it (ghost cells of the fine field
+// enter at the boundary), which preserves integrals: a fine point source of weight 1/h^3 becomes a
+// coarse one of weight 1/(2h)^3.
+__global__ __launch_bounds__(256) void k_restrict(G f, G c, const float *__restrict__ uf, float *__restrict__ uc,
+                                                  int full)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = (long long)c.nx * c.ny * c.nz;
+    if (t >= n) return;
+    const int i = (int)(t % c.nx);
+    const int j = (int)((t / c.nx) % c.ny);
+    const int k = (int)(t / ((long long)c.nx * c.ny));
+    const long long p = f.idx(2 * i, 2 * j, 2 * k);
+    if (!full) {
+        uc[c.idx(i, j, k)] = uf[p];
+        return;
+    }
+    const float w[3] = {0.25f, 0.5f, 0.25f};
+    float acc = 0.0f;
+    for (int a = 0; a < 3; ++a) {
+        float sy = 0.0f;
+        for (int b = 0; b < 3; ++b) {
+            const float *r = uf + p + (long long)(a - 1) * f.pz + (long long)(b - 1) * f.py;
+            const float sx = __builtin_fmaf(w[2], r[1], __builtin_fmaf(w[1], r[0], w[0] * r[-1]));
+            sy = __builtin_fmaf(w[b], sx, sy);
+        }
+        acc = __builtin_fmaf(w[a], sy, acc);
+    }
+    uc[c.idx(i, j, k)] = acc;
+}
+
+// max |u| over owned cells into out[0] (the corrector's per-application scale): one workgroup per z
+// plane, combined with an integer atomic max on the bit patterns (non-negative floats order like
+// their bits), so the result does not depend on scheduling.
+__global__ void k_zero1(float *out) { out[0] = 0.0f; }
+
+__global__ __launch_bounds__(256) void k_plane_absmax_into(G g, const float *__restrict__ u, float *out)
+{
+    const int k = blockIdx.x;
+    const int nxy = g.nx * g.ny;
+    float mx = 0.0f;
+    for (int t = threadIdx.x; t < nxy; t += 256) {
+        const int j = t / g.nx, i = t - j * g.nx;
+        mx = fmaxf(mx, fabsf(u[g.idx(i, j, k)]));
+    }
+    __shared__ float red[256];
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(reinterpret_cast<int *>(out), __float_as_int(red[0]));
+}
+
+int status() { return hipGetLastError() == hipSuccess ? RTM_OK : RTM_ELAUNCH; }
+unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+bool vol_ok(int nx, int ny, int nz) { return nx > 0 && ny > 0 && nz > 0 && nx % 16 == 0; }
+
+}  // namespace
+
+extern "C" {
+
+int rtm_cnn_conv3d(int32_t nx, int32_t ny, int32_t nz, const uint16_t *x, const uint16_t *w, const float *bias,
+                   int32_t relu, float *y32, int32_t y32_channels, uint16_t *y16, hipStream_t stream)
+{
+    if (!vol_ok(nx, ny, nz) || !x || !w || (!y32 && !y16)) return RTM_EINVAL;
+    if (y32 && (y32_channels < 1 || y32_channels > kC)) return RTM_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(x) & 15u) || (reinterpret_cast<uintptr_t>(w) & 7u)) return RTM_EINVAL;
+    if ((y16 && (reinterpret_cast<uintptr_t>(y16) & 7u)) || (y32 && (reinterpret_cast<uintptr_t>(y32) & 15u)))
+        return RTM_EINVAL;
+    if ((const void *)y16 == (const void *)x) return RTM_EALIAS;
+    const Vol v{nx, ny, nz};
+    constexpr int TY = 4;
+    const long long tiles = (long long)((nx + 63) / 64) * ((ny + TY - 1) / TY);
+    // about 2048 workgroups (several per CU) without cutting z into chunks thinner than needed
+    long long chunks = (2048 + tiles - 1) / tiles;
+    if (chunks > nz) chunks = nz;
+    const int zc = (int)((nz + chunks - 1) / chunks);
+    const int nzc = (nz + zc - 1) / zc;
+    hipLaunchKernelGGL(k_conv3d<TY>, dim3((nx + 63) / 64, (ny + TY - 1) / TY, nzc), dim3(64 * TY), 0, stream, v, zc,
+                       x, w, bias, (int)relu, y32, (int)y32_channels, y16);
+    return status();
+}
+
+int rtm_cnn_conv3d_wgrad(int32_t nx, int32_t ny, int32_t nz, const uint16_t *x, const float *dz, float *dw, float *db,
+                         hipStream_t stream)
+{
+    if (!vol_ok(nx, ny, nz) || !x || !dz || !dw || !db) return RTM_EINVAL;
+    const Vol v{nx, ny, nz};
+    hipLaunchKernelGGL(k_conv3d_wgrad, dim3((nx + 63) / 64, (ny + 3) / 4, nz), dim3(256), 0, stream, v, x, dz, dw, db);
+    return status();
+}
+
+int rtm_cnn_relu_backward(int32_t nx, int32_t ny, int32_t nz, const float *y, const float *dy, int32_t relu,
+                          int32_t channels, float *dz32, uint16_t *dz16, hipStream_t stream)
+{
+    if (!vol_ok(nx, ny, nz) || !dy || !dz32 || !dz16 || (relu && !y) || channels < 0 || channels > kC)
+        return RTM_EINVAL;
+    const Vol v{nx, ny, nz};
+    const long long n = (long long)nx * ny * nz * kC;
+    hipLaunchKernelGGL(k_relu_backward, dim3(nblk(n)), dim3(256), 0, stream, v, y, dy, (int)relu, (int)channels, dz32,
+                       dz16);
+    return status();
+}
+
+int rtm_cnn_loss_grad(int32_t nx, int32_t ny, int32_t nz, const float *out, const float *target, int32_t channels,
+                      float weight, const float *mask, float *dz32, uint16_t *dz16, double *loss, hipStream_t stream)
+{
+    if (!vol_ok(nx, ny, nz) || !out || !target || !dz32 || !dz16 || channels < 0 || channels > kC || !(weight >= 0.0f))
+        return RTM_EINVAL;
+    const Vol v{nx, ny, nz};
+    const long long n = (long long)nx * ny * nz * kC;
+    hipLaunchKernelGGL(k_loss_grad, dim3(nblk(n)), dim3(256), 0, stream, v, out, target, (int)channels, weight, mask,
+                       dz32, dz16, loss);
+    return status();
+}
+
+int rtm_cnn_weight_flip(const uint16_t *w, uint16_t *wt, hipStream_t stream)
+{
+    if (!w || !wt || w == wt) return RTM_EINVAL;
+    hipLaunchKernelGGL(k_weight_flip, dim3(nblk(kTaps * kC * kC)), dim3(256), 0, stream, w, wt);
+    return status();
+}
+
+int rtm_cnn_adam(float *param, const float *grad, float *m1, float *m2, int32_t n, float lr, float beta1, float beta2,
+                 float eps, int32_t step, uint16_t *param_bf16, hipStream_t stream)
+{
+    if (!param || !grad || !m1 || !m2 || n < 0 || step < 1) return RTM_EINVAL;
+    if (n == 0) return RTM_OK;
+    const float c1 = 1.0f - (float)__builtin_pow(beta1, step), c2 = 1.0f - (float)__builtin_pow(beta2, step);
+    hipLaunchKernelGGL(k_adam, dim3(nblk(n)), dim3(256), 0, stream, param, grad, m1, m2, (int)n, lr, beta1, beta2, eps,
+                       c1, c2, param_bf16);
+    return status();
+}
+
+int rtm_cnn_to_bf16(const float *a, uint16_t *b, int32_t n, hipStream_t stream)
+{
+    if (!a || !b || n < 0) return RTM_EINVAL;
+    if (n == 0) return RTM_OK;
+    hipLaunchKernelGGL(k_to_bf16, dim3(nblk(n)), dim3(256), 0, stream, a, b, (int)n);
+    return status();
+}
+
+int rtm_cnn_pack_input(const rtm_grid *grid, const float *u_cur, const float *u_prv, const float *velocity,
+                       float v_ref, float v_scale, const float *scale, const float *noise, uint16_t *x,
+                       hipStream_t stream)
+{
+    if (!grid || !u_cur || !u_prv || !velocity || !scale || !x || !(v_scale > 0.0f)) return RTM_EINVAL;
+    if (!vol_ok(grid->nx, grid->ny, grid->nz)) return RTM_EINVAL;
+    const G g = make_g(grid);
+    const Vol v{grid->nx, grid->ny, grid->nz};
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_pack_input, dim3(nblk(n)), dim3(256), 0, stream, g, v, u_cur, u_prv, velocity, v_ref,
+                       1.0f / v_scale, scale, noise, x);
+    return status();
+}
+
+int rtm_cnn_apply_correction(const rtm_grid *grid, float *u_cur, float *u_prv, const float *out, int32_t out_channels,
+                             const float *mask, const float *scale, hipStream_t stream)
+{
+    if (!grid || !u_cur || !u_prv || !out || !scale || u_cur == u_prv || out_channels < 2 || out_channels > kC)
+        return RTM_EINVAL;
+    const G g = make_g(grid);
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_apply_correction, dim3(nblk(n)), dim3(256), 0, stream, g, u_cur, u_prv, out,
+                       (int)out_channels, mask, scale);
+    return status();
+}
+
+int rtm_cnn_target(const rtm_grid *grid, const float *ref_cur, const float *ref_prv, const float *u_cur,
+                   const float *u_prv, const float *scale, const float *noise, float *target, hipStream_t stream)
+{
+    if (!grid || !ref_cur || !ref_prv || !u_cur || !u_prv || !scale || !target) return RTM_EINVAL;
+    const G g = make_g(grid);
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_target, dim3(nblk(n)), dim3(256), 0, stream, g, ref_cur, ref_prv, u_cur, u_prv, scale, noise,
+                       target);
+    return status();
+}
+
+int rtm_restrict(const rtm_grid *fine, const rtm_grid *coarse, const float *u_fine, float *u_coarse, int32_t mode,
+                 hipStream_t stream)
+{
+    if (!fine || !coarse || !u_fine || !u_coarse) return RTM_EINVAL;
+    if (mode != RTM_RESTRICT_INJECT && mode != RTM_RESTRICT_FULL) return RTM_EINVAL;
+    if (mode == RTM_RESTRICT_FULL && (2 * coarse->nx - 1 > fine->nx || 2 * coarse->ny - 1 > fine->ny ||
+                                      2 * coarse->nz - 1 > fine->nz))
+        return RTM_EINVAL;
+    if (2 * (coarse->nx - 1) >= fine->nx || 2 * (coarse->ny - 1) >= fine->ny || 2 * (coarse->nz - 1) >= fine->nz)
+        return RTM_EINVAL;
+    const G f = make_g(fine), c = make_g(coarse);
+    const long long n = (long long)c.nx * c.ny * c.nz;
+    hipLaunchKernelGGL(k_restrict, dim3(nblk(n)), dim3(256), 0, stream, f, c, u_fine, u_coarse,
+                       (int)(mode == RTM_RESTRICT_FULL));
+    return status();
+}
+
+int rtm_field_absmax(const rtm_grid *grid, const float *u, float *out, hipStream_t stream)
+{
+    if (!grid || !u || !out) return RTM_EINVAL;
+    const G g = make_g(grid);
+    hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, stream, out);
+    int st = status();
+    if (st != RTM_OK) return st;
+    hipLaunchKernelGGL(k_plane_absmax_into, dim3(g.nz), dim3(256), 0, stream, g, u, out);
+    return status();
+}
+
+}  // extern "C"

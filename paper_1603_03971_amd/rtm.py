@@ -42,7 +42,7 @@ class ShotImager:
     """Forward pass with kept snapshots and backward pass with imaging, for one shot."""
 
     def __init__(self, grid: Grid, kappa_bg: torch.Tensor, v_bg, src_ijk, wavelet, rec_ijk, nsteps: int,
-                 image_every: int = 4, schedule: str = "overlap", snapshots=None):
+                 image_every: int = 4, schedule: str = "overlap", snapshots=None, corrector=None):
         self.g = grid
         self.kappa = kappa_bg
         self.v_bg = v_bg
@@ -53,6 +53,9 @@ class ShotImager:
         self.s = int(image_every)
         self.schedule = schedule
         self.snapshots = snapshots            # None = FP32 pinned levels, else a snapshot codec
+        # optional on_level hook that edits the state (e.g. a learned dispersion correction), run
+        # before imaging; one hook for both passes or a (forward, backward) pair
+        self.corrector = corrector if isinstance(corrector, (tuple, list)) else (corrector, corrector)
 
     def forward(self):
         """Source wavefield; returns {k: snapshot} for k in T."""
@@ -63,6 +66,8 @@ class ShotImager:
         snaps = {}
 
         def keep(k, p):
+            if self.corrector[0] is not None:
+                self.corrector[0](k, p)
             if k % self.s == 0:
                 if self.snapshots is None:
                     snaps[k] = p.pin_current()
@@ -84,6 +89,8 @@ class ShotImager:
         image = g.field()
 
         def correlate(level, p):
+            if self.corrector[1] is not None:
+                self.corrector[1](level, p)
             k = N + 1 - level                 # forward level this receiver level pairs with
             if k in snaps:
                 if self.snapshots is None:
@@ -96,9 +103,10 @@ class ShotImager:
 
 
 def migrate_shot(grid: Grid, kappa_bg, v_bg, src_ijk, wavelet, rec_ijk, data_true, data_bg, nsteps: int,
-                 image_every: int = 4, schedule: str = "overlap", snapshots=None) -> torch.Tensor:
+                 image_every: int = 4, schedule: str = "overlap", snapshots=None, corrector=None) -> torch.Tensor:
     """Zero-lag RTM image (padded device field) of one shot from its recorded traces."""
-    imager = ShotImager(grid, kappa_bg, v_bg, src_ijk, wavelet, rec_ijk, nsteps, image_every, schedule, snapshots)
+    imager = ShotImager(grid, kappa_bg, v_bg, src_ijk, wavelet, rec_ijk, nsteps, image_every, schedule, snapshots,
+                        corrector)
     snaps = imager.forward()
     return imager.backward(snaps, data_true, data_bg)
 

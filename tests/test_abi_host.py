@@ -106,3 +106,24 @@ def test_host_helpers_match_oracle(abi):
     t = np.arange(300) * dt
     np.testing.assert_allclose(abi.rtm_ricker(300, dt, 15.0, 0.1), oracle.ricker(t, 15.0, 0.1).astype(np.float32),
                                rtol=0, atol=2e-7)
+
+
+def test_injection_mask():
+    """The corrector's weight: 0 at and near injection cells and in the sponge, 1 in the clear
+    interior, a linear ramp between."""
+    from types import SimpleNamespace
+
+    from paper_1603_03971_amd.learned import injection_mask
+
+    g = SimpleNamespace(shape=(20, 24, 32), sponge_width=2)
+    m = injection_mask(g, [(16, 12, 10)], r0=2.0, width=3.0)
+    assert m.dtype == np.float32 and m.shape == (20, 24, 32)
+    assert m[10, 12, 16] == 0.0 and m[10, 12, 18] == 0.0          # within r0
+    assert abs(m[10, 12, 19] - 1.0 / 3.0) < 1e-6                   # distance 3: one third up the ramp
+    assert m[10, 12, 24] == 1.0                                    # clear of source and sponge
+    assert (m[:, :, 0] == 0).all() and (m[:, :, 1] == 0).all()     # sponge cells
+    assert abs(m[10, 12, 2] - 1.0 / 3.0) < 1e-6                    # first cell past the sponge
+    plane = np.stack(np.meshgrid(np.arange(32), np.arange(24), indexing="xy"), -1).reshape(-1, 2)
+    rec = np.concatenate([plane, np.full((len(plane), 1), 6)], axis=1)
+    mp = injection_mask(g, rec)
+    assert (mp[6] == 0).all() and (mp[8] == 0).all() and mp[14, 12, 16] == 1.0

@@ -224,7 +224,7 @@ int rtm_image_accumulate_coded(const rtm_grid *grid, float *image, const uint16_
 /* y = conv3x3x3(x, w) + bias (bias may be NULL; relu != 0: max(y, 0)), written as compact FP32
  * (y32, [voxel][y32_channels]: only the first y32_channels of the 16 output channels, 1..16) and/or
  * as a BF16 volume with halo (y16, all 16 channels); either may be NULL but not both.  Alignment:
- * x and y32 16 bytes, w and y16 8 bytes; y16 must not alias x. */
+ * x, w and y32 16 bytes, y16 8 bytes; y16 must not alias x. */
 int rtm_cnn_conv3d(int32_t nx, int32_t ny, int32_t nz, const uint16_t *x, const uint16_t *w, const float *bias,
                    int32_t relu, float *y32, int32_t y32_channels, uint16_t *y16, hipStream_t stream);
 

@@ -11,15 +11,22 @@
 
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 
 #include "rtm.h"
 
 namespace {
 
+// Rows (waves) per forward-convolution workgroup: 4 or 8 (a build-time choice).
+#ifndef RTM_CONV_TY
+#define RTM_CONV_TY 4
+#endif
+
 constexpr int kC = 16;          // channels
 constexpr int kTaps = 27;
 
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t f2bf(float x)
@@ -40,17 +47,22 @@ struct Vol {
     }
 };
 
-// Forward convolution, as MFMAs with M = output channel, N = 16 voxels along x, K = 16 input
-// channels, one per tap: D[co][voxel] += W_t[co][ci] X[voxel + tap][ci].  MFMA lane layout
-// (16x16x16): A[m = l % 16][k = 4(l/16) + i], B[k = 4(l/16) + i][n = l % 16],
-// D[m = 4(l/16) + i][n = l % 16]; so lane l holds W_t[co = l % 16][ci = 4(l/16) ..] (in registers
-// for the whole launch), reads X[voxel = l % 16][ci = 4(l/16) ..] (8 bytes) and ends with four
-// consecutive output channels of one voxel, which makes every store of a wave one contiguous run.
+// Forward convolution, as MFMAs with M = output channel, N = 16 voxels along x and K = 32: two
+// taps of 16 input channels each, D[co][voxel] += sum over the pair's taps and ci of
+// W_t[co][ci] X[voxel + tap][ci] (v_mfma_f32_16x16x32_bf16).  The MFMA sums over k, so any mapping of
+// (tap, ci) onto a lane's k slots is exact as long as A and B use the same one: here lanes of
+// k-group q < 2 carry the pair's first tap, channels 8q..8q+7, and lanes of q >= 2 its second tap,
+// channels 8(q-2)..; lane l holds W[co = l % 16][those ci] (A, in registers for the whole launch)
+// and X[voxel = l % 16][those ci] (B, one 16-byte LDS read).  Output (16x16 D layout): lane l ends
+// with channels 4(l/16)..4(l/16)+3 of voxel l % 16, so the stores of a wave are one contiguous run.
 //
 // A workgroup of TY waves owns a tile of 64 (x) by TY (y) voxels and marches through a chunk of z
-// planes.  The input planes z-1, z, z+1 of the tile (with a one-voxel rim) sit in an LDS ring of
-// three; the next plane is fetched into registers while the current one is computed.  Wave w
-// computes row y0 + w: four 16-voxel segments, 27 MFMAs each per plane.
+// planes, input plane by input plane: the plane (with a one-voxel rim) is staged in LDS once
+// (double buffered, the next plane fetched into registers meanwhile), each of its 16-byte fragments
+// is read once and feeds the three output planes it touches (three accumulator sets, rotating),
+// and the output plane that has received all three of its input planes is stored.  Per input plane
+// and wave: 4 segments x 5 tap pairs (the 9 in-plane taps, the last pair half empty) = 20 LDS reads
+// and x 3 output planes = 60 MFMAs.
 template <int TY>
 __global__ __launch_bounds__(64 * TY) void k_conv3d(Vol v, int zc, const uint16_t *__restrict__ x,
                                                     const uint16_t *__restrict__ w, const float *__restrict__ bias,
@@ -62,11 +74,12 @@ __global__ __launch_bounds__(64 * TY) void k_conv3d(Vol v, int zc, const uint16_
     constexpr int CHUNKS = PX * PY * 2;          // its 16-byte pieces
     constexpr int NT = 64 * TY;
     constexpr int NCH = (CHUNKS + NT - 1) / NT;
-    __shared__ __align__(16) uint16_t lds[3 * PLANE];
+    static_assert(NCH <= 4, "plane pieces per thread");
+    __shared__ __align__(16) uint16_t lds[2 * PLANE];
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int m = lane & 15, q = lane >> 4;
+    const int n = lane & 15, q = lane >> 4;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
     const int z0 = blockIdx.z * zc;
     const int z1 = min(v.nz, z0 + zc);
@@ -75,16 +88,32 @@ __global__ __launch_bounds__(64 * TY) void k_conv3d(Vol v, int zc, const uint16_
     const long long sy = (long long)(v.nx + 2) * kC;
     const long long sz = sy * (v.ny + 2);
 
-    v4s wf[kTaps];
+    // in-plane tap positions p = 3 dy + dx (offsets + 1); pair j covers positions 2j and 2j + 1
+    // (pair 4: position 8 and nothing).  Lanes of q < 2 take the first, q >= 2 the second.
+    const int hi = q >> 1;                       // which tap of the pair this lane carries
+    const int ci0 = 8 * (q & 1);
+    v8bf wf[3][5];
 #pragma unroll
-    for (int t = 0; t < kTaps; ++t)
-        wf[t] = *reinterpret_cast<const v4s *>(w + ((t * kC + m) * kC + 4 * q));
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const int pos = 2 * j + hi;
+            if (pos < 9) {
+                const int t = 9 * dz + pos;
+                wf[dz][j] = *reinterpret_cast<const v8bf *>(w + ((t * kC + n) * kC + ci0));
+            } else {
+                wf[dz][j] = v8bf{};
+            }
+        }
+    // LDS offset (BF16 elements) of this lane's fragment for pair j: its position's row and column
+    int poff[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const int pos = min(2 * j + hi, 8);      // pair 4, second half: a valid place, zero weights
+        const int dy = pos / 3, dx = pos % 3;
+        poff[j] = ((wave + dy) * PX + n + dx) * kC + ci0;
+    }
 
-    // piece c of a plane: voxel (row r, column col) of the rim-extended tile, half c & 1 of its channels;
-    // rows and columns past the volume's zero halo are clamped onto it (their values are never used).
-    // Threads past the last piece repeat it (the same bytes to the same place), so that no load or
-    // store is predicated.
-    static_assert(NCH <= 4, "plane pieces per thread");
     long long g0, g1, g2, g3;
     int l0, l1, l2, l3;
     auto piece = [&](int i, long long &go, int &lo) {
@@ -107,91 +136,116 @@ __global__ __launch_bounds__(64 * TY) void k_conv3d(Vol v, int zc, const uint16_
         if constexpr (NCH > 2) p2 = *reinterpret_cast<const int4 *>(src_ + g2);                        \
         if constexpr (NCH > 3) p3 = *reinterpret_cast<const int4 *>(src_ + g3);                        \
     }
-#define CONV_STASH(slot)                                                                               \
+#define CONV_STASH(buf)                                                                                \
     {                                                                                                  \
-        uint16_t *dst_ = lds + (slot) * PLANE;                                                         \
+        uint16_t *dst_ = lds + (buf) * PLANE;                                                          \
         *reinterpret_cast<int4 *>(dst_ + l0) = p0;                                                     \
         if constexpr (NCH > 1) *reinterpret_cast<int4 *>(dst_ + l1) = p1;                              \
         if constexpr (NCH > 2) *reinterpret_cast<int4 *>(dst_ + l2) = p2;                              \
         if constexpr (NCH > 3) *reinterpret_cast<int4 *>(dst_ + l3) = p3;                              \
     }
 
-    // padded plane pz lives in ring slot pz % 3; output plane z needs padded planes z, z + 1, z + 2
-    CONV_FETCH(z0)
-    CONV_STASH(z0 % 3)
-    CONV_FETCH(z0 + 1)
-    CONV_STASH((z0 + 1) % 3)
-    CONV_FETCH(min(z0 + 2, v.nz + 1))
-    for (int z = z0; z < z1; ++z) {
-        __syncthreads();                      // everyone is done with slot (z + 2) % 3 (plane z - 1)
-        CONV_STASH((z + 2) % 3)
-        __syncthreads();
-        CONV_FETCH(min(z + 3, v.nz + 1))      // the plane after next (clamped past the end: unused)
-        // all four segments and rows are computed (rows past ny and segments past nx read clamped
-        // rim data and are not stored), so the MFMA sequence has no branches
-        v4f acc[4];
+    float bi[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) acc[s] = v4f{0.f, 0.f, 0.f, 0.f};
-        const int b0 = (z % 3) * PLANE, b1 = ((z + 1) % 3) * PLANE, b2 = ((z + 2) % 3) * PLANE;
-        const uint16_t *lane_base = lds + (wave * PX + m) * kC + 4 * q;
-        auto tap_ptr = [&](int t) {
-            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;        // offsets + 1
-            const int bz = dz == 0 ? b0 : (dz == 1 ? b1 : b2);
-            return lane_base + bz + (dy * PX + dx) * kC;
-        };
-        // software pipeline: the four B fragments of tap t + 1 are read from LDS before the four
-        // MFMAs of tap t are issued, so LDS latency overlaps matrix work
-        v4s cur[4], nxt[4];
-        {
-            const uint16_t *r0 = tap_ptr(0);
+    for (int i = 0; i < 4; ++i) bi[i] = bias ? bias[4 * q + i] : 0.0f;
+
+    // output plane z accumulates in set z % 3; input plane zi feeds outputs zi + 1 (dz = 0), zi (1)
+    // and zi - 1 (2); after it, output zi - 1 is complete
+    v4f acc[3][4];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) cur[s] = *reinterpret_cast<const v4s *>(r0 + s * 16 * kC);
-        }
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int t = 0; t < kTaps; ++t) {
-            if (t + 1 < kTaps) {
-                const uint16_t *r1 = tap_ptr(t + 1);
-#pragma unroll
-                for (int s = 0; s < 4; ++s) nxt[s] = *reinterpret_cast<const v4s *>(r1 + s * 16 * kC);
-            }
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-                acc[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[t], cur[s], acc[s], 0, 0, 0);
-#pragma unroll
-            for (int s = 0; s < 4; ++s) cur[s] = nxt[s];
-        }
-        if (y >= v.ny) continue;
-        float bi[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) bi[i] = bias ? bias[4 * q + i] : 0.0f;
+        for (int s = 0; s < 4; ++s) acc[a][s] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    auto store = [&](const v4f *o, int zo) {
+        if (y >= v.ny || zo < z0) return;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             if (s >= nseg) break;
-            const int xv = x0 + 16 * s + m;
+            const int xv = x0 + 16 * s + n;
             float r[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                r[i] = acc[s][i] + bi[i];
+                r[i] = o[s][i] + bi[i];
                 if (relu) r[i] = fmaxf(r[i], 0.0f);
             }
             if (y16) {
                 uint2 pk;
                 pk.x = (uint32_t)f2bf(r[0]) | ((uint32_t)f2bf(r[1]) << 16);
                 pk.y = (uint32_t)f2bf(r[2]) | ((uint32_t)f2bf(r[3]) << 16);
-                *reinterpret_cast<uint2 *>(y16 + v.at(xv, y, z) * kC + 4 * q) = pk;
+                *reinterpret_cast<uint2 *>(y16 + v.at(xv, y, zo) * kC + 4 * q) = pk;
             }
             if (y32) {
-                const long long o = v.flat(xv, y, z) * y32c;
+                const long long o32 = v.flat(xv, y, zo) * y32c;
                 if (y32c == kC) {
-                    *reinterpret_cast<float4 *>(y32 + o + 4 * q) = make_float4(r[0], r[1], r[2], r[3]);
+                    *reinterpret_cast<float4 *>(y32 + o32 + 4 * q) = make_float4(r[0], r[1], r[2], r[3]);
                 } else {
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
-                        if (4 * q + i < y32c) y32[o + 4 * q + i] = r[i];
+                        if (4 * q + i < y32c) y32[o32 + 4 * q + i] = r[i];
                 }
             }
         }
+    };
+
+    // one input plane (staged in buffer `buf`) into the three accumulator sets; A0, A1, A2 are the
+    // sets of outputs zi + 1, zi, zi - 1 (compile-time, so the accumulators stay in registers)
+    auto plane = [&](auto A0, auto A1, auto A2, int buf) {
+        const uint16_t *base = lds + buf * PLANE;
+        v8bf cur[4], nxt[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) cur[s] = *reinterpret_cast<const v8bf *>(base + poff[0] + s * 16 * kC);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            if (j + 1 < 5) {
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    nxt[s] = *reinterpret_cast<const v8bf *>(base + poff[j + 1] + s * 16 * kC);
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                acc[A0][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[0][j], cur[s], acc[A0][s], 0, 0, 0);
+                acc[A1][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[1][j], cur[s], acc[A1][s], 0, 0, 0);
+                acc[A2][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[2][j], cur[s], acc[A2][s], 0, 0, 0);
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) cur[s] = nxt[s];
+        }
+    };
+
+    // input planes zi = z0 - 1 .. z1 (padded index zi + 1); plane k of the march sits in buffer k & 1
+    CONV_FETCH(z0)
+    CONV_STASH(0)
+    CONV_FETCH(z0 + 1)
+    __syncthreads();
+    const int nin = z1 - z0 + 2;
+    auto step = [&](auto R, int k) {
+        // input plane zi = z0 - 1 + k; output plane z accumulates in set (z - z0 + 2) % 3, so with
+        // r = k % 3 (compile-time R): output zi + 1 in set (r + 2) % 3, zi in (r + 1) % 3, zi - 1 in r
+        constexpr int r = decltype(R)::value;
+        constexpr int setP = (r + 2) % 3;
+        constexpr int set0 = (r + 1) % 3;
+        constexpr int setM = r;
+        const int buf = k & 1;
+        plane(std::integral_constant<int, setP>{}, std::integral_constant<int, set0>{},
+              std::integral_constant<int, setM>{}, buf);
+        if (k + 1 < nin) {
+            CONV_STASH(buf ^ 1)
+            CONV_FETCH(min(z0 + k + 2, v.nz + 1))
+        }
+        store(acc[setM], z0 - 2 + k);           // output zi - 1 is complete
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc[setM][s] = v4f{0.f, 0.f, 0.f, 0.f};
+        __syncthreads();
+    };
+    int k = 0;
+    for (; k + 3 <= nin; k += 3) {
+        step(std::integral_constant<int, 0>{}, k);
+        step(std::integral_constant<int, 1>{}, k + 1);
+        step(std::integral_constant<int, 2>{}, k + 2);
     }
+    if (k < nin) step(std::integral_constant<int, 0>{}, k);
+    if (k + 1 < nin) step(std::integral_constant<int, 1>{}, k + 1);
 #undef CONV_FETCH
 #undef CONV_STASH
 }
@@ -507,12 +561,12 @@ int rtm_cnn_conv3d(int32_t nx, int32_t ny, int32_t nz, const uint16_t *x, const 
 {
     if (!vol_ok(nx, ny, nz) || !x || !w || (!y32 && !y16)) return RTM_EINVAL;
     if (y32 && (y32_channels < 1 || y32_channels > kC)) return RTM_EINVAL;
-    if ((reinterpret_cast<uintptr_t>(x) & 15u) || (reinterpret_cast<uintptr_t>(w) & 7u)) return RTM_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(x) & 15u) || (reinterpret_cast<uintptr_t>(w) & 15u)) return RTM_EINVAL;
     if ((y16 && (reinterpret_cast<uintptr_t>(y16) & 7u)) || (y32 && (reinterpret_cast<uintptr_t>(y32) & 15u)))
         return RTM_EINVAL;
     if ((const void *)y16 == (const void *)x) return RTM_EALIAS;
     const Vol v{nx, ny, nz};
-    constexpr int TY = 4;
+    constexpr int TY = RTM_CONV_TY;
     const long long tiles = (long long)((nx + 63) / 64) * ((ny + TY - 1) / TY);
     // about 2048 workgroups (several per CU) without cutting z into chunks thinner than needed
     long long chunks = (2048 + tiles - 1) / tiles;

@@ -5,6 +5,10 @@
       and, for counter calibration, a plain device copy of 1 GiB (reads and writes exactly 1 GiB).
       Run it under `rocprofv3 --pmc FETCH_SIZE` and, separately, `rocprofv3 --pmc WRITE_SIZE`.
 
+  python3 -m paper_1603_03971_amd.profile conv [--n 384] [--launches 10]
+      runs the corrector network's forward pass (three 3x3x3 convolutions, 16 channels, BF16 MFMA)
+      on an n^3 volume `launches` times, for a kernel trace of the convolution.
+
   python3 -m paper_1603_03971_amd.profile summarize --stats DIR --fetch DIR --write DIR --out FILE
       reads rocprofv3 CSV output (kernel stats of a benchmark run, counter collections of the two
       runs above) and writes a short text summary plus the traffic record that bench.py reports
@@ -48,6 +52,21 @@ def run_interior(n: int, launches: int):
     torch.cuda.synchronize()
     wx, hy, R = _abi.rtm_halo_region(g.c)
     print(json.dumps({"interior_points": (n - 2 * wx) * (n - 2 * hy) * (n - 2 * R), "copy_bytes": COPY_BYTES}))
+
+
+def run_conv(n: int, launches: int):
+    import torch
+
+    from . import learned
+
+    ws = learned.Workspace(n, n, n, train=False)
+    net = learned.CorrectorNet(seed=1, out_init=1.0)
+    ws.x.copy_(torch.randn(ws.x.numel(), dtype=torch.bfloat16, device="cuda").view(torch.int16))
+    for _ in range(launches):
+        learned.forward(net, ws)
+    torch.cuda.synchronize()
+    flop = 3 * n ** 3 * 27 * 16 * 16 * 2
+    print(json.dumps({"voxels": n ** 3, "layers": 3, "algorithmic_flop_per_forward": flop}))
 
 
 def _csv(d: str, name: str):
@@ -117,6 +136,9 @@ def main(argv=None):
     a = sub.add_parser("interior")
     a.add_argument("--n", type=int, default=512)
     a.add_argument("--launches", type=int, default=10)
+    cv = sub.add_parser("conv")
+    cv.add_argument("--n", type=int, default=384)
+    cv.add_argument("--launches", type=int, default=10)
     b = sub.add_parser("summarize")
     b.add_argument("--stats", required=True)
     b.add_argument("--fetch")
@@ -127,6 +149,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
     if args.cmd == "interior":
         run_interior(args.n, args.launches)
+    elif args.cmd == "conv":
+        run_conv(args.n, args.launches)
     else:
         summarize(args.stats, args.fetch, args.write, args.out, args.n, args.command)
 

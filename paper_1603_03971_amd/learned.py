@@ -618,7 +618,8 @@ def compare_rtm(fine: Grid, v_true, v_bg, src_f, rec_f, nsteps_f: int, fpeak: fl
     learned corrector.  The recorded data are modelled on the fine grid (d_true in v_true, d_bg in
     v_bg) and decimated in time for the coarse runs; sources and receivers sit on even fine cells,
     i.e. on coarse cells.  Returns a dict of images (host arrays on the coarse grid), relative L2
-    errors against the fine image (decimated, and full-weighted), and migration wall times.
+    errors against the fine image (decimated, and full-weighted; over the whole volume and over the
+    target zone below the acquisition plane and outside the sponge), and migration wall times.
     snapshots_fine: None (FP32 levels) or "bf16"/"f16" coded snapshots for the fine run (memory)."""
     from . import snapshots as snapcodec
     from .rtm import migrate_shot, model_shot
@@ -660,6 +661,10 @@ def compare_rtm(fine: Grid, v_true, v_bg, src_f, rec_f, nsteps_f: int, fpeak: fl
     dc_true = d_true[1::2].contiguous()
     dc_bg = d_bg[1::2].contiguous()
     out = {"t_fine": t_fine, "ref_decimated": ref_dec, "ref_full_weighted": ref_fw}
+    # target zone: below the shallowest source or receiver by 6 coarse cells, outside the sponge
+    W = coarse.sponge_width
+    zt = int(max(src_c[:, 2].max(), rec_c[:, 2].max())) + 6
+    zone = (slice(zt, coarse.nz - W), slice(W, coarse.ny - W), slice(W, coarse.nx - W))
     runs = [("plain", None)]
     if net is not None:
         cf, cb = Corrector(net, coarse, vbc, every), Corrector(net, coarse, vbc, every)
@@ -674,6 +679,9 @@ def compare_rtm(fine: Grid, v_true, v_bg, src_f, rec_f, nsteps_f: int, fpeak: fl
         out[f"img_{name}"] = im
         out[f"err_{name}_decimated"] = float(np.linalg.norm(im - ref_dec) / np.linalg.norm(ref_dec))
         out[f"err_{name}_full_weighted"] = float(np.linalg.norm(im - ref_fw) / np.linalg.norm(ref_fw))
+        out[f"err_{name}_zone_decimated"] = float(np.linalg.norm((im - ref_dec)[zone]) / np.linalg.norm(ref_dec[zone]))
+        out[f"err_{name}_zone_full_weighted"] = float(np.linalg.norm((im - ref_fw)[zone]) /
+                                                      np.linalg.norm(ref_fw[zone]))
         say(f"coarse migration ({name}) {t:.3f} s")
     return out
 

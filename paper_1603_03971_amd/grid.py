@@ -24,7 +24,10 @@ class Grid:
 
     def __init__(self, nx: int, ny: int, nz: int, h: float, dt: float, radius: int = 4,
                  sponge_width: int = 16, sponge_alpha: float = 0.015, device: str | torch.device = "cuda",
-                 x_align: int = 32, pitch_y: int | None = None):
+                 x_align: int = 32, pitch_y: int | None = None, sponge_profiles=None):
+        """sponge_profiles: optional host arrays (gx [nx], gy [ny], gz [nz]) used instead of the
+        profiles computed from sponge_width and sponge_alpha; a subdomain of a decomposed grid passes
+        its slices of the global profiles."""
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.h, self.dt, self.radius = float(h), float(dt), int(radius)
         self.device = torch.device(device)
@@ -36,9 +39,15 @@ class Grid:
         # shift so that padded element 2R of row 0 is x_align-aligned (allocations are 256 B aligned)
         self._shift = (-(2 * R)) % self.x_align
         self.sponge_width, self.sponge_alpha = int(sponge_width), float(sponge_alpha)
-        self.gx = self._sponge(self.nx)
-        self.gy = self._sponge(self.ny)
-        self.gz = self._sponge(self.nz)
+        if sponge_profiles is None:
+            self.gx = self._sponge(self.nx)
+            self.gy = self._sponge(self.ny)
+            self.gz = self._sponge(self.nz)
+        else:
+            prof = [np.ascontiguousarray(a, dtype=np.float32) for a in sponge_profiles]
+            if [len(a) for a in prof] != [self.nx, self.ny, self.nz]:
+                raise ValueError("sponge profiles must have nx, ny and nz entries")
+            self.gx, self.gy, self.gz = (torch.from_numpy(a).to(self.device) for a in prof)
         self.c = _abi.rtm_grid_init(self.nx, self.ny, self.nz, R, self.pitch_y, self.pitch_z, self.gx, self.gy,
                                     self.gz)
         off = _abi.rtm_face_layout(self.c)

@@ -38,7 +38,6 @@ def test_corrected_coarse_beats_plain_coarse(trained):
     """Held-out model (seed 6000, point source, 15 Hz): after 300 coarse steps the corrected coarse
     field is closer to the restricted fine field than the plain coarse field."""
     from paper_1603_03971_amd import learned
-    from paper_1603_03971_amd.grid import Grid
 
     net, pairs, _ = trained
     fine, coarse = pairs.fine, pairs.coarse

@@ -672,16 +672,19 @@ def compare_rtm(fine: Grid, v_true, v_bg, src_f, rec_f, nsteps_f: int, fpeak: fl
 # -------------------------------------------------------------------------------------------------
 # Command line: train a corrector, compare RTM shots
 # -------------------------------------------------------------------------------------------------
-DEFAULTS = {"every": 8, "fpeak": 15.0, "relu": False}
+DEFAULTS = {"every": 8, "fpeak": 15.0, "band": (6.0, 16.0), "relu": False}
 
 
 def train_corrector(n: int = 96, models: int = 200, first_seed: int = 5000, every: int = DEFAULTS["every"],
-                    fpeak: float = DEFAULTS["fpeak"], nsteps_coarse: int = 300, epochs: int = 10, lr: float = 1e-3,
+                    fpeak=DEFAULTS["fpeak"], nsteps_coarse: int = 300, epochs: int = 10, lr: float = 1e-3,
                     relu: bool = DEFAULTS["relu"], seed: int = 1, log=None):
     """Train a corrector on `models` seeded fine/coarse pairs (fine n^3, h = 10 m, v in [1500, 3000]
-    m/s, alternating point-source and receiver-plane problems).  Returns (net, pairs, loss history)."""
+    m/s, alternating point-source and receiver-plane problems).  fpeak: one peak frequency, or a
+    (low, high) band from which each model draws its own (seeded).  Returns (net, pairs, losses)."""
     fine = Grid(n, n, n, 10.0, Grid.stable_dt(4, 10.0, 3000.0))
     coarse = coarse_grid(fine)
+    if isinstance(fpeak, (tuple, list)):
+        fpeak = np.random.default_rng(first_seed).uniform(float(fpeak[0]), float(fpeak[1]), models)
     pairs = PairSet(fine, coarse, every, nsteps_coarse, fpeak, range(first_seed, first_seed + models),
                     kinds=("source", "receivers"))
     net = CorrectorNet(seed=seed, relu=relu)
@@ -699,7 +702,9 @@ def main(argv=None):
     t.add_argument("--n", type=int, default=96)
     t.add_argument("--models", type=int, default=200)
     t.add_argument("--every", type=int, default=DEFAULTS["every"])
-    t.add_argument("--fp", type=float, default=DEFAULTS["fpeak"])
+    t.add_argument("--fp-band", type=float, nargs=2, default=list(DEFAULTS["band"]), metavar=("LOW", "HIGH"),
+                   help="band from which each training model draws its peak frequency")
+    t.add_argument("--fp", type=float, default=None, help="one peak frequency for every model instead")
     t.add_argument("--steps", type=int, default=300, help="coarse steps per training model")
     t.add_argument("--epochs", type=int, default=10)
     t.add_argument("--relu", action="store_true")
@@ -721,7 +726,8 @@ def main(argv=None):
 
     if a.cmd == "train":
         t0 = time.perf_counter()
-        net, pairs, hist = train_corrector(a.n, a.models, every=a.every, fpeak=a.fp, nsteps_coarse=a.steps,
+        net, pairs, hist = train_corrector(a.n, a.models, every=a.every,
+                                           fpeak=a.fp if a.fp is not None else tuple(a.fp_band), nsteps_coarse=a.steps,
                                            epochs=a.epochs, relu=a.relu,
                                            log=lambda e, l: say(f"epoch {e}: loss {l:.4e}"))
         with_net, zero = window_loss(net, pairs)

@@ -672,7 +672,7 @@ def compare_rtm(fine: Grid, v_true, v_bg, src_f, rec_f, nsteps_f: int, fpeak: fl
 # -------------------------------------------------------------------------------------------------
 # Command line: train a corrector, compare RTM shots
 # -------------------------------------------------------------------------------------------------
-DEFAULTS = {"every": 8, "fpeak": 15.0, "band": (6.0, 16.0), "relu": False}
+DEFAULTS = {"every": 16, "fpeak": 15.0, "band": (6.0, 16.0), "relu": False}
 
 
 def train_corrector(n: int = 96, models: int = 200, first_seed: int = 5000, every: int = DEFAULTS["every"],

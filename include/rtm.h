@@ -215,7 +215,14 @@ int rtm_image_accumulate_coded(const rtm_grid *grid, float *image, const uint16_
                                int32_t format, const float *rcv, float weight, hipStream_t stream);
 
 /* ---- learned dispersion corrector: a 3-D CNN on BF16 MFMA (FP32 accumulation) --------------- */
-/* Activations are channel-last BF16 volumes of 16 channels with a one-voxel zero halo: channel c of
+/* Not part of the paper, whose §II propagates on one fine grid: these calls correct a coarse-grid
+ * propagation (twice the spacing, the radius-2 stencil, twice the step) towards the fine one.  They
+ * implement standard operations: 3-D convolution and its weight and data gradients (implicit GEMM),
+ * ReLU, Adam (Kingma & Ba 2014), full-weighting restriction (the multigrid restriction operator).
+ * Like the propagator calls they only enqueue work on `stream` and return RTM_OK, RTM_EINVAL (null or
+ * misaligned pointers, nx not a multiple of 16, sizes or counts out of range), RTM_EALIAS (an output
+ * aliasing the input it is computed from), RTM_ELAUNCH or RTM_EDEVICE (not a gfx950 device).
+ * Activations are channel-last BF16 volumes of 16 channels with a one-voxel zero halo: channel c of
  * voxel (i, j, k) of an nx*ny*nz volume is element (((k+1)(ny+2) + (j+1))(nx+2) + (i+1)) * 16 + c.
  * "Compact" FP32 channel-last volumes have no halo: element ((k ny + j) nx + i) * 16 + c.  nx must
  * be a multiple of 16.  Weights of a 3x3x3 layer are BF16 [27 taps][16 out][16 in], tap

@@ -9,6 +9,7 @@
 // voxels, four consecutive channels per lane) and B_t the tap's weights kept in registers.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstring>
 #include <type_traits>
@@ -405,6 +406,15 @@ struct G {
 
 G make_g(const rtm_grid *gr) { return G{gr->nx, gr->ny, gr->nz, gr->radius, gr->pitch_y, gr->pitch_z}; }
 
+// The geometry checks of the propagator calls: sizes, radius and pitches consistent.
+bool grid_ok(const rtm_grid *gr)
+{
+    if (!gr || (gr->radius != 2 && gr->radius != 4)) return false;
+    const int R = gr->radius;
+    if (gr->nx < 2 * R || gr->ny < 2 * R || gr->nz < 2 * R) return false;
+    return gr->pitch_y >= (int64_t)gr->nx + 2 * R && gr->pitch_z >= gr->pitch_y * ((int64_t)gr->ny + 2 * R);
+}
+
 // Network input: channel 0 = a = u^n / s, 1 = d = (u^n - u^{n-1}) / s, 2 = m a, 3 = m d with the
 // material m = (v - v_ref) / v_scale, others 0; s is read from the device (scale[0]); BF16,
 // channel-last with a zero halo.  The difference of the two levels, about a tenth of either, is
@@ -548,6 +558,29 @@ __global__ __launch_bounds__(256) void k_plane_absmax_into(G g, const float *__r
 }
 
 int status() { return hipGetLastError() == hipSuccess ? RTM_OK : RTM_ELAUNCH; }
+
+// The kernels are built for gfx950 only: the current device is checked once per device.
+std::atomic<int> g_cnn_dev[64];   // 0 unknown, 1 gfx950, -1 other
+
+int device_ok()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return RTM_EDEVICE;
+    int st = g_cnn_dev[dev].load(std::memory_order_relaxed);
+    if (st == 0) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return RTM_EDEVICE;
+        st = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : -1;
+        g_cnn_dev[dev].store(st, std::memory_order_relaxed);
+    }
+    return st == 1 ? RTM_OK : RTM_EDEVICE;
+}
+
+#define CNN_CHECK_DEVICE()                                                                             \
+    do {                                                                                               \
+        const int dst_ = device_ok();                                                                  \
+        if (dst_ != RTM_OK) return dst_;                                                               \
+    } while (0)
 unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 bool vol_ok(int nx, int ny, int nz) { return nx > 0 && ny > 0 && nz > 0 && nx % 16 == 0; }
@@ -573,6 +606,7 @@ int rtm_cnn_conv3d(int32_t nx, int32_t ny, int32_t nz, const uint16_t *x, const 
     if (chunks > nz) chunks = nz;
     const int zc = (int)((nz + chunks - 1) / chunks);
     const int nzc = (nz + zc - 1) / zc;
+    CNN_CHECK_DEVICE();
     hipLaunchKernelGGL(k_conv3d<TY>, dim3((nx + 63) / 64, (ny + TY - 1) / TY, nzc), dim3(64 * TY), 0, stream, v, zc,
                        x, w, bias, (int)relu, y32, (int)y32_channels, y16);
     return status();
@@ -583,6 +617,7 @@ int rtm_cnn_conv3d_wgrad(int32_t nx, int32_t ny, int32_t nz, const uint16_t *x, 
 {
     if (!vol_ok(nx, ny, nz) || !x || !dz || !dw || !db) return RTM_EINVAL;
     const Vol v{nx, ny, nz};
+    CNN_CHECK_DEVICE();
     hipLaunchKernelGGL(k_conv3d_wgrad, dim3((nx + 63) / 64, (ny + 3) / 4, nz), dim3(256), 0, stream, v, x, dz, dw, db);
     return status();
 }
@@ -594,6 +629,7 @@ int rtm_cnn_relu_backward(int32_t nx, int32_t ny, int32_t nz, const float *y, co
         return RTM_EINVAL;
     const Vol v{nx, ny, nz};
     const long long n = (long long)nx * ny * nz * kC;
+    CNN_CHECK_DEVICE();
     hipLaunchKernelGGL(k_relu_backward, dim3(nblk(n)), dim3(256), 0, stream, v, y, dy, (int)relu, (int)channels, dz32,
                        dz16);
     return status();
@@ -606,6 +642,7 @@ int rtm_cnn_loss_grad(int32_t nx, int32_t ny, int32_t nz, const float *out, cons
         return RTM_EINVAL;
     const Vol v{nx, ny, nz};
     const long long n = (long long)nx * ny * nz * kC;
+    CNN_CHECK_DEVICE();
     hipLaunchKernelGGL(k_loss_grad, dim3(nblk(n)), dim3(256), 0, stream, v, out, target, (int)channels, weight, mask,
                        dz32, dz16, loss);
     return status();
@@ -614,6 +651,7 @@ int rtm_cnn_loss_grad(int32_t nx, int32_t ny, int32_t nz, const float *out, cons
 int rtm_cnn_weight_flip(const uint16_t *w, uint16_t *wt, hipStream_t stream)
 {
     if (!w || !wt || w == wt) return RTM_EINVAL;
+    CNN_CHECK_DEVICE();
     hipLaunchKernelGGL(k_weight_flip, dim3(nblk(kTaps * kC * kC)), dim3(256), 0, stream, w, wt);
     return status();
 }
@@ -624,6 +662,7 @@ int rtm_cnn_adam(float *param, const float *grad, float *m1, float *m2, int32_t 
     if (!param || !grad || !m1 || !m2 || n < 0 || step < 1) return RTM_EINVAL;
     if (n == 0) return RTM_OK;
     const float c1 = 1.0f - (float)__builtin_pow(beta1, step), c2 = 1.0f - (float)__builtin_pow(beta2, step);
+    CNN_CHECK_DEVICE();
     hipLaunchKernelGGL(k_adam, dim3(nblk(n)), dim3(256), 0, stream, param, grad, m1, m2, (int)n, lr, beta1, beta2, eps,
                        c1, c2, param_bf16);
     return status();
@@ -633,6 +672,7 @@ int rtm_cnn_to_bf16(const float *a, uint16_t *b, int32_t n, hipStream_t stream)
 {
     if (!a || !b || n < 0) return RTM_EINVAL;
     if (n == 0) return RTM_OK;
+    CNN_CHECK_DEVICE();
     hipLaunchKernelGGL(k_to_bf16, dim3(nblk(n)), dim3(256), 0, stream, a, b, (int)n);
     return status();
 }
@@ -641,11 +681,12 @@ int rtm_cnn_pack_input(const rtm_grid *grid, const float *u_cur, const float *u_
                        float v_ref, float v_scale, const float *scale, const float *noise, uint16_t *x,
                        hipStream_t stream)
 {
-    if (!grid || !u_cur || !u_prv || !velocity || !scale || !x || !(v_scale > 0.0f)) return RTM_EINVAL;
+    if (!grid_ok(grid) || !u_cur || !u_prv || !velocity || !scale || !x || !(v_scale > 0.0f)) return RTM_EINVAL;
     if (!vol_ok(grid->nx, grid->ny, grid->nz)) return RTM_EINVAL;
     const G g = make_g(grid);
     const Vol v{grid->nx, grid->ny, grid->nz};
     const long long n = (long long)g.nx * g.ny * g.nz;
+    CNN_CHECK_DEVICE();
     hipLaunchKernelGGL(k_pack_input, dim3(nblk(n)), dim3(256), 0, stream, g, v, u_cur, u_prv, velocity, v_ref,
                        1.0f / v_scale, scale, noise, x);
     return status();
@@ -654,10 +695,12 @@ int rtm_cnn_pack_input(const rtm_grid *grid, const float *u_cur, const float *u_
 int rtm_cnn_apply_correction(const rtm_grid *grid, float *u_cur, float *u_prv, const float *out, int32_t out_channels,
                              const float *mask, const float *scale, hipStream_t stream)
 {
-    if (!grid || !u_cur || !u_prv || !out || !scale || u_cur == u_prv || out_channels < 2 || out_channels > kC)
+    if (!grid_ok(grid) || !u_cur || !u_prv || !out || !scale || u_cur == u_prv || out_channels < 2 ||
+        out_channels > kC)
         return RTM_EINVAL;
     const G g = make_g(grid);
     const long long n = (long long)g.nx * g.ny * g.nz;
+    CNN_CHECK_DEVICE();
     hipLaunchKernelGGL(k_apply_correction, dim3(nblk(n)), dim3(256), 0, stream, g, u_cur, u_prv, out,
                        (int)out_channels, mask, scale);
     return status();
@@ -666,9 +709,10 @@ int rtm_cnn_apply_correction(const rtm_grid *grid, float *u_cur, float *u_prv, c
 int rtm_cnn_target(const rtm_grid *grid, const float *ref_cur, const float *ref_prv, const float *u_cur,
                    const float *u_prv, const float *scale, const float *noise, float *target, hipStream_t stream)
 {
-    if (!grid || !ref_cur || !ref_prv || !u_cur || !u_prv || !scale || !target) return RTM_EINVAL;
+    if (!grid_ok(grid) || !ref_cur || !ref_prv || !u_cur || !u_prv || !scale || !target) return RTM_EINVAL;
     const G g = make_g(grid);
     const long long n = (long long)g.nx * g.ny * g.nz;
+    CNN_CHECK_DEVICE();
     hipLaunchKernelGGL(k_target, dim3(nblk(n)), dim3(256), 0, stream, g, ref_cur, ref_prv, u_cur, u_prv, scale, noise,
                        target);
     return status();
@@ -677,15 +721,15 @@ int rtm_cnn_target(const rtm_grid *grid, const float *ref_cur, const float *ref_
 int rtm_restrict(const rtm_grid *fine, const rtm_grid *coarse, const float *u_fine, float *u_coarse, int32_t mode,
                  hipStream_t stream)
 {
-    if (!fine || !coarse || !u_fine || !u_coarse) return RTM_EINVAL;
+    if (!grid_ok(fine) || !grid_ok(coarse) || !u_fine || !u_coarse) return RTM_EINVAL;
     if (mode != RTM_RESTRICT_INJECT && mode != RTM_RESTRICT_FULL) return RTM_EINVAL;
-    if (mode == RTM_RESTRICT_FULL && (2 * coarse->nx - 1 > fine->nx || 2 * coarse->ny - 1 > fine->ny ||
-                                      2 * coarse->nz - 1 > fine->nz))
-        return RTM_EINVAL;
+    // fine (2i, 2j, 2k) must be owned for every coarse cell (full weighting then reads at most one
+    // ghost layer, which exists since the radius is >= 2)
     if (2 * (coarse->nx - 1) >= fine->nx || 2 * (coarse->ny - 1) >= fine->ny || 2 * (coarse->nz - 1) >= fine->nz)
         return RTM_EINVAL;
     const G f = make_g(fine), c = make_g(coarse);
     const long long n = (long long)c.nx * c.ny * c.nz;
+    CNN_CHECK_DEVICE();
     hipLaunchKernelGGL(k_restrict, dim3(nblk(n)), dim3(256), 0, stream, f, c, u_fine, u_coarse,
                        (int)(mode == RTM_RESTRICT_FULL));
     return status();
@@ -693,8 +737,9 @@ int rtm_restrict(const rtm_grid *fine, const rtm_grid *coarse, const float *u_fi
 
 int rtm_field_absmax(const rtm_grid *grid, const float *u, float *out, hipStream_t stream)
 {
-    if (!grid || !u || !out) return RTM_EINVAL;
+    if (!grid_ok(grid) || !u || !out) return RTM_EINVAL;
     const G g = make_g(grid);
+    CNN_CHECK_DEVICE();
     hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, stream, out);
     int st = status();
     if (st != RTM_OK) return st;

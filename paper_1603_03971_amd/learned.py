@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import math
 import time
+from dataclasses import asdict, dataclass
 
 import numpy as np
 import torch
@@ -670,9 +671,101 @@ def compare_rtm(fine: Grid, v_true, v_bg, src_f, rec_f, nsteps_f: int, fpeak: fl
 
 
 # -------------------------------------------------------------------------------------------------
-# Command line: train a corrector, compare RTM shots
+# Trained correctors and the fallback rule
 # -------------------------------------------------------------------------------------------------
 DEFAULTS = {"every": 16, "fpeak": 15.0, "band": (6.0, 16.0), "relu": False}
+TRAIN_H, TRAIN_VMIN, TRAIN_VMAX = 10.0, 1500.0, 3000.0
+
+
+@dataclass
+class CorrectorSpec:
+    """What a trained corrector is valid for.  It learned the difference between two particular
+    discretisations (fine spacing h and step dt, and their coarse companions) over a range of media
+    and frequencies; outside them the plain fine grid is the solver to use."""
+    h: float
+    dt: float
+    vmin: float
+    vmax: float
+    fp_low: float
+    fp_high: float
+    every: int
+    relu: bool
+
+
+def save_corrector(path: str, net: CorrectorNet, spec: CorrectorSpec):
+    """Parameters and the validity record in one .npz file (plain arrays, no pickles)."""
+    np.savez(path, params=net.state(), **{k: np.asarray(v) for k, v in asdict(spec).items()})
+
+
+def load_corrector(path: str, device="cuda"):
+    """(net, spec) from save_corrector's file; a bare .npy of parameters gives spec None."""
+    if path.endswith(".npy"):
+        params, spec = np.load(path), None
+    else:
+        with np.load(path) as f:
+            params = f["params"]
+            spec = CorrectorSpec(**{k: (f[k].item()) for k in CorrectorSpec.__dataclass_fields__})
+    net = CorrectorNet(device=device, relu=bool(spec.relu) if spec is not None else DEFAULTS["relu"])
+    net.load(params)
+    return net, spec
+
+
+def applicable(spec: CorrectorSpec | None, fine, v, fpeak: float, rtol: float = 1e-6, vslack: float = 0.02):
+    """(ok, reason): may this corrector stand in for the fine grid on this problem?  The grid must
+    have the trained spacing and step, radius 4 and even sizes whose halves suit the network
+    (multiple of 16 along x); the velocities must lie in the trained range (within vslack) and the
+    peak frequency in the trained band.  Otherwise the fine grid is used."""
+    if spec is None:
+        return False, "no validity record"
+    if fine.radius != 4:
+        return False, "fine grid radius is not 4"
+    if abs(fine.h - spec.h) > rtol * spec.h or abs(fine.dt - spec.dt) > rtol * spec.dt:
+        return False, f"spacing/step {fine.h}/{fine.dt:.6g} differ from the trained {spec.h}/{spec.dt:.6g}"
+    if fine.nx % 2 or fine.ny % 2 or fine.nz % 2 or (fine.nx // 2) % 16:
+        return False, "fine sizes must be even with nx / 2 a multiple of 16"
+    vmin, vmax = float(np.min(v)), float(np.max(v))
+    if vmin < spec.vmin * (1 - vslack) or vmax > spec.vmax * (1 + vslack):
+        return False, f"velocities {vmin:.0f}..{vmax:.0f} m/s outside the trained {spec.vmin:.0f}..{spec.vmax:.0f}"
+    if not spec.fp_low <= fpeak <= spec.fp_high:
+        return False, f"peak frequency {fpeak} Hz outside the trained {spec.fp_low}..{spec.fp_high} Hz"
+    return True, "ok"
+
+
+def migrate(fine: Grid, v_bg, src_f, rec_f, wavelet_fpeak: float, data_true, data_bg, nsteps_f: int,
+            image_every_f: int = 4, corrector=None, schedule: str = "serial"):
+    """One-shot RTM of recorded data (device traces sampled on the fine step) with the fallback rule:
+    the corrected coarse grid when `corrector` = (net, spec) applies to this problem (and its image
+    comes out finite), the plain fine grid otherwise.  Returns {"image": padded field, "grid": the
+    grid it lives on, "solver": "coarse+corrector" or "fine", "reason": why}."""
+    from .rtm import migrate_shot
+
+    src_f = np.asarray(src_f, dtype=np.int64).reshape(-1, 3)
+    rec_f = np.asarray(rec_f, dtype=np.int64).reshape(-1, 3)
+    net, spec = corrector if corrector is not None else (None, None)
+    ok, reason = applicable(spec, fine, v_bg, wavelet_fpeak)
+    if ok and ((src_f % 2).any() or (rec_f % 2).any() or nsteps_f % 2 or image_every_f % 2):
+        ok, reason = False, "sources, receivers, step count and imaging interval must be even"
+    if ok:
+        coarse = coarse_grid(fine)
+        vbc = coarse_velocity(v_bg)
+        cf, cb = Corrector(net, coarse, vbc, spec.every), Corrector(net, coarse, vbc, spec.every)
+        cf.set_mask(injection_mask(coarse, src_f // 2))
+        cb.set_mask(injection_mask(coarse, rec_f // 2))
+        img = migrate_shot(coarse, coarse.kappa_from_velocity(vbc), vbc, src_f // 2,
+                           coarse.ricker(nsteps_f // 2, wavelet_fpeak), rec_f // 2, data_true[1::2].contiguous(),
+                           data_bg[1::2].contiguous() if data_bg is not None else None, nsteps_f // 2,
+                           image_every_f // 2, schedule, corrector=(cf, cb))
+        if bool(torch.isfinite(coarse.owned(img)).all()):
+            return {"image": img, "grid": coarse, "solver": "coarse+corrector", "reason": reason}
+        reason = "the corrected coarse image is not finite"
+    img = migrate_shot(fine, fine.kappa_from_velocity(v_bg), v_bg, src_f, fine.ricker(nsteps_f, wavelet_fpeak), rec_f,
+                       data_true, data_bg, nsteps_f, image_every_f, schedule)
+    return {"image": img, "grid": fine, "solver": "fine", "reason": reason}
+
+
+# -------------------------------------------------------------------------------------------------
+# Command line: train a corrector, compare RTM shots
+# -------------------------------------------------------------------------------------------------
 
 
 def train_corrector(n: int = 96, models: int = 200, first_seed: int = 5000, every: int = DEFAULTS["every"],
@@ -680,16 +773,20 @@ def train_corrector(n: int = 96, models: int = 200, first_seed: int = 5000, ever
                     relu: bool = DEFAULTS["relu"], seed: int = 1, log=None):
     """Train a corrector on `models` seeded fine/coarse pairs (fine n^3, h = 10 m, v in [1500, 3000]
     m/s, alternating point-source and receiver-plane problems).  fpeak: one peak frequency, or a
-    (low, high) band from which each model draws its own (seeded).  Returns (net, pairs, losses)."""
-    fine = Grid(n, n, n, 10.0, Grid.stable_dt(4, 10.0, 3000.0))
+    (low, high) band from which each model draws its own (seeded).  Returns (net, pairs, losses,
+    spec)."""
+    fine = Grid(n, n, n, TRAIN_H, Grid.stable_dt(4, TRAIN_H, TRAIN_VMAX))
     coarse = coarse_grid(fine)
+    band = (float(fpeak[0]), float(fpeak[1])) if isinstance(fpeak, (tuple, list)) else (float(fpeak), float(fpeak))
     if isinstance(fpeak, (tuple, list)):
-        fpeak = np.random.default_rng(first_seed).uniform(float(fpeak[0]), float(fpeak[1]), models)
+        fpeak = np.random.default_rng(first_seed).uniform(band[0], band[1], models)
     pairs = PairSet(fine, coarse, every, nsteps_coarse, fpeak, range(first_seed, first_seed + models),
                     kinds=("source", "receivers"))
     net = CorrectorNet(seed=seed, relu=relu)
     hist = train(net, pairs, epochs, lr=lr, lr_final=lr / 5, log=log)
-    return net, pairs, hist
+    spec = CorrectorSpec(h=fine.h, dt=fine.dt, vmin=TRAIN_VMIN, vmax=TRAIN_VMAX, fp_low=band[0], fp_high=band[1],
+                         every=int(every), relu=bool(relu))
+    return net, pairs, hist, spec
 
 
 def main(argv=None):
@@ -698,7 +795,7 @@ def main(argv=None):
 
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     sub = ap.add_subparsers(dest="cmd", required=True)
-    t = sub.add_parser("train", help="train a corrector and save its parameters (.npy)")
+    t = sub.add_parser("train", help="train a corrector and save it with its validity record (.npz)")
     t.add_argument("--n", type=int, default=96)
     t.add_argument("--models", type=int, default=200)
     t.add_argument("--every", type=int, default=DEFAULTS["every"])
@@ -713,7 +810,7 @@ def main(argv=None):
     c.add_argument("--weights", required=True)
     c.add_argument("--n", type=int, default=96)
     c.add_argument("--steps", type=int, default=600, help="fine steps")
-    c.add_argument("--every", type=int, default=DEFAULTS["every"])
+    c.add_argument("--every", type=int, default=DEFAULTS["every"], help="used when the weights carry no record")
     c.add_argument("--fp", type=float, default=DEFAULTS["fpeak"])
     c.add_argument("--relu", action="store_true")
     c.add_argument("--image-every", type=int, default=4, help="fine steps between imaging levels")
@@ -726,20 +823,22 @@ def main(argv=None):
 
     if a.cmd == "train":
         t0 = time.perf_counter()
-        net, pairs, hist = train_corrector(a.n, a.models, every=a.every,
-                                           fpeak=a.fp if a.fp is not None else tuple(a.fp_band), nsteps_coarse=a.steps,
-                                           epochs=a.epochs, relu=a.relu,
-                                           log=lambda e, l: say(f"epoch {e}: loss {l:.4e}"))
+        net, pairs, hist, spec = train_corrector(a.n, a.models, every=a.every,
+                                                 fpeak=a.fp if a.fp is not None else tuple(a.fp_band),
+                                                 nsteps_coarse=a.steps, epochs=a.epochs, relu=a.relu,
+                                                 log=lambda e, l: say(f"epoch {e}: loss {l:.4e}"))
         with_net, zero = window_loss(net, pairs)
-        np.save(a.out, net.state())
+        save_corrector(a.out, net, spec)
         say(json.dumps({"windows": len(pairs), "generation_s": round(pairs.gen_seconds, 2),
                         "train_s": round(time.perf_counter() - t0, 2), "window_loss": with_net,
                         "window_loss_zero_correction": zero, "out": a.out}))
         return 0
     n = a.n
-    fine = Grid(n, n, n, 10.0, Grid.stable_dt(4, 10.0, 3000.0))
-    net = CorrectorNet(relu=a.relu)
-    net.load(np.load(a.weights))
+    fine = Grid(n, n, n, TRAIN_H, Grid.stable_dt(4, TRAIN_H, TRAIN_VMAX))
+    net, spec = load_corrector(a.weights)
+    if spec is None:
+        net = CorrectorNet(relu=a.relu)
+        net.load(np.load(a.weights))
     z_ref = (fine.sponge_width + 4) // 2 * 2            # source and receivers just below the sponge
     # reflectors 20 to 60 cells below the shot, shallow enough for the recording time; gentler dips on
     # large models keep them inside that depth range across the whole plane
@@ -747,8 +846,13 @@ def main(argv=None):
                                                  max_dip_deg=15.0 if n <= 128 else 3.0)
     rec = synth.surface_receivers(n, n, k=z_ref, stride=2)
     src = [(n // 2 // 2 * 2, n // 2 // 2 * 2, z_ref)]
-    say(f"compare: fine {n}^3, {a.steps} steps, {a.fp} Hz, corrector every {a.every} coarse steps")
-    r = compare_rtm(fine, v_true, v_bg, src, rec, a.steps, a.fp, net, a.every, image_every_f=a.image_every,
+    every = a.every
+    if spec is not None:
+        every = spec.every
+        ok, why = applicable(spec, fine, v_bg, a.fp)
+        say(f"fallback rule: corrector {'applies' if ok else 'does not apply'} ({why})")
+    say(f"compare: fine {n}^3, {a.steps} steps, {a.fp} Hz, corrector every {every} coarse steps")
+    r = compare_rtm(fine, v_true, v_bg, src, rec, a.steps, a.fp, net, every, image_every_f=a.image_every,
                     repeats=a.repeats, snapshots_fine=a.snapshots, log=say)
     say(json.dumps({k: v for k, v in r.items() if not k.startswith(("img", "ref"))}))
     return 0

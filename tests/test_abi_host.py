@@ -127,3 +127,23 @@ def test_injection_mask():
     rec = np.concatenate([plane, np.full((len(plane), 1), 6)], axis=1)
     mp = injection_mask(g, rec)
     assert (mp[6] == 0).all() and (mp[8] == 0).all() and mp[14, 12, 16] == 1.0
+
+
+def test_corrector_fallback_rule():
+    """learned.applicable: the corrected coarse grid stands in for the fine one only inside the
+    corrector's validity record."""
+    from types import SimpleNamespace
+
+    from paper_1603_03971_amd.learned import CorrectorSpec, applicable
+
+    spec = CorrectorSpec(h=10.0, dt=7.5e-4, vmin=1500.0, vmax=3000.0, fp_low=6.0, fp_high=16.0, every=16,
+                         relu=False)
+    fine = SimpleNamespace(h=10.0, dt=7.5e-4, radius=4, nx=96, ny=64, nz=70)
+    v = np.full((70, 64, 96), 2000.0)
+    assert applicable(spec, fine, v, 15.0) == (True, "ok")
+    assert not applicable(None, fine, v, 15.0)[0]
+    assert not applicable(spec, fine, v, 20.0)[0]                                   # frequency
+    assert not applicable(spec, fine, np.full_like(v, 4000.0), 15.0)[0]             # velocity
+    assert not applicable(spec, SimpleNamespace(**{**vars(fine), "dt": 5e-4}), v, 15.0)[0]
+    assert not applicable(spec, SimpleNamespace(**{**vars(fine), "nx": 80}), v, 15.0)[0]   # 40 % 16
+    assert not applicable(spec, SimpleNamespace(**{**vars(fine), "radius": 2}), v, 15.0)[0]

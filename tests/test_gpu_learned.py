@@ -18,16 +18,16 @@ def trained():
     from paper_1603_03971_amd import learned
 
     _say("learned: generating 16 fine/coarse pairs (96^3 / 48^3, 15 Hz) and training")
-    net, pairs, hist = learned.train_corrector(n=96, models=16, first_seed=5000, every=8, fpeak=15.0,
-                                               nsteps_coarse=300, epochs=10)
+    net, pairs, hist, spec = learned.train_corrector(n=96, models=16, first_seed=5000, every=8, fpeak=15.0,
+                                                     nsteps_coarse=300, epochs=10)
     _say(f"  loss per epoch {hist[0]:.3e} ... {hist[-1]:.3e}")
-    return net, pairs, hist
+    return net, pairs, hist, spec
 
 
 def test_training_lowers_the_window_loss(trained):
     from paper_1603_03971_amd import learned
 
-    net, pairs, hist = trained
+    net, pairs, hist, _ = trained
     with_net, zero = learned.window_loss(net, pairs)
     _say(f"window loss {with_net:.3e} vs zero correction {zero:.3e}")
     assert hist[-1] < hist[0]
@@ -39,7 +39,7 @@ def test_corrected_coarse_beats_plain_coarse(trained):
     field is closer to the restricted fine field than the plain coarse field."""
     from paper_1603_03971_amd import learned
 
-    net, pairs, _ = trained
+    net, pairs, _, _ = trained
     fine, coarse = pairs.fine, pairs.coarse
     prob = learned.Problem(fine, coarse, 6000, 15.0, kind="source")
     ref = coarse.download(learned.fine_final_restricted(fine, coarse, prob, 300))
@@ -58,7 +58,7 @@ def test_correction_is_zero_on_zero_state_and_masked_cells(trained):
     from paper_1603_03971_amd import learned, synth
     from paper_1603_03971_amd.propagator import Propagator
 
-    net, pairs, _ = trained
+    net, pairs, _, _ = trained
     coarse = pairs.coarse
     vel = pairs.vel[0]
     kap = coarse.kappa_from_velocity(vel.view(coarse.shape))
@@ -76,3 +76,38 @@ def test_correction_is_zero_on_zero_state_and_masked_cells(trained):
     after = coarse.download(p.u_cur)
     assert np.array_equal(after[mask == 0], u0.astype(np.float32)[mask == 0])
     assert not np.array_equal(after, u0.astype(np.float32))
+
+
+def test_saved_corrector_and_fallback_rule(trained, tmp_path):
+    """The validity record travels with the parameters; migrate() uses the corrected coarse grid
+    inside it and falls back to the fine grid outside it (here: a frequency the net was not
+    trained for)."""
+    import torch
+
+    from paper_1603_03971_amd import learned, synth
+    from paper_1603_03971_amd.grid import Grid
+    from paper_1603_03971_amd.rtm import model_shot
+
+    net, _, _, spec = trained
+    path = str(tmp_path / "corrector.npz")
+    learned.save_corrector(path, net, spec)
+    net2, spec2 = learned.load_corrector(path)
+    assert spec2 == spec
+    assert torch.equal(net2.p, net.p) and torch.equal(net2.p16, net.p16)
+
+    n = 64
+    fine = Grid(n, n, n, spec.h, spec.dt)
+    v_true, v_bg = synth.dipping_reflector_model(fine.shape, spec.h, seed=5, z0_cells=(30, 45), max_dip_deg=10.0)
+    src = [(32, 32, 20)]
+    rec = synth.surface_receivers(n, n, k=20, stride=2)
+    nsteps = 240
+    for fp, expect in ((15.0, "coarse+corrector"), (9.0, "fine")):
+        wav = fine.ricker(nsteps, fp)
+        vs = [v_bg[20, 32, 32]]
+        d_t = model_shot(fine, fine.kappa_from_velocity(v_true), vs, src, wav, rec, nsteps, "serial")
+        d_b = model_shot(fine, fine.kappa_from_velocity(v_bg), vs, src, wav, rec, nsteps, "serial")
+        out = learned.migrate(fine, v_bg, src, rec, fp, d_t, d_b, nsteps, corrector=(net2, spec2))
+        _say(f"migrate at {fp} Hz: {out['solver']} ({out['reason']})")
+        assert out["solver"] == expect
+        img = out["grid"].download(out["image"])
+        assert np.isfinite(img).all() and np.abs(img).max() > 0

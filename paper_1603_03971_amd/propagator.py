@@ -68,7 +68,12 @@ class Sources:
 
 class Propagator:
     def __init__(self, grid: Grid, kappa: torch.Tensor, *, sources: Sources | list | None = None,
-                 receivers=None, boundary: str = "zero", schedule: str = "overlap"):
+                 receivers=None, boundary: str = "zero", schedule: str = "overlap", debug: bool = False):
+        """debug: NaN-poison mode.  Buffers taken fresh for a new time level (when a pinned level
+        blocks the in-place rotation) start as NaN, ghost ring included, and after every step the
+        owned cells of the new level must be finite; a kernel that read a cell nobody wrote (an unset
+        ghost, an edge or corner of the ring, a stale buffer) would carry NaN into them.  The check
+        synchronises every step, so it is for testing, not for timing."""
         self.grid = grid
         self.kappa = kappa
         if sources is None:
@@ -96,6 +101,7 @@ class Propagator:
         self.sI = torch.cuda.Stream(device=grid.device)
         self._ev_int = None
         self.interior_events = None   # list of (start, end) timing events around rtm_step_interior
+        self.debug = bool(debug)
 
     # ------------------------------------------------------------------------------------------
     def set_state(self, u_cur_host=None, u_prv_host=None, n: int = 0):
@@ -140,7 +146,18 @@ class Propagator:
     def _next_buffer(self) -> torch.Tensor:
         if self.u_prv.data_ptr() not in self.pinned:
             return self.u_prv                       # in-place over u^{n-1}
-        return self.pool.pop() if self.pool else self.grid.field(fill=None)
+        buf = self.pool.pop() if self.pool else self.grid.field(fill=None)
+        if self.debug:
+            # after everything queued so far (a recycled buffer may still be read), on the current
+            # stream, which both step streams then wait for
+            self.sync()
+            buf.fill_(float("nan"))
+        return buf
+
+    def _check_finite(self, u: torch.Tensor):
+        self.sync()
+        if not bool(torch.isfinite(self.grid.owned(u)).all()):
+            raise RuntimeError(f"NaN-poison check: level {self.n} has non-finite owned cells")
 
     # ------------------------------------------------------------------------------------------
     def step(self, traces: torch.Tensor | None = None):
@@ -200,6 +217,8 @@ class Propagator:
             self._ev_int = ev_int
         self.u_prv, self.u_cur = self.u_cur, u_nxt
         self.n = n + 1
+        if self.debug:
+            self._check_finite(u_nxt)
 
     @property
     def level_stream(self):

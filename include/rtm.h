@@ -137,6 +137,14 @@ int rtm_step_halo(const rtm_grid *grid, float *u_nxt, const float *u_cur, const 
 int rtm_step_interior(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv,
                       const float *kappa, hipStream_t stream);
 
+/* Phases 1 and 4 in one launch, for a subdomain with no exchange to overlap (a single-GPU run with
+ * physical or periodic boundaries): the update of every owned cell, reading u_cur on owned and ghost
+ * cells.  Bitwise identical to rtm_step_halo followed by rtm_step_interior (the same per-point
+ * expression); the face pack and unpack still follow it when ghosts must be refreshed.  Same
+ * arguments and status codes as rtm_step_halo. */
+int rtm_step_whole(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv,
+                   const float *kappa, hipStream_t stream);
+
 /* Phase 2 (section II): copy the R outermost owned layers of u on each face into `faces` (one
  * buffer of rtm_face_layout()[6] elements, slots as described there).  Bitwise copy.  Each slot must
  * hold fewer than 2^31 elements (RTM_EINVAL otherwise); the same limit applies to unpack. */
@@ -267,8 +275,8 @@ int rtm_cnn_to_bf16(const float *a, uint16_t *b, int32_t n, hipStream_t stream);
 
 /* Network input from a coarse-grid state: channel 0 = a = u^n / s, 1 = d = (u^n - u^{n-1}) / s (the
  * difference formed in FP32), 2 = m a, 3 = m d with m = (velocity[voxel] - v_ref) / v_scale (velocity
- * compact FP32 over the owned cells), others 0, with s = scale[0] read on the device (s = 0 gives zero
- * channels).  v_scale > 0.  noise: NULL, or compact FP32 [voxel][2] added to a and d before the
+ * compact FP32 over the owned cells), channels 4..15 zero, with s = scale[0] read on the device
+ * (s = 0 gives zero channels).  v_scale > 0.  noise: NULL, or compact FP32 [voxel][2] added to a and d before the
  * products and the rounding (training-time augmentation; the random numbers are the caller's). */
 int rtm_cnn_pack_input(const rtm_grid *grid, const float *u_cur, const float *u_prv, const float *velocity,
                        float v_ref, float v_scale, const float *scale, const float *noise, uint16_t *x,

@@ -54,6 +54,7 @@ def _load():
         "rtm_halo_region": ([gp, ctypes.POINTER(i32)], ctypes.c_int),
         "rtm_step_halo": ([gp, vp, vp, vp, vp, vp], ctypes.c_int),
         "rtm_step_interior": ([gp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "rtm_step_whole": ([gp, vp, vp, vp, vp, vp], ctypes.c_int),
         "rtm_pack_halo": ([gp, vp, vp, vp], ctypes.c_int),
         "rtm_unpack_halo": ([gp, vp, ctypes.POINTER(vp), vp], ctypes.c_int),
         "rtm_inject": ([gp, vp, vp, vp, vp, i32, vp], ctypes.c_int),
@@ -176,6 +177,11 @@ def rtm_step_halo(grid, u_nxt, u_cur, u_prv, kappa, stream=None):
 def rtm_step_interior(grid, u_nxt, u_cur, u_prv, kappa, stream=None):
     _check(_lib.rtm_step_interior(ctypes.byref(grid), _p(u_nxt), _p(u_cur), _p(u_prv), _p(kappa), _s(stream)),
            "rtm_step_interior")
+
+
+def rtm_step_whole(grid, u_nxt, u_cur, u_prv, kappa, stream=None):
+    _check(_lib.rtm_step_whole(ctypes.byref(grid), _p(u_nxt), _p(u_cur), _p(u_prv), _p(kappa), _s(stream)),
+           "rtm_step_whole")
 
 
 def rtm_pack_halo(grid, u, faces, stream=None):

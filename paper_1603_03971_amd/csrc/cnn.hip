@@ -9,6 +9,7 @@
 // voxels, four consecutive channels per lane) and B_t the tap's weights kept in registers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstdint>
 #include <cstring>
@@ -444,12 +445,11 @@ __global__ __launch_bounds__(256) void k_pack_input(G g, Vol v, const float *__r
         d += noise[2 * t + 1];
     }
     const float m = (vel[t] - v_ref) * v_inv;
-    o[0] = f2bf(a);
-    o[1] = f2bf(d);
-    o[2] = f2bf(m * a);
-    o[3] = f2bf(m * d);
-#pragma unroll
-    for (int c = 4; c < kC; ++c) o[c] = 0;
+    // the whole 32-byte voxel in two 16-byte stores (a partial store would leave lines to merge)
+    uint4 lo = make_uint4((uint32_t)f2bf(a) | ((uint32_t)f2bf(d) << 16),
+                          (uint32_t)f2bf(m * a) | ((uint32_t)f2bf(m * d) << 16), 0u, 0u);
+    reinterpret_cast<uint4 *>(o)[0] = lo;
+    reinterpret_cast<uint4 *>(o)[1] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 // Apply the correction (out: [voxel][oc], in the input's level-and-difference form): u^n += s o0 and
@@ -533,19 +533,20 @@ __global__ __launch_bounds__(256) void k_restrict(G f, G c, const float *__restr
     uc[c.idx(i, j, k)] = acc;
 }
 
-// max |u| over owned cells into out[0] (the corrector's per-application scale): one workgroup per z
-// plane, combined with an integer atomic max on the bit patterns (non-negative floats order like
-// their bits), so the result does not depend on scheduling.
+// max |u| over owned cells into out[0] (the corrector's per-application scale): workgroups stride
+// over the rows, each thread over a row's cells, and the workgroup maxima are combined with an
+// integer atomic max on the bit patterns (non-negative floats order like their bits), so the result
+// does not depend on scheduling.
 __global__ void k_zero1(float *out) { out[0] = 0.0f; }
 
-__global__ __launch_bounds__(256) void k_plane_absmax_into(G g, const float *__restrict__ u, float *out)
+__global__ __launch_bounds__(256) void k_absmax_rows(G g, const float *__restrict__ u, float *out)
 {
-    const int k = blockIdx.x;
-    const int nxy = g.nx * g.ny;
+    const long long rows = (long long)g.nz * g.ny;
     float mx = 0.0f;
-    for (int t = threadIdx.x; t < nxy; t += 256) {
-        const int j = t / g.nx, i = t - j * g.nx;
-        mx = fmaxf(mx, fabsf(u[g.idx(i, j, k)]));
+    for (long long r = blockIdx.x; r < rows; r += gridDim.x) {
+        const int k = (int)(r / g.ny), j = (int)(r - (long long)k * g.ny);
+        const float *row = u + g.idx(0, j, k);
+        for (int i = threadIdx.x; i < g.nx; i += 256) mx = fmaxf(mx, fabsf(row[i]));
     }
     __shared__ float red[256];
     red[threadIdx.x] = mx;
@@ -743,7 +744,9 @@ int rtm_field_absmax(const rtm_grid *grid, const float *u, float *out, hipStream
     hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, stream, out);
     int st = status();
     if (st != RTM_OK) return st;
-    hipLaunchKernelGGL(k_plane_absmax_into, dim3(g.nz), dim3(256), 0, stream, g, u, out);
+    const long long rows = (long long)g.nz * g.ny;
+    hipLaunchKernelGGL(k_absmax_rows, dim3((unsigned)std::min<long long>(rows, 2048)), dim3(256), 0, stream, g, u,
+                       out);
     return status();
 }
 

@@ -860,6 +860,19 @@ int launch_interior(const Geo &g, float *un, const float *uc, const float *up, c
     return launch_box_scalar<R, OP>(g, un, uc, up, kap, boxes[0], st);
 }
 
+// Every owned cell in one launch: a single box of the tiled kernel (the interior variant) over the
+// whole owned block; like the halo call it reads the ghost ring.
+template <int R, int OP = OP_FORWARD>
+int launch_all(const Geo &g, float *un, const float *uc, const float *up, const float *kap, hipStream_t st)
+{
+    const int boxes[1][6] = {{0, g.nx, 0, g.ny, 0, g.nz}};
+    if (vector_path(g, un, uc, up, kap)) {
+        const int var = g_opt.interior_variant.load(std::memory_order_relaxed);
+        return launch_tiled_variant<R, OP>(var, g, un, uc, up, kap, boxes, 1, st);
+    }
+    return launch_box_scalar<R, OP>(g, un, uc, up, kap, boxes[0], st);
+}
+
 // Every owned cell (halo region, then the rest) with one of the stencil operations.
 template <int OP>
 int launch_whole(const Geo &g, float *un, const float *uc, const float *up, const float *kap, hipStream_t st)
@@ -1024,6 +1037,16 @@ int rtm_step_interior(const rtm_grid *grid, float *u_nxt, const float *u_cur, co
     const Geo g = make_geo(grid);
     return g.R == 4 ? launch_interior<4>(g, u_nxt, u_cur, u_prv, kappa, stream)
                     : launch_interior<2>(g, u_nxt, u_cur, u_prv, kappa, stream);
+}
+
+int rtm_step_whole(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv, const float *kappa,
+                   hipStream_t stream)
+{
+    const int st = step_common(grid, u_nxt, u_cur, u_prv, kappa);
+    if (st != RTM_OK) return st;
+    const Geo g = make_geo(grid);
+    return g.R == 4 ? launch_all<4>(g, u_nxt, u_cur, u_prv, kappa, stream)
+                    : launch_all<2>(g, u_nxt, u_cur, u_prv, kappa, stream);
 }
 
 int rtm_pack_halo(const rtm_grid *grid, const float *u, float *faces, hipStream_t stream)

@@ -362,7 +362,7 @@ class Problem:
         kf = fine.kappa_from_velocity(self.v)
         w = fine.injection_weights(self._vel_at(self.v, self.src_f))
         prop = Propagator(fine, kf, sources=Sources(fine, self.src_f, w, fine.ricker(nsteps, self.fpeak)[:, None]),
-                          receivers=self.rec_f, schedule="serial")
+                          receivers=self.rec_f, schedule="fused")
         self.traces = prop.new_traces(nsteps)
         prop.run(nsteps, self.traces)
 
@@ -451,7 +451,7 @@ class PairSet:
             r.zero_()
         # restricted fine levels at coarse levels jK (cur) and jK - 1 (prv), j = 0..nwin
         kf = fine.kappa_from_velocity(prob.v)
-        pf = Propagator(fine, kf, sources=prob.fine_sources(fine, 2 * self.nsteps_c), schedule="serial")
+        pf = Propagator(fine, kf, sources=prob.fine_sources(fine, 2 * self.nsteps_c), schedule="fused")
 
         def grab(level, p):
             if level % (2 * K) == 0:
@@ -462,7 +462,7 @@ class PairSet:
         pf.run(2 * self.nsteps_c, on_level=grab)
         del kf, pf
         kc = coarse.kappa_from_velocity(prob.vc)
-        pc = Propagator(coarse, kc, sources=prob.coarse_sources(coarse, self.nsteps_c), schedule="serial")
+        pc = Propagator(coarse, kc, sources=prob.coarse_sources(coarse, self.nsteps_c), schedule="fused")
         if self._corr is None:
             a, b = coarse.field(), coarse.field()
             for j in range(self.skip, nwin):
@@ -562,7 +562,7 @@ def window_loss(net: CorrectorNet, pairs) -> tuple[float, float]:
 def fine_final_restricted(fine: Grid, coarse: Grid, prob: Problem, nsteps_coarse: int) -> torch.Tensor:
     """The fine solution after 2 * nsteps_coarse steps, restricted to the coarse grid."""
     kf = fine.kappa_from_velocity(prob.v)
-    pf = Propagator(fine, kf, sources=prob.fine_sources(fine, 2 * nsteps_coarse), schedule="serial")
+    pf = Propagator(fine, kf, sources=prob.fine_sources(fine, 2 * nsteps_coarse), schedule="fused")
     pf.run(2 * nsteps_coarse)
     out = coarse.field()
     _abi.rtm_restrict(fine.c, coarse.c, pf.u_cur, out, _cur(), mode=RESTRICT)
@@ -575,7 +575,7 @@ def coarse_final(coarse: Grid, prob: Problem, nsteps_coarse: int, corrector: Cor
     if corrector is not None:
         corrector.set_velocity(prob.vc)
         corrector.set_mask(prob.mask(coarse))
-    pc = Propagator(coarse, kc, sources=prob.coarse_sources(coarse, nsteps_coarse), schedule="serial")
+    pc = Propagator(coarse, kc, sources=prob.coarse_sources(coarse, nsteps_coarse), schedule="fused")
     pc.run(nsteps_coarse, on_level=corrector)
     return pc.u_cur
 
@@ -596,7 +596,7 @@ def _timed(fn, repeats: int = 1):
 
 
 def compare_rtm(fine: Grid, v_true, v_bg, src_f, rec_f, nsteps_f: int, fpeak: float, net: CorrectorNet | None,
-                every: int, image_every_f: int = 4, repeats: int = 2, schedule: str = "serial",
+                every: int, image_every_f: int = 4, repeats: int = 2, schedule: str = "fused",
                 snapshots_fine: str | None = None, log=None):
     """Migrate one shot on the fine grid (the reference) and on the coarse grid without and with the
     learned corrector.  The recorded data are modelled on the fine grid (d_true in v_true, d_bg in
@@ -732,7 +732,7 @@ def applicable(spec: CorrectorSpec | None, fine, v, fpeak: float, rtol: float = 
 
 
 def migrate(fine: Grid, v_bg, src_f, rec_f, wavelet_fpeak: float, data_true, data_bg, nsteps_f: int,
-            image_every_f: int = 4, corrector=None, schedule: str = "serial"):
+            image_every_f: int = 4, corrector=None, schedule: str = "fused"):
     """One-shot RTM of recorded data (device traces sampled on the fine step) with the fallback rule:
     the corrected coarse grid when `corrector` = (net, spec) applies to this problem (and its image
     comes out finite), the plain fine grid otherwise.  Returns {"image": padded field, "grid": the

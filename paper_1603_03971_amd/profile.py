@@ -9,6 +9,11 @@
       runs the corrector network's forward pass (three 3x3x3 convolutions, 16 channels, BF16 MFMA)
       on an n^3 volume `launches` times, for a kernel trace of the convolution.
 
+  python3 -m paper_1603_03971_amd.profile corrected [--n 384] [--steps 160] [--every 16]
+      runs `steps` coarse-grid steps (radius 2, the coarse companion of a 2n^3 fine grid) of a point
+      source in a smooth medium with the dispersion corrector applied every `every` steps, for a
+      kernel trace of the corrected coarse propagation (stencil calls, network, glue).
+
   python3 -m paper_1603_03971_amd.profile summarize --stats DIR --fetch DIR --write DIR --out FILE
       reads rocprofv3 CSV output (kernel stats of a benchmark run, counter collections of the two
       runs above) and writes a short text summary plus the traffic record that bench.py reports
@@ -67,6 +72,30 @@ def run_conv(n: int, launches: int):
     torch.cuda.synchronize()
     flop = 3 * n ** 3 * 27 * 16 * 16 * 2
     print(json.dumps({"voxels": n ** 3, "layers": 3, "algorithmic_flop_per_forward": flop}))
+
+
+def run_corrected(n: int, steps: int, every: int):
+    import numpy as np
+    import torch
+
+    from . import learned, synth
+    from .grid import Grid
+    from .propagator import Propagator, Sources
+
+    fine = Grid(2 * n, 2 * n, 2 * n, learned.TRAIN_H, Grid.stable_dt(4, learned.TRAIN_H, learned.TRAIN_VMAX))
+    coarse = learned.coarse_grid(fine)
+    del fine
+    v = synth.random_smooth_velocity(coarse.shape, seed=11, vmin=1500.0, vmax=3000.0, sigma=5.0).astype(np.float32)
+    kap = coarse.kappa_from_velocity(v)
+    c = n // 2
+    src = Sources(coarse, [(c, c, c)], coarse.injection_weights([v[c, c, c]]), coarse.ricker(steps, 15.0)[:, None])
+    net = learned.CorrectorNet(seed=1)
+    corr = learned.Corrector(net, coarse, v, every)
+    corr.set_mask(learned.injection_mask(coarse, [(c, c, c)]))
+    prop = Propagator(coarse, kap, sources=src, schedule="fused")
+    prop.run(steps, on_level=corr)
+    torch.cuda.synchronize()
+    print(json.dumps({"coarse_cells": coarse.points, "steps": steps, "corrections": corr.applied}))
 
 
 def _csv(d: str, name: str):
@@ -139,6 +168,10 @@ def main(argv=None):
     cv = sub.add_parser("conv")
     cv.add_argument("--n", type=int, default=384)
     cv.add_argument("--launches", type=int, default=10)
+    cr = sub.add_parser("corrected")
+    cr.add_argument("--n", type=int, default=384)
+    cr.add_argument("--steps", type=int, default=160)
+    cr.add_argument("--every", type=int, default=16)
     b = sub.add_parser("summarize")
     b.add_argument("--stats", required=True)
     b.add_argument("--fetch")
@@ -151,6 +184,8 @@ def main(argv=None):
         run_interior(args.n, args.launches)
     elif args.cmd == "conv":
         run_conv(args.n, args.launches)
+    elif args.cmd == "corrected":
+        run_corrected(args.n, args.steps, args.every)
     else:
         summarize(args.stats, args.fetch, args.write, args.out, args.n, args.command)
 

@@ -14,7 +14,10 @@ a pointer swap with no copy).  Time levels rotate by pointer: by default u^{n+1}
 u^{n-1} in place (two buffers), and a level that must outlive the rotation (an RTM snapshot) is
 "pinned" so that the next write goes to a fresh buffer instead of copying it.
 
-The "serial" schedule runs the same calls on one stream; both give bitwise identical fields.
+The "serial" schedule runs the same calls on one stream; both give bitwise identical fields.  The
+"fused" schedule, for one subdomain with nothing to overlap, updates every owned cell in one launch
+(rtm_step_whole) instead of the halo and interior calls, then injects, refreshes the ghosts and
+records on one stream; it too is bitwise identical.
 """
 from __future__ import annotations
 
@@ -86,7 +89,7 @@ class Propagator:
         if boundary not in ("zero", "periodic"):
             raise ValueError(boundary)
         self.boundary = boundary
-        if schedule not in ("overlap", "serial"):
+        if schedule not in ("overlap", "serial", "fused"):
             raise ValueError(schedule)
         self.schedule = schedule
         self.u_prv = grid.field()
@@ -167,7 +170,18 @@ class Propagator:
         u_cur, u_prv, kap = self.u_cur, self.u_prv, self.kappa
         n = self.n
         tr_ptr = None if traces is None or self.nrec == 0 else traces.data_ptr() + 4 * n * self.nrec
-        if self.schedule == "serial":
+        if self.schedule == "fused":
+            st = torch.cuda.current_stream()
+            _abi.rtm_step_whole(c, u_nxt, u_cur, u_prv, kap, st)
+            for s in self.sources:
+                s.inject(g, u_nxt, n, 0, st)
+                s.inject(g, u_nxt, n, 1, st)
+            if any(r is not None for r in self.recv):
+                _abi.rtm_pack_halo(c, u_nxt, self.send, st)
+            _abi.rtm_unpack_halo(c, u_nxt, self.recv, st)
+            if tr_ptr is not None:
+                _abi.rtm_record(c, u_nxt, self.rec_idx, tr_ptr, self.nrec, st)
+        elif self.schedule == "serial":
             st = torch.cuda.current_stream()
             _abi.rtm_step_halo(c, u_nxt, u_cur, u_prv, kap, st)
             if self.interior_events is not None:
@@ -223,7 +237,7 @@ class Propagator:
     @property
     def level_stream(self):
         """Stream on which the newest level is complete (for work that reads it)."""
-        return torch.cuda.current_stream() if self.schedule == "serial" else self.sI
+        return self.sI if self.schedule == "overlap" else torch.cuda.current_stream()
 
     def sync(self):
         """Make the caller's current stream wait for everything enqueued so far."""

@@ -57,8 +57,8 @@ def test_ragged_layered_parity(torch_cuda, schedule):
 
 
 def test_schedules_and_variants_bitwise(torch_cuda):
-    """Halo-first on two streams, single stream, every interior kernel variant and z chunking, and
-    unaligned pitches (scalar path) all give the same bits."""
+    """Halo-first on two streams, single stream, the one-launch whole step, every interior kernel
+    variant and z chunking, and unaligned pitches (scalar path) all give the same bits."""
     from paper_1603_03971_amd import _abi
 
     v, h, nsteps, src = problems.ragged_inputs(seed=9)
@@ -67,6 +67,8 @@ def test_schedules_and_variants_bitwise(torch_cuda):
     runs = {}
     try:
         runs["overlap"] = problems.gpu_forward_problem(v, h, nsteps, src, schedule="overlap")["u_cur"]
+        runs["fused"] = problems.gpu_forward_problem(v, h, nsteps, src, schedule="fused")["u_cur"]
+        runs["fused_unaligned"] = problems.gpu_forward_problem(v, h, nsteps, src, schedule="fused", x_align=1)["u_cur"]
         for var in (1, 2, 3):
             _abi.rtm_set_option(_abi.RTM_OPT_INTERIOR_VARIANT, var)
             runs[f"variant{var}"] = problems.gpu_forward_problem(v, h, nsteps, src)["u_cur"]
@@ -310,3 +312,33 @@ def test_two_subdomain_split_bitwise(torch_cuda):
     prv = np.concatenate([h_[1] for h_ in halves], axis=2)
     assert np.abs(ref_cur).max() > 0
     assert np.array_equal(cur, ref_cur) and np.array_equal(prv, ref_prv)
+
+
+@pytest.mark.parametrize("radius", [4, 2])
+def test_whole_step_equals_halo_then_interior(torch_cuda, radius):
+    """rtm_step_whole and rtm_step_halo + rtm_step_interior give the same bits on ragged boxes of
+    random fields (ghost ring included), and both leave the ghost ring untouched."""
+    torch = torch_cuda
+    from paper_1603_03971_amd import _abi
+    from paper_1603_03971_amd.grid import Grid
+
+    rng = np.random.default_rng(77 + radius)
+    for (nx, ny, nz) in ((150, 41, 70), (9, 21, 13), (130, 9, 40)):
+        g = Grid(nx, ny, nz, 10.0, 1e-3, radius=radius, sponge_width=3)
+        uc, up, kap = g.field(), g.field(), g.field()
+        for f in (uc, up):
+            g.padded(f).copy_(torch.from_numpy(rng.standard_normal(g.padded(f).shape).astype(np.float32)))
+        g.owned(kap).copy_(torch.from_numpy(rng.uniform(0.01, 0.1, g.shape).astype(np.float32)))
+        a, b = g.field(fill=float("nan")), g.field(fill=float("nan"))
+        st = torch.cuda.current_stream()
+        _abi.rtm_step_halo(g.c, a, uc, up, kap, st)
+        _abi.rtm_step_interior(g.c, a, uc, up, kap, st)
+        _abi.rtm_step_whole(g.c, b, uc, up, kap, st)
+        torch.cuda.synchronize()
+        oa, ob = g.download(a), g.download(b)
+        assert np.isfinite(ob).all() and np.array_equal(oa, ob), (radius, nx, ny, nz)
+        pb = g.padded(b).cpu().numpy()
+        R = radius
+        ring = np.ones(pb.shape, dtype=bool)
+        ring[R:-R, R:-R, R:-R] = False
+        assert np.isnan(pb[ring]).all()

@@ -164,6 +164,24 @@ def main():
         result["step_hbm_frac"] = round(step_bytes / (wall / args.steps) / 1e9 / HBM_PEAK_GBS, 4)
     if args.phases:
         result["phases_us"] = time_phases(g, prop, traces)
+    # the same steps in one launch each (rtm_step_whole, bitwise the same fields): what one GPU with
+    # nothing to overlap can do; reported beside the halo-first value, not as it
+    del prop
+    fused = Propagator(g, kap, sources=src, receivers=rec, schedule="fused")
+    fsteps = min(args.steps, 300)
+    ftr = fused.new_traces(fsteps + 10)
+    fused.run(10, ftr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fused.run(fsteps, ftr)
+    torch.cuda.synchronize()
+    fwall = time.perf_counter() - t0
+    result["fused_schedule"] = {"value": round(pts * fsteps / fwall / 1e9, 3), "unit": "Gpts/s",
+                                "ms_per_step": round(fwall / fsteps * 1e3, 4), "steps": fsteps,
+                                "what": "one launch per step over all owned cells (rtm_step_whole), then inject, "
+                                        "ghost refresh and record; bitwise the same fields as the halo-first "
+                                        "sequence, which the value measures"}
+    del fused
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(n, h, prof, args.cpu_seconds)
     print(json.dumps(result), flush=True)

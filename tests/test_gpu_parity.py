@@ -342,3 +342,39 @@ def test_whole_step_equals_halo_then_interior(torch_cuda, radius):
         ring = np.ones(pb.shape, dtype=bool)
         ring[R:-R, R:-R, R:-R] = False
         assert np.isnan(pb[ring]).all()
+
+
+@pytest.mark.parametrize("schedule", ["overlap", "serial", "fused"])
+def test_radius2_parity(torch_cuda, schedule):
+    """The radius-2 (4th-order) path that the coarse grid of the learned corrector runs: a ragged
+    layered box with a scaled sponge, sources in the shell and inside, against the FP64 oracle."""
+    v = np.array(synth_layered((38, 41, 70)))
+    src = [(35, 20, 19), (1, 2, 30), (68, 39, 2)]
+    rec = [(2, 2, 2), (69, 40, 37), (35, 20, 10)]
+    kw = dict(rec_ijk=rec, sponge_width=8, alpha=0.015 * 2 * math.sqrt(2.0), radius=2)
+    gpu = problems.gpu_forward_problem(v, 20.0, 120, src, schedule=schedule, **kw)
+    ref = problems.oracle_forward_problem(v, 20.0, 120, src, **kw)
+    e_u = problems.rel_l2(gpu["u_cur"], ref["u_cur"])
+    e_t = problems.rel_l2(gpu["traces"], ref["traces"])
+    _say(f"radius 2 {schedule}: u {e_u:.3e} traces {e_t:.3e}")
+    assert e_u <= 1e-4 and e_t <= 1e-4
+
+
+def test_smallest_boxes_parity(torch_cuda):
+    """The smallest legal boxes (2R cells per axis, R = 4 and R = 2): every cell is in the halo
+    region, the interior call has nothing to do, and the fused step covers everything."""
+    for radius, n in ((4, 8), (2, 4)):
+        v = np.full((n, n + 1, n + 2), 2000.0)
+        src = [(n // 2, n // 2, n // 2)]
+        for schedule in ("serial", "fused"):
+            gpu = problems.gpu_forward_problem(v, 10.0, 40, src, sponge_width=0, radius=radius, schedule=schedule)
+            ref = problems.oracle_forward_problem(v, 10.0, 40, src, sponge_width=0, radius=radius)
+            e = problems.rel_l2(gpu["u_cur"], ref["u_cur"])
+            _say(f"smallest box R={radius} {schedule}: {e:.3e}")
+            assert e <= 1e-4
+
+
+def synth_layered(shape):
+    from paper_1603_03971_amd import synth
+
+    return synth.layered_velocity(shape, 20.0, seed=12, vmin=1500.0, vmax=3000.0)

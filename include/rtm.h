@@ -289,6 +289,23 @@ int rtm_cnn_pack_input(const rtm_grid *grid, const float *u_cur, const float *u_
 int rtm_cnn_apply_correction(const rtm_grid *grid, float *u_cur, float *u_prv, const float *out, int32_t out_channels,
                              const float *mask, const float *scale, hipStream_t stream);
 
+/* The first layer straight from the coarse-grid state, in one launch: y16 = the BF16 output of
+ * rtm_cnn_conv3d(x, w, bias, relu) where x is what rtm_cnn_pack_input(grid, u_cur, u_prv, velocity,
+ * v_ref, v_scale, scale, NULL) would write, bitwise the same, without x being written or read
+ * (the input formed in LDS as each plane is staged).  nx, ny, nz are the grid's; y16 is a BF16
+ * volume with halo of that size (8-byte aligned), w 16-byte aligned. */
+int rtm_cnn_conv3d_first(const rtm_grid *grid, const float *u_cur, const float *u_prv, const float *velocity,
+                         float v_ref, float v_scale, const float *scale, const uint16_t *w, const float *bias,
+                         int32_t relu, uint16_t *y16, hipStream_t stream);
+
+/* The last layer applied as the correction, in one launch: the same u_cur and u_prv, bitwise, as
+ * rtm_cnn_conv3d(x, w, bias, relu) into a compact FP32 [voxel][2] output followed by
+ * rtm_cnn_apply_correction(grid, u_cur, u_prv, that output, 2, mask, scale), without the output
+ * being written.  x is a BF16 volume with halo of the grid's size (16-byte aligned, like w); it
+ * must not overlap u_cur or u_prv, which must differ. */
+int rtm_cnn_conv3d_apply(const rtm_grid *grid, const uint16_t *x, const uint16_t *w, const float *bias, int32_t relu,
+                         float *u_cur, float *u_prv, const float *mask, const float *scale, hipStream_t stream);
+
 /* Training target in the same form: channel 0 = (ref^n - u^n) / s, channel 1 =
  * ((ref^n - ref^{n-1}) - (u^n - u^{n-1})) / s, others 0 (compact FP32).  With noise (NULL, or the
  * [voxel][2] array given to rtm_cnn_pack_input) the noise is subtracted too. */

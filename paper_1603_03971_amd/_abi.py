@@ -76,6 +76,8 @@ def _load():
         "rtm_cnn_to_bf16": ([vp, vp, i32, vp], ctypes.c_int),
         "rtm_cnn_pack_input": ([gp, vp, vp, vp, f32, f32, vp, vp, vp, vp], ctypes.c_int),
         "rtm_cnn_apply_correction": ([gp, vp, vp, vp, i32, vp, vp, vp], ctypes.c_int),
+        "rtm_cnn_conv3d_first": ([gp, vp, vp, vp, f32, f32, vp, vp, vp, i32, vp, vp], ctypes.c_int),
+        "rtm_cnn_conv3d_apply": ([gp, vp, vp, vp, i32, vp, vp, vp, vp, vp], ctypes.c_int),
         "rtm_cnn_target": ([gp, vp, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "rtm_restrict": ([gp, gp, vp, vp, i32, vp], ctypes.c_int),
         "rtm_field_absmax": ([gp, vp, vp, vp], ctypes.c_int),
@@ -281,6 +283,17 @@ def rtm_cnn_pack_input(grid, u_cur, u_prv, velocity, v_ref, v_scale, scale, x, n
 def rtm_cnn_apply_correction(grid, u_cur, u_prv, out, scale, stream=None, out_channels=16, mask=None):
     _check(_lib.rtm_cnn_apply_correction(ctypes.byref(grid), _p(u_cur), _p(u_prv), _p(out), out_channels, _p(mask),
                                          _p(scale), _s(stream)), "rtm_cnn_apply_correction")
+
+
+def rtm_cnn_conv3d_first(grid, u_cur, u_prv, velocity, v_ref, v_scale, scale, w, bias, relu, y16, stream=None):
+    _check(_lib.rtm_cnn_conv3d_first(ctypes.byref(grid), _p(u_cur), _p(u_prv), _p(velocity), v_ref, v_scale,
+                                     _p(scale), _p(w), _p(bias), int(relu), _p(y16), _s(stream)),
+           "rtm_cnn_conv3d_first")
+
+
+def rtm_cnn_conv3d_apply(grid, x, w, bias, relu, u_cur, u_prv, scale, mask=None, stream=None):
+    _check(_lib.rtm_cnn_conv3d_apply(ctypes.byref(grid), _p(x), _p(w), _p(bias), int(relu), _p(u_cur), _p(u_prv),
+                                     _p(mask), _p(scale), _s(stream)), "rtm_cnn_conv3d_apply")
 
 
 def rtm_cnn_target(grid, ref_cur, ref_prv, u_cur, u_prv, scale, target, noise=None, stream=None):

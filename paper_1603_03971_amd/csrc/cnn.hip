@@ -49,6 +49,45 @@ struct Vol {
     }
 };
 
+// Padded coarse-grid geometry (the rtm_grid layout): owned cell (i, j, k) of a field.
+struct G {
+    int nx, ny, nz, R;
+    long long py, pz;
+    __device__ __forceinline__ long long idx(int i, int j, int k) const
+    {
+        return (long long)(k + R) * pz + (long long)(j + R) * py + (i + R);
+    }
+};
+
+// Network input of one voxel from the two levels and the velocity: a = u^n / s, d = (u^n - u^{n-1})
+// / s (the difference formed in FP32 before any rounding), m = (v - v_ref) / v_scale.  The pack
+// kernel and the first convolution's fused loader both form them here, so they round identically.
+__device__ __forceinline__ void input_levels(float uc, float up, float inv, float &a, float &d)
+{
+    a = uc * inv;
+    d = (uc - up) * inv;
+}
+__device__ __forceinline__ float input_material(float vel, float v_ref, float v_inv) { return (vel - v_ref) * v_inv; }
+// Channels 0..7 of the voxel as BF16 (a, d, m a, m d, then zeros).
+__device__ __forceinline__ uint4 input_voxel(float a, float d, float m)
+{
+    return make_uint4((uint32_t)f2bf(a) | ((uint32_t)f2bf(d) << 16),
+                      (uint32_t)f2bf(m * a) | ((uint32_t)f2bf(m * d) << 16), 0u, 0u);
+}
+
+// What the fused first and last layers read and write besides the activation volumes.
+struct Glue {
+    G g;                                  // the coarse grid (same nx, ny, nz as the volume)
+    const float *u_cur, *u_prv, *vel;     // first layer: the levels and the compact velocity
+    float v_ref, v_inv;
+    const float *scale;                   // s, on the device
+    float *c_cur, *c_prv;                 // last layer: the levels it corrects
+    const float *mask;                    // last layer: per-voxel weight of the correction, or null
+};
+
+constexpr int kFromVolume = 0, kFromFields = 1;   // where the input plane comes from
+constexpr int kToVolume = 0, kToFields = 1;       // where the output goes
+
 // Forward convolution, as MFMAs with M = output channel, N = 16 voxels along x and K = 32: two
 // taps of 16 input channels each, D[co][voxel] += sum over the pair's taps and ci of
 // W_t[co][ci] X[voxel + tap][ci] (v_mfma_f32_16x16x32_bf16).  The MFMA sums over k, so any mapping of
@@ -65,11 +104,17 @@ struct Vol {
 // and the output plane that has received all three of its input planes is stored.  Per input plane
 // and wave: 4 segments x 5 tap pairs (the 9 in-plane taps, the last pair half empty) = 20 LDS reads
 // and x 3 output planes = 60 MFMAs.
-template <int TY>
+//
+// IN = kFromFields: the first layer of the corrector, with the input volume never written: the
+// loader forms each staged voxel from the two levels and the velocity (input_voxel, as the pack
+// kernel does) and zero outside the grid, as the volume's halo is.  OUT = kToFields: the last
+// layer, whose channels 0 and 1 are applied to the levels in place (as the apply kernel does with
+// them) instead of being stored.
+template <int TY, int IN, int OUT>
 __global__ __launch_bounds__(64 * TY) void k_conv3d(Vol v, int zc, const uint16_t *__restrict__ x,
                                                     const uint16_t *__restrict__ w, const float *__restrict__ bias,
                                                     int relu, float *__restrict__ y32, int y32c,
-                                                    uint16_t *__restrict__ y16)
+                                                    uint16_t *__restrict__ y16, Glue gl)
 {
     constexpr int TX = 64, PX = TX + 2, PY = TY + 2;
     constexpr int PLANE = PX * PY * kC;          // BF16 elements of one staged plane
@@ -130,21 +175,75 @@ __global__ __launch_bounds__(64 * TY) void k_conv3d(Vol v, int zc, const uint16_
     piece(2, g2, l2);
     piece(3, g3, l3);
     int4 p0, p1, p2, p3;
+    // fused first layer: this thread's (at most two) voxels of the staged plane, their grid cells
+    // and the raw operands in flight
+    constexpr int NV = (PX * PY + NT - 1) / NT;
+    static_assert(NV <= 2, "staged voxels per thread");
+    int fi0 = 0, fj0 = 0, fo0 = 0, fi1 = 0, fj1 = 0, fo1 = 0;
+    bool fin0 = false, fin1 = false, fok0 = false, fok1 = false;
+    float fu0 = 0.f, fp0 = 0.f, fv0 = 0.f, fu1 = 0.f, fp1 = 0.f, fv1 = 0.f;
+    float inv = 0.0f;
+    if constexpr (IN == kFromFields) {
+        auto fvox = [&](int i, int &vi, int &vj, int &vo, bool &vin) {
+            const int vv = min((int)threadIdx.x + i * NT, PX * PY - 1);
+            const int r = vv / PX, col = vv - r * PX;
+            vi = x0 + col - 1;
+            vj = y0 + r - 1;
+            vo = vv * kC;
+            vin = vi >= 0 && vi < v.nx && vj >= 0 && vj < v.ny;
+        };
+        fvox(0, fi0, fj0, fo0, fin0);
+        fvox(1, fi1, fj1, fo1, fin1);
+        const float s_ = gl.scale[0];
+        inv = s_ > 0.0f ? 1.0f / s_ : 0.0f;
+    }
+#define FIELD_FETCH1(I, kk)                                                                            \
+    {                                                                                                  \
+        fok##I = fin##I && (kk) >= 0 && (kk) < v.nz;                                                   \
+        if (fok##I) {                                                                                  \
+            const long long gp_ = gl.g.idx(fi##I, fj##I, (kk));                                        \
+            fu##I = gl.u_cur[gp_];                                                                     \
+            fp##I = gl.u_prv[gp_];                                                                     \
+            fv##I = gl.vel[v.flat(fi##I, fj##I, (kk))];                                                \
+        }                                                                                              \
+    }
+#define FIELD_STASH1(I, dst)                                                                           \
+    {                                                                                                  \
+        uint4 d_ = make_uint4(0u, 0u, 0u, 0u);                                                         \
+        if (fok##I) {                                                                                  \
+            float a_, dd_;                                                                             \
+            input_levels(fu##I, fp##I, inv, a_, dd_);                                                  \
+            d_ = input_voxel(a_, dd_, input_material(fv##I, gl.v_ref, gl.v_inv));                     \
+        }                                                                                              \
+        *reinterpret_cast<uint4 *>((dst) + fo##I) = d_;                                                \
+        *reinterpret_cast<uint4 *>((dst) + fo##I + 8) = make_uint4(0u, 0u, 0u, 0u);                    \
+    }
 #define CONV_FETCH(pz)                                                                                 \
     {                                                                                                  \
-        const uint16_t *src_ = x + (long long)(pz) * sz;                                               \
-        p0 = *reinterpret_cast<const int4 *>(src_ + g0);                                               \
-        if constexpr (NCH > 1) p1 = *reinterpret_cast<const int4 *>(src_ + g1);                        \
-        if constexpr (NCH > 2) p2 = *reinterpret_cast<const int4 *>(src_ + g2);                        \
-        if constexpr (NCH > 3) p3 = *reinterpret_cast<const int4 *>(src_ + g3);                        \
+        if constexpr (IN == kFromVolume) {                                                             \
+            const uint16_t *src_ = x + (long long)(pz) * sz;                                           \
+            p0 = *reinterpret_cast<const int4 *>(src_ + g0);                                           \
+            if constexpr (NCH > 1) p1 = *reinterpret_cast<const int4 *>(src_ + g1);                    \
+            if constexpr (NCH > 2) p2 = *reinterpret_cast<const int4 *>(src_ + g2);                    \
+            if constexpr (NCH > 3) p3 = *reinterpret_cast<const int4 *>(src_ + g3);                    \
+        } else {                                                                                       \
+            const int kk_ = (pz) - 1;                                                                  \
+            FIELD_FETCH1(0, kk_)                                                                       \
+            if constexpr (NV > 1) FIELD_FETCH1(1, kk_)                                                 \
+        }                                                                                              \
     }
 #define CONV_STASH(buf)                                                                                \
     {                                                                                                  \
         uint16_t *dst_ = lds + (buf) * PLANE;                                                          \
-        *reinterpret_cast<int4 *>(dst_ + l0) = p0;                                                     \
-        if constexpr (NCH > 1) *reinterpret_cast<int4 *>(dst_ + l1) = p1;                              \
-        if constexpr (NCH > 2) *reinterpret_cast<int4 *>(dst_ + l2) = p2;                              \
-        if constexpr (NCH > 3) *reinterpret_cast<int4 *>(dst_ + l3) = p3;                              \
+        if constexpr (IN == kFromVolume) {                                                             \
+            *reinterpret_cast<int4 *>(dst_ + l0) = p0;                                                 \
+            if constexpr (NCH > 1) *reinterpret_cast<int4 *>(dst_ + l1) = p1;                          \
+            if constexpr (NCH > 2) *reinterpret_cast<int4 *>(dst_ + l2) = p2;                          \
+            if constexpr (NCH > 3) *reinterpret_cast<int4 *>(dst_ + l3) = p3;                          \
+        } else {                                                                                       \
+            FIELD_STASH1(0, dst_)                                                                      \
+            if constexpr (NV > 1) FIELD_STASH1(1, dst_)                                                \
+        }                                                                                              \
     }
 
     float bi[4];
@@ -159,6 +258,27 @@ __global__ __launch_bounds__(64 * TY) void k_conv3d(Vol v, int zc, const uint16_
 #pragma unroll
         for (int s = 0; s < 4; ++s) acc[a][s] = v4f{0.f, 0.f, 0.f, 0.f};
 
+    // fused last layer: lane l corrects voxel x0 + l of the output plane; its two levels and mask
+    // value are loaded when the plane's step starts (fetch_levels) and used when it ends
+    const float csc = (OUT == kToFields) ? gl.scale[0] : 0.0f;
+    const bool own = (OUT == kToFields) && y < v.ny && (lane >> 4) < nseg;
+    float lc = 0.f, lp = 0.f, lm = 0.f, a0 = 0.f, a1 = 0.f;
+    long long lg = 0;
+    auto fetch_levels = [&](int zo) {
+        if (own && zo >= z0) {
+            lg = gl.g.idx(x0 + lane, y, zo);
+            lc = gl.c_cur[lg];
+            lp = gl.c_prv[lg];
+            lm = gl.mask ? gl.mask[v.flat(x0 + lane, y, zo)] : 1.0f;
+        }
+    };
+    auto apply_levels = [&](int zo) {
+        if (own && zo >= z0) {
+            const float sv = gl.mask ? csc * lm : csc;
+            gl.c_cur[lg] = __builtin_fmaf(sv, a0, lc);
+            gl.c_prv[lg] = __builtin_fmaf(sv, a0 - a1, lp);
+        }
+    };
     auto store = [&](const v4f *o, int zo) {
         if (y >= v.ny || zo < z0) return;
 #pragma unroll
@@ -170,6 +290,16 @@ __global__ __launch_bounds__(64 * TY) void k_conv3d(Vol v, int zc, const uint16_
             for (int i = 0; i < 4; ++i) {
                 r[i] = o[s][i] + bi[i];
                 if (relu) r[i] = fmaxf(r[i], 0.0f);
+            }
+            if constexpr (OUT == kToFields) {
+                // channels 0 and 1 of segment s sit in lanes 0..15 (q = 0); lane l applies them to
+                // voxel x0 + l (segment l / 16, position l % 16), so move them there
+                const float c0 = __shfl(r[0], n), c1 = __shfl(r[1], n);
+                if ((lane >> 4) == s) {
+                    a0 = c0;
+                    a1 = c1;
+                }
+                continue;
             }
             if (y16) {
                 uint2 pk;
@@ -229,6 +359,7 @@ __global__ __launch_bounds__(64 * TY) void k_conv3d(Vol v, int zc, const uint16_
         constexpr int set0 = (r + 1) % 3;
         constexpr int setM = r;
         const int buf = k & 1;
+        if constexpr (OUT == kToFields) fetch_levels(z0 - 2 + k);
         plane(std::integral_constant<int, setP>{}, std::integral_constant<int, set0>{},
               std::integral_constant<int, setM>{}, buf);
         if (k + 1 < nin) {
@@ -236,6 +367,7 @@ __global__ __launch_bounds__(64 * TY) void k_conv3d(Vol v, int zc, const uint16_
             CONV_FETCH(min(z0 + k + 2, v.nz + 1))
         }
         store(acc[setM], z0 - 2 + k);           // output zi - 1 is complete
+        if constexpr (OUT == kToFields) apply_levels(z0 - 2 + k);
 #pragma unroll
         for (int s = 0; s < 4; ++s) acc[setM][s] = v4f{0.f, 0.f, 0.f, 0.f};
         __syncthreads();
@@ -250,6 +382,8 @@ __global__ __launch_bounds__(64 * TY) void k_conv3d(Vol v, int zc, const uint16_
     if (k + 1 < nin) step(std::integral_constant<int, 1>{}, k + 1);
 #undef CONV_FETCH
 #undef CONV_STASH
+#undef FIELD_FETCH1
+#undef FIELD_STASH1
 }
 
 // Weight gradient.  dw[t][co][ci] += sum over voxels of dz[voxel][co] x[voxel + tap][ci], as MFMAs
@@ -396,14 +530,6 @@ __global__ void k_to_bf16(const float *__restrict__ a, uint16_t *__restrict__ b,
 // ---------------------------------------------------------------------------------------------
 // Glue between the coarse-grid wavefield (padded rtm_grid layout) and the network
 // ---------------------------------------------------------------------------------------------
-struct G {
-    int nx, ny, nz, R;
-    long long py, pz;
-    __device__ __forceinline__ long long idx(int i, int j, int k) const
-    {
-        return (long long)(k + R) * pz + (long long)(j + R) * py + (i + R);
-    }
-};
 
 G make_g(const rtm_grid *gr) { return G{gr->nx, gr->ny, gr->nz, gr->radius, gr->pitch_y, gr->pitch_z}; }
 
@@ -438,17 +564,15 @@ __global__ __launch_bounds__(256) void k_pack_input(G g, Vol v, const float *__r
     const float inv = s > 0.0f ? 1.0f / s : 0.0f;
     const long long p = g.idx(i, j, k);
     uint16_t *o = x + v.at(i, j, k) * kC;
-    const float uc = u_cur[p];
-    float a = uc * inv, d = (uc - u_prv[p]) * inv;
+    float a, d;
+    input_levels(u_cur[p], u_prv[p], inv, a, d);
     if (noise) {
         a += noise[2 * t];
         d += noise[2 * t + 1];
     }
-    const float m = (vel[t] - v_ref) * v_inv;
+    const float m = input_material(vel[t], v_ref, v_inv);
     // the whole 32-byte voxel in two 16-byte stores (a partial store would leave lines to merge)
-    uint4 lo = make_uint4((uint32_t)f2bf(a) | ((uint32_t)f2bf(d) << 16),
-                          (uint32_t)f2bf(m * a) | ((uint32_t)f2bf(m * d) << 16), 0u, 0u);
-    reinterpret_cast<uint4 *>(o)[0] = lo;
+    reinterpret_cast<uint4 *>(o)[0] = input_voxel(a, d, m);
     reinterpret_cast<uint4 *>(o)[1] = make_uint4(0u, 0u, 0u, 0u);
 }
 
@@ -586,6 +710,23 @@ unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 bool vol_ok(int nx, int ny, int nz) { return nx > 0 && ny > 0 && nz > 0 && nx % 16 == 0; }
 
+// Forward convolution launch: tiles of 64 x TY voxels, z cut into chunks so that there are about
+// 2048 workgroups (several per CU) without chunks thinner than needed.
+template <int IN, int OUT>
+int launch_conv(const Vol &v, const uint16_t *x, const uint16_t *w, const float *bias, int relu, float *y32, int y32c,
+                uint16_t *y16, const Glue &gl, hipStream_t stream)
+{
+    constexpr int TY = RTM_CONV_TY;
+    const long long tiles = (long long)((v.nx + 63) / 64) * ((v.ny + TY - 1) / TY);
+    long long chunks = (2048 + tiles - 1) / tiles;
+    if (chunks > v.nz) chunks = v.nz;
+    const int zc = (int)((v.nz + chunks - 1) / chunks);
+    const int nzc = (v.nz + zc - 1) / zc;
+    hipLaunchKernelGGL((k_conv3d<TY, IN, OUT>), dim3((v.nx + 63) / 64, (v.ny + TY - 1) / TY, nzc), dim3(64 * TY), 0,
+                       stream, v, zc, x, w, bias, relu ? 1 : 0, y32, y32c, y16, gl);
+    return status();
+}
+
 }  // namespace
 
 extern "C" {
@@ -599,18 +740,49 @@ int rtm_cnn_conv3d(int32_t nx, int32_t ny, int32_t nz, const uint16_t *x, const 
     if ((y16 && (reinterpret_cast<uintptr_t>(y16) & 7u)) || (y32 && (reinterpret_cast<uintptr_t>(y32) & 15u)))
         return RTM_EINVAL;
     if ((const void *)y16 == (const void *)x) return RTM_EALIAS;
-    const Vol v{nx, ny, nz};
-    constexpr int TY = RTM_CONV_TY;
-    const long long tiles = (long long)((nx + 63) / 64) * ((ny + TY - 1) / TY);
-    // about 2048 workgroups (several per CU) without cutting z into chunks thinner than needed
-    long long chunks = (2048 + tiles - 1) / tiles;
-    if (chunks > nz) chunks = nz;
-    const int zc = (int)((nz + chunks - 1) / chunks);
-    const int nzc = (nz + zc - 1) / zc;
     CNN_CHECK_DEVICE();
-    hipLaunchKernelGGL(k_conv3d<TY>, dim3((nx + 63) / 64, (ny + TY - 1) / TY, nzc), dim3(64 * TY), 0, stream, v, zc,
-                       x, w, bias, (int)relu, y32, (int)y32_channels, y16);
-    return status();
+    Glue gl;
+    std::memset(&gl, 0, sizeof(gl));
+    return launch_conv<kFromVolume, kToVolume>(Vol{nx, ny, nz}, x, w, bias, relu, y32, y32_channels, y16, gl, stream);
+}
+
+int rtm_cnn_conv3d_first(const rtm_grid *grid, const float *u_cur, const float *u_prv, const float *velocity,
+                         float v_ref, float v_scale, const float *scale, const uint16_t *w, const float *bias,
+                         int32_t relu, uint16_t *y16, hipStream_t stream)
+{
+    if (!grid_ok(grid) || !vol_ok(grid->nx, grid->ny, grid->nz)) return RTM_EINVAL;
+    if (!u_cur || !u_prv || !velocity || !scale || !w || !y16 || !(v_scale > 0.0f)) return RTM_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(w) & 15u) || (reinterpret_cast<uintptr_t>(y16) & 7u)) return RTM_EINVAL;
+    CNN_CHECK_DEVICE();
+    Glue gl;
+    std::memset(&gl, 0, sizeof(gl));
+    gl.g = make_g(grid);
+    gl.u_cur = u_cur;
+    gl.u_prv = u_prv;
+    gl.vel = velocity;
+    gl.v_ref = v_ref;
+    gl.v_inv = 1.0f / v_scale;
+    gl.scale = scale;
+    return launch_conv<kFromFields, kToVolume>(Vol{grid->nx, grid->ny, grid->nz}, nullptr, w, bias, relu, nullptr, 0,
+                                               y16, gl, stream);
+}
+
+int rtm_cnn_conv3d_apply(const rtm_grid *grid, const uint16_t *x, const uint16_t *w, const float *bias, int32_t relu,
+                         float *u_cur, float *u_prv, const float *mask, const float *scale, hipStream_t stream)
+{
+    if (!grid_ok(grid) || !vol_ok(grid->nx, grid->ny, grid->nz)) return RTM_EINVAL;
+    if (!x || !w || !u_cur || !u_prv || !scale || u_cur == u_prv) return RTM_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(x) & 15u) || (reinterpret_cast<uintptr_t>(w) & 15u)) return RTM_EINVAL;
+    CNN_CHECK_DEVICE();
+    Glue gl;
+    std::memset(&gl, 0, sizeof(gl));
+    gl.g = make_g(grid);
+    gl.scale = scale;
+    gl.c_cur = u_cur;
+    gl.c_prv = u_prv;
+    gl.mask = mask;
+    return launch_conv<kFromVolume, kToFields>(Vol{grid->nx, grid->ny, grid->nz}, x, w, bias, relu, nullptr, 0,
+                                               nullptr, gl, stream);
 }
 
 int rtm_cnn_conv3d_wgrad(int32_t nx, int32_t ny, int32_t nz, const uint16_t *x, const float *dz, float *dw, float *db,

@@ -164,21 +164,25 @@ class CorrectorNet:
 
 class Workspace:
     """Activation buffers for one nx * ny * nz volume.  BF16 volumes carry a one-voxel zero halo
-    (written once, here); compact FP32 volumes hold the values the backward pass needs."""
+    (written once, here); compact FP32 volumes hold the values the backward pass needs.  A fused
+    workspace (inference through the fused first and last layers) has no input or output volume."""
 
-    def __init__(self, nx: int, ny: int, nz: int, train: bool = False, device="cuda"):
+    def __init__(self, nx: int, ny: int, nz: int, train: bool = False, device="cuda", fused: bool = False):
         if nx % 16:
             raise ValueError("the network volume needs nx % 16 == 0")
+        if fused and train:
+            raise ValueError("a training workspace keeps the input and output volumes")
         self.dims = (int(nx), int(ny), int(nz))
         dev = torch.device(device)
         npad = (nx + 2) * (ny + 2) * (nz + 2) * C
         n = nx * ny * nz * C
-        self.x = torch.zeros(npad, dtype=torch.int16, device=dev)
+        self.x = None if fused else torch.zeros(npad, dtype=torch.int16, device=dev)
         self.h1 = torch.zeros(npad, dtype=torch.int16, device=dev)
         self.h2 = torch.zeros(npad, dtype=torch.int16, device=dev)
         # FP32 output: all 16 channels for training (the loss kernels read that layout), only the two
         # correction channels for inference
-        self.out = torch.zeros(n if train else nx * ny * nz * OUT_CHANNELS, dtype=torch.float32, device=dev)
+        self.out = None if fused else \
+            torch.zeros(n if train else nx * ny * nz * OUT_CHANNELS, dtype=torch.float32, device=dev)
         self.out_channels = C if train else OUT_CHANNELS
         self.train = train
         if train:
@@ -237,7 +241,7 @@ class Corrector:
         if every < 1:
             raise ValueError("every >= 1")
         self.net, self.g, self.every = net, grid, int(every)
-        self.ws = Workspace(grid.nx, grid.ny, grid.nz, train=False, device=grid.device)
+        self.ws = Workspace(grid.nx, grid.ny, grid.nz, device=grid.device, fused=True)
         self.scale = torch.zeros(1, dtype=torch.float32, device=grid.device)
         self.applied = 0
         self.mask = None
@@ -273,10 +277,14 @@ class Corrector:
             fresh.copy_(prop.u_prv)
             prop.u_prv = fresh
         _abi.rtm_field_absmax(g.c, prop.u_cur, self.scale, st)
-        _abi.rtm_cnn_pack_input(g.c, prop.u_cur, prop.u_prv, self.vel, V_REF, V_SCALE, self.scale, self.ws.x, stream=st)
-        forward(self.net, self.ws, st)
-        _abi.rtm_cnn_apply_correction(g.c, prop.u_cur, prop.u_prv, self.ws.out, self.scale, st,
-                                      out_channels=self.ws.out_channels, mask=self.mask)
+        # the network of `forward`, with the input packing fused into the first layer and the
+        # correction applied by the last (bitwise the same as pack, forward, apply)
+        net, ws, r = self.net, self.ws, int(self.net.relu)
+        _abi.rtm_cnn_conv3d_first(g.c, prop.u_cur, prop.u_prv, self.vel, V_REF, V_SCALE, self.scale, net.w16(0),
+                                  net.bias(0), r, ws.h1, st)
+        _abi.rtm_cnn_conv3d(g.nx, g.ny, g.nz, ws.h1, net.w16(1), net.bias(1), r, None, ws.h2, st)
+        _abi.rtm_cnn_conv3d_apply(g.c, ws.h2, net.w16(2), net.bias(2), 0, prop.u_cur, prop.u_prv, self.scale,
+                                  mask=self.mask, stream=st)
         prop.exchange_ghosts(prop.u_cur, st)
         if prop.schedule == "overlap":
             prop.level_stream.wait_stream(st)

@@ -77,9 +77,26 @@ def cpu_baseline(n: int, h: float, v_prof, target_s: float):
         el = time.perf_counter() - t0
         if el >= target_s or steps >= 200:
             break
+    # one more step on a single thread (the multi-threaded step is bitwise the same)
+    t1 = time.perf_counter()
+    oracle.step(u, up, kap, (sp, sp, sp), 4, False, 1, out=out)
+    el1 = time.perf_counter() - t1
     return {"value": n ** 3 * steps / el / 1e9, "unit": "Gpts/s", "cores": threads, "kind": "oracle",
             "sample": f"{steps} FP64 oracle steps of the {n}^3 layered workload (random wavefield), "
-                      f"{threads} OpenMP threads, {el:.1f} s"}
+                      f"{threads} OpenMP threads, {el:.1f} s",
+            "single_thread": {"value": n ** 3 / el1 / 1e9, "unit": "Gpts/s", "sample": f"1 step, {el1:.1f} s"},
+            "host": {"nproc": os.cpu_count(), "cpu": cpu_model()}}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():

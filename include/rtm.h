@@ -98,8 +98,9 @@ const char *rtm_strerror(int status);
  *   RTM_OPT_INTERIOR_VARIANT  workgroup shape of the interior call's tiled kernel: 0 = 16x16 threads
  *                             (64x16 cells), 1 = 32x8 (128x8 cells, default), 2 = 16x8 (64x8 cells),
  *                             3 = scalar per-cell kernels for both calls.
- *   RTM_OPT_ZCHUNK            z planes per workgroup of the tiled kernels; 0 = automatic (one wave of
- *                             resident workgroups over the whole chip).
+ *   RTM_OPT_ZCHUNK            z planes per workgroup of the tiled kernels; 0 = automatic: at radius 4
+ *                             at most one wave of resident workgroups over the whole chip, at radius 2
+ *                             chunks of 16 planes.
  *   RTM_OPT_XCD_REMAP         1 = give each XCD a contiguous range of tiles (default), 0 = hardware order.
  *   RTM_OPT_HALO_X_WIDTH      width of the halo region's x strips (default 64 = one tile);
  *   RTM_OPT_HALO_Y_WIDTH      height of its y strips (default 16); see rtm_halo_region.

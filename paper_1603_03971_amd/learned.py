@@ -198,6 +198,8 @@ class Workspace:
 
 def forward(net: CorrectorNet, ws: Workspace, stream=None):
     """ws.out = net(ws.x): three convolutions, ReLU after the first two."""
+    if ws.x is None:
+        raise ValueError("a fused workspace has no input volume: the Corrector runs the fused layers")
     st = stream if stream is not None else _cur()
     nx, ny, nz = ws.dims
     keep = ws.train

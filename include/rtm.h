@@ -126,9 +126,9 @@ int rtm_halo_region(const rtm_grid *grid, int32_t widths[3]);
 /* ---- the per-time-step phases (device work, enqueued on `stream`) -------------------------- */
 
 /* Phase 1 (section II): the update of u_nxt on the halo region (rtm_halo_region): every owned cell
- * within R of a face, which is what the neighbours need, widened in x and y to whole tiles.  Reads u_cur on owned and ghost cells (ghosts from the previous
- * unpack), u_prv and kappa at the cell.  u_nxt may equal u_prv (two-buffer in-place update);
- * u_nxt == u_cur is RTM_EALIAS. */
+ * within R of a face, which is what the neighbours need, widened in x and y to whole tiles.  Reads
+ * u_cur on owned and ghost cells (ghosts from the previous unpack), u_prv and kappa at the cell.
+ * u_nxt may equal u_prv (two-buffer in-place update); u_nxt == u_cur is RTM_EALIAS. */
 int rtm_step_halo(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv,
                   const float *kappa, hipStream_t stream);
 

@@ -96,8 +96,9 @@ const char *rtm_strerror(int status);
  * per-point expression), but the halo and interior calls of one step must see the same options, so
  * change them only between steps.
  *   RTM_OPT_INTERIOR_VARIANT  workgroup shape of the interior call's tiled kernel: 0 = 16x16 threads
- *                             (64x16 cells), 1 = 32x8 (128x8 cells, default), 2 = 16x8 (64x8 cells),
- *                             3 = scalar per-cell kernels for both calls.
+ *                             (64x16 cells), 1 = 32x8 (128x8 cells), 2 = 16x8 (64x8 cells),
+ *                             3 = scalar per-cell kernels for both calls, 4 = 32x16 (128x16 cells,
+ *                             two workgroups per CU; default).
  *   RTM_OPT_ZCHUNK            z planes per workgroup of the tiled kernels; 0 = automatic: at radius 4
  *                             at most one wave of resident workgroups over the whole chip, at radius 2
  *                             chunks of 16 planes.
@@ -113,6 +114,8 @@ enum {
     RTM_OPT_HALO_Y_WIDTH = 5,
 };
 int rtm_set_option(int32_t option, int32_t value);
+/* The current value of an option (>= 0), or RTM_EINVAL for an unknown option. */
+int rtm_get_option(int32_t option);
 
 /* The halo region of a grid under the current options: widths = {wx, hy, R} with
  * wx = max(R, min(RTM_OPT_HALO_X_WIDTH, nx / 2)) and hy = max(R, min(RTM_OPT_HALO_Y_WIDTH, ny / 2)).

@@ -51,6 +51,7 @@ def _load():
         "rtm_face_layout": ([gp, ctypes.POINTER(i64)], ctypes.c_int),
         "rtm_index": ([gp, i32, i32, i32], i64),
         "rtm_set_option": ([i32, i32], ctypes.c_int),
+        "rtm_get_option": ([i32], ctypes.c_int),
         "rtm_halo_region": ([gp, ctypes.POINTER(i32)], ctypes.c_int),
         "rtm_step_halo": ([gp, vp, vp, vp, vp, vp], ctypes.c_int),
         "rtm_step_interior": ([gp, vp, vp, vp, vp, vp], ctypes.c_int),
@@ -162,6 +163,13 @@ def rtm_index(grid: rtm_grid, i: int, j: int, k: int) -> int:
 
 def rtm_set_option(option: int, value: int):
     _check(_lib.rtm_set_option(option, value), "rtm_set_option")
+
+
+def rtm_get_option(option: int) -> int:
+    v = _lib.rtm_get_option(option)
+    if v < 0:
+        raise RTMError(v, "rtm_get_option")
+    return v
 
 
 def rtm_halo_region(grid):

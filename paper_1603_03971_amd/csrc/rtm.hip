@@ -171,8 +171,8 @@ struct BoxList {
 };
 
 template <int R, int BX, int BY, int OP>
-__global__ __launch_bounds__(BX *BY) void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up,
-                                                  const float *kap, BoxList bl)
+__global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(BX * BY >= 512 ? 4 : 1)))
+void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, const float *kap, BoxList bl)
 {
     constexpr int NT = BX * BY;
     constexpr int TX = 4 * BX;
@@ -647,7 +647,8 @@ constexpr int kMaxDevices = 64;
 std::atomic<int> g_dev_ok[kMaxDevices];   // 0 unknown, 1 gfx950, -1 other
 
 struct Options {
-    std::atomic<int> interior_variant{1};  // 0: 16x16 threads (64 x 16 cells), 1: 32x8, 2: 16x8, 3: scalar
+    std::atomic<int> interior_variant{4};  // 0: 16x16 threads (64 x 16 cells), 1: 32x8, 2: 16x8, 3: scalar,
+                                           // 4: 32x16 (128 x 16 cells, two workgroups per CU)
     std::atomic<int> zchunk{0};            // 0: automatic
     std::atomic<int> xcd_remap{1};
     std::atomic<int> halo_x_width{64};     // x strips of the halo region
@@ -788,6 +789,7 @@ int launch_tiled_variant(int var, const Geo &g, float *un, const float *uc, cons
     switch (var) {
     case 1: return launch_tiled<R, 32, 8, OP>(g, un, uc, up, kap, boxes, nbox, st);
     case 2: return launch_tiled<R, 16, 8, OP>(g, un, uc, up, kap, boxes, nbox, st);
+    case 4: return launch_tiled<R, 32, 16, OP>(g, un, uc, up, kap, boxes, nbox, st);
     default: return launch_tiled<R, 16, 16, OP>(g, un, uc, up, kap, boxes, nbox, st);
     }
 }
@@ -1290,7 +1292,7 @@ int rtm_set_option(int32_t option, int32_t value)
 {
     switch (option) {
     case RTM_OPT_INTERIOR_VARIANT:
-        if (value < 0 || value > 3) return RTM_EINVAL;
+        if (value < 0 || value > 4) return RTM_EINVAL;
         g_opt.interior_variant.store(value);
         return RTM_OK;
     case RTM_OPT_ZCHUNK:
@@ -1308,6 +1310,18 @@ int rtm_set_option(int32_t option, int32_t value)
         if (value < 1) return RTM_EINVAL;
         g_opt.halo_y_width.store(value);
         return RTM_OK;
+    default: return RTM_EINVAL;
+    }
+}
+
+int rtm_get_option(int32_t option)
+{
+    switch (option) {
+    case RTM_OPT_INTERIOR_VARIANT: return g_opt.interior_variant.load();
+    case RTM_OPT_ZCHUNK: return g_opt.zchunk.load();
+    case RTM_OPT_XCD_REMAP: return g_opt.xcd_remap.load();
+    case RTM_OPT_HALO_X_WIDTH: return g_opt.halo_x_width.load();
+    case RTM_OPT_HALO_Y_WIDTH: return g_opt.halo_y_width.load();
     default: return RTM_EINVAL;
     }
 }

@@ -98,6 +98,11 @@ def run_corrected(n: int, steps: int, every: int):
     print(json.dumps({"coarse_cells": coarse.points, "steps": steps, "corrections": corr.applied}))
 
 
+# The radius-4 interior call's kernel under the default options (the 32 x 16-thread tile); the
+# one-launch whole step runs the same kernel over a larger box.
+INTERIOR_KERNEL = "k_tiled<4, 32, 16, 0>"
+
+
 def _csv(d: str, name: str):
     files = glob.glob(os.path.join(d, "**", name), recursive=True)
     if not files:
@@ -132,12 +137,12 @@ def summarize(stats_dir, fetch_dir, write_dir, out, n, commands):
     # (the interior box is the smaller), so the dispatches are split by it.
     shapes = {}
     for r in _csv(stats_dir, "*kernel_trace.csv"):
-        if "k_tiled<4, 32, 8, 0>" in r["Kernel_Name"]:
+        if INTERIOR_KERNEL in r["Kernel_Name"]:
             shapes.setdefault(int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"]), []).append(
                 (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
     interior_avg_us = None
     if shapes:
-        lines += ["", "Launch shapes of k_tiled<4, 32, 8, 0> (kernel trace):",
+        lines += ["", f"Launch shapes of {INTERIOR_KERNEL} (kernel trace):",
                   f"    {'call':32s} {'workgroups':>10s} {'calls':>6s} {'avg us':>10s}"]
         for i, grid in enumerate(sorted(shapes)):
             d = shapes[grid]
@@ -148,8 +153,8 @@ def summarize(stats_dir, fetch_dir, write_dir, out, n, commands):
     record = {"n": n, "kernel_source_sha256_16": kernel_source_hash(), "interior_avg_us_kernel_trace": interior_avg_us}
     if fetch_dir and write_dir:
         fr, wr = _csv(fetch_dir, "*counter_collection.csv"), _csv(write_dir, "*counter_collection.csv")
-        f_int, nf = _counter(fr, "k_tiled<4, 32, 8, 0>", "FETCH_SIZE")
-        w_int, nw = _counter(wr, "k_tiled<4, 32, 8, 0>", "WRITE_SIZE")
+        f_int, nf = _counter(fr, INTERIOR_KERNEL, "FETCH_SIZE")
+        w_int, nw = _counter(wr, INTERIOR_KERNEL, "WRITE_SIZE")
         # the 1 GiB copy is the largest copy dispatch of the run
         f_cp, _ = _counter(fr, "opy", "FETCH_SIZE", largest=True)
         w_cp, _ = _counter(wr, "opy", "WRITE_SIZE", largest=True)

@@ -83,6 +83,9 @@ def test_validation_before_device(abi):
     assert L.rtm_image_accumulate(gp, 4096, 4096, 1 << 40, 1.0, None) == abi.RTM_EALIAS
     assert L.rtm_set_option(99, 0) == abi.RTM_EINVAL
     assert L.rtm_set_option(abi.RTM_OPT_INTERIOR_VARIANT, 7) == abi.RTM_EINVAL
+    assert L.rtm_get_option(99) == abi.RTM_EINVAL
+    assert L.rtm_get_option(abi.RTM_OPT_INTERIOR_VARIANT) == 4          # the 32x16 tile by default
+    assert L.rtm_get_option(abi.RTM_OPT_ZCHUNK) == 0
 
 
 def test_face_layout_and_index(abi):

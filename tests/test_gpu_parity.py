@@ -65,14 +65,16 @@ def test_schedules_and_variants_bitwise(torch_cuda):
     nsteps = 30
     base = problems.gpu_forward_problem(v, h, nsteps, src, schedule="serial")["u_cur"]
     runs = {}
+    default_variant = _abi.rtm_get_option(_abi.RTM_OPT_INTERIOR_VARIANT)
     try:
         runs["overlap"] = problems.gpu_forward_problem(v, h, nsteps, src, schedule="overlap")["u_cur"]
         runs["fused"] = problems.gpu_forward_problem(v, h, nsteps, src, schedule="fused")["u_cur"]
         runs["fused_unaligned"] = problems.gpu_forward_problem(v, h, nsteps, src, schedule="fused", x_align=1)["u_cur"]
-        for var in (1, 2, 3):
+        for var in (0, 1, 2, 3, 4):
             _abi.rtm_set_option(_abi.RTM_OPT_INTERIOR_VARIANT, var)
             runs[f"variant{var}"] = problems.gpu_forward_problem(v, h, nsteps, src)["u_cur"]
-        _abi.rtm_set_option(_abi.RTM_OPT_INTERIOR_VARIANT, 0)
+            runs[f"variant{var}_fused"] = problems.gpu_forward_problem(v, h, nsteps, src, schedule="fused")["u_cur"]
+        _abi.rtm_set_option(_abi.RTM_OPT_INTERIOR_VARIANT, default_variant)
         for zc in (1, 7, 1000):
             _abi.rtm_set_option(_abi.RTM_OPT_ZCHUNK, zc)
             runs[f"zchunk{zc}"] = problems.gpu_forward_problem(v, h, nsteps, src)["u_cur"]
@@ -83,7 +85,7 @@ def test_schedules_and_variants_bitwise(torch_cuda):
         runs["x_align4"] = problems.gpu_forward_problem(v, h, nsteps, src, x_align=4)["u_cur"]
         runs["unaligned_pitch"] = problems.gpu_forward_problem(v, h, nsteps, src, x_align=1)["u_cur"]
     finally:
-        _abi.rtm_set_option(_abi.RTM_OPT_INTERIOR_VARIANT, 0)
+        _abi.rtm_set_option(_abi.RTM_OPT_INTERIOR_VARIANT, default_variant)
         _abi.rtm_set_option(_abi.RTM_OPT_ZCHUNK, 0)
         _abi.rtm_set_option(_abi.RTM_OPT_XCD_REMAP, 1)
     assert np.any(base != 0)

@@ -653,6 +653,7 @@ struct Options {
     std::atomic<int> xcd_remap{1};
     std::atomic<int> halo_x_width{64};     // x strips of the halo region
     std::atomic<int> halo_y_width{16};     // y strips of the halo region
+    std::atomic<int> halo_variant{0};      // tile shape of the halo call (as interior_variant; 5: 16x32)
 };
 Options g_opt;
 
@@ -790,6 +791,7 @@ int launch_tiled_variant(int var, const Geo &g, float *un, const float *uc, cons
     case 1: return launch_tiled<R, 32, 8, OP>(g, un, uc, up, kap, boxes, nbox, st);
     case 2: return launch_tiled<R, 16, 8, OP>(g, un, uc, up, kap, boxes, nbox, st);
     case 4: return launch_tiled<R, 32, 16, OP>(g, un, uc, up, kap, boxes, nbox, st);
+    case 5: return launch_tiled<R, 16, 32, OP>(g, un, uc, up, kap, boxes, nbox, st);
     default: return launch_tiled<R, 16, 16, OP>(g, un, uc, up, kap, boxes, nbox, st);
     }
 }
@@ -848,7 +850,9 @@ int launch_halo(const Geo &g, float *un, const float *uc, const float *up, const
     const Region r = halo_region(g.nx, g.ny, R);
     int boxes[6][6];
     const int nb = halo_boxes(g, r, boxes);
-    if (vector_path(g, un, uc, up, kap)) return launch_tiled_variant<R, OP>(0, g, un, uc, up, kap, boxes, nb, st);
+    if (vector_path(g, un, uc, up, kap))
+        return launch_tiled_variant<R, OP>(g_opt.halo_variant.load(std::memory_order_relaxed), g, un, uc, up, kap,
+                                           boxes, nb, st);
     for (int i = 0; i < nb; ++i) {
         const int rc = launch_box_scalar<R, OP>(g, un, uc, up, kap, boxes[i], st);
         if (rc != RTM_OK) return rc;
@@ -1292,7 +1296,7 @@ int rtm_set_option(int32_t option, int32_t value)
 {
     switch (option) {
     case RTM_OPT_INTERIOR_VARIANT:
-        if (value < 0 || value > 4) return RTM_EINVAL;
+        if (value < 0 || value > 5) return RTM_EINVAL;
         g_opt.interior_variant.store(value);
         return RTM_OK;
     case RTM_OPT_ZCHUNK:
@@ -1310,6 +1314,10 @@ int rtm_set_option(int32_t option, int32_t value)
         if (value < 1) return RTM_EINVAL;
         g_opt.halo_y_width.store(value);
         return RTM_OK;
+    case RTM_OPT_HALO_VARIANT:
+        if (value < 0 || value > 5 || value == 3) return RTM_EINVAL;
+        g_opt.halo_variant.store(value);
+        return RTM_OK;
     default: return RTM_EINVAL;
     }
 }
@@ -1322,6 +1330,7 @@ int rtm_get_option(int32_t option)
     case RTM_OPT_XCD_REMAP: return g_opt.xcd_remap.load();
     case RTM_OPT_HALO_X_WIDTH: return g_opt.halo_x_width.load();
     case RTM_OPT_HALO_Y_WIDTH: return g_opt.halo_y_width.load();
+    case RTM_OPT_HALO_VARIANT: return g_opt.halo_variant.load();
     default: return RTM_EINVAL;
     }
 }

@@ -178,6 +178,43 @@ def summarize(stats_dir, fetch_dir, write_dir, out, n, commands):
     print(text)
 
 
+def summarize_corrected(stats_dir, out, n, steps, every, commands):
+    """Per-step and per-correction costs of the `corrected` run from its kernel statistics."""
+    rows = _csv(stats_dir, "*kernel_stats.csv")
+    lines = [f"# rocprofv3 summary: corrected coarse propagation, {n}^3 coarse grid (radius 2, the companion of a",
+             f"# {2 * n}^3 fine grid), point source, {steps} steps in the fused schedule, the corrector applied "
+             f"every {every} steps", "", "Commands (from /tmp, TMPDIR=/tmp, PYTHONPATH=<repo root>):"]
+    lines += [f"    {c}" for c in commands] + [""]
+    lines += ["Kernel statistics (k_conv3d<TY, IN, OUT>: <4, 1, 0> is the first layer reading the wavefield,",
+              "<4, 0, 0> the middle layer, <4, 0, 1> the last layer applying the correction to the levels):",
+              f"    {'kernel':60s} {'calls':>6s} {'avg us':>9s} {'total ms':>9s} {'share %':>8s}"]
+    tot, avg, calls = {}, {}, {}
+    for i, r in enumerate(rows):
+        name = r["Name"].replace("(anonymous namespace)::", "")
+        tot[name] = float(r["TotalDurationNs"]) / 1e3
+        avg[name] = float(r["AverageNs"]) / 1e3
+        calls[name] = int(r["Calls"])
+        if i < 12:
+            lines.append(f"    {name[:60]:60s} {r['Calls']:>6s} {avg[name]:9.1f} {tot[name] / 1e3:9.2f} "
+                         f"{float(r['Percentage']):8.2f}")
+
+    def total(*subs):
+        return sum(v for k, v in tot.items() if any(x in k for x in subs))
+    ncorr = max(1, sum(v for k, v in calls.items() if "k_absmax_rows" in k))   # one scale per correction
+    update = [v for k, v in avg.items() if "k_tiled<2," in k]
+    step = total("k_tiled<2,", "k_inject", "k_unpack") / steps
+    corr = total("k_conv3d", "k_absmax_rows", "k_zero1", "k_pack(") / ncorr
+    lines += ["", f"Per coarse step (one-launch update, inject, ghost refresh): {step:.0f} us"
+                  + (f" (the update {update[0]:.0f} us)" if update else ""),
+              f"Per correction (scale, first layer with the input packing, middle layer, last layer applying the "
+              f"correction): {corr / 1e3:.2f} ms",
+              f"    -> corrected propagation {step + corr / every:.0f} us per coarse step at K = {every}"]
+    text = "\n".join(lines) + "\n"
+    with open(out, "w") as f:
+        f.write(text)
+    print(text)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -198,6 +235,13 @@ def main(argv=None):
     b.add_argument("--out", required=True)
     b.add_argument("--n", type=int, default=512)
     b.add_argument("--command", action="append", default=[])
+    bc = sub.add_parser("summarize-corrected")
+    bc.add_argument("--stats", required=True)
+    bc.add_argument("--out", required=True)
+    bc.add_argument("--n", type=int, default=384)
+    bc.add_argument("--steps", type=int, default=160)
+    bc.add_argument("--every", type=int, default=16)
+    bc.add_argument("--command", action="append", default=[])
     args = ap.parse_args(argv)
     if args.cmd == "interior":
         run_interior(args.n, args.launches)
@@ -205,6 +249,8 @@ def main(argv=None):
         run_conv(args.n, args.launches)
     elif args.cmd == "corrected":
         run_corrected(args.n, args.steps, args.every)
+    elif args.cmd == "summarize-corrected":
+        summarize_corrected(args.stats, args.out, args.n, args.steps, args.every, args.command)
     else:
         summarize(args.stats, args.fetch, args.write, args.out, args.n, args.command)
 

@@ -57,8 +57,8 @@ def test_ragged_layered_parity(torch_cuda, schedule):
 
 
 def test_schedules_and_variants_bitwise(torch_cuda):
-    """Halo-first on two streams, single stream, the one-launch whole step, every interior kernel
-    variant and z chunking, and unaligned pitches (scalar path) all give the same bits."""
+    """Halo-first on two streams, single stream, the one-launch whole step, every interior and halo
+    kernel variant and z chunking, and unaligned pitches (scalar path) all give the same bits."""
     from paper_1603_03971_amd import _abi
 
     v, h, nsteps, src = problems.ragged_inputs(seed=9)
@@ -75,6 +75,10 @@ def test_schedules_and_variants_bitwise(torch_cuda):
             runs[f"variant{var}"] = problems.gpu_forward_problem(v, h, nsteps, src)["u_cur"]
             runs[f"variant{var}_fused"] = problems.gpu_forward_problem(v, h, nsteps, src, schedule="fused")["u_cur"]
         _abi.rtm_set_option(_abi.RTM_OPT_INTERIOR_VARIANT, default_variant)
+        for var in (1, 2, 4, 5):
+            _abi.rtm_set_option(_abi.RTM_OPT_HALO_VARIANT, var)
+            runs[f"halo_variant{var}"] = problems.gpu_forward_problem(v, h, nsteps, src)["u_cur"]
+        _abi.rtm_set_option(_abi.RTM_OPT_HALO_VARIANT, 0)
         for zc in (1, 7, 1000):
             _abi.rtm_set_option(_abi.RTM_OPT_ZCHUNK, zc)
             runs[f"zchunk{zc}"] = problems.gpu_forward_problem(v, h, nsteps, src)["u_cur"]
@@ -86,6 +90,7 @@ def test_schedules_and_variants_bitwise(torch_cuda):
         runs["unaligned_pitch"] = problems.gpu_forward_problem(v, h, nsteps, src, x_align=1)["u_cur"]
     finally:
         _abi.rtm_set_option(_abi.RTM_OPT_INTERIOR_VARIANT, default_variant)
+        _abi.rtm_set_option(_abi.RTM_OPT_HALO_VARIANT, 0)
         _abi.rtm_set_option(_abi.RTM_OPT_ZCHUNK, 0)
         _abi.rtm_set_option(_abi.RTM_OPT_XCD_REMAP, 1)
     assert np.any(base != 0)

@@ -195,9 +195,9 @@ def main():
     fwall = time.perf_counter() - t0
     result["fused_schedule"] = {"value": round(pts * fsteps / fwall / 1e9, 3), "unit": "Gpts/s",
                                 "ms_per_step": round(fwall / fsteps * 1e3, 4), "steps": fsteps,
-                                "what": "one launch per step over all owned cells (rtm_step_whole), then inject, "
-                                        "ghost refresh and record; bitwise the same fields as the halo-first "
-                                        "sequence, which the value measures"}
+                                "what": "one launch per step over all owned cells (rtm_step_whole), then inject "
+                                        "and record (the zero ghost ring written once per buffer); bitwise the "
+                                        "same fields as the halo-first sequence, which the value measures"}
     del fused
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(n, h, prof, args.cpu_seconds)

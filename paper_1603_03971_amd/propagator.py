@@ -17,9 +17,13 @@ u^{n-1} in place (two buffers), and a level that must outlive the rotation (an R
 The "serial" schedule runs the same calls on one stream; both give bitwise identical fields.  The
 "fused" schedule, for one subdomain with nothing to overlap, updates every owned cell in one launch
 (rtm_step_whole) instead of the halo and interior calls, then injects, refreshes the ghosts and
-records on one stream; it too is bitwise identical.
+records on one stream; it too is bitwise identical.  With no face received (the physical boundary),
+the ghost ring of a level buffer holds zeros once written, and the refresh is skipped for buffers
+known to be in that state.
 """
 from __future__ import annotations
+
+import weakref
 
 import numpy as np
 import torch
@@ -94,6 +98,11 @@ class Propagator:
         self.schedule = schedule
         self.u_prv = grid.field()
         self.u_cur = grid.field()
+        # level buffers whose ghost ring is known to hold zeros (the physical boundary's ghosts), by
+        # buffer identity: the fused schedule skips the ghost refresh for them when no face is received
+        self._zero_ghosts: dict[int, weakref.ref] = {}
+        self._mark_zero_ghosts(self.u_prv)
+        self._mark_zero_ghosts(self.u_cur)
         self.pinned: set[int] = set()
         self.pool: list[torch.Tensor] = []
         self.send = grid.faces()
@@ -124,6 +133,15 @@ class Propagator:
         st = stream if stream is not None else torch.cuda.current_stream()
         _abi.rtm_pack_halo(self.grid.c, u, self.send, st)
         _abi.rtm_unpack_halo(self.grid.c, u, self.recv, st)
+        if all(r is None for r in self.recv):
+            self._mark_zero_ghosts(u)
+
+    def _mark_zero_ghosts(self, u: torch.Tensor):
+        self._zero_ghosts[u.data_ptr()] = weakref.ref(u)
+
+    def _ghosts_known_zero(self, u: torch.Tensor) -> bool:
+        r = self._zero_ghosts.get(u.data_ptr())
+        return r is not None and r() is u
 
     def pin_current(self):
         """Keep the buffer of the newest level: later steps will not write into it."""
@@ -139,10 +157,13 @@ class Propagator:
         """Continue from existing device levels (u^n, u^{n-1}) without copying them; u_prv may be
         overwritten by the next step unless it is pinned.  u_cur's ghosts must be current."""
         self.sync()
+        self._zero_ghosts.pop(u_prv.data_ptr(), None)     # its ghosts are the caller's: refreshed on reuse
         self.u_cur, self.u_prv, self.n = u_cur, u_prv, n
 
     def unpin(self, t: torch.Tensor, recycle: bool = True):
         self.pinned.discard(t.data_ptr())
+        # the caller may have written anything into it meanwhile: its ghosts are refreshed on reuse
+        self._zero_ghosts.pop(t.data_ptr(), None)
         if recycle:
             self.pool.append(t)
 
@@ -178,7 +199,12 @@ class Propagator:
                 s.inject(g, u_nxt, n, 1, st)
             if any(r is not None for r in self.recv):
                 _abi.rtm_pack_halo(c, u_nxt, self.send, st)
-            _abi.rtm_unpack_halo(c, u_nxt, self.recv, st)
+                _abi.rtm_unpack_halo(c, u_nxt, self.recv, st)
+            elif not self._ghosts_known_zero(u_nxt):
+                # no face is received: the ghosts are the boundary's zeros, written once per buffer
+                # (the updates write owned cells only)
+                _abi.rtm_unpack_halo(c, u_nxt, self.recv, st)
+                self._mark_zero_ghosts(u_nxt)
             if tr_ptr is not None:
                 _abi.rtm_record(c, u_nxt, self.rec_idx, tr_ptr, self.nrec, st)
         elif self.schedule == "serial":

@@ -712,6 +712,43 @@ unsigned blocks_for(long long n) { return (unsigned)((n + kThreads - 1) / kThrea
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+int cu_count()
+{
+    static std::atomic<int> cached{0};
+    int n = cached.load(std::memory_order_relaxed);
+    if (n == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = 256;
+        cached.store(n, std::memory_order_relaxed);
+    }
+    return n;
+}
+
+// z chunk of a launch over one deep box of `tiles` XY tiles and depth wz.  Each chunk re-reads 2R
+// planes it does not write, and the launch lasts about as long as its busiest CU:
+//     cost(nzc) = ceil(tiles * nzc / CUs) * (wz / nzc + 2R)    (in tile-planes).
+// Among chunkings within 3% of the least cost the one with the fewest workgroups wins: fewer,
+// longer streams use HBM better (512^3 whole step with 32x16 tiles: 2 chunks, one workgroup per
+// CU, 454 us; 4 chunks 501 us; 3 chunks, 384 workgroups on 256 CUs, 559 us).
+int balanced_zchunk(int tiles, int wz, int R, int cus)
+{
+    const int max_nzc = std::max(1, wz / 16);
+    long long best = -1;
+    long long cost[64 + 1];
+    const int n_try = std::min(max_nzc, 64);
+    for (int nzc = 1; nzc <= n_try; ++nzc) {
+        const int zc = (wz + nzc - 1) / nzc;
+        const long long blocks = (long long)tiles * ((wz + zc - 1) / zc);
+        cost[nzc] = ((blocks + cus - 1) / cus) * (long long)(zc + 2 * R);
+        if (best < 0 || cost[nzc] < best) best = cost[nzc];
+    }
+    for (int nzc = 1; nzc <= n_try; ++nzc)   // fewest workgroups first
+        if (cost[nzc] * 100 <= best * 103) return (wz + nzc - 1) / nzc;
+    return wz;
+}
+
 // Launch the tiled kernel over up to kMaxBoxes boxes {x0, x1, y0, y1, z0, z1} (empty ones skipped).
 template <int R, int BX, int BY, int OP>
 int launch_tiled(const Geo &g, float *un, const float *uc, const float *up, const float *kap, const int (*boxes)[6],
@@ -746,6 +783,8 @@ int launch_tiled(const Geo &g, float *un, const float *uc, const float *up, cons
         // 16 planes for R = 2, and several short waves of workgroups balance better than one long
         // one (384^3 whole step: 237 us at 16 planes against 266 us for one wave).
         zc = 16;
+    } else if (zc <= 0 && tiles > 0 && bl.nbox == 1) {
+        zc = balanced_zchunk(tiles, wz, R, cu_count());
     } else if (zc <= 0 && tiles > 0) {
         // One wave of workgroups: split z so that tiles x chunks is at most the number of workgroups
         // the whole chip holds at once (CUs x resident workgroups per CU), with chunks of >= 16

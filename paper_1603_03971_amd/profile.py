@@ -98,9 +98,10 @@ def run_corrected(n: int, steps: int, every: int):
     print(json.dumps({"coarse_cells": coarse.points, "steps": steps, "corrections": corr.applied}))
 
 
-# The radius-4 interior call's kernel under the default options (the 32 x 16-thread tile); the
-# one-launch whole step runs the same kernel over a larger box.
+# The radius-4 interior and halo calls' kernels under the default options (32 x 16- and 16 x 16-thread
+# tiles); the one-launch whole step runs the interior kernel over the whole block.
 INTERIOR_KERNEL = "k_tiled<4, 32, 16, 0>"
+HALO_KERNEL = "k_tiled<4, 16, 16, 0>"
 
 
 def _csv(d: str, name: str):
@@ -133,23 +134,29 @@ def summarize(stats_dir, fetch_dir, write_dir, out, n, commands):
         name = r["Name"].replace("(anonymous namespace)::", "")[:60]
         avg = float(r["AverageNs"]) / 1e3
         lines.append(f"    {name:60s} {r['Calls']:>6s} {avg:10.2f} {float(r['Percentage']):8.2f}")
-    # The interior call and the one-launch whole step share this kernel; they differ in grid size
-    # (the interior box is the smaller), so the dispatches are split by it.
-    shapes = {}
-    for r in _csv(stats_dir, "*kernel_trace.csv"):
-        if INTERIOR_KERNEL in r["Kernel_Name"]:
-            shapes.setdefault(int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"]), []).append(
-                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    # The interior call and the one-launch whole step share this kernel.  In the halo-first sequence
+    # the interior call is the dispatch right after the halo call's; the others are whole steps.
+    trace = sorted(_csv(stats_dir, "*kernel_trace.csv"), key=lambda r: int(r["Start_Timestamp"]))
+    calls = {"rtm_step_interior": [], "rtm_step_whole (fused schedule)": []}
+    grids = {}
+    prev = ""
+    for r in trace:
+        name = r["Kernel_Name"]
+        if INTERIOR_KERNEL in name:
+            what = "rtm_step_interior" if HALO_KERNEL in prev else "rtm_step_whole (fused schedule)"
+            calls[what].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+            grids.setdefault(what, set()).add(int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"]))
+        prev = name
     interior_avg_us = None
-    if shapes:
-        lines += ["", f"Launch shapes of {INTERIOR_KERNEL} (kernel trace):",
+    if any(calls.values()):
+        lines += ["", f"Launches of {INTERIOR_KERNEL} (kernel trace):",
                   f"    {'call':32s} {'workgroups':>10s} {'calls':>6s} {'avg us':>10s}"]
-        for i, grid in enumerate(sorted(shapes)):
-            d = shapes[grid]
-            what = "rtm_step_interior" if i == 0 else "rtm_step_whole (fused schedule)"
-            lines.append(f"    {what:32s} {grid:10d} {len(d):6d} {sum(d) / len(d):10.2f}")
-        d = shapes[min(shapes)]
-        interior_avg_us = sum(d) / len(d)
+        for what, d in calls.items():
+            if d:
+                wg = ",".join(str(x) for x in sorted(grids[what]))
+                lines.append(f"    {what:32s} {wg:>10s} {len(d):6d} {sum(d) / len(d):10.2f}")
+        d = calls["rtm_step_interior"]
+        interior_avg_us = sum(d) / len(d) if d else None
     record = {"n": n, "kernel_source_sha256_16": kernel_source_hash(), "interior_avg_us_kernel_trace": interior_avg_us}
     if fetch_dir and write_dir:
         fr, wr = _csv(fetch_dir, "*counter_collection.csv"), _csv(write_dir, "*counter_collection.csv")

@@ -589,23 +589,63 @@ __device__ __forceinline__ uint16_t f32_to_f16_rne(float x)
 __device__ __forceinline__ float f16_to_f32(uint16_t c) { return (float)__builtin_bit_cast(_Float16, c); }
 
 // scales[k] = max |u| over the owned cells of plane k (one workgroup per plane).
-__global__ __launch_bounds__(kThreads) void k_plane_absmax(Geo g, const float *__restrict__ u, float *__restrict__ scales)
+// scales[k] = max |u| over owned plane k: one 1024-thread workgroup per plane with four loads in
+// flight per thread (float4 rows when VEC: nx % 4 == 0 and every row start 16-byte aligned), then a
+// wave-shuffle and LDS reduction.  A maximum is exact in any order.
+constexpr int kAbsmaxThreads = 1024;
+
+template <bool VEC>
+__global__ __launch_bounds__(kAbsmaxThreads) void k_plane_absmax(Geo g, const float *__restrict__ u,
+                                                                 float *__restrict__ scales)
 {
     const int k = blockIdx.x;
-    const int nxy = g.nx * g.ny;
     float m = 0.0f;
-    for (int t = threadIdx.x; t < nxy; t += blockDim.x) {
-        const int j = t / g.nx, i = t - j * g.nx;
-        m = fmaxf(m, fabsf(u[pidx(g, i, j, k)]));
+    if constexpr (VEC) {
+        const int w4 = g.nx >> 2;
+        const int n4 = w4 * g.ny;
+        for (int t0 = threadIdx.x; t0 < n4; t0 += 4 * kAbsmaxThreads) {
+            float4 v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int t = t0 + q * kAbsmaxThreads;
+                v[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (t < n4) {
+                    const int j = t / w4, i4 = t - j * w4;
+                    v[q] = ld4(u + pidx(g, 4 * i4, j, k));
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                m = fmaxf(m, fmaxf(fmaxf(fabsf(v[q].x), fabsf(v[q].y)), fmaxf(fabsf(v[q].z), fabsf(v[q].w))));
+        }
+    } else {
+        const int nxy = g.nx * g.ny;
+        for (int t0 = threadIdx.x; t0 < nxy; t0 += 4 * kAbsmaxThreads) {
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int t = t0 + q * kAbsmaxThreads;
+                v[q] = 0.0f;
+                if (t < nxy) {
+                    const int j = t / g.nx, i = t - j * g.nx;
+                    v[q] = u[pidx(g, i, j, k)];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) m = fmaxf(m, fabsf(v[q]));
+        }
     }
-    __shared__ float red[kThreads];
-    red[threadIdx.x] = m;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    __shared__ float red[kAbsmaxThreads / 64];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
-    for (int w = kThreads / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
+    if (threadIdx.x < 64) {
+        m = threadIdx.x < kAbsmaxThreads / 64 ? red[threadIdx.x] : 0.0f;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+        if (threadIdx.x == 0) scales[k] = m;
     }
-    if (threadIdx.x == 0) scales[k] = red[0];
 }
 
 // codes[(k ny + j) nx + i] = RNE(u / scales[k]) in the 16-bit format; a zero scale gives zero codes.
@@ -1304,7 +1344,11 @@ int rtm_snapshot_encode(const rtm_grid *grid, const float *u, uint16_t *codes, f
     st = check_device();
     if (st != RTM_OK) return st;
     const Geo g = make_geo(grid);
-    hipLaunchKernelGGL(k_plane_absmax, dim3(g.nz), dim3(kThreads), 0, stream, g, u, scales);
+    const bool vec = g.nx % 4 == 0 && aligned16(u + g.R * (g.pz + g.py + 1)) && g.py % 4 == 0 && g.pz % 4 == 0;
+    if (vec)
+        hipLaunchKernelGGL((k_plane_absmax<true>), dim3(g.nz), dim3(kAbsmaxThreads), 0, stream, g, u, scales);
+    else
+        hipLaunchKernelGGL((k_plane_absmax<false>), dim3(g.nz), dim3(kAbsmaxThreads), 0, stream, g, u, scales);
     st = launch_status();
     if (st != RTM_OK) return st;
     hipLaunchKernelGGL(k_encode, dim3(blocks_for(n)), dim3(kThreads), 0, stream, g, u, scales, codes, (int)format);

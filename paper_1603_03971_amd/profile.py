@@ -14,6 +14,12 @@
       source in a smooth medium with the dispersion corrector applied every `every` steps, for a
       kernel trace of the corrected coarse propagation (stencil calls, network, glue).
 
+  python3 -m paper_1603_03971_amd.profile shot [--nx 512 --ny 512 --nz 256] [--steps 2000] [--every 4]
+      one full-size RTM shot over three dipping reflectors (seed 3; v(z) = 1500 + 0.75 z m/s; source
+      at (nx/2, ny/2, 20), receivers every 2 cells at depth 20): models the true and background
+      data, then migrates them with FP32, BF16 and FP16 source snapshots (best of --repeats), and
+      prints the times, the snapshot memory and each coded image's rel-L2 against the FP32 image.
+
   python3 -m paper_1603_03971_amd.profile summarize --stats DIR --fetch DIR --write DIR --out FILE
       reads rocprofv3 CSV output (kernel stats of a benchmark run, counter collections of the two
       runs above) and writes a short text summary plus the traffic record that bench.py reports
@@ -102,6 +108,67 @@ def run_corrected(n: int, steps: int, every: int):
 # tiles); the one-launch whole step runs the interior kernel over the whole block.
 INTERIOR_KERNEL = "k_tiled<4, 32, 16, 0>"
 HALO_KERNEL = "k_tiled<4, 16, 16, 0>"
+
+
+def run_shot(nx: int, ny: int, nz: int, steps: int, every: int, repeats: int, schedule: str):
+    import time
+
+    import numpy as np
+    import torch
+
+    from . import rtm, snapshots, synth
+    from .grid import Grid
+
+    def say(msg):
+        print(msg, flush=True)
+
+    h = 10.0
+    v_true, v_bg = synth.dipping_reflector_model((nz, ny, nx), h, seed=3)
+    dt = Grid.stable_dt(4, h, float(max(v_true.max(), v_bg.max())))
+    g = Grid(nx, ny, nz, h, dt)
+    src = np.array([[nx // 2, ny // 2, 20]], dtype=np.int64)
+    rec = synth.surface_receivers(nx, ny, k=20, stride=2)
+    wav = g.ricker(steps, 15.0)
+    kap_true, kap_bg = g.kappa_from_velocity(v_true), g.kappa_from_velocity(v_bg)
+    vs = v_bg[src[:, 2], src[:, 1], src[:, 0]]
+    del v_true
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d_true = rtm.model_shot(g, kap_true, vs, src, wav, rec, steps, schedule)
+    d_bg = rtm.model_shot(g, kap_bg, vs, src, wav, rec, steps, schedule)
+    torch.cuda.synchronize()
+    t_model = time.perf_counter() - t0
+    del kap_true
+    say(f"data modelled: {len(rec)} receivers x {steps} steps, two propagations in {t_model:.3f} s")
+    out = {"grid": [nx, ny, nz], "steps": steps, "image_every": every, "receivers": int(len(rec)),
+           "schedule": schedule, "t_model_two_shots_s": round(t_model, 4)}
+    images = {}
+    for fmt in ("f32", "bf16", "f16"):
+        best = None
+        for _ in range(max(1, repeats)):
+            codec = snapshots.make(fmt)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            img = rtm.migrate_shot(g, kap_bg, v_bg, src, wav, rec, d_true, d_bg, steps, every, schedule,
+                                   codec(g) if codec is not None else None)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            best = t if best is None else min(best, t)
+            images[fmt] = g.download(img).astype(np.float64)
+            del img
+        torch.cuda.empty_cache()
+        nsnap = steps // every
+        per = g.bytes_per_field() if fmt == "f32" else snapshots.CodedSnapshots(g, fmt).bytes_per_snapshot()
+        out[f"t_migrate_{fmt}_s"] = round(best, 4)
+        out[f"snapshot_GB_{fmt}"] = round(nsnap * per / 1e9, 2)
+        say(f"migration with {fmt} snapshots: {best:.3f} s ({nsnap} snapshots, {nsnap * per / 1e9:.1f} GB)")
+    ref = images["f32"]
+    nref = float(np.linalg.norm(ref))
+    for fmt in ("bf16", "f16"):
+        out[f"image_rel_l2_{fmt}_vs_f32"] = float(np.linalg.norm(images[fmt] - ref) / nref)
+    out["image_norm"] = nref
+    out["image_finite"] = bool(all(np.isfinite(im).all() for im in images.values()))
+    print(json.dumps(out), flush=True)
 
 
 def _csv(d: str, name: str):
@@ -235,6 +302,14 @@ def main(argv=None):
     cr.add_argument("--n", type=int, default=384)
     cr.add_argument("--steps", type=int, default=160)
     cr.add_argument("--every", type=int, default=16)
+    sh = sub.add_parser("shot")
+    sh.add_argument("--nx", type=int, default=512)
+    sh.add_argument("--ny", type=int, default=512)
+    sh.add_argument("--nz", type=int, default=256)
+    sh.add_argument("--steps", type=int, default=2000)
+    sh.add_argument("--every", type=int, default=4)
+    sh.add_argument("--repeats", type=int, default=2)
+    sh.add_argument("--schedule", default="fused", choices=["overlap", "serial", "fused"])
     b = sub.add_parser("summarize")
     b.add_argument("--stats", required=True)
     b.add_argument("--fetch")
@@ -256,6 +331,8 @@ def main(argv=None):
         run_conv(args.n, args.launches)
     elif args.cmd == "corrected":
         run_corrected(args.n, args.steps, args.every)
+    elif args.cmd == "shot":
+        run_shot(args.nx, args.ny, args.nz, args.steps, args.every, args.repeats, args.schedule)
     elif args.cmd == "summarize-corrected":
         summarize_corrected(args.stats, args.out, args.n, args.steps, args.every, args.command)
     else:

@@ -663,23 +663,41 @@ __global__ __launch_bounds__(256) void k_restrict(G f, G c, const float *__restr
 // does not depend on scheduling.
 __global__ void k_zero1(float *out) { out[0] = 0.0f; }
 
-__global__ __launch_bounds__(256) void k_absmax_rows(G g, const float *__restrict__ u, float *out)
+// max |u| over the owned cells into out[0] (zeroed by k_zero1 first): a grid-stride walk over the
+// cells, x fastest, with four loads in flight per thread, then a wave-shuffle and LDS reduction per
+// workgroup and one atomic max of the bit pattern (ordered like the value for non-negative floats).
+// I is the index type: 32-bit when the cell count allows.
+template <typename I>
+__global__ __launch_bounds__(256) void k_absmax_cells(G g, const float *__restrict__ u, float *out)
 {
-    const long long rows = (long long)g.nz * g.ny;
+    const I n = (I)g.nx * (I)g.ny * (I)g.nz;
+    const I stride = (I)gridDim.x * 256;
     float mx = 0.0f;
-    for (long long r = blockIdx.x; r < rows; r += gridDim.x) {
-        const int k = (int)(r / g.ny), j = (int)(r - (long long)k * g.ny);
-        const float *row = u + g.idx(0, j, k);
-        for (int i = threadIdx.x; i < g.nx; i += 256) mx = fmaxf(mx, fabsf(row[i]));
+    for (I t0 = (I)blockIdx.x * 256 + threadIdx.x; t0 < n; t0 += 4 * stride) {
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const I t = t0 + (I)q * stride;
+            v[q] = 0.0f;
+            if (t < n) {
+                const I r = t / (I)g.nx;
+                const int i = (int)(t - r * (I)g.nx);
+                const int k = (int)(r / (I)g.ny), j = (int)(r - (I)k * (I)g.ny);
+                v[q] = u[g.idx(i, j, k)];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) mx = fmaxf(mx, fabsf(v[q]));
     }
-    __shared__ float red[256];
-    red[threadIdx.x] = mx;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+    __shared__ float red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+        atomicMax(reinterpret_cast<int *>(out), __float_as_int(mx));
     }
-    if (threadIdx.x == 0) atomicMax(reinterpret_cast<int *>(out), __float_as_int(red[0]));
 }
 
 int status() { return hipGetLastError() == hipSuccess ? RTM_OK : RTM_ELAUNCH; }
@@ -916,9 +934,12 @@ int rtm_field_absmax(const rtm_grid *grid, const float *u, float *out, hipStream
     hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, stream, out);
     int st = status();
     if (st != RTM_OK) return st;
-    const long long rows = (long long)g.nz * g.ny;
-    hipLaunchKernelGGL(k_absmax_rows, dim3((unsigned)std::min<long long>(rows, 2048)), dim3(256), 0, stream, g, u,
-                       out);
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    const unsigned blocks = (unsigned)std::max<long long>(1, std::min<long long>((n + 1023) / 1024, 4096));
+    if (n + 4LL * 256 * blocks < (1LL << 31))
+        hipLaunchKernelGGL(k_absmax_cells<int>, dim3(blocks), dim3(256), 0, stream, g, u, out);
+    else
+        hipLaunchKernelGGL(k_absmax_cells<long long>, dim3(blocks), dim3(256), 0, stream, g, u, out);
     return status();
 }
 

@@ -363,3 +363,32 @@ def test_conv3d_partial_output_channels_and_noise_inputs():
     ra32, rb32 = ra.astype(np.float32), rb.astype(np.float32)
     assert np.array_equal(t[..., 0], (ra32 - a32) * half - noise[..., 0])
     assert np.array_equal(t[..., 1], ((ra32 - rb32) - (a32 - b32)) * half - noise[..., 1])
+
+
+@pytest.mark.parametrize("radius,shape", [(2, (37, 5, 48)), (4, (9, 70, 64)), (2, (4, 4, 16))])
+def test_field_absmax_covers_every_owned_cell_and_no_ghost(radius, shape):
+    """rtm_field_absmax on ragged grids: the extreme sits in turn at each corner cell (one of them
+    negative), while the ghost ring holds larger values that must not count."""
+    import torch
+
+    from paper_1603_03971_amd import _abi
+    from paper_1603_03971_amd.grid import Grid
+
+    nz, ny, nx = shape
+    g = Grid(nx, ny, nz, 10.0, Grid.stable_dt(radius, 10.0, 3000.0), radius=radius, sponge_width=2)
+    st = torch.cuda.current_stream()
+    base = np.random.default_rng(1700 + nx).uniform(-1.0, 1.0, g.shape).astype(np.float32)
+    s = torch.zeros(1, dtype=torch.float32, device="cuda")
+    corners = [(k, j, i) for k in (0, nz - 1) for j in (0, ny - 1) for i in (0, nx - 1)]
+    for n, (k, j, i) in enumerate(corners):
+        a = base.copy()
+        peak = np.float32(3.0 + n) * (np.float32(-1.0) if n % 2 else np.float32(1.0))
+        a[k, j, i] = peak
+        f = g.upload(a)
+        pad = g.padded(f)
+        pad[0].fill_(1e6)                       # a ghost plane below the box
+        pad[:, :, 0].fill_(-1e6)                # a ghost column
+        g.owned(f).copy_(torch.from_numpy(a).cuda())
+        _abi.rtm_field_absmax(g.c, f, s, st)
+        torch.cuda.synchronize()
+        assert float(s.item()) == abs(float(peak)), (k, j, i)

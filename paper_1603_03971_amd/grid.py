@@ -7,8 +7,6 @@ which lets the interior kernel issue aligned float4 loads and whole cache lines.
 """
 from __future__ import annotations
 
-import math
-
 import numpy as np
 import torch
 
@@ -153,7 +151,3 @@ class Grid:
     def __repr__(self):
         return (f"Grid({self.nx}x{self.ny}x{self.nz}, h={self.h}, dt={self.dt:.6g}, R={self.radius}, "
                 f"pitch_y={self.pitch_y}, pitch_z={self.pitch_z})")
-
-
-def gpts(points: int, steps: int, seconds: float) -> float:
-    return points * steps / seconds / 1e9 if seconds > 0 else math.nan

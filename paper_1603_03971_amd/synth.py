@@ -115,18 +115,3 @@ def random_positions(n: int, nx: int, ny: int, k: int, seed: int, margin: int = 
 def random_field(shape, seed: int, scale: float = 1.0) -> np.ndarray:
     """Standard-normal test field (FP64)."""
     return scale * np.random.default_rng(seed).standard_normal(shape)
-
-
-def random_cells(n: int, shape, seed: int, margin: int = 0) -> np.ndarray:
-    """`n` distinct seeded cells (i, j, k) at least `margin` cells from every face."""
-    nz, ny, nx = shape
-    rng = np.random.default_rng(seed)
-    seen = set()
-    out = []
-    while len(out) < n:
-        c = (int(rng.integers(margin, nx - margin)), int(rng.integers(margin, ny - margin)),
-             int(rng.integers(margin, nz - margin)))
-        if c not in seen:
-            seen.add(c)
-            out.append(c)
-    return np.array(out, dtype=np.int64)

@@ -96,10 +96,11 @@ const char *rtm_strerror(int status);
  * per-point expression), but the halo and interior calls of one step must see the same options, so
  * change them only between steps.
  *   RTM_OPT_INTERIOR_VARIANT  workgroup shape of the interior call's tiled kernel: 0 = 16x16 threads
- *                             (64x16 cells), 1 = 32x8 (128x8 cells), 2 = 16x8 (64x8 cells),
- *                             3 = scalar per-cell kernels for both calls, 4 = 32x16 (128x16 cells,
- *                             two workgroups per CU; default), 5 = 16x32 (64x32 cells).
+ *                             (64x16 cells), 1 = 32x8 (128x8 cells), 2 = 16x8 (64x8 cells; default),
+ *                             3 = scalar per-cell kernels for every call, 4 = 32x16 (128x16 cells,
+ *                             two workgroups per CU), 5 = 16x32 (64x32 cells).
  *   RTM_OPT_HALO_VARIANT      the halo call's workgroup shape, numbered as above (not 3); default 0.
+ *   RTM_OPT_WHOLE_VARIANT     rtm_step_whole's workgroup shape, numbered as above (not 3); default 4.
  *   RTM_OPT_ZCHUNK            z planes per workgroup of the tiled kernels; 0 = automatic: at radius 4
  *                             at most one wave of resident workgroups over the whole chip, at radius 2
  *                             chunks of 16 planes.
@@ -114,6 +115,7 @@ enum {
     RTM_OPT_HALO_X_WIDTH = 4,
     RTM_OPT_HALO_Y_WIDTH = 5,
     RTM_OPT_HALO_VARIANT = 6,
+    RTM_OPT_WHOLE_VARIANT = 7,
 };
 int rtm_set_option(int32_t option, int32_t value);
 /* The current value of an option (>= 0), or RTM_EINVAL for an unknown option. */

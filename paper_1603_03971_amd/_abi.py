@@ -17,7 +17,7 @@ RTM_OK, RTM_EINVAL, RTM_EALIAS, RTM_ELAUNCH, RTM_EDEVICE = 0, -1, -2, -3, -4
 RTM_SNAP_BF16, RTM_SNAP_F16 = 1, 2
 RTM_RESTRICT_INJECT, RTM_RESTRICT_FULL = 0, 1
 RTM_OPT_INTERIOR_VARIANT, RTM_OPT_ZCHUNK, RTM_OPT_XCD_REMAP, RTM_OPT_HALO_X_WIDTH, RTM_OPT_HALO_Y_WIDTH = 1, 2, 3, 4, 5
-RTM_OPT_HALO_VARIANT = 6
+RTM_OPT_HALO_VARIANT, RTM_OPT_WHOLE_VARIANT = 6, 7
 
 
 class RTMError(RuntimeError):

@@ -687,8 +687,9 @@ constexpr int kMaxDevices = 64;
 std::atomic<int> g_dev_ok[kMaxDevices];   // 0 unknown, 1 gfx950, -1 other
 
 struct Options {
-    std::atomic<int> interior_variant{4};  // 0: 16x16 threads (64 x 16 cells), 1: 32x8, 2: 16x8, 3: scalar,
-                                           // 4: 32x16 (128 x 16 cells, two workgroups per CU)
+    std::atomic<int> interior_variant{2};  // 0: 16x16 threads (64 x 16 cells), 1: 32x8, 2: 16x8, 3: scalar,
+                                           // 4: 32x16 (128 x 16 cells, two workgroups per CU), 5: 16x32
+    std::atomic<int> whole_variant{4};     // tile shape of the one-launch whole step (not 3)
     std::atomic<int> zchunk{0};            // 0: automatic
     std::atomic<int> xcd_remap{1};
     std::atomic<int> halo_x_width{64};     // x strips of the halo region
@@ -958,7 +959,7 @@ int launch_all(const Geo &g, float *un, const float *uc, const float *up, const 
 {
     const int boxes[1][6] = {{0, g.nx, 0, g.ny, 0, g.nz}};
     if (vector_path(g, un, uc, up, kap)) {
-        const int var = g_opt.interior_variant.load(std::memory_order_relaxed);
+        const int var = g_opt.whole_variant.load(std::memory_order_relaxed);
         return launch_tiled_variant<R, OP>(var, g, un, uc, up, kap, boxes, 1, st);
     }
     return launch_box_scalar<R, OP>(g, un, uc, up, kap, boxes[0], st);
@@ -1401,6 +1402,10 @@ int rtm_set_option(int32_t option, int32_t value)
         if (value < 0 || value > 5 || value == 3) return RTM_EINVAL;
         g_opt.halo_variant.store(value);
         return RTM_OK;
+    case RTM_OPT_WHOLE_VARIANT:
+        if (value < 0 || value > 5 || value == 3) return RTM_EINVAL;
+        g_opt.whole_variant.store(value);
+        return RTM_OK;
     default: return RTM_EINVAL;
     }
 }
@@ -1414,6 +1419,7 @@ int rtm_get_option(int32_t option)
     case RTM_OPT_HALO_X_WIDTH: return g_opt.halo_x_width.load();
     case RTM_OPT_HALO_Y_WIDTH: return g_opt.halo_y_width.load();
     case RTM_OPT_HALO_VARIANT: return g_opt.halo_variant.load();
+    case RTM_OPT_WHOLE_VARIANT: return g_opt.whole_variant.load();
     default: return RTM_EINVAL;
     }
 }

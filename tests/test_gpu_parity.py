@@ -79,6 +79,10 @@ def test_schedules_and_variants_bitwise(torch_cuda):
             _abi.rtm_set_option(_abi.RTM_OPT_HALO_VARIANT, var)
             runs[f"halo_variant{var}"] = problems.gpu_forward_problem(v, h, nsteps, src)["u_cur"]
         _abi.rtm_set_option(_abi.RTM_OPT_HALO_VARIANT, 0)
+        for var in (0, 1, 2, 5):
+            _abi.rtm_set_option(_abi.RTM_OPT_WHOLE_VARIANT, var)
+            runs[f"whole_variant{var}"] = problems.gpu_forward_problem(v, h, nsteps, src, schedule="fused")["u_cur"]
+        _abi.rtm_set_option(_abi.RTM_OPT_WHOLE_VARIANT, 4)
         for zc in (1, 7, 1000):
             _abi.rtm_set_option(_abi.RTM_OPT_ZCHUNK, zc)
             runs[f"zchunk{zc}"] = problems.gpu_forward_problem(v, h, nsteps, src)["u_cur"]
@@ -91,6 +95,7 @@ def test_schedules_and_variants_bitwise(torch_cuda):
     finally:
         _abi.rtm_set_option(_abi.RTM_OPT_INTERIOR_VARIANT, default_variant)
         _abi.rtm_set_option(_abi.RTM_OPT_HALO_VARIANT, 0)
+        _abi.rtm_set_option(_abi.RTM_OPT_WHOLE_VARIANT, 4)
         _abi.rtm_set_option(_abi.RTM_OPT_ZCHUNK, 0)
         _abi.rtm_set_option(_abi.RTM_OPT_XCD_REMAP, 1)
     assert np.any(base != 0)

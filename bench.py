@@ -4,8 +4,8 @@ Workload: 512^3 cells, h = 10 m, seeded layered medium (20 layers, 1500-4500 m/s
 with sigma = 3 cells, seed 2), radius-4 star stencil with leapfrog, dt at half the stability limit,
 15 Hz Ricker point source at the centre, 16-cell sponge, and the halo-first step schedule with all
 six 4-wide faces packed and unpacked on the device (one subdomain's share; zero-receive exchange).
-A step is one pass of the whole per-step sequence: halo stencil, source injection, pack, exchange,
-unpack, interior stencil, receiver recording.
+A step is one pass of the whole per-step sequence: halo stencil, interior stencil, source injection,
+pack, exchange, unpack, receiver recording.
 
 Prints one JSON line: G point-updates/s over the timed steps, the interior kernel's achieved HBM
 bandwidth against the 8 TB/s peak (algorithmic bytes / HIP-event kernel time), and the FP64 CPU
@@ -216,6 +216,7 @@ def time_phases(g, prop, traces, reps: int = 20):
     phases = {
         "halo": lambda: _abi.rtm_step_halo(c, u_nxt, u_cur, u_prv, prop.kappa, st),
         "pack": lambda: _abi.rtm_pack_halo(c, u_nxt, prop.send, st),
+        "halo_pack": lambda: _abi.rtm_step_halo_pack(c, u_nxt, u_cur, u_prv, prop.kappa, prop.send, st),
         "unpack": lambda: _abi.rtm_unpack_halo(c, u_nxt, prop.recv, st),
         "interior": lambda: _abi.rtm_step_interior(c, u_nxt, u_cur, u_prv, prop.kappa, st),
         "record": lambda: _abi.rtm_record(c, u_nxt, prop.rec_idx, traces, prop.nrec, st),

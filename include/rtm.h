@@ -158,6 +158,24 @@ int rtm_step_whole(const rtm_grid *grid, float *u_nxt, const float *u_cur, const
  * hold fewer than 2^31 elements (RTM_EINVAL otherwise); the same limit applies to unpack. */
 int rtm_pack_halo(const rtm_grid *grid, const float *u, float *faces, hipStream_t stream);
 
+/* Phases 1 and 2 in one launch (section II): rtm_step_halo and then rtm_pack_halo of u_nxt into
+ * `faces`, bitwise the same fields and face buffer; the halo call's workgroups write each face cell
+ * they compute straight into its slot, so the faces are not read back from u_nxt.  Radius 4 with the
+ * vectorised layout, nx % 4 == 0 and a 16-byte aligned `faces`; otherwise the two calls run one
+ * after the other.  Sources injected afterwards into face cells must be re-copied with
+ * rtm_pack_cells.  For schedules that need the faces before the interior call (an exchange that
+ * overlaps it); with nothing to overlap, packing after the interior call is cheaper on the whole.
+ * Same status codes as the two calls; `faces` must not overlap any field. */
+int rtm_step_halo_pack(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv,
+                       const float *kappa, float *faces, hipStream_t stream);
+
+/* For each of the n padded indices idx (int64, device) of owned cells, copy u[idx] into every face
+ * slot that holds that cell (as rtm_pack_halo would); indices of cells outside every face, or not
+ * owned, are skipped.  Used after injecting sources into face cells of a level packed by
+ * rtm_step_halo_pack.  n >= 0; `faces` must not overlap u. */
+int rtm_pack_cells(const rtm_grid *grid, const float *u, const int64_t *idx, int32_t n, float *faces,
+                   hipStream_t stream);
+
 /* Phase 6 (section II): write slot f of the received faces into the R-wide ghost layer of u on face
  * f (face f of u receives what the neighbour across face f packed from its opposite face).
  * faces[f] is a device pointer to that slot's data (slot size as in rtm_face_layout), or NULL for a

@@ -58,6 +58,8 @@ def _load():
         "rtm_step_interior": ([gp, vp, vp, vp, vp, vp], ctypes.c_int),
         "rtm_step_whole": ([gp, vp, vp, vp, vp, vp], ctypes.c_int),
         "rtm_pack_halo": ([gp, vp, vp, vp], ctypes.c_int),
+        "rtm_step_halo_pack": ([gp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "rtm_pack_cells": ([gp, vp, vp, i32, vp, vp], ctypes.c_int),
         "rtm_unpack_halo": ([gp, vp, ctypes.POINTER(vp), vp], ctypes.c_int),
         "rtm_inject": ([gp, vp, vp, vp, vp, i32, vp], ctypes.c_int),
         "rtm_record": ([gp, vp, vp, vp, i32, vp], ctypes.c_int),
@@ -197,6 +199,16 @@ def rtm_step_whole(grid, u_nxt, u_cur, u_prv, kappa, stream=None):
 
 def rtm_pack_halo(grid, u, faces, stream=None):
     _check(_lib.rtm_pack_halo(ctypes.byref(grid), _p(u), _p(faces), _s(stream)), "rtm_pack_halo")
+
+
+def rtm_step_halo_pack(grid, u_nxt, u_cur, u_prv, kappa, faces, stream=None):
+    _check(_lib.rtm_step_halo_pack(ctypes.byref(grid), _p(u_nxt), _p(u_cur), _p(u_prv), _p(kappa), _p(faces),
+                                   _s(stream)), "rtm_step_halo_pack")
+
+
+def rtm_pack_cells(grid, u, idx, n, faces, stream=None):
+    _check(_lib.rtm_pack_cells(ctypes.byref(grid), _p(u), _p(idx), int(n), _p(faces), _s(stream)),
+           "rtm_pack_cells")
 
 
 def rtm_unpack_halo(grid, u, faces, stream=None):

@@ -170,9 +170,17 @@ struct BoxList {
     int remap;
 };
 
-template <int R, int BX, int BY, int OP>
+// Where a halo launch with PACK also writes the face cells it computes: the face buffer and the six
+// slot offsets of rtm_face_layout.
+struct PackOut {
+    float *faces;
+    long long off[6];
+};
+
+template <int R, int BX, int BY, int OP, bool PACK = false>
 __global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(BX * BY >= 512 ? 4 : 1)))
-void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, const float *kap, BoxList bl)
+void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, const float *kap, BoxList bl,
+             PackOut po)
 {
     constexpr int NT = BX * BY;
     constexpr int TX = 4 * BX;
@@ -355,7 +363,19 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
             }
             float *dst = un + pc + dz;
             if (full) {
-                st4(dst, make_float4(out[0], out[1], out[2], out[3]));
+                const float4 o4 = make_float4(out[0], out[1], out[2], out[3]);
+                st4(dst, o4);
+                if constexpr (PACK) {
+                    // the float4 is one row of a face's R-thick layer (R = 4, nx % 4 == 0): copy it into
+                    // each face slot that holds it, in the slot order of rtm_pack_halo
+                    const long long nx = g.nx, ny = g.ny;
+                    if (x < R) st4(po.faces + po.off[0] + ((long long)k * ny + y) * R, o4);
+                    if (x >= g.nx - R) st4(po.faces + po.off[1] + ((long long)k * ny + y) * R, o4);
+                    if (y < R) st4(po.faces + po.off[2] + ((long long)k * R + y) * nx + x, o4);
+                    if (y >= g.ny - R) st4(po.faces + po.off[3] + ((long long)k * R + (y - (g.ny - R))) * nx + x, o4);
+                    if (k < R) st4(po.faces + po.off[4] + ((long long)k * ny + y) * nx + x, o4);
+                    if (k >= g.nz - R) st4(po.faces + po.off[5] + ((long long)(k - (g.nz - R)) * ny + y) * nx + x, o4);
+                }
             } else {
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
@@ -451,6 +471,32 @@ __global__ __launch_bounds__(kThreads) void k_pack4(Geo g, const float *__restri
     const int j = s.oy + (int)(row % (unsigned)s.wy);
     const int k = s.oz + (int)(row / (unsigned)s.wy);
     st4(faces + fo.off[f] + 4 * t, ld4(u + pidx(g, i, j, k)));
+}
+
+// faces[slot position of cell p] = u[p] for each owned cell p of the list in each face slot that holds
+// it (a cell within R of two or three faces is in two or three slots); other indices are skipped.
+__global__ __launch_bounds__(kThreads) void k_pack_cells(Geo g, const float *__restrict__ u,
+                                                         const long long *__restrict__ idx, int n,
+                                                         float *__restrict__ faces, FaceOffsets fo)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    const long long p = idx[m];
+    const int R = g.R;
+    const long long kk = p / g.pz, rem = p - kk * g.pz;
+    const long long jj = rem / g.py, ii = rem - jj * g.py;
+    if (p < 0 || kk < R || kk >= (long long)g.nz + R || jj < R || jj >= (long long)g.ny + R || ii < R ||
+        ii >= (long long)g.nx + R)
+        return;
+    const int i = (int)ii - R, j = (int)jj - R, k = (int)kk - R;
+    const float v = u[p];
+    const long long nx = g.nx, ny = g.ny;
+    if (i < R) faces[fo.off[0] + ((long long)k * ny + j) * R + i] = v;
+    if (i >= g.nx - R) faces[fo.off[1] + ((long long)k * ny + j) * R + (i - (g.nx - R))] = v;
+    if (j < R) faces[fo.off[2] + ((long long)k * R + j) * nx + i] = v;
+    if (j >= g.ny - R) faces[fo.off[3] + ((long long)k * R + (j - (g.ny - R))) * nx + i] = v;
+    if (k < R) faces[fo.off[4] + ((long long)k * ny + j) * nx + i] = v;
+    if (k >= g.nz - R) faces[fo.off[5] + ((long long)(k - (g.nz - R)) * ny + j) * nx + i] = v;
 }
 
 __global__ __launch_bounds__(kThreads) void k_unpack4(Geo g, float *__restrict__ u, FacePtrs src)
@@ -791,9 +837,9 @@ int balanced_zchunk(int tiles, int wz, int R, int cus)
 }
 
 // Launch the tiled kernel over up to kMaxBoxes boxes {x0, x1, y0, y1, z0, z1} (empty ones skipped).
-template <int R, int BX, int BY, int OP>
+template <int R, int BX, int BY, int OP, bool PACK = false>
 int launch_tiled(const Geo &g, float *un, const float *uc, const float *up, const float *kap, const int (*boxes)[6],
-                 int nbox, hipStream_t st)
+                 int nbox, hipStream_t st, const PackOut *po = nullptr)
 {
     constexpr int TX = 4 * BX;
     BoxList bl;
@@ -834,7 +880,7 @@ int launch_tiled(const Geo &g, float *un, const float *uc, const float *up, cons
         int occ = resident.load(std::memory_order_relaxed);
         if (occ == 0) {
             int per_cu = 0, cus = 0, dev = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tiled<R, BX, BY, OP>, BX * BY, 0) !=
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tiled<R, BX, BY, OP, PACK>, BX * BY, 0) !=
                 hipSuccess)
                 per_cu = 2;
             if (hipGetDevice(&dev) != hipSuccess ||
@@ -859,20 +905,24 @@ int launch_tiled(const Geo &g, float *un, const float *uc, const float *up, cons
     if (nb >= (1ll << 31)) return RTM_EINVAL;
     bl.nblk = (int)nb;
     bl.remap = g_opt.xcd_remap.load(std::memory_order_relaxed);
-    hipLaunchKernelGGL((k_tiled<R, BX, BY, OP>), dim3((unsigned)nb), dim3(BX * BY), 0, st, g, un, uc, up, kap, bl);
+    PackOut pk;
+    std::memset(&pk, 0, sizeof(pk));
+    if (po) pk = *po;
+    hipLaunchKernelGGL((k_tiled<R, BX, BY, OP, PACK>), dim3((unsigned)nb), dim3(BX * BY), 0, st, g, un, uc, up, kap,
+                       bl, pk);
     return launch_status();
 }
 
-template <int R, int OP>
+template <int R, int OP, bool PACK = false>
 int launch_tiled_variant(int var, const Geo &g, float *un, const float *uc, const float *up, const float *kap,
-                         const int (*boxes)[6], int nbox, hipStream_t st)
+                         const int (*boxes)[6], int nbox, hipStream_t st, const PackOut *po = nullptr)
 {
     switch (var) {
-    case 1: return launch_tiled<R, 32, 8, OP>(g, un, uc, up, kap, boxes, nbox, st);
-    case 2: return launch_tiled<R, 16, 8, OP>(g, un, uc, up, kap, boxes, nbox, st);
-    case 4: return launch_tiled<R, 32, 16, OP>(g, un, uc, up, kap, boxes, nbox, st);
-    case 5: return launch_tiled<R, 16, 32, OP>(g, un, uc, up, kap, boxes, nbox, st);
-    default: return launch_tiled<R, 16, 16, OP>(g, un, uc, up, kap, boxes, nbox, st);
+    case 1: return launch_tiled<R, 32, 8, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po);
+    case 2: return launch_tiled<R, 16, 8, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po);
+    case 4: return launch_tiled<R, 32, 16, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po);
+    case 5: return launch_tiled<R, 16, 32, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po);
+    default: return launch_tiled<R, 16, 16, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po);
     }
 }
 
@@ -938,6 +988,17 @@ int launch_halo(const Geo &g, float *un, const float *uc, const float *up, const
         if (rc != RTM_OK) return rc;
     }
     return RTM_OK;
+}
+
+// The halo call that also writes the six faces (radius 4, float4 layout; see rtm_step_halo_pack).
+int launch_halo_pack(const Geo &g, float *un, const float *uc, const float *up, const float *kap, const PackOut &po,
+                     hipStream_t st)
+{
+    const Region r = halo_region(g.nx, g.ny, 4);
+    int boxes[6][6];
+    const int nb = halo_boxes(g, r, boxes);
+    return launch_tiled_variant<4, OP_FORWARD, true>(g_opt.halo_variant.load(std::memory_order_relaxed), g, un, uc,
+                                                     up, kap, boxes, nb, st, &po);
 }
 
 template <int R, int OP = OP_FORWARD>
@@ -1161,6 +1222,50 @@ int rtm_pack_halo(const rtm_grid *grid, const float *u, float *faces, hipStream_
     } else {
         hipLaunchKernelGGL(k_pack, dim3(blocks_for(mx), 6), dim3(kThreads), 0, stream, g, u, faces, fo);
     }
+    return launch_status();
+}
+
+int rtm_step_halo_pack(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv,
+                       const float *kappa, float *faces, hipStream_t stream)
+{
+    int st = step_common(grid, u_nxt, u_cur, u_prv, kappa);
+    if (st != RTM_OK) return st;
+    if (!faces) return RTM_EINVAL;
+    long long off[7];
+    fill_face_offsets(grid, off);
+    for (int f = 0; f < 6; ++f)
+        if (off[f + 1] - off[f] >= (1ll << 31)) return RTM_EINVAL;
+    const long long tot = padded_total(grid);
+    if (ranges_overlap(faces, off[6], u_nxt, tot) || ranges_overlap(faces, off[6], u_cur, tot) ||
+        ranges_overlap(faces, off[6], u_prv, tot) || ranges_overlap(faces, off[6], kappa, tot))
+        return RTM_EALIAS;
+    const Geo g = make_geo(grid);
+    if (g.R == 4 && vector_path(g, u_nxt, u_cur, u_prv, kappa) && faces_vec(g, u_nxt) && aligned16(faces)) {
+        PackOut po;
+        po.faces = faces;
+        for (int f = 0; f < 6; ++f) po.off[f] = off[f];
+        return launch_halo_pack(g, u_nxt, u_cur, u_prv, kappa, po, stream);
+    }
+    st = rtm_step_halo(grid, u_nxt, u_cur, u_prv, kappa, stream);
+    if (st != RTM_OK) return st;
+    return rtm_pack_halo(grid, u_nxt, faces, stream);
+}
+
+int rtm_pack_cells(const rtm_grid *grid, const float *u, const int64_t *idx, int32_t n, float *faces,
+                   hipStream_t stream)
+{
+    int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (n < 0 || (n > 0 && (!u || !idx || !faces))) return RTM_EINVAL;
+    if (n == 0) return RTM_OK;
+    FaceOffsets fo;
+    fill_face_offsets(grid, fo.off);
+    if (ranges_overlap(faces, fo.off[6], u, padded_total(grid))) return RTM_EALIAS;
+    st = check_device();
+    if (st != RTM_OK) return st;
+    const Geo g = make_geo(grid);
+    hipLaunchKernelGGL(k_pack_cells, dim3(blocks_for(n)), dim3(kThreads), 0, stream, g, u,
+                       reinterpret_cast<const long long *>(idx), (int)n, faces, fo);
     return launch_status();
 }
 

@@ -3,8 +3,9 @@
 One step n (u^{n+1} from u^n and u^{n-1}) runs, in the default "overlap" schedule, on two HIP
 streams like the paper's halo-first schedule with a communication thread:
 
-    halo stream H:      wait(interior n-1) -> rtm_step_halo -> inject shell sources -> [halo done]
-                        -> rtm_pack_halo -> exchange -> rtm_unpack_halo
+    halo stream H:      wait(interior n-1) -> rtm_step_halo_pack (the halo update, which also writes
+                        the faces) -> inject shell sources and re-copy those in faces -> [halo done]
+                        -> exchange -> rtm_unpack_halo
     interior stream I:  rtm_step_interior -> inject interior sources -> wait(halo done)
                         -> rtm_record -> [level n+1 complete]
 
@@ -14,7 +15,9 @@ a pointer swap with no copy).  Time levels rotate by pointer: by default u^{n+1}
 u^{n-1} in place (two buffers), and a level that must outlive the rotation (an RTM snapshot) is
 "pinned" so that the next write goes to a fresh buffer instead of copying it.
 
-The "serial" schedule runs the same calls on one stream; both give bitwise identical fields.  The
+The "serial" schedule runs the same phases on one stream (halo, interior, injection, pack, unpack,
+record: on one GPU nothing needs the faces before the interior call); both give bitwise identical
+fields.  The
 "fused" schedule, for one subdomain with nothing to overlap, updates every owned cell in one launch
 (rtm_step_whole) instead of the halo and interior calls, then injects, refreshes the ghosts and
 records on one stream; it too is bitwise identical.  With no face received (the physical boundary),
@@ -53,6 +56,12 @@ class Sources:
             amp_t = torch.flip(amp_t, dims=[0])
         self.nsteps = amp_t.shape[0]
         shell = grid.in_halo(ijk)
+        # halo-region cells within R of a face: packed by the halo call before their injection, so
+        # re-copied into the face buffer after it (rtm_pack_cells)
+        R = grid.radius
+        face = shell & ((ijk[:, 0] < R) | (ijk[:, 0] >= grid.nx - R) | (ijk[:, 1] < R) | (ijk[:, 1] >= grid.ny - R)
+                        | (ijk[:, 2] < R) | (ijk[:, 2] >= grid.nz - R))
+        self.face_idx = torch.from_numpy(grid.index(ijk[face])).to(grid.device) if face.any() else None
         self.sets = []
         for mask in (shell, ~shell):
             sel = np.nonzero(mask)[0]
@@ -71,6 +80,12 @@ class Sources:
         idx, w, a = s
         cnt = idx.numel()
         _abi.rtm_inject(grid.c, u, idx, w, a.data_ptr() + 4 * n * cnt, cnt, stream)
+
+    def repack(self, grid: Grid, u: torch.Tensor, n: int, faces: torch.Tensor, stream):
+        """After the halo-region injection of row n: copy the injected face cells into `faces`."""
+        if self.face_idx is None or n >= self.nsteps:
+            return
+        _abi.rtm_pack_cells(grid.c, u, self.face_idx, self.face_idx.numel(), faces, stream)
 
 
 class Propagator:
@@ -208,6 +223,9 @@ class Propagator:
             if tr_ptr is not None:
                 _abi.rtm_record(c, u_nxt, self.rec_idx, tr_ptr, self.nrec, st)
         elif self.schedule == "serial":
+            # one stream: the interior call right after the halo call, whose reads it shares through
+            # the caches, and the pack after the injections (packing before the interior call, alone
+            # or inside the halo call, made the interior call 16-20 us slower at 512^3)
             st = torch.cuda.current_stream()
             _abi.rtm_step_halo(c, u_nxt, u_cur, u_prv, kap, st)
             if self.interior_events is not None:
@@ -232,12 +250,12 @@ class Propagator:
             else:
                 sH.wait_stream(torch.cuda.current_stream())
                 sI.wait_stream(torch.cuda.current_stream())
-            _abi.rtm_step_halo(c, u_nxt, u_cur, u_prv, kap, sH)
+            _abi.rtm_step_halo_pack(c, u_nxt, u_cur, u_prv, kap, self.send, sH)
             for s in self.sources:
                 s.inject(g, u_nxt, n, 0, sH)
+                s.repack(g, u_nxt, n, self.send, sH)
             ev_halo = torch.cuda.Event()
             ev_halo.record(sH)
-            _abi.rtm_pack_halo(c, u_nxt, self.send, sH)
             _abi.rtm_unpack_halo(c, u_nxt, self.recv, sH)
             if self.interior_events is not None:
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -215,6 +215,82 @@ def test_periodic_standing_wave(torch_cuda):
     assert problems.rel_l2(u, ref["u_cur"]) < 1e-4
 
 
+@pytest.mark.parametrize("radius,shape,x_align", [(4, (48, 40, 36), 32), (4, (68, 36, 20), 32),
+                                                    (4, (50, 40, 36), 32), (4, (48, 40, 36), 1),
+                                                    (2, (48, 24, 20), 32)])
+def test_halo_pack_equals_halo_then_pack(torch_cuda, radius, shape, x_align):
+    """rtm_step_halo_pack gives the fields and the face buffer of rtm_step_halo then rtm_pack_halo,
+    bitwise, for every halo tile shape (the fused path: radius 4, vectorised layout, nx % 4 == 0; the
+    other cases take the two calls); after injecting into face, edge and corner cells, rtm_pack_cells
+    brings the fused face buffer to what a fresh pack gives."""
+    torch = torch_cuda
+    from paper_1603_03971_amd import _abi
+    from paper_1603_03971_amd.grid import Grid
+
+    nx, ny, nz = shape
+    g = Grid(nx, ny, nz, 10.0, Grid.stable_dt(radius, 10.0, 3000.0), radius=radius, sponge_width=3,
+             x_align=x_align)
+    rng = np.random.default_rng(2100 + nx + radius)
+    u, up = g.upload(rng.standard_normal(g.shape)), g.upload(rng.standard_normal(g.shape))
+    kap = g.upload(rng.uniform(0.01, 0.05, g.shape))
+    st = torch.cuda.current_stream()
+    R = radius
+    cells = np.array([[0, 5, 7], [nx - 1, ny - 1, nz - 1], [2, 0, nz // 2], [nx // 2, ny - 2, 1],
+                      [nx // 2, ny // 2, nz - 3], [R, R, R], [nx // 2, ny // 2, nz // 2]])
+    idx = torch.from_numpy(g.index(cells)).cuda()
+    w = torch.full((len(cells),), 0.75, dtype=torch.float32, device="cuda")
+    amp = torch.linspace(1.0, 2.0, len(cells), dtype=torch.float32, device="cuda")
+    default = _abi.rtm_get_option(_abi.RTM_OPT_HALO_VARIANT)
+    try:
+        for var in (0, 1, 2, 4, 5):
+            _abi.rtm_set_option(_abi.RTM_OPT_HALO_VARIANT, var)
+            out_a, out_b = g.field(), g.field()
+            fa, fb = g.faces(), g.faces()
+            _abi.rtm_step_halo(g.c, out_a, u, up, kap, st)
+            _abi.rtm_pack_halo(g.c, out_a, fa, st)
+            _abi.rtm_step_halo_pack(g.c, out_b, u, up, kap, fb, st)
+            torch.cuda.synchronize()
+            assert torch.equal(out_a, out_b), var
+            assert torch.equal(fa, fb), var
+            assert fa.abs().max() > 0
+            for out, f, fused in ((out_a, fa, False), (out_b, fb, True)):
+                _abi.rtm_inject(g.c, out, idx, w, amp, len(cells), st)
+                if fused:
+                    _abi.rtm_pack_cells(g.c, out, idx, len(cells), f, st)
+                else:
+                    _abi.rtm_pack_halo(g.c, out, f, st)
+            torch.cuda.synchronize()
+            assert torch.equal(fa, fb), var
+    finally:
+        _abi.rtm_set_option(_abi.RTM_OPT_HALO_VARIANT, default)
+
+
+def test_periodic_face_sources_schedules_bitwise(torch_cuda):
+    """Periodic self-exchange, where the packed faces become the ghosts, with sources in face, edge
+    and corner cells: the halo-first schedules (faces packed by the halo call, injected face cells
+    re-copied) equal the one-launch schedule (faces packed after the injection), bitwise."""
+    torch = torch_cuda
+    from paper_1603_03971_amd.grid import Grid
+    from paper_1603_03971_amd.propagator import Propagator, Sources
+
+    nx, ny, nz = 48, 36, 32
+    g = Grid(nx, ny, nz, 10.0, Grid.stable_dt(4, 10.0, 3000.0), sponge_width=0)
+    kap = g.kappa_from_velocity(np.random.default_rng(2200).uniform(2000.0, 3000.0, g.shape))
+    cells = [(0, 10, 10), (nx - 1, 0, nz - 1), (20, 1, 15), (30, ny - 3, 2), (24, 18, 16)]
+    nsteps = 40
+    w = g.injection_weights([2500.0] * len(cells))
+    amp = np.random.default_rng(2201).standard_normal((nsteps, len(cells))).astype(np.float32)
+    out = {}
+    for schedule in ("serial", "overlap", "fused"):
+        prop = Propagator(g, kap, sources=Sources(g, cells, w, amp), boundary="periodic", schedule=schedule)
+        prop.run(nsteps)
+        torch.cuda.synchronize()
+        out[schedule] = g.download(prop.u_cur)
+    assert np.abs(out["fused"]).max() > 0
+    for schedule in ("serial", "overlap"):
+        assert np.array_equal(out[schedule], out["fused"]), schedule
+
+
 def test_inject_and_record_exact(torch_cuda):
     torch = torch_cuda
     from paper_1603_03971_amd import _abi

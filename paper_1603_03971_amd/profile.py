@@ -106,8 +106,9 @@ def run_corrected(n: int, steps: int, every: int):
 
 # The radius-4 tiled kernels under the default options: the interior call's (16 x 8-thread tiles),
 # the halo call's (16 x 16) and the one-launch whole step's (32 x 16).
-INTERIOR_KERNEL = "k_tiled<4, 16, 8, 0>"
-HALO_KERNEL = "k_tiled<4, 16, 16, 0>"
+# (name prefixes: the demangled names go on with the kernel's last template argument, e.g. ", false>")
+INTERIOR_KERNEL = "k_tiled<4, 16, 8, 0"
+HALO_KERNEL = "k_tiled<4, 16, 16, 0"
 TILED_R4 = "k_tiled<4, "
 
 

@@ -1228,7 +1228,8 @@ int rtm_pack_halo(const rtm_grid *grid, const float *u, float *faces, hipStream_
 int rtm_step_halo_pack(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv,
                        const float *kappa, float *faces, hipStream_t stream)
 {
-    int st = step_common(grid, u_nxt, u_cur, u_prv, kappa);
+    // the face buffer's own checks first: every argument error is reported before the device check
+    int st = check_grid(grid);
     if (st != RTM_OK) return st;
     if (!faces) return RTM_EINVAL;
     long long off[7];
@@ -1239,6 +1240,8 @@ int rtm_step_halo_pack(const rtm_grid *grid, float *u_nxt, const float *u_cur, c
     if (ranges_overlap(faces, off[6], u_nxt, tot) || ranges_overlap(faces, off[6], u_cur, tot) ||
         ranges_overlap(faces, off[6], u_prv, tot) || ranges_overlap(faces, off[6], kappa, tot))
         return RTM_EALIAS;
+    st = step_common(grid, u_nxt, u_cur, u_prv, kappa);
+    if (st != RTM_OK) return st;
     const Geo g = make_geo(grid);
     if (g.R == 4 && vector_path(g, u_nxt, u_cur, u_prv, kappa) && faces_vec(g, u_nxt) && aligned16(faces)) {
         PackOut po;

@@ -77,6 +77,13 @@ def test_validation_before_device(abi):
     assert L.rtm_step_interior(gp, 4096, 4096 + 8, 4096 * 1000, 4096 * 2000, None) == abi.RTM_EALIAS
     assert L.rtm_pack_halo(gp, None, 4096, None) == abi.RTM_EINVAL
     assert L.rtm_pack_halo(gp, 4096, 4096 + 4 * total - 64, None) == abi.RTM_EALIAS
+    assert L.rtm_step_halo_pack(gp, 4096, 1 << 36, 1 << 37, 1 << 38, None, None) == abi.RTM_EINVAL
+    assert L.rtm_step_halo_pack(gp, 4096, 1 << 36, 1 << 37, 1 << 38, 4096 + 4 * total - 64, None) == abi.RTM_EALIAS
+    assert L.rtm_step_halo_pack(gp, None, 1 << 36, 1 << 37, 1 << 38, 1 << 39, None) == abi.RTM_EINVAL
+    assert L.rtm_pack_cells(gp, 4096, 64, -1, 1 << 39, None) == abi.RTM_EINVAL
+    assert L.rtm_pack_cells(gp, 4096, 64, 0, 1 << 39, None) == abi.RTM_OK             # nothing to do
+    assert L.rtm_pack_cells(gp, 4096, 64, 3, None, None) == abi.RTM_EINVAL
+    assert L.rtm_pack_cells(gp, 4096, 64, 3, 4096 + 16, None) == abi.RTM_EALIAS
     assert L.rtm_inject(gp, 4096, 64, 64, 64, -1, None) == abi.RTM_EINVAL
     assert L.rtm_inject(gp, 4096, 64, 64, 64, 0, None) == abi.RTM_OK                # nothing to do
     assert L.rtm_record(gp, 4096, 64, 64, -5, None) == abi.RTM_EINVAL

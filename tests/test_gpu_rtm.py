@@ -144,3 +144,38 @@ def test_nan_poison_debug_mode():
     assert np.abs(ref).max() > 0
     for key, tr in out.items():
         assert np.array_equal(tr, ref), key
+
+
+def test_fused_schedule_refreshes_ghosts_of_handed_in_levels():
+    """The one-launch schedule writes a level buffer's zero ghost ring once and then trusts it; a
+    u^{n-1} handed in through set_levels with NaN in its ghost ring becomes the next level, so its
+    ghosts must be written again: the run matches one from clean buffers bitwise (owned cells)."""
+    import torch
+
+    from paper_1603_03971_amd.grid import Grid
+    from paper_1603_03971_amd.propagator import Propagator, Sources
+
+    v_true, v_bg, src, rec = small_rtm_inputs()
+    nz, ny, nx = v_bg.shape
+    g = Grid(nx, ny, nz, 10.0, Grid.stable_dt(4, 10.0, float(v_true.max())), sponge_width=8)
+    kap = g.kappa_from_velocity(v_true)
+    src = np.asarray(src)
+    w = g.injection_weights(v_true[src[:, 2], src[:, 1], src[:, 0]])
+    nsteps = 60
+    amp = np.repeat(g.ricker(nsteps, 20.0)[:, None], len(w), axis=1)
+    finals = []
+    for poison in (False, True):
+        prop = Propagator(g, kap, sources=Sources(g, src, w, amp), receivers=rec, schedule="fused")
+        tr = prop.new_traces(nsteps)
+        prop.run(30, tr)
+        torch.cuda.synchronize()
+        cur, prv = g.field(), g.field(fill=float("nan") if poison else 0.0)
+        cur.copy_(prop.u_cur)                      # ghosts current (zero), as set_levels requires
+        g.owned(prv).copy_(g.owned(prop.u_prv))    # owned cells only: the ghost ring stays NaN
+        prop.set_levels(cur, prv, prop.n)
+        prop.run(nsteps - 30, tr)
+        torch.cuda.synchronize()
+        finals.append((g.download(prop.u_cur), tr.cpu().numpy()))
+    assert np.isfinite(finals[1][0]).all()
+    assert np.array_equal(finals[0][0], finals[1][0])
+    assert np.array_equal(finals[0][1], finals[1][1])

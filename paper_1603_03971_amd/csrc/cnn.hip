@@ -3,10 +3,10 @@
 //
 // Activations are channel-last BF16 volumes with 16 channels and a one-voxel zero halo: element
 // (c, i, j, k) of an nx*ny*nz volume lives at (((k+1)(ny+2) + (j+1))(nx+2) + (i+1)) * 16 + c.  A
-// 3x3x3 convolution with 16 input and 16 output channels is an implicit GEMM: for a block of 16
-// voxels along x, D[voxel][co] = sum over the 27 taps of A_t[voxel][ci] B_t[ci][co], one
-// 16x16x16 MFMA per tap, with A_t read straight from the activation volume (the tap's shifted
-// voxels, four consecutive channels per lane) and B_t the tap's weights kept in registers.
+// 3x3x3 convolution with 16 input and 16 output channels is an implicit GEMM over blocks of 16
+// voxels along x: the forward kernel sums two taps per 16x16x32 MFMA with the weights in registers
+// and the shifted voxels from a staged input plane (k_conv3d); the weight gradient uses one
+// 16x16x16 MFMA per tap with the voxels as the reduction dimension (k_conv3d_wgrad).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -4,7 +4,7 @@
 // stencil, unpack); the scheme is the radius-R star stencil with second-order leapfrog and a
 // Cerjan sponge:  u^{n+1} = g (2 u^n - g u^{n-1} + kappa L u^n).
 //
-// Every stencil kernel evaluates the same per-point expression (point_update) on the same operands
+// Every stencil kernel evaluates the same per-point expression (point_op) on the same operands
 // in the same order, with explicit FMAs and FP contraction disabled at compile time, so any split of
 // a step between the halo and interior calls produces bitwise identical wavefields.
 #include <hip/hip_runtime.h>
@@ -13,7 +13,6 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
-#include <mutex>
 #include <type_traits>
 #include <utility>
 
@@ -1013,7 +1012,7 @@ int launch_interior(const Geo &g, float *un, const float *uc, const float *up, c
     return launch_box_scalar<R, OP>(g, un, uc, up, kap, boxes[0], st);
 }
 
-// Every owned cell in one launch: a single box of the tiled kernel (the interior variant) over the
+// Every owned cell in one launch: a single box of the tiled kernel (its own tile option) over the
 // whole owned block; like the halo call it reads the ghost ring.
 template <int R, int OP = OP_FORWARD>
 int launch_all(const Geo &g, float *un, const float *uc, const float *up, const float *kap, hipStream_t st)

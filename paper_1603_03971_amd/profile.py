@@ -24,6 +24,12 @@
       reads rocprofv3 CSV output (kernel stats of a benchmark run, counter collections of the two
       runs above) and writes a short text summary plus the traffic record that bench.py reports
       (keyed by a hash of the kernel source, so stale counters are never reported).
+
+  python3 -m paper_1603_03971_amd.profile summarize-conv --stats DIR --out FILE [--n 384]
+  python3 -m paper_1603_03971_amd.profile summarize-corrected --stats DIR --out FILE [--n 384 ...]
+      the same for kernel traces of the `conv` and `corrected` runs (per-launch rates; per-step and
+      per-correction costs).
+  Every summarize mode takes --command (repeatable): the commands recorded in the summary.
 """
 from __future__ import annotations
 

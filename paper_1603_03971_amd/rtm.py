@@ -8,6 +8,9 @@ same update in reverse time, injecting the time-reversed residual traces at the 
 forward level k = N - m.  Image: the zero-lag cross-correlation I = sum_{k in T} u^k r^{N+1-k}
 (Claerbout 1971), accumulated in FP32 by rtm_image_accumulate.
 
+The helpers default to the propagator's one-launch schedule (one GPU, nothing to overlap); every
+schedule gives the same bits.
+
 Source and receiver weights are the point-source weights (v dt)^2 / h^3 at their cells.  The
 residual d_true - d_bg is injected as two injections (+w d_true, -w d_bg), so no trace arithmetic
 happens outside the library's kernels.
@@ -28,7 +31,7 @@ def _cells_velocity(v, ijk):
 
 
 def model_shot(grid: Grid, kappa: torch.Tensor, v_at_src, src_ijk, wavelet, rec_ijk, nsteps: int,
-               schedule: str = "overlap") -> torch.Tensor:
+               schedule: str = "fused") -> torch.Tensor:
     """Forward modelling of one shot: traces (nsteps, nrec) on the device."""
     w = grid.injection_weights(v_at_src)
     amp = np.repeat(np.asarray(wavelet, dtype=np.float32)[:nsteps, None], len(w), axis=1)
@@ -42,7 +45,7 @@ class ShotImager:
     """Forward pass with kept snapshots and backward pass with imaging, for one shot."""
 
     def __init__(self, grid: Grid, kappa_bg: torch.Tensor, v_bg, src_ijk, wavelet, rec_ijk, nsteps: int,
-                 image_every: int = 4, schedule: str = "overlap", snapshots=None, corrector=None):
+                 image_every: int = 4, schedule: str = "fused", snapshots=None, corrector=None):
         self.g = grid
         self.kappa = kappa_bg
         self.v_bg = v_bg
@@ -103,7 +106,7 @@ class ShotImager:
 
 
 def migrate_shot(grid: Grid, kappa_bg, v_bg, src_ijk, wavelet, rec_ijk, data_true, data_bg, nsteps: int,
-                 image_every: int = 4, schedule: str = "overlap", snapshots=None, corrector=None) -> torch.Tensor:
+                 image_every: int = 4, schedule: str = "fused", snapshots=None, corrector=None) -> torch.Tensor:
     """Zero-lag RTM image (padded device field) of one shot from its recorded traces."""
     imager = ShotImager(grid, kappa_bg, v_bg, src_ijk, wavelet, rec_ijk, nsteps, image_every, schedule, snapshots,
                         corrector)
@@ -112,7 +115,7 @@ def migrate_shot(grid: Grid, kappa_bg, v_bg, src_ijk, wavelet, rec_ijk, data_tru
 
 
 def rtm_shot(grid: Grid, v_true, v_bg, src_ijk, rec_ijk, nsteps: int, fpeak: float = 15.0, image_every: int = 4,
-             schedule: str = "overlap", snapshots=None):
+             schedule: str = "fused", snapshots=None):
     """Synthetic one-shot RTM: model d_true and d_bg, migrate the reflection data with the background.
     Returns (image field, d_true, d_bg)."""
     kap_true = grid.kappa_from_velocity(v_true)

@@ -91,7 +91,9 @@ def test_rtm_serial_schedule_bitwise(reduced_case):
     args, _ = reduced_case
     a = gpu_rtm(*args, schedule="serial")[0]
     b = gpu_rtm(*args, schedule="overlap")[0]
+    c = gpu_rtm(*args, schedule="fused")[0]
     assert np.array_equal(a, b)
+    assert np.array_equal(a, c)
 
 
 def test_rtm_image_linear_in_data(reduced_case):

@@ -36,8 +36,12 @@ class Shot:
 class MisfitProblem:
     """J(v) = 1/2 sum over shots, steps and receivers of (d - d_obs)^2 on one grid."""
 
-    def __init__(self, grid: Grid, nsteps: int, wavelet, shots: list[Shot], checkpoint_every: int = 50):
+    def __init__(self, grid: Grid, nsteps: int, wavelet, shots: list[Shot], checkpoint_every: int = 50,
+                 schedule: str = "fused"):
+        """schedule: the propagator schedule of the forward and recomputation runs (all give the
+        same bits; the one-launch schedule is the fastest on one GPU)."""
         self.g = grid
+        self.schedule = schedule
         self.nsteps = int(nsteps)
         self.wavelet = np.asarray(wavelet, dtype=np.float32)[:nsteps]
         self.shots = shots
@@ -54,7 +58,8 @@ class MisfitProblem:
 
     def model(self, kappa: torch.Tensor, shot: Shot, amp=None) -> torch.Tensor:
         """Traces of one shot (device (nsteps, nrec)); amp overrides the source series."""
-        prop = Propagator(self.g, kappa, sources=self._sources(shot, amp), receivers=shot.rec_ijk, schedule="serial")
+        prop = Propagator(self.g, kappa, sources=self._sources(shot, amp), receivers=shot.rec_ijk,
+                          schedule=self.schedule)
         tr = prop.new_traces(self.nsteps)
         prop.run(self.nsteps, tr)
         return tr
@@ -62,7 +67,7 @@ class MisfitProblem:
     def forward(self, kappa: torch.Tensor, shot: Shot, misfit: torch.Tensor):
         """Forward run with checkpoints; returns (checkpoints {n: (u^n, u^{n-1})}, residual traces)."""
         g = self.g
-        prop = Propagator(g, kappa, sources=self._sources(shot), receivers=shot.rec_ijk, schedule="serial")
+        prop = Propagator(g, kappa, sources=self._sources(shot), receivers=shot.rec_ijk, schedule=self.schedule)
         tr = prop.new_traces(self.nsteps)
         ckpt = {}
         for n in range(self.nsteps):
@@ -87,7 +92,7 @@ class MisfitProblem:
         ones = torch.ones(len(shot.rec_ijk), dtype=torch.float32, device=g.device)
         src_idx = torch.from_numpy(g.index(shot.src_ijk)).to(g.device)
         mu_a, mu_b = g.field(), g.field()           # mu^{m+1}, mu^{m+2}
-        prop = Propagator(g, kappa, sources=self._sources(shot), schedule="serial")
+        prop = Propagator(g, kappa, sources=self._sources(shot), schedule=self.schedule)
         nseg = (N + C - 1) // C
         for seg in range(nseg - 1, -1, -1):
             n0, n1 = seg * C, min(N, seg * C + C)

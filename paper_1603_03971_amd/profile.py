@@ -20,6 +20,12 @@
       data, then migrates them with FP32, BF16 and FP16 source snapshots (best of --repeats), and
       prints the times, the snapshot memory and each coded image's rel-L2 against the FP32 image.
 
+  python3 -m paper_1603_03971_amd.profile gradient [--n 256] [--shots 8] [--steps 1500] [--every 50]
+      the misfit gradient at full size: true model 20 flat layers (seed 4), start model that smoothed
+      with sigma = 8 cells, shots at seeded positions at depth 20, receivers every 2 cells at depth
+      20; models the observed data, times J and dJ/dv (forward with checkpoints, recomputation,
+      adjoint), and checks <dJ/dv, d> against a central difference of J along a smooth direction d.
+
   python3 -m paper_1603_03971_amd.profile summarize --stats DIR --fetch DIR --write DIR --out FILE
       reads rocprofv3 CSV output (kernel stats of a benchmark run, counter collections of the two
       runs above) and writes a short text summary plus the traffic record that bench.py reports
@@ -176,6 +182,65 @@ def run_shot(nx: int, ny: int, nz: int, steps: int, every: int, repeats: int, sc
         out[f"image_rel_l2_{fmt}_vs_f32"] = float(np.linalg.norm(images[fmt] - ref) / nref)
     out["image_norm"] = nref
     out["image_finite"] = bool(all(np.isfinite(im).all() for im in images.values()))
+    print(json.dumps(out), flush=True)
+
+
+def run_gradient(n: int, nshots: int, steps: int, every: int, eps: float):
+    import time
+
+    import numpy as np
+    import torch
+
+    from . import synth
+    from .adjoint import MisfitProblem, Shot
+    from .grid import Grid
+
+    def say(msg):
+        print(msg, flush=True)
+
+    h = 10.0
+    shape = (n, n, n)
+    v_true = np.ascontiguousarray(synth.layered_velocity(shape, h, seed=4))
+    v0 = synth.smooth(v_true, 8.0)
+    g = Grid(n, n, n, h, Grid.stable_dt(4, h, float(max(v_true.max(), v0.max()))))
+    src = synth.random_positions(nshots, n, n, k=20, seed=4, margin=16)
+    rec = synth.surface_receivers(n, n, k=20, stride=2)
+    wav = g.ricker(steps, 15.0)
+    shots = [Shot([s], g.injection_weights([v0[s[2], s[1], s[0]]]), rec) for s in src]
+    prob = MisfitProblem(g, steps, wav, shots, checkpoint_every=every)
+    kt = g.kappa_from_velocity(v_true)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sh in shots:
+        sh.observed = prob.model(kt, sh)
+    torch.cuda.synchronize()
+    t_obs = time.perf_counter() - t0
+    del kt
+    say(f"observed data: {nshots} shots x {steps} steps x {len(rec)} receivers in {t_obs:.3f} s")
+    v0_d = torch.from_numpy(v0.astype(np.float32)).cuda()
+    prob.misfit_and_gradient(v0_d)                  # warm-up (allocations)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, gv = prob.misfit_and_gradient(v0_d)
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    say(f"J and dJ/dv: {t_grad:.3f} s (J = {J:.6e})")
+    # central difference along a smooth direction of unit maximum (m/s)
+    d = synth.smooth(np.random.default_rng(5).standard_normal(shape), 8.0)
+    d = (d / np.abs(d).max()).astype(np.float32)
+    dd = torch.from_numpy(d).cuda()
+    t0 = time.perf_counter()
+    jp = prob.misfit(v0_d + eps * dd)
+    jm = prob.misfit(v0_d - eps * dd)
+    torch.cuda.synchronize()
+    t_fd = time.perf_counter() - t0
+    fd = (jp - jm) / (2 * eps)
+    ad = float((gv.double() * dd.double()).sum().item())
+    out = {"grid": [n, n, n], "shots": nshots, "steps": steps, "receivers": int(len(rec)), "checkpoint_every": every,
+           "schedule": prob.schedule, "t_observed_s": round(t_obs, 4), "t_misfit_and_gradient_s": round(t_grad, 4),
+           "t_two_misfits_s": round(t_fd, 4), "J": J, "directional_adjoint": ad, "directional_fd": fd,
+           "eps_m_per_s": eps, "rel_diff": abs(ad - fd) / max(abs(fd), 1e-300),
+           "gradient_finite": bool(torch.isfinite(gv).all().item())}
     print(json.dumps(out), flush=True)
 
 
@@ -354,6 +419,12 @@ def main(argv=None):
     sh.add_argument("--every", type=int, default=4)
     sh.add_argument("--repeats", type=int, default=2)
     sh.add_argument("--schedule", default="fused", choices=["overlap", "serial", "fused"])
+    gr = sub.add_parser("gradient")
+    gr.add_argument("--n", type=int, default=256)
+    gr.add_argument("--shots", type=int, default=8)
+    gr.add_argument("--steps", type=int, default=1500)
+    gr.add_argument("--every", type=int, default=50)
+    gr.add_argument("--eps", type=float, default=2.5, help="central-difference step in m/s")
     b = sub.add_parser("summarize")
     b.add_argument("--stats", required=True)
     b.add_argument("--fetch")
@@ -380,6 +451,8 @@ def main(argv=None):
         run_conv(args.n, args.launches)
     elif args.cmd == "corrected":
         run_corrected(args.n, args.steps, args.every)
+    elif args.cmd == "gradient":
+        run_gradient(args.n, args.shots, args.steps, args.every, args.eps)
     elif args.cmd == "shot":
         run_shot(args.nx, args.ny, args.nz, args.steps, args.every, args.repeats, args.schedule)
     elif args.cmd == "summarize-conv":

@@ -1025,13 +1025,12 @@ int launch_all(const Geo &g, float *un, const float *uc, const float *up, const 
     return launch_box_scalar<R, OP>(g, un, uc, up, kap, boxes[0], st);
 }
 
-// Every owned cell (halo region, then the rest) with one of the stencil operations.
+// Every owned cell with one of the stencil operations, in one launch (the adjoint recursion and the
+// gradient accumulation have no exchange to overlap, so they need no halo-first split).
 template <int OP>
 int launch_whole(const Geo &g, float *un, const float *uc, const float *up, const float *kap, hipStream_t st)
 {
-    int rc = g.R == 4 ? launch_halo<4, OP>(g, un, uc, up, kap, st) : launch_halo<2, OP>(g, un, uc, up, kap, st);
-    if (rc != RTM_OK) return rc;
-    return g.R == 4 ? launch_interior<4, OP>(g, un, uc, up, kap, st) : launch_interior<2, OP>(g, un, uc, up, kap, st);
+    return g.R == 4 ? launch_all<4, OP>(g, un, uc, up, kap, st) : launch_all<2, OP>(g, un, uc, up, kap, st);
 }
 
 bool faces_vec(const Geo &g, const float *u)

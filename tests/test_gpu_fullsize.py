@@ -54,7 +54,7 @@ def test_fullsize_sampled_cells_match_oracle(layered):
     u0 = synth.random_field((N, N, N), seed=101)
     um = synth.random_field((N, N, N), seed=102)
     _say("fullsize: gpu 512^3 x 20 steps from a seeded random state")
-    g, prop, dt_gpu = _gpu_run(prof, nsteps, u0, um)
+    g, prop, dt_gpu = _gpu_run(prof, nsteps, u0, um, schedule="serial")     # the benchmark's schedule
     u_gpu = g.owned(prop.u_cur)
     c = N // 2
     # cells in every region of the split: source, x strips and their edges, y strips, z slabs, corners
@@ -94,7 +94,7 @@ def test_fullsize_sampled_cells_match_oracle(layered):
 def test_fullsize_mirror_symmetry_after_1000_steps(layered):
     """Centred source, medium layered along z, square x-y extent: u(i, j, k) = u(j, i, k) bitwise
     after the benchmark's 1000 steps (the update is symmetric in its x and y operands)."""
-    g, prop, _ = _gpu_run(layered, 1000)
+    g, prop, _ = _gpu_run(layered, 1000, schedule="serial")
     u = g.owned(prop.u_cur)
     ut = u.transpose(1, 2)
     import torch

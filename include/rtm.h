@@ -101,9 +101,11 @@ const char *rtm_strerror(int status);
  *                             two workgroups per CU), 5 = 16x32 (64x32 cells).
  *   RTM_OPT_HALO_VARIANT      the halo call's workgroup shape, numbered as above (not 3); default 0.
  *   RTM_OPT_WHOLE_VARIANT     rtm_step_whole's workgroup shape, numbered as above (not 3); default 4.
- *   RTM_OPT_ZCHUNK            z planes per workgroup of the tiled kernels; 0 = automatic: at radius 4
- *                             at most one wave of resident workgroups over the whole chip, at radius 2
- *                             chunks of 16 planes.
+ *   RTM_OPT_ZCHUNK            z planes per workgroup of the tiled kernels; 0 = automatic: at radius 4,
+ *                             for one-box launches (interior, whole step, adjoint, gradient) the
+ *                             chunking that balances the work of the busiest CU with the fewest
+ *                             workgroups, for the halo call at most one wave of resident workgroups
+ *                             over the whole chip; at radius 2 chunks of 16 planes.
  *   RTM_OPT_XCD_REMAP         1 = give each XCD a contiguous range of tiles (default), 0 = hardware order.
  *   RTM_OPT_HALO_X_WIDTH      width of the halo region's x strips (default 64 = one tile);
  *   RTM_OPT_HALO_Y_WIDTH      height of its y strips (default 16); see rtm_halo_region.

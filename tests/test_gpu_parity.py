@@ -402,6 +402,88 @@ def test_two_subdomain_split_bitwise(torch_cuda):
     assert np.array_equal(cur, ref_cur) and np.array_equal(prv, ref_prv)
 
 
+@pytest.mark.parametrize("fused_pack", [False, True])
+def test_2x2x2_subdomain_split_bitwise(torch_cuda, fused_pack):
+    """A 2x2x2 decomposition on one GPU: eight subdomains, each with its own halo call, shell
+    sources and pack (or the halo call that packs, with injected face cells re-copied), interior call
+    and unpack; every face between subdomains receives the neighbour's packed send slot (no copy),
+    outer faces zero ghosts.  After 60 steps with sources on the cuts (a corner cell of three faces
+    among them), the eight blocks are bitwise the single-domain solution."""
+    torch = torch_cuda
+    from paper_1603_03971_amd import _abi, synth
+    from paper_1603_03971_amd.grid import Grid
+    from paper_1603_03971_amd.propagator import Sources
+
+    nx, ny, nz, nsteps = 144, 72, 64, 60
+    cut = (64, 40, 28)
+    h = 10.0
+    dt = Grid.stable_dt(4, h, 3000.0)
+    v = synth.random_smooth_velocity((nz, ny, nx), seed=41, vmin=1500.0, vmax=3000.0)
+    whole = Grid(nx, ny, nz, h, dt, sponge_width=6)
+    gx, gy, gz = (t.cpu().numpy() for t in (whole.gx, whole.gy, whole.gz))
+    spans = [((0, cut[0]), (cut[0], nx)), ((0, cut[1]), (cut[1], ny)), ((0, cut[2]), (cut[2], nz))]
+    src = np.array([[cut[0] - 1, cut[1] - 1, cut[2] - 1], [cut[0], 20, 10], [30, cut[1], 40], [100, 60, cut[2]],
+                    [cut[0] - 3, cut[1] + 2, cut[2] - 2], [20, 15, 12], [120, 55, 50]])
+    amp = whole.ricker(nsteps, 20.0)
+    w = whole.injection_weights(v[src[:, 2], src[:, 1], src[:, 0]])
+    amps = np.repeat(amp[:, None], len(src), axis=1)
+    st = torch.cuda.current_stream()
+
+    def run(blocks, fused):
+        doms = {}
+        for key, (g, o, vv) in blocks.items():
+            sel = np.all((src >= o) & (src < o + np.array([g.nx, g.ny, g.nz])), axis=1)
+            doms[key] = {"g": g, "kap": g.kappa_from_velocity(vv), "a": g.field(), "b": g.field(),
+                         "send": g.faces(), "src": Sources(g, src[sel] - o, w[sel], amps[:, sel]) if sel.any() else None}
+        for (ix, iy, iz), d in doms.items():
+            d["recv"] = [None] * 6
+            for f, (dx, dy, dz, sf) in enumerate([(-1, 0, 0, 1), (1, 0, 0, 0), (0, -1, 0, 3), (0, 1, 0, 2),
+                                                  (0, 0, -1, 5), (0, 0, 1, 4)]):
+                nb = doms.get((ix + dx, iy + dy, iz + dz))
+                if nb is not None:
+                    d["recv"][f] = nb["g"].face_slots(nb["send"])[sf]
+        for n in range(nsteps):
+            for d in doms.values():                       # halo, shell sources, pack
+                g, nxt = d["g"], d["b"]
+                if fused:
+                    _abi.rtm_step_halo_pack(g.c, nxt, d["a"], d["b"], d["kap"], d["send"], st)
+                else:
+                    _abi.rtm_step_halo(g.c, nxt, d["a"], d["b"], d["kap"], st)
+                if d["src"] is not None:
+                    d["src"].inject(g, nxt, n, 0, st)
+                    if fused:
+                        d["src"].repack(g, nxt, n, d["send"], st)
+                if not fused:
+                    _abi.rtm_pack_halo(g.c, nxt, d["send"], st)
+            for d in doms.values():                       # interior, interior sources
+                g, nxt = d["g"], d["b"]
+                _abi.rtm_step_interior(g.c, nxt, d["a"], d["b"], d["kap"], st)
+                if d["src"] is not None:
+                    d["src"].inject(g, nxt, n, 1, st)
+            for d in doms.values():                       # unpack
+                _abi.rtm_unpack_halo(d["g"].c, d["b"], d["recv"], st)
+                d["a"], d["b"] = d["b"], d["a"]
+        torch.cuda.synchronize()
+        return {k: (d["g"].download(d["a"]), d["g"].download(d["b"])) for k, d in doms.items()}
+
+    _say("2x2x2: single domain")
+    ((ref_cur, ref_prv),) = run({(0, 0, 0): (whole, np.zeros(3, dtype=np.int64), v)}, False).values()
+    blocks = {}
+    for ix in range(2):
+        for iy in range(2):
+            for iz in range(2):
+                (x0, x1), (y0, y1), (z0, z1) = spans[0][ix], spans[1][iy], spans[2][iz]
+                g = Grid(x1 - x0, y1 - y0, z1 - z0, h, dt, sponge_profiles=(gx[x0:x1], gy[y0:y1], gz[z0:z1]))
+                blocks[(ix, iy, iz)] = (g, np.array([x0, y0, z0]), v[z0:z1, y0:y1, x0:x1])
+    _say(f"2x2x2: eight subdomains (fused pack {fused_pack})")
+    parts = run(blocks, fused_pack)
+    assert np.abs(ref_cur).max() > 0
+    for (ix, iy, iz), (cur, prv) in parts.items():
+        (x0, x1), (y0, y1), (z0, z1) = spans[0][ix], spans[1][iy], spans[2][iz]
+        assert np.array_equal(cur, ref_cur[z0:z1, y0:y1, x0:x1]), (ix, iy, iz)
+        assert np.array_equal(prv, ref_prv[z0:z1, y0:y1, x0:x1]), (ix, iy, iz)
+
+
 @pytest.mark.parametrize("radius", [4, 2])
 def test_whole_step_equals_halo_then_interior(torch_cuda, radius):
     """rtm_step_whole and rtm_step_halo + rtm_step_interior give the same bits on ragged boxes of

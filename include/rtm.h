@@ -101,6 +101,8 @@ const char *rtm_strerror(int status);
  *                             two workgroups per CU), 5 = 16x32 (64x32 cells).
  *   RTM_OPT_HALO_VARIANT      the halo call's workgroup shape, numbered as above (not 3); default 0.
  *   RTM_OPT_WHOLE_VARIANT     rtm_step_whole's workgroup shape, numbered as above (not 3); default 4.
+ *                             The one-launch adjoint and gradient calls take it too, except that the
+ *                             adjoint runs 4 and 5 (tiles held to 128 registers) as 0.
  *   RTM_OPT_ZCHUNK            z planes per workgroup of the tiled kernels; 0 = automatic: at radius 4,
  *                             for one-box launches (interior, whole step, adjoint, gradient) the
  *                             chunking that balances the work of the busiest CU with the fewest
@@ -213,10 +215,15 @@ int rtm_image_accumulate(const rtm_grid *grid, float *image, const float *src, c
 /* One step of the transposed recursion of the forward update u^{n+1} = G (2 + K L) u^n - G^2 u^{n-1}
  * (G = diag(g), K = diag(kappa), L symmetric with the zero ghosts of a physical boundary):
  *     mu_out = 2 g mu_a + L(kappa g mu_a) - g^2 mu_b,
- * with mu_a the adjoint state one level later and mu_b two levels later.  `work` is a caller-owned
- * padded field whose ghost cells are zero; it receives kappa g mu_a on the owned cells.  mu_out may
- * equal mu_b (in-place two-buffer recursion).  Adjoint sources (the residual traces, R^T y) are added
- * with rtm_inject afterwards.  Every owned cell is updated. */
+ * with mu_a the adjoint state one level later and mu_b two levels later.  Cells outside the owned
+ * block count as zero in kappa g mu_a, so the ghost values of mu_a, mu_b and kappa do not matter.
+ * One launch of the tiled kernel, which forms kappa g mu_a itself as it loads each plane.  `work` is a
+ * caller-owned padded field whose ghost cells are zero, used only by the per-cell path (pointers not
+ * 16-byte aligned, pitches not multiples of 4, or RTM_OPT_INTERIOR_VARIANT = 3): that path writes
+ * kappa g mu_a into its owned cells and then differentiates it; the results are bitwise the same.
+ * mu_out may equal mu_b (in-place two-buffer recursion); no ghost cell of mu_out is written.  Adjoint
+ * sources (the residual traces, R^T y) are added with rtm_inject afterwards.  Every owned cell is
+ * updated. */
 int rtm_adjoint_step(const rtm_grid *grid, float *mu_out, const float *mu_a, const float *mu_b, const float *kappa,
                      float *work, hipStream_t stream);
 

@@ -47,6 +47,7 @@ __device__ __forceinline__ float axis_sum(float xm, float xp, float ym, float yp
 // centre operands a, b and the sponge factor g:
 //   OP_FORWARD   u = u^n,            a = u^{n-1}, b = kappa:   g (2 u^n - g u^{n-1} + kappa L u^n)
 //   OP_ADJOINT   u = kappa g mu_a,   a = mu_a,    b = mu_b:    2 g mu_a + L(kappa g mu_a) - g^2 mu_b
+//                (the tiled kernel forms u itself from mu_a and kappa as it loads each plane)
 //   OP_GRADIENT  u = u^n,            a = mu,      b = grad:    grad + g mu L u^n
 enum { OP_FORWARD = 0, OP_ADJOINT = 1, OP_GRADIENT = 2 };
 
@@ -176,11 +177,27 @@ struct PackOut {
     long long off[6];
 };
 
+// kappa g mu for the four cells of a float4, in the order (kappa (gxy gz)) mu, and exactly zero for
+// the cells whose bit in `in` is clear (cells outside the owned block: their values are never read).
+__device__ __forceinline__ float4 weight4(float4 mu, float4 kp, const float (&gxy)[4], float gz, unsigned in)
+{
+    float4 w;
+    w.x = (in & 1u) ? (kp.x * (gxy[0] * gz)) * mu.x : 0.0f;
+    w.y = (in & 2u) ? (kp.y * (gxy[1] * gz)) * mu.y : 0.0f;
+    w.z = (in & 4u) ? (kp.z * (gxy[2] * gz)) * mu.z : 0.0f;
+    w.w = (in & 8u) ? (kp.w * (gxy[3] * gz)) * mu.w : 0.0f;
+    return w;
+}
+
 template <int R, int BX, int BY, int OP, bool PACK = false>
 __global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(BX * BY >= 512 ? 4 : 1)))
 void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, const float *kap, BoxList bl,
-             PackOut po)
+             PackOut po, const float *__restrict__ rk)
 {
+    // OP_ADJOINT: the stencil field is kappa g mu_a, formed here from two loads per ring element (uc =
+    // mu_a, rk = kappa) instead of being read from a field written by a separate pass; the ring
+    // elements of cells outside the owned block are zero, as the ghosts of such a field would be.
+    constexpr bool WR = (OP == OP_ADJOINT);
     constexpr int NT = BX * BY;
     constexpr int TX = 4 * BX;
     constexpr int TY = BY;
@@ -233,6 +250,7 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
     long long hoff[HPT];
     int hrow[HPT], hcol[HPT];
     bool hok[HPT];
+    int hxx[HPT], hyy[HPT];
 #pragma unroll
     for (int h = 0; h < HPT; ++h) {
         const int t = tid + h * NT;
@@ -240,6 +258,8 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
         hoff[h] = p0;
         hrow[h] = 0;
         hcol[h] = 0;
+        hxx[h] = X;
+        hyy[h] = Y;
         if (t < 2 * R * BX) {
             const int yr = t / BX, col = t % BX;
             const int row = yr < R ? Y - R + yr : Y + TY + (yr - R);
@@ -248,6 +268,8 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
             hcol[h] = 1 + col;
             hok[h] = (xx < xlim) && (row < ylim);
             hoff[h] = hok[h] ? pidx(g, xx, row, zs) : p0;
+            hxx[h] = xx;
+            hyy[h] = row;
         } else if (t < NH) {
             const int t2 = t - 2 * R * BX;
             const int side = t2 / BY, r = t2 % BY;
@@ -257,6 +279,25 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
             hcol[h] = side == 0 ? 0 : 1 + BX;
             hok[h] = (side == 0 ? (X - 1 >= bx.x0 - R) : (xx < xlim)) && (row < ylim);
             hoff[h] = hok[h] ? pidx(g, xx, row, zs) : p0;
+            hxx[h] = xx;
+            hyy[h] = row;
+        }
+    }
+    // WR: the x-y sponge factors of each halo item's four cells and which of them are owned cells
+    float hg[HPT][4];
+    unsigned hin[HPT];
+    if constexpr (WR) {
+#pragma unroll
+        for (int h = 0; h < HPT; ++h) {
+            const int yi = min(max(hyy[h], 0), g.ny - 1);
+            const bool yin = hok[h] && hyy[h] >= 0 && hyy[h] < g.ny;
+            hin[h] = 0u;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int xe = hxx[h] + e;
+                hg[h][e] = g.gx[min(max(xe, 0), g.nx - 1)] * g.gy[yi];
+                if (yin && xe >= 0 && xe < g.nx) hin[h] |= 1u << e;
+            }
         }
     }
 
@@ -264,12 +305,17 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
 #pragma unroll
     for (int m = 0; m < 5; ++m) c[m] = g.c[m];
     float gxy[4];
+    unsigned cin = 0u;                      // WR: which cells of this thread's column are owned
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int xi = min(max(x + e, 0), g.nx - 1);
         const int yi = min(y, g.ny - 1);
         gxy[e] = g.gx[xi] * g.gy[yi];
+        if (x + e >= 0 && x + e < g.nx && y < g.ny) cin |= 1u << e;
     }
+    // WR: the z sponge factor of plane p and whether p is an owned plane
+    auto gzp = [&](int p) { return g.gz[min(max(p, 0), g.nz - 1)]; };
+    auto zin = [&](int p) { return (p >= 0 && p < g.nz) ? 0xfu : 0u; };
 
     // Two rings.  (1) Registers: this thread's float4 of plane p of u_cur lives in
     // q[(p - zs + R) % QR]; the z loop is unrolled by QR so every ring index is a compile-time
@@ -278,23 +324,50 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
     // same time as the neighbouring tiles read them as their own centre rows, while they are in L2.
     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
     float4 q[QR];
+    float4 qm = zero4, qk = zero4;          // WR: mu and kappa of the centre plane in flight
+    if constexpr (WR) {
 #pragma unroll
-    for (int m = 0; m < 2 * R + 1; ++m) q[m] = ld4(uc + pcl + (long long)(m - R) * pz);
+        for (int m = 0; m < 2 * R; ++m) {
+            const long long o = pcl + (long long)(m - R) * pz;
+            q[m] = weight4(ld4(uc + o), ld4(rk + o), gxy, gzp(zs - R + m), cin & zin(zs - R + m));
+        }
+        qm = ld4(uc + pcl + (long long)R * pz);
+        qk = ld4(rk + pcl + (long long)R * pz);
+        q[2 * R] = zero4;
+    } else {
+#pragma unroll
+        for (int m = 0; m < 2 * R + 1; ++m) q[m] = ld4(uc + pcl + (long long)(m - R) * pz);
+    }
     q[QR - 1] = zero4;
     // LDS planes zs .. zs+R-1 (those that exist)
     for (int d = 0; d < R && zs + d < ze; ++d) {
         float4 hv[HPT];
+        if constexpr (WR) {
+            const float gz = gzp(zs + d);
+            const unsigned zm = zin(zs + d);
 #pragma unroll
-        for (int h = 0; h < HPT; ++h) hv[h] = ld4(uc + hoff[h] + (long long)d * pz);
-        lds[d][R + ly][1 + lx] = ld4(uc + pcl + (long long)d * pz);
+            for (int h = 0; h < HPT; ++h) {
+                const long long o = hoff[h] + (long long)d * pz;
+                hv[h] = weight4(ld4(uc + o), ld4(rk + o), hg[h], gz, hin[h] & zm);
+            }
+            const long long o = pcl + (long long)d * pz;
+            lds[d][R + ly][1 + lx] = weight4(ld4(uc + o), ld4(rk + o), gxy, gz, cin & zm);
+        } else {
+#pragma unroll
+            for (int h = 0; h < HPT; ++h) hv[h] = ld4(uc + hoff[h] + (long long)d * pz);
+            lds[d][R + ly][1 + lx] = ld4(uc + pcl + (long long)d * pz);
+        }
 #pragma unroll
         for (int h = 0; h < HPT; ++h)
             if (tid + h * NT < NH) lds[d][hrow[h]][hcol[h]] = hv[h];
     }
-    // halo of plane zs + R (written in the first iteration)
-    float4 hv[HPT];
+    // halo of plane zs + R (written in the first iteration); WR keeps mu in hv and kappa in hk
+    float4 hv[HPT], hk[HPT];
 #pragma unroll
-    for (int h = 0; h < HPT; ++h) hv[h] = ld4(uc + hoff[h] + (long long)R * pz);
+    for (int h = 0; h < HPT; ++h) {
+        hv[h] = ld4(uc + hoff[h] + (long long)R * pz);
+        if constexpr (WR) hk[h] = ld4(rk + hoff[h] + (long long)R * pz);
+    }
     // operands of plane k (u_prv, kappa and the z sponge factor) arrive one plane ahead, in the same
     // batch of loads, so waiting for them never waits for the loads issued for later planes
     float4 pv[2], kv[2];
@@ -313,12 +386,26 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
         const int b = s & 1;               // operand slot of plane k
         const long long dz = (long long)(k - zs) * pz;
         const int sw = (sk + R < S) ? sk + R : sk + R - S;   // LDS slot of plane k + R
+        // WR: plane k + R of the ring, from the mu and kappa loaded during the previous plane
+        float gzr = 0.0f;
+        unsigned zmr = 0u;
+        if constexpr (WR) {
+            gzr = gzp(k + R);
+            zmr = zin(k + R);
+            q[(s + 2 * R) % QR] = weight4(qm, qk, gxy, gzr, cin & zmr);
+        }
         // stage plane k + R (centre from the register ring, halo from the pending loads)
         if (k + R < ze) {
             lds[sw][R + ly][1 + lx] = q[(s + 2 * R) % QR];
 #pragma unroll
-            for (int h = 0; h < HPT; ++h)
-                if (tid + h * NT < NH) lds[sw][hrow[h]][hcol[h]] = hv[h];
+            for (int h = 0; h < HPT; ++h) {
+                if (tid + h * NT < NH) {
+                    if constexpr (WR)
+                        lds[sw][hrow[h]][hcol[h]] = weight4(hv[h], hk[h], hg[h], gzr, hin[h] & zmr);
+                    else
+                        lds[sw][hrow[h]][hcol[h]] = hv[h];
+                }
+            }
         }
         __syncthreads();
 
@@ -330,9 +417,19 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
         {
             const long long kn = min(k + 1, ze - 1) - zs;          // plane of u_prv / kappa
             const long long kh = min(k + R + 1, ze - 1) - zs;      // plane of the halo
-            q[(s + 2 * R + 1) % QR] = ld4(uc + pcl + (kn + R) * pz);
+            if constexpr (WR) {
+                qm = ld4(uc + pcl + (kn + R) * pz);
+                qk = ld4(rk + pcl + (kn + R) * pz);
 #pragma unroll
-            for (int h = 0; h < HPT; ++h) hv[h] = ld4(uc + hoff[h] + kh * pz);
+                for (int h = 0; h < HPT; ++h) {
+                    hv[h] = ld4(uc + hoff[h] + kh * pz);
+                    hk[h] = ld4(rk + hoff[h] + kh * pz);
+                }
+            } else {
+                q[(s + 2 * R + 1) % QR] = ld4(uc + pcl + (kn + R) * pz);
+#pragma unroll
+                for (int h = 0; h < HPT; ++h) hv[h] = ld4(uc + hoff[h] + kh * pz);
+            }
             pv[b ^ 1] = ld4(up + pca + kn * pz);
             kv[b ^ 1] = ld4(kap + pca + kn * pz);
             gzv[b ^ 1] = g.gz[zs + kn];
@@ -836,9 +933,10 @@ int balanced_zchunk(int tiles, int wz, int R, int cus)
 }
 
 // Launch the tiled kernel over up to kMaxBoxes boxes {x0, x1, y0, y1, z0, z1} (empty ones skipped).
+// rk: kappa for OP_ADJOINT (see k_tiled), unused otherwise.
 template <int R, int BX, int BY, int OP, bool PACK = false>
 int launch_tiled(const Geo &g, float *un, const float *uc, const float *up, const float *kap, const int (*boxes)[6],
-                 int nbox, hipStream_t st, const PackOut *po = nullptr)
+                 int nbox, hipStream_t st, const PackOut *po = nullptr, const float *rk = nullptr)
 {
     constexpr int TX = 4 * BX;
     BoxList bl;
@@ -908,20 +1006,21 @@ int launch_tiled(const Geo &g, float *un, const float *uc, const float *up, cons
     std::memset(&pk, 0, sizeof(pk));
     if (po) pk = *po;
     hipLaunchKernelGGL((k_tiled<R, BX, BY, OP, PACK>), dim3((unsigned)nb), dim3(BX * BY), 0, st, g, un, uc, up, kap,
-                       bl, pk);
+                       bl, pk, rk);
     return launch_status();
 }
 
 template <int R, int OP, bool PACK = false>
 int launch_tiled_variant(int var, const Geo &g, float *un, const float *uc, const float *up, const float *kap,
-                         const int (*boxes)[6], int nbox, hipStream_t st, const PackOut *po = nullptr)
+                         const int (*boxes)[6], int nbox, hipStream_t st, const PackOut *po = nullptr,
+                         const float *rk = nullptr)
 {
     switch (var) {
-    case 1: return launch_tiled<R, 32, 8, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po);
-    case 2: return launch_tiled<R, 16, 8, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po);
-    case 4: return launch_tiled<R, 32, 16, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po);
-    case 5: return launch_tiled<R, 16, 32, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po);
-    default: return launch_tiled<R, 16, 16, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po);
+    case 1: return launch_tiled<R, 32, 8, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po, rk);
+    case 2: return launch_tiled<R, 16, 8, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po, rk);
+    case 4: return launch_tiled<R, 32, 16, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po, rk);
+    case 5: return launch_tiled<R, 16, 32, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po, rk);
+    default: return launch_tiled<R, 16, 16, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po, rk);
     }
 }
 
@@ -1030,7 +1129,22 @@ int launch_all(const Geo &g, float *un, const float *uc, const float *up, const 
 template <int OP>
 int launch_whole(const Geo &g, float *un, const float *uc, const float *up, const float *kap, hipStream_t st)
 {
+    static_assert(OP != OP_ADJOINT, "the adjoint goes through launch_adjoint");
     return g.R == 4 ? launch_all<4, OP>(g, un, uc, up, kap, st) : launch_all<2, OP>(g, un, uc, up, kap, st);
+}
+
+// The adjoint step over every owned cell in one launch of the tiled kernel, which forms kappa g mu_a
+// from mu_a and kappa as it loads (no weight field).  Tile option: the one-launch call's, except that
+// the 128-register tiles (32 x 16, 16 x 32), which the two extra loads per ring element would spill,
+// take 16 x 16.  The caller has checked vector_path.
+template <int R>
+int launch_adjoint(const Geo &g, float *mu_out, const float *mu_a, const float *mu_b, const float *kappa,
+                   hipStream_t st)
+{
+    const int boxes[1][6] = {{0, g.nx, 0, g.ny, 0, g.nz}};
+    int var = g_opt.whole_variant.load(std::memory_order_relaxed);
+    if (var == 4 || var == 5) var = 0;
+    return launch_tiled_variant<R, OP_ADJOINT>(var, g, mu_out, mu_a, mu_a, mu_b, boxes, 1, st, nullptr, kappa);
 }
 
 bool faces_vec(const Geo &g, const float *u)
@@ -1386,11 +1500,17 @@ int rtm_adjoint_step(const rtm_grid *grid, float *mu_out, const float *mu_a, con
     st = check_device();
     if (st != RTM_OK) return st;
     const Geo g = make_geo(grid);
+    if (vector_path(g, mu_out, mu_a, mu_b, kappa))
+        return g.R == 4 ? launch_adjoint<4>(g, mu_out, mu_a, mu_b, kappa, stream)
+                        : launch_adjoint<2>(g, mu_out, mu_a, mu_b, kappa, stream);
+    // scalar path: kappa g mu_a into `work` (zero ghosts), then the per-cell update reads it
     const long long n = (long long)g.nx * g.ny * g.nz;
     hipLaunchKernelGGL(k_adjoint_weight, dim3(blocks_for(n)), dim3(kThreads), 0, stream, g, work, mu_a, kappa);
     st = launch_status();
     if (st != RTM_OK) return st;
-    return launch_whole<OP_ADJOINT>(g, mu_out, work, mu_a, mu_b, stream);
+    const int box[6] = {0, g.nx, 0, g.ny, 0, g.nz};
+    return g.R == 4 ? launch_box_scalar<4, OP_ADJOINT>(g, mu_out, work, mu_a, mu_b, box, stream)
+                    : launch_box_scalar<2, OP_ADJOINT>(g, mu_out, work, mu_a, mu_b, box, stream);
 }
 
 int rtm_gradient_accumulate(const rtm_grid *grid, float *grad, const float *u, const float *mu, hipStream_t stream)

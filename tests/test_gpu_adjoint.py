@@ -40,6 +40,67 @@ def test_adjoint_step_matches_oracle():
     assert e <= 1e-6
 
 
+@pytest.mark.parametrize("radius", [4, 2])
+def test_adjoint_tiled_equals_per_cell_path_bitwise(radius):
+    """The tiled adjoint kernel forms kappa g mu_a from two loads per ring element; the per-cell path
+    (unaligned layouts) reads it from `work`, written by a separate pass.  Every tile option and z
+    chunking, in place (mu_out = mu_b) or not, gives the per-cell path's bits, with NaN in the ghost
+    cells of mu_a, mu_b and kappa (the tiled kernel must zero what lies outside the owned block), and
+    no ghost cell of the output is written."""
+    import torch
+
+    from paper_1603_03971_amd import _abi
+    from paper_1603_03971_amd.grid import Grid
+
+    shape = (37, 45, 70)      # nz, ny, nx: ragged tiles in x and y, several z chunks
+    nz, ny, nx = shape
+    g = Grid(nx, ny, nz, 10.0, Grid.stable_dt(radius, 10.0, 3000.0), radius=radius, sponge_width=6)
+    v = synth.random_smooth_velocity(shape, seed=74, vmin=1500, vmax=3000)
+    ma, mb = synth.random_field(shape, 75), synth.random_field(shape, 76)
+    st = torch.cuda.current_stream()
+    nan = float("nan")
+
+    def poisoned(src):
+        f = g.field(fill=nan)
+        g.owned(f).copy_(src)
+        return f
+
+    kap = poisoned(g.owned(g.kappa_from_velocity(v)))
+    mu_a = poisoned(torch.from_numpy(ma.astype(np.float32)).cuda())
+    mu_b_host = torch.from_numpy(mb.astype(np.float32)).cuda()
+    work = g.field()
+
+    def run(in_place):
+        mu_b = poisoned(mu_b_host)
+        out = mu_b if in_place else g.field(fill=nan)
+        _abi.rtm_adjoint_step(g.c, out, mu_a, mu_b, kap, work, st)
+        torch.cuda.synchronize()
+        pad = g.padded(out).clone()
+        pad[radius:radius + nz, radius:radius + ny, radius:radius + nx] = 0.0
+        if not in_place:
+            assert int(torch.isnan(pad).sum()) == pad.numel() - nx * ny * nz, "a ghost cell was written"
+        return g.download(out)
+
+    iv = _abi.rtm_get_option(_abi.RTM_OPT_INTERIOR_VARIANT)
+    wv = _abi.rtm_get_option(_abi.RTM_OPT_WHOLE_VARIANT)
+    try:
+        _abi.rtm_set_option(_abi.RTM_OPT_INTERIOR_VARIANT, 3)          # the per-cell path
+        ref = run(False)
+        _abi.rtm_set_option(_abi.RTM_OPT_INTERIOR_VARIANT, iv)
+        assert np.all(np.isfinite(ref)) and np.any(ref != 0)
+        for var in (0, 1, 2, 4, 5):
+            _abi.rtm_set_option(_abi.RTM_OPT_WHOLE_VARIANT, var)
+            for zc in (0, 5):
+                _abi.rtm_set_option(_abi.RTM_OPT_ZCHUNK, zc)
+                for in_place in (False, True):
+                    _say(f"adjoint tiled R={radius} variant {var} zchunk {zc} in place {in_place}")
+                    assert np.array_equal(run(in_place), ref), (var, zc, in_place)
+    finally:
+        _abi.rtm_set_option(_abi.RTM_OPT_INTERIOR_VARIANT, iv)
+        _abi.rtm_set_option(_abi.RTM_OPT_WHOLE_VARIANT, wv)
+        _abi.rtm_set_option(_abi.RTM_OPT_ZCHUNK, 0)
+
+
 def test_gradient_kernel_matches_oracle():
     import torch
 

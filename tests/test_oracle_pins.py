@@ -7,6 +7,7 @@ brute force.  A dropped term, a wrong sign or a swapped axis anywhere in the ora
 one of them.
 """
 import math
+import os
 from fractions import Fraction as Fr
 
 import numpy as np
@@ -14,13 +15,26 @@ import pytest
 
 import oracle
 
-# Centred second-derivative weights, the textbook values (Fornberg 1988, table 1).
-TEXTBOOK = {
-    1: [Fr(-2), Fr(1)],
-    2: [Fr(-5, 2), Fr(4, 3), Fr(-1, 12)],
-    3: [Fr(-49, 18), Fr(3, 2), Fr(-3, 20), Fr(1, 90)],
-    4: [Fr(-205, 72), Fr(8, 5), Fr(-1, 5), Fr(8, 315), Fr(-1, 560)],
-}
+
+def _load_textbook():
+    """Centred second-derivative weights, the published table (Fornberg 1988, Table 1), from
+    tests/golden/fornberg_second_derivative.txt: {R: [c_0, ..., c_R]} as exact fractions."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "fornberg_second_derivative.txt")
+    table = {}
+    with open(path) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                r, *cs = line.split()
+                table[int(r)] = [Fr(c) for c in cs]
+    return table
+
+
+TEXTBOOK = _load_textbook()
+
+
+def test_textbook_table_complete():
+    assert sorted(TEXTBOOK) == [1, 2, 3, 4]
+    assert all(len(TEXTBOOK[r]) == r + 1 for r in TEXTBOOK)
 
 
 @pytest.mark.parametrize("radius", [1, 2, 3, 4])

@@ -158,8 +158,8 @@ int rtm_step_whole(const rtm_grid *grid, float *u_nxt, const float *u_cur, const
                    const float *kappa, hipStream_t stream);
 
 /* Phase 2 (section II): copy the R outermost owned layers of u on each face into `faces` (one
- * buffer of rtm_face_layout()[6] elements, slots as described there).  Bitwise copy.  Each slot must
- * hold fewer than 2^31 elements (RTM_EINVAL otherwise); the same limit applies to unpack. */
+ * buffer of rtm_face_layout()[6] elements, slots as described there).  Bitwise copy.  Any slot size
+ * (counters are 64-bit where a slot holds 2^31 elements or more). */
 int rtm_pack_halo(const rtm_grid *grid, const float *u, float *faces, hipStream_t stream);
 
 /* Phases 1 and 2 in one launch (section II): rtm_step_halo and then rtm_pack_halo of u_nxt into

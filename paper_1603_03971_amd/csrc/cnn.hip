@@ -25,6 +25,11 @@ namespace {
 #endif
 
 constexpr int kC = 16;          // channels
+
+// Elementwise kernels walk their items with a grid-sized stride and 64-bit counters (nblk caps the
+// grid), so volumes of more than 2^32 items fit a launch.
+__device__ __forceinline__ long long first_item() { return (long long)blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ long long item_stride() { return (long long)gridDim.x * blockDim.x; }
 constexpr int kTaps = 27;
 
 typedef short v4s __attribute__((ext_vector_type(4)));
@@ -447,18 +452,18 @@ __global__ __launch_bounds__(256) void k_relu_backward(Vol v, const float *__res
                                                        int relu, int cmask, float *__restrict__ dz32,
                                                        uint16_t *__restrict__ dz16)
 {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long n = (long long)v.nx * v.ny * v.nz * kC;
-    if (t >= n) return;
-    const int c = (int)(t % kC);
-    const long long vox = t / kC;
-    const int i = (int)(vox % v.nx);
-    const int jj = (int)((vox / v.nx) % v.ny);
-    const int kk = (int)(vox / ((long long)v.nx * v.ny));
-    float d = c < cmask ? dy[t] : 0.0f;
-    if (relu && !(y[t] > 0.0f)) d = 0.0f;
-    dz32[t] = d;
-    dz16[v.at(i, jj, kk) * kC + c] = f2bf(d);
+    for (long long t = first_item(); t < n; t += item_stride()) {
+        const int c = (int)(t % kC);
+        const long long vox = t / kC;
+        const int i = (int)(vox % v.nx);
+        const int jj = (int)((vox / v.nx) % v.ny);
+        const int kk = (int)(vox / ((long long)v.nx * v.ny));
+        float d = c < cmask ? dy[t] : 0.0f;
+        if (relu && !(y[t] > 0.0f)) d = 0.0f;
+        dz32[t] = d;
+        dz16[v.at(i, jj, kk) * kC + c] = f2bf(d);
+    }
 }
 
 // Output-layer gradient of L = 1/2 sum over voxels and channels < cmask of w (out - target)^2 with
@@ -469,10 +474,10 @@ __global__ __launch_bounds__(256) void k_loss_grad(Vol v, const float *__restric
                                                    float *__restrict__ dz32, uint16_t *__restrict__ dz16,
                                                    double *__restrict__ loss)
 {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long n = (long long)v.nx * v.ny * v.nz * kC;
-    float d = 0.0f;
-    if (t < n) {
+    double part = 0.0;                         // this thread's share of L
+    for (long long t = first_item(); t < n; t += item_stride()) {
+        float d = 0.0f;
         const int c = (int)(t % kC);
         const long long vox = t / kC;
         const int i = (int)(vox % v.nx);
@@ -482,11 +487,12 @@ __global__ __launch_bounds__(256) void k_loss_grad(Vol v, const float *__restric
         if (c < cmask) d = out[t] - tgt[t];
         dz32[t] = wv * d;
         dz16[v.at(i, jj, kk) * kC + c] = f2bf(wv * d);
-        d *= sqrtf(wv);                        // the loss term below is wv d^2 / 2
+        d *= sqrtf(wv);                        // the loss term is wv d^2 / 2
+        part += 0.5 * (double)d * (double)d;
     }
     if (!loss) return;
     __shared__ double red[256];
-    red[threadIdx.x] = 0.5 * (double)d * (double)d;
+    red[threadIdx.x] = part;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
@@ -509,22 +515,21 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
                        float *__restrict__ m2, int n, float lr, float b1, float b2, float eps, float c1, float c2,
                        uint16_t *__restrict__ p16)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const float gt = g[t];
-    const float a = b1 * m1[t] + (1.0f - b1) * gt;
-    const float b = b2 * m2[t] + (1.0f - b2) * gt * gt;
-    m1[t] = a;
-    m2[t] = b;
-    const float val = p[t] - lr * (a / c1) / (sqrtf(b / c2) + eps);
-    p[t] = val;
-    if (p16) p16[t] = f2bf(val);
+    for (long long t = first_item(); t < n; t += item_stride()) {
+        const float gt = g[t];
+        const float a = b1 * m1[t] + (1.0f - b1) * gt;
+        const float b = b2 * m2[t] + (1.0f - b2) * gt * gt;
+        m1[t] = a;
+        m2[t] = b;
+        const float val = p[t] - lr * (a / c1) / (sqrtf(b / c2) + eps);
+        p[t] = val;
+        if (p16) p16[t] = f2bf(val);
+    }
 }
 
 __global__ void k_to_bf16(const float *__restrict__ a, uint16_t *__restrict__ b, int n)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) b[t] = f2bf(a[t]);
+    for (long long t = first_item(); t < n; t += item_stride()) b[t] = f2bf(a[t]);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -554,26 +559,26 @@ __global__ __launch_bounds__(256) void k_pack_input(G g, Vol v, const float *__r
                                                     float v_ref, float v_inv, const float *__restrict__ scale,
                                                     const float *__restrict__ noise, uint16_t *__restrict__ x)
 {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long n = (long long)g.nx * g.ny * g.nz;
-    if (t >= n) return;
-    const int i = (int)(t % g.nx);
-    const int j = (int)((t / g.nx) % g.ny);
-    const int k = (int)(t / ((long long)g.nx * g.ny));
-    const float s = scale[0];
-    const float inv = s > 0.0f ? 1.0f / s : 0.0f;
-    const long long p = g.idx(i, j, k);
-    uint16_t *o = x + v.at(i, j, k) * kC;
-    float a, d;
-    input_levels(u_cur[p], u_prv[p], inv, a, d);
-    if (noise) {
-        a += noise[2 * t];
-        d += noise[2 * t + 1];
+    for (long long t = first_item(); t < n; t += item_stride()) {
+        const int i = (int)(t % g.nx);
+        const int j = (int)((t / g.nx) % g.ny);
+        const int k = (int)(t / ((long long)g.nx * g.ny));
+        const float s = scale[0];
+        const float inv = s > 0.0f ? 1.0f / s : 0.0f;
+        const long long p = g.idx(i, j, k);
+        uint16_t *o = x + v.at(i, j, k) * kC;
+        float a, d;
+        input_levels(u_cur[p], u_prv[p], inv, a, d);
+        if (noise) {
+            a += noise[2 * t];
+            d += noise[2 * t + 1];
+        }
+        const float m = input_material(vel[t], v_ref, v_inv);
+        // the whole 32-byte voxel in two 16-byte stores (a partial store would leave lines to merge)
+        reinterpret_cast<uint4 *>(o)[0] = input_voxel(a, d, m);
+        reinterpret_cast<uint4 *>(o)[1] = make_uint4(0u, 0u, 0u, 0u);
     }
-    const float m = input_material(vel[t], v_ref, v_inv);
-    // the whole 32-byte voxel in two 16-byte stores (a partial store would leave lines to merge)
-    reinterpret_cast<uint4 *>(o)[0] = input_voxel(a, d, m);
-    reinterpret_cast<uint4 *>(o)[1] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 // Apply the correction (out: [voxel][oc], in the input's level-and-difference form): u^n += s o0 and
@@ -583,17 +588,17 @@ __global__ __launch_bounds__(256) void k_apply_correction(G g, float *u_cur, flo
                                                           int oc, const float *__restrict__ mask,
                                                           const float *__restrict__ scale)
 {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long n = (long long)g.nx * g.ny * g.nz;
-    if (t >= n) return;
-    const int i = (int)(t % g.nx);
-    const int j = (int)((t / g.nx) % g.ny);
-    const int k = (int)(t / ((long long)g.nx * g.ny));
-    const float s = mask ? scale[0] * mask[t] : scale[0];
-    const long long p = g.idx(i, j, k);
-    const float o0 = out[t * oc + 0], o1 = out[t * oc + 1];
-    u_cur[p] = __builtin_fmaf(s, o0, u_cur[p]);
-    u_prv[p] = __builtin_fmaf(s, o0 - o1, u_prv[p]);
+    for (long long t = first_item(); t < n; t += item_stride()) {
+        const int i = (int)(t % g.nx);
+        const int j = (int)((t / g.nx) % g.ny);
+        const int k = (int)(t / ((long long)g.nx * g.ny));
+        const float s = mask ? scale[0] * mask[t] : scale[0];
+        const long long p = g.idx(i, j, k);
+        const float o0 = out[t * oc + 0], o1 = out[t * oc + 1];
+        u_cur[p] = __builtin_fmaf(s, o0, u_cur[p]);
+        u_prv[p] = __builtin_fmaf(s, o0 - o1, u_prv[p]);
+    }
 }
 
 // Training target in the input's form: channel 0 = (ref^n - u^n) / s, channel 1 =
@@ -604,25 +609,25 @@ __global__ __launch_bounds__(256) void k_target(G g, const float *__restrict__ r
                                                 const float *__restrict__ scale, const float *__restrict__ noise,
                                                 float *__restrict__ tgt)
 {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long n = (long long)g.nx * g.ny * g.nz;
-    if (t >= n) return;
-    const int i = (int)(t % g.nx);
-    const int j = (int)((t / g.nx) % g.ny);
-    const int k = (int)(t / ((long long)g.nx * g.ny));
-    const float s = scale[0];
-    const float inv = s > 0.0f ? 1.0f / s : 0.0f;
-    const long long p = g.idx(i, j, k);
-    float *o = tgt + t * kC;
-    const float rc = ref_cur[p], uc = u_cur[p];
-    o[0] = (rc - uc) * inv;
-    o[1] = ((rc - ref_prv[p]) - (uc - u_prv[p])) * inv;
-    if (noise) {
-        o[0] -= noise[2 * t];
-        o[1] -= noise[2 * t + 1];
+    for (long long t = first_item(); t < n; t += item_stride()) {
+        const int i = (int)(t % g.nx);
+        const int j = (int)((t / g.nx) % g.ny);
+        const int k = (int)(t / ((long long)g.nx * g.ny));
+        const float s = scale[0];
+        const float inv = s > 0.0f ? 1.0f / s : 0.0f;
+        const long long p = g.idx(i, j, k);
+        float *o = tgt + t * kC;
+        const float rc = ref_cur[p], uc = u_cur[p];
+        o[0] = (rc - uc) * inv;
+        o[1] = ((rc - ref_prv[p]) - (uc - u_prv[p])) * inv;
+        if (noise) {
+            o[0] -= noise[2 * t];
+            o[1] -= noise[2 * t + 1];
+        }
+    #pragma unroll
+        for (int c = 2; c < kC; ++c) o[c] = 0.0f;
     }
-#pragma unroll
-    for (int c = 2; c < kC; ++c) o[c] = 0.0f;
 }
 
 // Fine -> coarse restriction.  Injection: coarse (i, j, k) takes fine (2i, 2j, 2k).  Full weighting:
@@ -632,29 +637,29 @@ __global__ __launch_bounds__(256) void k_target(G g, const float *__restrict__ r
 __global__ __launch_bounds__(256) void k_restrict(G f, G c, const float *__restrict__ uf, float *__restrict__ uc,
                                                   int full)
 {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long n = (long long)c.nx * c.ny * c.nz;
-    if (t >= n) return;
-    const int i = (int)(t % c.nx);
-    const int j = (int)((t / c.nx) % c.ny);
-    const int k = (int)(t / ((long long)c.nx * c.ny));
-    const long long p = f.idx(2 * i, 2 * j, 2 * k);
-    if (!full) {
-        uc[c.idx(i, j, k)] = uf[p];
-        return;
-    }
-    const float w[3] = {0.25f, 0.5f, 0.25f};
-    float acc = 0.0f;
-    for (int a = 0; a < 3; ++a) {
-        float sy = 0.0f;
-        for (int b = 0; b < 3; ++b) {
-            const float *r = uf + p + (long long)(a - 1) * f.pz + (long long)(b - 1) * f.py;
-            const float sx = __builtin_fmaf(w[2], r[1], __builtin_fmaf(w[1], r[0], w[0] * r[-1]));
-            sy = __builtin_fmaf(w[b], sx, sy);
+    for (long long t = first_item(); t < n; t += item_stride()) {
+        const int i = (int)(t % c.nx);
+        const int j = (int)((t / c.nx) % c.ny);
+        const int k = (int)(t / ((long long)c.nx * c.ny));
+        const long long p = f.idx(2 * i, 2 * j, 2 * k);
+        if (!full) {
+            uc[c.idx(i, j, k)] = uf[p];
+            continue;
         }
-        acc = __builtin_fmaf(w[a], sy, acc);
+        const float w[3] = {0.25f, 0.5f, 0.25f};
+        float acc = 0.0f;
+        for (int a = 0; a < 3; ++a) {
+            float sy = 0.0f;
+            for (int b = 0; b < 3; ++b) {
+                const float *r = uf + p + (long long)(a - 1) * f.pz + (long long)(b - 1) * f.py;
+                const float sx = __builtin_fmaf(w[2], r[1], __builtin_fmaf(w[1], r[0], w[0] * r[-1]));
+                sy = __builtin_fmaf(w[b], sx, sy);
+            }
+            acc = __builtin_fmaf(w[a], sy, acc);
+        }
+        uc[c.idx(i, j, k)] = acc;
     }
-    uc[c.idx(i, j, k)] = acc;
 }
 
 // max |u| over owned cells into out[0] (the corrector's per-application scale): workgroups stride
@@ -724,7 +729,9 @@ int device_ok()
         const int dst_ = device_ok();                                                                  \
         if (dst_ != RTM_OK) return dst_;                                                               \
     } while (0)
-unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+// Workgroups for n items; the elementwise kernels stride by the grid beyond the cap, so volumes of
+// more than 2^32 items fit one launch dimension.
+unsigned nblk(long long n, int t = 256) { return (unsigned)std::min<long long>((n + t - 1) / t, 1ll << 20); }
 
 bool vol_ok(int nx, int ny, int nz) { return nx > 0 && ny > 0 && nz > 0 && nx % 16 == 0; }
 

@@ -112,6 +112,12 @@ struct Slab {
     int wx, wy, wz;   // extent
 };
 
+// Elementwise kernels walk their items with a grid-sized stride and 64-bit counters, so a launch of
+// at most kMaxBlocks workgroups covers fields of more than 2^32 cells (one HIP launch dimension
+// holds fewer than 2^32 work-items); below kMaxBlocks * kThreads items every thread takes one item.
+__device__ __forceinline__ long long first_item() { return (long long)blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ long long item_stride() { return (long long)gridDim.x * blockDim.x; }
+
 // Scalar update over one box [x0,x1) x [y0,y1) x [z0,z1) (fallback for layouts the vectorised
 // kernel cannot take).
 template <int R, int OP>
@@ -119,12 +125,12 @@ __global__ __launch_bounds__(kThreads) void k_box(Geo g, float *un, const float 
                                                   const float *kap, int x0, int x1, int y0, int y1, int z0, int z1)
 {
     const long long wx = x1 - x0, wy = y1 - y0, wz = z1 - z0;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= wx * wy * wz) return;
-    const int i = x0 + (int)(t % wx);
-    const int j = y0 + (int)((t / wx) % wy);
-    const int k = z0 + (int)(t / (wx * wy));
-    update_cell<R, OP>(g, un, uc, up, kap, i, j, k);
+    for (long long t = first_item(); t < wx * wy * wz; t += item_stride()) {
+        const int i = x0 + (int)(t % wx);
+        const int j = y0 + (int)((t / wx) % wy);
+        const int k = z0 + (int)(t / (wx * wy));
+        update_cell<R, OP>(g, un, uc, up, kap, i, j, k);
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -521,52 +527,57 @@ __device__ __forceinline__ Slab face_ghost(const Geo &g, int f)
     }
 }
 
+// The face kernels count in I: unsigned when every slot has fewer than 2^31 items (the division is
+// then 32-bit, and t + stride cannot wrap), long long otherwise.
+template <typename I>
 __global__ __launch_bounds__(kThreads) void k_pack(Geo g, const float *__restrict__ u, float *__restrict__ faces,
                                                    FaceOffsets fo)
 {
     const int f = blockIdx.y;
     const Slab s = face_owned(g, f);
-    const unsigned cnt = (unsigned)s.wx * (unsigned)s.wy * (unsigned)s.wz;
-    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= cnt) return;
-    const unsigned row = t / (unsigned)s.wx;
-    const int i = s.ox + (int)(t - row * (unsigned)s.wx);
-    const int j = s.oy + (int)(row % (unsigned)s.wy);
-    const int k = s.oz + (int)(row / (unsigned)s.wy);
-    faces[fo.off[f] + t] = u[pidx(g, i, j, k)];
+    const I cnt = (I)s.wx * (I)s.wy * (I)s.wz;
+    for (I t = (I)first_item(); t < cnt; t += (I)item_stride()) {
+        const I row = t / (I)s.wx;
+        const int i = s.ox + (int)(t - row * (I)s.wx);
+        const int j = s.oy + (int)(row % (I)s.wy);
+        const int k = s.oz + (int)(row / (I)s.wy);
+        faces[fo.off[f] + t] = u[pidx(g, i, j, k)];
+    }
 }
 
+template <typename I>
 __global__ __launch_bounds__(kThreads) void k_unpack(Geo g, float *__restrict__ u, FacePtrs src)
 {
     const int f = blockIdx.y;
     const Slab s = face_ghost(g, f);
-    const unsigned cnt = (unsigned)s.wx * (unsigned)s.wy * (unsigned)s.wz;
-    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= cnt) return;
-    const unsigned row = t / (unsigned)s.wx;
-    const int i = s.ox + (int)(t - row * (unsigned)s.wx);
-    const int j = s.oy + (int)(row % (unsigned)s.wy);
-    const int k = s.oz + (int)(row / (unsigned)s.wy);
+    const I cnt = (I)s.wx * (I)s.wy * (I)s.wz;
     const float *p = src.p[f];
-    u[pidx(g, i, j, k)] = p ? p[t] : 0.0f;
+    for (I t = (I)first_item(); t < cnt; t += (I)item_stride()) {
+        const I row = t / (I)s.wx;
+        const int i = s.ox + (int)(t - row * (I)s.wx);
+        const int j = s.oy + (int)(row % (I)s.wy);
+        const int k = s.oz + (int)(row / (I)s.wy);
+        u[pidx(g, i, j, k)] = p ? p[t] : 0.0f;
+    }
 }
 
 // float4 forms, used when R = 4, nx % 4 == 0 and every pointer and pitch is 16-byte aligned: then each
 // face row starts on a float4 boundary and one thread moves four consecutive cells.
+template <typename I>
 __global__ __launch_bounds__(kThreads) void k_pack4(Geo g, const float *__restrict__ u, float *__restrict__ faces,
                                                     FaceOffsets fo)
 {
     const int f = blockIdx.y;
     const Slab s = face_owned(g, f);
-    const unsigned w4 = (unsigned)s.wx >> 2;
-    const unsigned cnt = w4 * (unsigned)s.wy * (unsigned)s.wz;
-    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= cnt) return;
-    const unsigned row = t / w4;
-    const int i = s.ox + 4 * (int)(t - row * w4);
-    const int j = s.oy + (int)(row % (unsigned)s.wy);
-    const int k = s.oz + (int)(row / (unsigned)s.wy);
-    st4(faces + fo.off[f] + 4 * t, ld4(u + pidx(g, i, j, k)));
+    const I w4 = (I)(s.wx >> 2);
+    const I cnt = w4 * (I)s.wy * (I)s.wz;
+    for (I t = (I)first_item(); t < cnt; t += (I)item_stride()) {
+        const I row = t / w4;
+        const int i = s.ox + 4 * (int)(t - row * w4);
+        const int j = s.oy + (int)(row % (I)s.wy);
+        const int k = s.oz + (int)(row / (I)s.wy);
+        st4(faces + fo.off[f] + 4 * (long long)t, ld4(u + pidx(g, i, j, k)));
+    }
 }
 
 // faces[slot position of cell p] = u[p] for each owned cell p of the list in each face slot that holds
@@ -575,40 +586,41 @@ __global__ __launch_bounds__(kThreads) void k_pack_cells(Geo g, const float *__r
                                                          const long long *__restrict__ idx, int n,
                                                          float *__restrict__ faces, FaceOffsets fo)
 {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= n) return;
-    const long long p = idx[m];
     const int R = g.R;
-    const long long kk = p / g.pz, rem = p - kk * g.pz;
-    const long long jj = rem / g.py, ii = rem - jj * g.py;
-    if (p < 0 || kk < R || kk >= (long long)g.nz + R || jj < R || jj >= (long long)g.ny + R || ii < R ||
-        ii >= (long long)g.nx + R)
-        return;
-    const int i = (int)ii - R, j = (int)jj - R, k = (int)kk - R;
-    const float v = u[p];
     const long long nx = g.nx, ny = g.ny;
-    if (i < R) faces[fo.off[0] + ((long long)k * ny + j) * R + i] = v;
-    if (i >= g.nx - R) faces[fo.off[1] + ((long long)k * ny + j) * R + (i - (g.nx - R))] = v;
-    if (j < R) faces[fo.off[2] + ((long long)k * R + j) * nx + i] = v;
-    if (j >= g.ny - R) faces[fo.off[3] + ((long long)k * R + (j - (g.ny - R))) * nx + i] = v;
-    if (k < R) faces[fo.off[4] + ((long long)k * ny + j) * nx + i] = v;
-    if (k >= g.nz - R) faces[fo.off[5] + ((long long)(k - (g.nz - R)) * ny + j) * nx + i] = v;
+    for (long long m = first_item(); m < n; m += item_stride()) {
+        const long long p = idx[m];
+        const long long kk = p / g.pz, rem = p - kk * g.pz;
+        const long long jj = rem / g.py, ii = rem - jj * g.py;
+        if (p < 0 || kk < R || kk >= (long long)g.nz + R || jj < R || jj >= (long long)g.ny + R || ii < R ||
+            ii >= (long long)g.nx + R)
+            continue;
+        const int i = (int)ii - R, j = (int)jj - R, k = (int)kk - R;
+        const float v = u[p];
+        if (i < R) faces[fo.off[0] + ((long long)k * ny + j) * R + i] = v;
+        if (i >= g.nx - R) faces[fo.off[1] + ((long long)k * ny + j) * R + (i - (g.nx - R))] = v;
+        if (j < R) faces[fo.off[2] + ((long long)k * R + j) * nx + i] = v;
+        if (j >= g.ny - R) faces[fo.off[3] + ((long long)k * R + (j - (g.ny - R))) * nx + i] = v;
+        if (k < R) faces[fo.off[4] + ((long long)k * ny + j) * nx + i] = v;
+        if (k >= g.nz - R) faces[fo.off[5] + ((long long)(k - (g.nz - R)) * ny + j) * nx + i] = v;
+    }
 }
 
+template <typename I>
 __global__ __launch_bounds__(kThreads) void k_unpack4(Geo g, float *__restrict__ u, FacePtrs src)
 {
     const int f = blockIdx.y;
     const Slab s = face_ghost(g, f);
-    const unsigned w4 = (unsigned)s.wx >> 2;
-    const unsigned cnt = w4 * (unsigned)s.wy * (unsigned)s.wz;
-    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= cnt) return;
-    const unsigned row = t / w4;
-    const int i = s.ox + 4 * (int)(t - row * w4);
-    const int j = s.oy + (int)(row % (unsigned)s.wy);
-    const int k = s.oz + (int)(row / (unsigned)s.wy);
+    const I w4 = (I)(s.wx >> 2);
+    const I cnt = w4 * (I)s.wy * (I)s.wz;
     const float *p = src.p[f];
-    st4(u + pidx(g, i, j, k), p ? ld4(p + 4 * t) : make_float4(0.f, 0.f, 0.f, 0.f));
+    for (I t = (I)first_item(); t < cnt; t += (I)item_stride()) {
+        const I row = t / w4;
+        const int i = s.ox + 4 * (int)(t - row * w4);
+        const int j = s.oy + (int)(row % (I)s.wy);
+        const int k = s.oz + (int)(row / (I)s.wy);
+        st4(u + pidx(g, i, j, k), p ? ld4(p + 4 * (long long)t) : make_float4(0.f, 0.f, 0.f, 0.f));
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -617,46 +629,45 @@ __global__ __launch_bounds__(kThreads) void k_unpack4(Geo g, float *__restrict__
 __global__ __launch_bounds__(kThreads) void k_inject(float *u, long long total, const int64_t *__restrict__ idx,
                                                      const float *__restrict__ w, const float *__restrict__ amp, int n)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const long long p = idx[s];
-    if (p < 0 || p >= total) return;
-    atomicAdd(u + p, w[s] * amp[s]);
+    for (long long s = first_item(); s < n; s += item_stride()) {
+        const long long p = idx[s];
+        if (p >= 0 && p < total) atomicAdd(u + p, w[s] * amp[s]);
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_record(const float *__restrict__ u, long long total,
                                                      const int64_t *__restrict__ idx, float *__restrict__ out, int n)
 {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    const long long p = idx[r];
-    out[r] = (p >= 0 && p < total) ? u[p] : 0.0f;
+    for (long long r = first_item(); r < n; r += item_stride()) {
+        const long long p = idx[r];
+        out[r] = (p >= 0 && p < total) ? u[p] : 0.0f;
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_image(Geo g, float *image, const float *__restrict__ src,
                                                     const float *__restrict__ rcv, float weight)
 {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long nxy = (long long)g.nx * g.ny;
-    if (t >= nxy * g.nz) return;
-    const int i = (int)(t % g.nx);
-    const int j = (int)((t / g.nx) % g.ny);
-    const int k = (int)(t / nxy);
-    const long long p = pidx(g, i, j, k);
-    image[p] = __builtin_fmaf(weight * src[p], rcv[p], image[p]);
+    for (long long t = first_item(); t < nxy * g.nz; t += item_stride()) {
+        const int i = (int)(t % g.nx);
+        const int j = (int)((t / g.nx) % g.ny);
+        const int k = (int)(t / nxy);
+        const long long p = pidx(g, i, j, k);
+        image[p] = __builtin_fmaf(weight * src[p], rcv[p], image[p]);
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_kappa(Geo g, float *__restrict__ kappa, const float *__restrict__ v,
                                                     float s)
 {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long nxy = (long long)g.nx * g.ny;
-    if (t >= nxy * g.nz) return;
-    const int i = (int)(t % g.nx);
-    const int j = (int)((t / g.nx) % g.ny);
-    const int k = (int)(t / nxy);
-    const float a = v[t] * s;
-    kappa[pidx(g, i, j, k)] = a * a;
+    for (long long t = first_item(); t < nxy * g.nz; t += item_stride()) {
+        const int i = (int)(t % g.nx);
+        const int j = (int)((t / g.nx) % g.ny);
+        const int k = (int)(t / nxy);
+        const float a = v[t] * s;
+        kappa[pidx(g, i, j, k)] = a * a;
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -666,14 +677,14 @@ __global__ __launch_bounds__(kThreads) void k_kappa(Geo g, float *__restrict__ k
 __global__ __launch_bounds__(kThreads) void k_adjoint_weight(Geo g, float *__restrict__ w, const float *__restrict__ mu,
                                                              const float *__restrict__ kap)
 {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long nxy = (long long)g.nx * g.ny;
-    if (t >= nxy * g.nz) return;
-    const int i = (int)(t % g.nx);
-    const int j = (int)((t / g.nx) % g.ny);
-    const int k = (int)(t / nxy);
-    const long long p = pidx(g, i, j, k);
-    w[p] = (kap[p] * sponge(g, i, j, k)) * mu[p];
+    for (long long t = first_item(); t < nxy * g.nz; t += item_stride()) {
+        const int i = (int)(t % g.nx);
+        const int j = (int)((t / g.nx) % g.ny);
+        const int k = (int)(t / nxy);
+        const long long p = pidx(g, i, j, k);
+        w[p] = (kap[p] * sponge(g, i, j, k)) * mu[p];
+    }
 }
 
 // resid = d - obs and misfit += 1/2 sum resid^2, summed in FP64 by one workgroup: each thread adds a
@@ -704,13 +715,13 @@ __global__ __launch_bounds__(kThreads) void k_velocity_gradient(Geo g, float *__
                                                                 const float *__restrict__ gk,
                                                                 const float *__restrict__ v, float s2)
 {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long nxy = (long long)g.nx * g.ny;
-    if (t >= nxy * g.nz) return;
-    const int i = (int)(t % g.nx);
-    const int j = (int)((t / g.nx) % g.ny);
-    const int k = (int)(t / nxy);
-    gv[t] = (2.0f * s2) * v[t] * gk[pidx(g, i, j, k)];
+    for (long long t = first_item(); t < nxy * g.nz; t += item_stride()) {
+        const int i = (int)(t % g.nx);
+        const int j = (int)((t / g.nx) % g.ny);
+        const int k = (int)(t / nxy);
+        gv[t] = (2.0f * s2) * v[t] * gk[pidx(g, i, j, k)];
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -743,16 +754,16 @@ __global__ __launch_bounds__(kAbsmaxThreads) void k_plane_absmax(Geo g, const fl
     const int k = blockIdx.x;
     float m = 0.0f;
     if constexpr (VEC) {
-        const int w4 = g.nx >> 2;
-        const int n4 = w4 * g.ny;
-        for (int t0 = threadIdx.x; t0 < n4; t0 += 4 * kAbsmaxThreads) {
+        const long long w4 = g.nx >> 2;
+        const long long n4 = w4 * g.ny;
+        for (long long t0 = threadIdx.x; t0 < n4; t0 += 4 * kAbsmaxThreads) {
             float4 v[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int t = t0 + q * kAbsmaxThreads;
+                const long long t = t0 + q * kAbsmaxThreads;
                 v[q] = make_float4(0.f, 0.f, 0.f, 0.f);
                 if (t < n4) {
-                    const int j = t / w4, i4 = t - j * w4;
+                    const int j = (int)(t / w4), i4 = (int)(t - j * w4);
                     v[q] = ld4(u + pidx(g, 4 * i4, j, k));
                 }
             }
@@ -761,15 +772,15 @@ __global__ __launch_bounds__(kAbsmaxThreads) void k_plane_absmax(Geo g, const fl
                 m = fmaxf(m, fmaxf(fmaxf(fabsf(v[q].x), fabsf(v[q].y)), fmaxf(fabsf(v[q].z), fabsf(v[q].w))));
         }
     } else {
-        const int nxy = g.nx * g.ny;
-        for (int t0 = threadIdx.x; t0 < nxy; t0 += 4 * kAbsmaxThreads) {
+        const long long nxy = (long long)g.nx * g.ny;
+        for (long long t0 = threadIdx.x; t0 < nxy; t0 += 4 * kAbsmaxThreads) {
             float v[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int t = t0 + q * kAbsmaxThreads;
+                const long long t = t0 + q * kAbsmaxThreads;
                 v[q] = 0.0f;
                 if (t < nxy) {
-                    const int j = t / g.nx, i = t - j * g.nx;
+                    const int j = (int)(t / g.nx), i = (int)(t - (long long)j * g.nx);
                     v[q] = u[pidx(g, i, j, k)];
                 }
             }
@@ -794,15 +805,15 @@ __global__ __launch_bounds__(kAbsmaxThreads) void k_plane_absmax(Geo g, const fl
 __global__ __launch_bounds__(kThreads) void k_encode(Geo g, const float *__restrict__ u, const float *__restrict__ scales,
                                                      uint16_t *__restrict__ codes, int fmt)
 {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long nxy = (long long)g.nx * g.ny;
-    if (t >= nxy * g.nz) return;
-    const int i = (int)(t % g.nx);
-    const int j = (int)((t / g.nx) % g.ny);
-    const int k = (int)(t / nxy);
-    const float sc = scales[k];
-    const float x = sc > 0.0f ? u[pidx(g, i, j, k)] / sc : 0.0f;
-    codes[t] = fmt == RTM_SNAP_BF16 ? f32_to_bf16_rne(x) : f32_to_f16_rne(x);
+    for (long long t = first_item(); t < nxy * g.nz; t += item_stride()) {
+        const int i = (int)(t % g.nx);
+        const int j = (int)((t / g.nx) % g.ny);
+        const int k = (int)(t / nxy);
+        const float sc = scales[k];
+        const float x = sc > 0.0f ? u[pidx(g, i, j, k)] / sc : 0.0f;
+        codes[t] = fmt == RTM_SNAP_BF16 ? f32_to_bf16_rne(x) : f32_to_f16_rne(x);
+    }
 }
 
 // image += weight * (decode(code) * scale) * rcv on owned cells.
@@ -810,16 +821,16 @@ __global__ __launch_bounds__(kThreads) void k_image_coded(Geo g, float *image, c
                                                           const float *__restrict__ scales, int fmt,
                                                           const float *__restrict__ rcv, float weight)
 {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long nxy = (long long)g.nx * g.ny;
-    if (t >= nxy * g.nz) return;
-    const int i = (int)(t % g.nx);
-    const int j = (int)((t / g.nx) % g.ny);
-    const int k = (int)(t / nxy);
-    const uint16_t c = codes[t];
-    const float s = (fmt == RTM_SNAP_BF16 ? bf16_to_f32(c) : f16_to_f32(c)) * scales[k];
-    const long long p = pidx(g, i, j, k);
-    image[p] = __builtin_fmaf(weight * s, rcv[p], image[p]);
+    for (long long t = first_item(); t < nxy * g.nz; t += item_stride()) {
+        const int i = (int)(t % g.nx);
+        const int j = (int)((t / g.nx) % g.ny);
+        const int k = (int)(t / nxy);
+        const uint16_t c = codes[t];
+        const float s = (fmt == RTM_SNAP_BF16 ? bf16_to_f32(c) : f16_to_f32(c)) * scales[k];
+        const long long p = pidx(g, i, j, k);
+        image[p] = __builtin_fmaf(weight * s, rcv[p], image[p]);
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -891,7 +902,9 @@ int launch_status()
     return e == hipSuccess ? RTM_OK : RTM_ELAUNCH;
 }
 
-unsigned blocks_for(long long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+// Workgroups for n items of an elementwise kernel (which strides by the grid beyond the cap).
+constexpr long long kMaxBlocks = 1ll << 20;
+unsigned blocks_for(long long n) { return (unsigned)std::min((n + kThreads - 1) / kThreads, kMaxBlocks); }
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
@@ -1321,18 +1334,23 @@ int rtm_pack_halo(const rtm_grid *grid, const float *u, float *faces, hipStream_
     if (!u || !faces) return RTM_EINVAL;
     FaceOffsets fo;
     fill_face_offsets(grid, fo.off);
-    for (int f = 0; f < 6; ++f)
-        if (fo.off[f + 1] - fo.off[f] >= (1ll << 31)) return RTM_EINVAL;
     if (ranges_overlap(faces, fo.off[6], u, padded_total(grid))) return RTM_EALIAS;
     st = check_device();
     if (st != RTM_OK) return st;
     const Geo g = make_geo(grid);
     long long mx = 0;
     for (int f = 0; f < 6; ++f) mx = std::max(mx, fo.off[f + 1] - fo.off[f]);
+    const bool narrow = mx < (1ll << 31);     // 32-bit face counters suffice
     if (faces_vec(g, u) && aligned16(faces)) {
-        hipLaunchKernelGGL(k_pack4, dim3(blocks_for(mx / 4), 6), dim3(kThreads), 0, stream, g, u, faces, fo);
+        if (narrow)
+            hipLaunchKernelGGL(k_pack4<unsigned>, dim3(blocks_for(mx / 4), 6), dim3(kThreads), 0, stream, g, u, faces, fo);
+        else
+            hipLaunchKernelGGL(k_pack4<long long>, dim3(blocks_for(mx / 4), 6), dim3(kThreads), 0, stream, g, u, faces, fo);
     } else {
-        hipLaunchKernelGGL(k_pack, dim3(blocks_for(mx), 6), dim3(kThreads), 0, stream, g, u, faces, fo);
+        if (narrow)
+            hipLaunchKernelGGL(k_pack<unsigned>, dim3(blocks_for(mx), 6), dim3(kThreads), 0, stream, g, u, faces, fo);
+        else
+            hipLaunchKernelGGL(k_pack<long long>, dim3(blocks_for(mx), 6), dim3(kThreads), 0, stream, g, u, faces, fo);
     }
     return launch_status();
 }
@@ -1346,8 +1364,6 @@ int rtm_step_halo_pack(const rtm_grid *grid, float *u_nxt, const float *u_cur, c
     if (!faces) return RTM_EINVAL;
     long long off[7];
     fill_face_offsets(grid, off);
-    for (int f = 0; f < 6; ++f)
-        if (off[f + 1] - off[f] >= (1ll << 31)) return RTM_EINVAL;
     const long long tot = padded_total(grid);
     if (ranges_overlap(faces, off[6], u_nxt, tot) || ranges_overlap(faces, off[6], u_cur, tot) ||
         ranges_overlap(faces, off[6], u_prv, tot) || ranges_overlap(faces, off[6], kappa, tot))
@@ -1391,8 +1407,6 @@ int rtm_unpack_halo(const rtm_grid *grid, float *u, const float *const faces[6],
     if (!u || !faces) return RTM_EINVAL;
     long long off[7];
     fill_face_offsets(grid, off);
-    for (int f = 0; f < 6; ++f)
-        if (off[f + 1] - off[f] >= (1ll << 31)) return RTM_EINVAL;
     FacePtrs fp;
     const long long tot = padded_total(grid);
     for (int f = 0; f < 6; ++f) {
@@ -1406,10 +1420,17 @@ int rtm_unpack_halo(const rtm_grid *grid, float *u, const float *const faces[6],
     for (int f = 0; f < 6; ++f) mx = std::max(mx, off[f + 1] - off[f]);
     bool vec = faces_vec(g, u);
     for (int f = 0; f < 6; ++f) vec = vec && (fp.p[f] == nullptr || aligned16(fp.p[f]));
+    const bool narrow = mx < (1ll << 31);     // 32-bit face counters suffice
     if (vec) {
-        hipLaunchKernelGGL(k_unpack4, dim3(blocks_for(mx / 4), 6), dim3(kThreads), 0, stream, g, u, fp);
+        if (narrow)
+            hipLaunchKernelGGL(k_unpack4<unsigned>, dim3(blocks_for(mx / 4), 6), dim3(kThreads), 0, stream, g, u, fp);
+        else
+            hipLaunchKernelGGL(k_unpack4<long long>, dim3(blocks_for(mx / 4), 6), dim3(kThreads), 0, stream, g, u, fp);
     } else {
-        hipLaunchKernelGGL(k_unpack, dim3(blocks_for(mx), 6), dim3(kThreads), 0, stream, g, u, fp);
+        if (narrow)
+            hipLaunchKernelGGL(k_unpack<unsigned>, dim3(blocks_for(mx), 6), dim3(kThreads), 0, stream, g, u, fp);
+        else
+            hipLaunchKernelGGL(k_unpack<long long>, dim3(blocks_for(mx), 6), dim3(kThreads), 0, stream, g, u, fp);
     }
     return launch_status();
 }

@@ -382,7 +382,7 @@ def summarize_corrected(stats_dir, out, n, steps, every, commands):
     ncorr = max(1, sum(v for k, v in calls.items() if "k_absmax_" in k))   # one scale per correction
     update = [v for k, v in avg.items() if "k_tiled<2," in k]
     step = total("k_tiled<2,", "k_inject", "k_unpack") / steps
-    corr = total("k_conv3d", "k_absmax_", "k_zero1", "k_pack(") / ncorr
+    corr = total("k_conv3d", "k_absmax_", "k_zero1", "k_pack(", "k_pack<") / ncorr
     lines += ["", f"Per coarse step (one-launch update, inject, ghost refresh): {step:.0f} us"
                   + (f" (the update {update[0]:.0f} us)" if update else ""),
               f"Per correction (scale, first layer with the input packing, middle layer, last layer applying the "

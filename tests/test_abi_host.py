@@ -87,6 +87,8 @@ def test_validation_before_device(abi):
     assert L.rtm_inject(gp, 4096, 64, 64, 64, -1, None) == abi.RTM_EINVAL
     assert L.rtm_inject(gp, 4096, 64, 64, 64, 0, None) == abi.RTM_OK                # nothing to do
     assert L.rtm_record(gp, 4096, 64, 64, -5, None) == abi.RTM_EINVAL
+    assert L.rtm_record(gp, None, None, None, 0, None) == abi.RTM_OK               # nothing to do
+    assert L.rtm_inject(gp, None, None, None, None, 0, None) == abi.RTM_OK
     assert L.rtm_image_accumulate(gp, 4096, 4096, 1 << 40, 1.0, None) == abi.RTM_EALIAS
     assert L.rtm_set_option(99, 0) == abi.RTM_EINVAL
     assert L.rtm_set_option(abi.RTM_OPT_INTERIOR_VARIANT, 7) == abi.RTM_EINVAL

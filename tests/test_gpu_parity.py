@@ -544,6 +544,30 @@ def test_smallest_boxes_parity(torch_cuda):
             assert e <= 1e-4
 
 
+def test_empty_problem_stays_zero(torch_cuda):
+    """No sources, no receivers, a zero state: every schedule keeps every cell exactly zero (nothing
+    reads an unset ghost or stale buffer), and a run of zero steps leaves a given state untouched."""
+    torch = torch_cuda
+    from paper_1603_03971_amd import synth
+    from paper_1603_03971_amd.grid import Grid
+    from paper_1603_03971_amd.propagator import Propagator
+
+    shape = (37, 45, 70)
+    g = Grid(shape[2], shape[1], shape[0], 10.0, Grid.stable_dt(4, 10.0, 3000.0))
+    kap = g.kappa_from_velocity(synth.random_smooth_velocity(shape, seed=77, vmin=1500, vmax=3000))
+    for schedule in ("serial", "overlap", "fused"):
+        prop = Propagator(g, kap, schedule=schedule)
+        traces = prop.new_traces(7)
+        prop.run(7, traces)
+        assert int(torch.count_nonzero(prop.u_cur)) == 0 and int(torch.count_nonzero(prop.u_prv)) == 0, schedule
+        assert int(torch.count_nonzero(traces)) == 0
+        u0, um = synth.random_field(shape, 78), synth.random_field(shape, 79)
+        prop.set_state(u0, um)
+        prop.run(0)
+        assert np.array_equal(g.download(prop.u_cur), u0.astype(np.float32))
+        assert np.array_equal(g.download(prop.u_prv), um.astype(np.float32))
+
+
 def synth_layered(shape):
     from paper_1603_03971_amd import synth
 

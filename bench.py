@@ -42,8 +42,12 @@ def parse():
 
 
 def kernel_source_hash() -> str:
-    with open(os.path.join(ROOT, "paper_1603_03971_amd", "csrc", "rtm.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of what the counted traffic depends on: the kernel source and the field layout."""
+    h = hashlib.sha256()
+    for part in (("csrc", "rtm.hip"), ("grid.py",)):
+        with open(os.path.join(ROOT, "paper_1603_03971_amd", *part), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def host_threads() -> int:

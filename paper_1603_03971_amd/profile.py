@@ -5,6 +5,10 @@
       and, for counter calibration, a plain device copy of 1 GiB (reads and writes exactly 1 GiB).
       Run it under `rocprofv3 --pmc FETCH_SIZE` and, separately, `rocprofv3 --pmc WRITE_SIZE`.
 
+  python3 -m paper_1603_03971_amd.profile halo [--n 512] [--launches 10]
+      the same for the halo call (rtm_step_halo: the z slabs, y strips and x strips of the halo
+      region), for its counters.
+
   python3 -m paper_1603_03971_amd.profile conv [--n 384] [--launches 10]
       runs the corrector network's forward pass (three 3x3x3 convolutions, 16 channels, BF16 MFMA)
       on an n^3 volume `launches` times, for a kernel trace of the convolution.
@@ -33,6 +37,10 @@
       runs above) and writes a short text summary plus the traffic record that bench.py reports
       (keyed by a hash of the kernel source, so stale counters are never reported).
 
+  python3 -m paper_1603_03971_amd.profile summarize-halo --fetch DIR --write DIR --out FILE [--stats DIR]
+      the halo call's HBM traffic from the counter runs of `halo` (and its kernel-trace time from the
+      benchmark's kernel statistics, if given).
+
   python3 -m paper_1603_03971_amd.profile summarize-conv --stats DIR --out FILE [--n 384]
   python3 -m paper_1603_03971_amd.profile summarize-corrected --stats DIR --out FILE [--n 384 ...]
       the same for kernel traces of the `conv` and `corrected` runs (per-launch rates; per-step and
@@ -53,7 +61,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_BYTES = 1 << 30
 
 
-def run_interior(n: int, launches: int):
+def run_interior(n: int, launches: int, call: str = "interior"):
     import numpy as np
     import torch
 
@@ -69,14 +77,16 @@ def run_interior(n: int, launches: int):
     g.owned(u).normal_()
     g.owned(up).normal_()
     s = torch.cuda.current_stream()
+    step = _abi.rtm_step_interior if call == "interior" else _abi.rtm_step_halo
     for _ in range(launches):
-        _abi.rtm_step_interior(g.c, up, u, up, kap, s)
+        step(g.c, up, u, up, kap, s)
     a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
     wx, hy, R = _abi.rtm_halo_region(g.c)
-    print(json.dumps({"interior_points": (n - 2 * wx) * (n - 2 * hy) * (n - 2 * R), "copy_bytes": COPY_BYTES}))
+    interior = (n - 2 * wx) * (n - 2 * hy) * (n - 2 * R)
+    print(json.dumps({f"{call}_points": interior if call == "interior" else n**3 - interior, "copy_bytes": COPY_BYTES}))
 
 
 def run_conv(n: int, launches: int):
@@ -292,8 +302,12 @@ def _counter(rows, kernel_substr: str, counter: str, largest: bool = False):
 
 
 def kernel_source_hash() -> str:
-    with open(os.path.join(ROOT, "paper_1603_03971_amd", "csrc", "rtm.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of what the counted traffic depends on: the kernel source and the field layout."""
+    h = hashlib.sha256()
+    for part in (("csrc", "rtm.hip"), ("grid.py",)):
+        with open(os.path.join(ROOT, "paper_1603_03971_amd", *part), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def summarize(stats_dir, fetch_dir, write_dir, out, n, commands):
@@ -354,6 +368,39 @@ def summarize(stats_dir, fetch_dir, write_dir, out, n, commands):
     with open(os.path.splitext(out)[0] + "_traffic.txt", "w") as f:
         json.dump(record, f)
         f.write("\n")
+    print(text)
+
+
+def summarize_halo(fetch_dir, write_dir, out, n, commands, stats_dir=None):
+    """HBM traffic of the halo call from the FETCH_SIZE / WRITE_SIZE runs of `halo`."""
+    fr, wr = _csv(fetch_dir, "*counter_collection.csv"), _csv(write_dir, "*counter_collection.csv")
+    f_h, nf = _counter(fr, HALO_KERNEL, "FETCH_SIZE")
+    w_h, nw = _counter(wr, HALO_KERNEL, "WRITE_SIZE")
+    f_cp, _ = _counter(fr, "opy", "FETCH_SIZE", largest=True)
+    w_cp, _ = _counter(wr, "opy", "WRITE_SIZE", largest=True)
+    kf = COPY_BYTES / (f_cp * 1024.0)
+    kw = COPY_BYTES / (w_cp * 1024.0)
+    rd, wt = f_h * 1024.0 * kf, w_h * 1024.0 * kw
+    pts = n**3 - (n - 128) * (n - 32) * (n - 8)
+    lines = [f"# rocprofv3 summary: HBM traffic of the halo call, {n}^3 layered forward workload", "",
+             "Commands:"] + [f"    {c}" for c in commands] + [""]
+    lines += ["Halo call (rtm_step_halo: two 4-plane z slabs, two 16-row y strips, two 64-column x strips):",
+              f"    cells {pts} (the interior call's box is the rest)",
+              f"    FETCH_SIZE {f_h:.0f} KiB ({nf} dispatches), WRITE_SIZE {w_h:.0f} KiB ({nw} dispatches)",
+              f"    calibration with a plain 1 GiB device copy: FETCH x {kf:.3f}, WRITE x {kw:.3f}",
+              f"    read {rd / 1e6:.1f} MB against 12 B x cells = {12 * pts / 1e6:.1f} MB (ratio {rd / (12 * pts):.3f})",
+              f"    written {wt / 1e6:.1f} MB against 4 B x cells = {4 * pts / 1e6:.1f} MB (ratio {wt / (4 * pts):.3f})",
+              f"    total {(rd + wt) / 1e6:.1f} MB per launch, {(rd + wt) / (16 * pts):.3f} x algorithmic"]
+    if stats_dir:
+        for r in _csv(stats_dir, "*kernel_stats.csv"):
+            if HALO_KERNEL in r["Name"]:
+                us = float(r["AverageNs"]) / 1e3
+                lines.append(f"    kernel trace of the benchmark run: {us:.1f} us per launch -> "
+                             f"{16 * pts / us / 1e6:.2f} TB/s algorithmic, {(rd + wt) / us / 1e6:.2f} TB/s moved")
+                break
+    text = "\n".join(lines) + "\n"
+    with open(out, "w") as f:
+        f.write(text)
     print(text)
 
 
@@ -436,6 +483,16 @@ def main(argv=None):
     a = sub.add_parser("interior")
     a.add_argument("--n", type=int, default=512)
     a.add_argument("--launches", type=int, default=10)
+    hl = sub.add_parser("halo")
+    hl.add_argument("--n", type=int, default=512)
+    hl.add_argument("--launches", type=int, default=10)
+    bh = sub.add_parser("summarize-halo")
+    bh.add_argument("--fetch", required=True)
+    bh.add_argument("--write", required=True)
+    bh.add_argument("--stats")
+    bh.add_argument("--out", required=True)
+    bh.add_argument("--n", type=int, default=512)
+    bh.add_argument("--command", action="append", default=[])
     cv = sub.add_parser("conv")
     cv.add_argument("--n", type=int, default=384)
     cv.add_argument("--launches", type=int, default=10)
@@ -481,6 +538,10 @@ def main(argv=None):
     args = ap.parse_args(argv)
     if args.cmd == "interior":
         run_interior(args.n, args.launches)
+    elif args.cmd == "halo":
+        run_interior(args.n, args.launches, call="halo")
+    elif args.cmd == "summarize-halo":
+        summarize_halo(args.fetch, args.write, args.out, args.n, args.command, args.stats)
     elif args.cmd == "conv":
         run_conv(args.n, args.launches)
     elif args.cmd == "corrected":

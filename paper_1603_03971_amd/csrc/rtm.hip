@@ -644,30 +644,64 @@ __global__ __launch_bounds__(kThreads) void k_record(const float *__restrict__ u
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_image(Geo g, float *image, const float *__restrict__ src,
-                                                    const float *__restrict__ rcv, float weight)
+// Owned-cell elementwise kernels walk the owned rows (j, k): one wave per row (a grid-stride loop over
+// rows with 64-bit counters), its lanes over x, four cells per lane when VEC (every row's owned cells
+// then start on a 16-byte boundary: R % 4 == 0, nx % 4 == 0 and both pitches multiples of 4).  One
+// division per row instead of three 64-bit divisions per cell keeps these kernels on HBM rather than
+// on integer arithmetic.  f(p, c, k) handles the cell(s) at padded index p and compact index c
+// ((k ny + j) nx + i) in plane k.
+constexpr int kRowWaves = kThreads / 64;
+
+template <bool VEC, typename F>
+__device__ __forceinline__ void owned_rows(const Geo &g, F &&f)
 {
-    const long long nxy = (long long)g.nx * g.ny;
-    for (long long t = first_item(); t < nxy * g.nz; t += item_stride()) {
-        const int i = (int)(t % g.nx);
-        const int j = (int)((t / g.nx) % g.ny);
-        const int k = (int)(t / nxy);
-        const long long p = pidx(g, i, j, k);
-        image[p] = __builtin_fmaf(weight * src[p], rcv[p], image[p]);
+    const int lane = threadIdx.x & 63;
+    const long long rows = (long long)g.ny * g.nz;
+    const long long wstride = (long long)gridDim.x * kRowWaves;
+    for (long long r = (long long)blockIdx.x * kRowWaves + (threadIdx.x >> 6); r < rows; r += wstride) {
+        const int k = (int)(r / g.ny), j = (int)(r - (long long)k * g.ny);
+        const long long p0 = pidx(g, 0, j, k), c0 = r * g.nx;
+        if constexpr (VEC) {
+            for (int i = 4 * lane; i < g.nx; i += 256) f(p0 + i, c0 + i, k);
+        } else {
+            for (int i = lane; i < g.nx; i += 64) f(p0 + i, c0 + i, k);
+        }
     }
 }
 
+template <bool VEC>
+__global__ __launch_bounds__(kThreads) void k_image(Geo g, float *image, const float *__restrict__ src,
+                                                    const float *__restrict__ rcv, float weight)
+{
+    owned_rows<VEC>(g, [&](long long p, long long, int) {
+        if constexpr (VEC) {
+            const float4 s4 = ld4(src + p), r4 = ld4(rcv + p);
+            float4 o = ld4(image + p);
+            o.x = __builtin_fmaf(weight * s4.x, r4.x, o.x);
+            o.y = __builtin_fmaf(weight * s4.y, r4.y, o.y);
+            o.z = __builtin_fmaf(weight * s4.z, r4.z, o.z);
+            o.w = __builtin_fmaf(weight * s4.w, r4.w, o.w);
+            st4(image + p, o);
+        } else {
+            image[p] = __builtin_fmaf(weight * src[p], rcv[p], image[p]);
+        }
+    });
+}
+
+template <bool VEC>
 __global__ __launch_bounds__(kThreads) void k_kappa(Geo g, float *__restrict__ kappa, const float *__restrict__ v,
                                                     float s)
 {
-    const long long nxy = (long long)g.nx * g.ny;
-    for (long long t = first_item(); t < nxy * g.nz; t += item_stride()) {
-        const int i = (int)(t % g.nx);
-        const int j = (int)((t / g.nx) % g.ny);
-        const int k = (int)(t / nxy);
-        const float a = v[t] * s;
-        kappa[pidx(g, i, j, k)] = a * a;
-    }
+    owned_rows<VEC>(g, [&](long long p, long long c, int) {
+        if constexpr (VEC) {
+            const float4 v4 = ld4(v + c);
+            const float a0 = v4.x * s, a1 = v4.y * s, a2 = v4.z * s, a3 = v4.w * s;
+            st4(kappa + p, make_float4(a0 * a0, a1 * a1, a2 * a2, a3 * a3));
+        } else {
+            const float a = v[c] * s;
+            kappa[p] = a * a;
+        }
+    });
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -711,17 +745,21 @@ __global__ __launch_bounds__(kReduceThreads) void k_residual(const float *__rest
 }
 
 // grad_v (compact, x fastest) = 2 v (dt/h)^2 grad_kappa (the chain rule through kappa = (v dt/h)^2).
+template <bool VEC>
 __global__ __launch_bounds__(kThreads) void k_velocity_gradient(Geo g, float *__restrict__ gv,
                                                                 const float *__restrict__ gk,
                                                                 const float *__restrict__ v, float s2)
 {
-    const long long nxy = (long long)g.nx * g.ny;
-    for (long long t = first_item(); t < nxy * g.nz; t += item_stride()) {
-        const int i = (int)(t % g.nx);
-        const int j = (int)((t / g.nx) % g.ny);
-        const int k = (int)(t / nxy);
-        gv[t] = (2.0f * s2) * v[t] * gk[pidx(g, i, j, k)];
-    }
+    const float two_s2 = 2.0f * s2;
+    owned_rows<VEC>(g, [&](long long p, long long c, int) {
+        if constexpr (VEC) {
+            const float4 v4 = ld4(v + c), k4 = ld4(gk + p);
+            st4(gv + c, make_float4(two_s2 * v4.x * k4.x, two_s2 * v4.y * k4.y, two_s2 * v4.z * k4.z,
+                                    two_s2 * v4.w * k4.w));
+        } else {
+            gv[c] = two_s2 * v[c] * gk[p];
+        }
+    });
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -802,35 +840,52 @@ __global__ __launch_bounds__(kAbsmaxThreads) void k_plane_absmax(Geo g, const fl
 }
 
 // codes[(k ny + j) nx + i] = RNE(u / scales[k]) in the 16-bit format; a zero scale gives zero codes.
+template <bool VEC>
 __global__ __launch_bounds__(kThreads) void k_encode(Geo g, const float *__restrict__ u, const float *__restrict__ scales,
                                                      uint16_t *__restrict__ codes, int fmt)
 {
-    const long long nxy = (long long)g.nx * g.ny;
-    for (long long t = first_item(); t < nxy * g.nz; t += item_stride()) {
-        const int i = (int)(t % g.nx);
-        const int j = (int)((t / g.nx) % g.ny);
-        const int k = (int)(t / nxy);
+    auto code = [&](float x, float sc) -> uint32_t {
+        const float q = sc > 0.0f ? x / sc : 0.0f;
+        return fmt == RTM_SNAP_BF16 ? f32_to_bf16_rne(q) : f32_to_f16_rne(q);
+    };
+    owned_rows<VEC>(g, [&](long long p, long long c, int k) {
         const float sc = scales[k];
-        const float x = sc > 0.0f ? u[pidx(g, i, j, k)] / sc : 0.0f;
-        codes[t] = fmt == RTM_SNAP_BF16 ? f32_to_bf16_rne(x) : f32_to_f16_rne(x);
-    }
+        if constexpr (VEC) {
+            const float4 u4 = ld4(u + p);
+            uint2 w;
+            w.x = code(u4.x, sc) | (code(u4.y, sc) << 16);
+            w.y = code(u4.z, sc) | (code(u4.w, sc) << 16);
+            *reinterpret_cast<uint2 *>(codes + c) = w;
+        } else {
+            codes[c] = (uint16_t)code(u[p], sc);
+        }
+    });
 }
 
 // image += weight * (decode(code) * scale) * rcv on owned cells.
+template <bool VEC>
 __global__ __launch_bounds__(kThreads) void k_image_coded(Geo g, float *image, const uint16_t *__restrict__ codes,
                                                           const float *__restrict__ scales, int fmt,
                                                           const float *__restrict__ rcv, float weight)
 {
-    const long long nxy = (long long)g.nx * g.ny;
-    for (long long t = first_item(); t < nxy * g.nz; t += item_stride()) {
-        const int i = (int)(t % g.nx);
-        const int j = (int)((t / g.nx) % g.ny);
-        const int k = (int)(t / nxy);
-        const uint16_t c = codes[t];
-        const float s = (fmt == RTM_SNAP_BF16 ? bf16_to_f32(c) : f16_to_f32(c)) * scales[k];
-        const long long p = pidx(g, i, j, k);
-        image[p] = __builtin_fmaf(weight * s, rcv[p], image[p]);
-    }
+    auto value = [&](uint32_t c, float sc) {
+        return (fmt == RTM_SNAP_BF16 ? bf16_to_f32((uint16_t)c) : f16_to_f32((uint16_t)c)) * sc;
+    };
+    owned_rows<VEC>(g, [&](long long p, long long c, int k) {
+        const float sc = scales[k];
+        if constexpr (VEC) {
+            const uint2 w = *reinterpret_cast<const uint2 *>(codes + c);
+            const float4 r4 = ld4(rcv + p);
+            float4 o = ld4(image + p);
+            o.x = __builtin_fmaf(weight * value(w.x & 0xFFFFu, sc), r4.x, o.x);
+            o.y = __builtin_fmaf(weight * value(w.x >> 16, sc), r4.y, o.y);
+            o.z = __builtin_fmaf(weight * value(w.y & 0xFFFFu, sc), r4.z, o.z);
+            o.w = __builtin_fmaf(weight * value(w.y >> 16, sc), r4.w, o.w);
+            st4(image + p, o);
+        } else {
+            image[p] = __builtin_fmaf(weight * value(codes[c], sc), rcv[p], image[p]);
+        }
+    });
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -907,6 +962,16 @@ constexpr long long kMaxBlocks = 1ll << 20;
 unsigned blocks_for(long long n) { return (unsigned)std::min((n + kThreads - 1) / kThreads, kMaxBlocks); }
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+// Workgroups for the owned-row kernels (kRowWaves rows each, grid-stride beyond the cap), and whether
+// every row's owned cells start on a float4 boundary of the padded layout.
+unsigned row_blocks(const Geo &g)
+{
+    const long long rows = (long long)g.ny * g.nz;
+    return (unsigned)std::min((rows + kRowWaves - 1) / kRowWaves, kMaxBlocks);
+}
+bool rows_vec(const Geo &g) { return g.R % 4 == 0 && g.nx % 4 == 0 && g.py % 4 == 0 && g.pz % 4 == 0; }
 
 int cu_count()
 {
@@ -1475,8 +1540,10 @@ int rtm_image_accumulate(const rtm_grid *grid, float *image, const float *src, c
     st = check_device();
     if (st != RTM_OK) return st;
     const Geo g = make_geo(grid);
-    const long long n = (long long)g.nx * g.ny * g.nz;
-    hipLaunchKernelGGL(k_image, dim3(blocks_for(n)), dim3(kThreads), 0, stream, g, image, src, rcv, weight);
+    if (rows_vec(g) && aligned16(image) && aligned16(src) && aligned16(rcv))
+        hipLaunchKernelGGL(k_image<true>, dim3(row_blocks(g)), dim3(kThreads), 0, stream, g, image, src, rcv, weight);
+    else
+        hipLaunchKernelGGL(k_image<false>, dim3(row_blocks(g)), dim3(kThreads), 0, stream, g, image, src, rcv, weight);
     return launch_status();
 }
 
@@ -1490,7 +1557,10 @@ int rtm_kappa_from_velocity(const rtm_grid *grid, float *kappa, const float *v, 
     st = check_device();
     if (st != RTM_OK) return st;
     const Geo g = make_geo(grid);
-    hipLaunchKernelGGL(k_kappa, dim3(blocks_for(n)), dim3(kThreads), 0, stream, g, kappa, v, dt_over_h);
+    if (rows_vec(g) && aligned16(kappa) && aligned16(v))
+        hipLaunchKernelGGL(k_kappa<true>, dim3(row_blocks(g)), dim3(kThreads), 0, stream, g, kappa, v, dt_over_h);
+    else
+        hipLaunchKernelGGL(k_kappa<false>, dim3(row_blocks(g)), dim3(kThreads), 0, stream, g, kappa, v, dt_over_h);
     return launch_status();
 }
 
@@ -1572,8 +1642,12 @@ int rtm_velocity_gradient(const rtm_grid *grid, float *grad_v, const float *grad
     st = check_device();
     if (st != RTM_OK) return st;
     const Geo g = make_geo(grid);
-    hipLaunchKernelGGL(k_velocity_gradient, dim3(blocks_for(n)), dim3(kThreads), 0, stream, g, grad_v, grad_kappa, v,
-                       dt_over_h * dt_over_h);
+    if (rows_vec(g) && aligned16(grad_v) && aligned16(grad_kappa) && aligned16(v))
+        hipLaunchKernelGGL(k_velocity_gradient<true>, dim3(row_blocks(g)), dim3(kThreads), 0, stream, g, grad_v,
+                           grad_kappa, v, dt_over_h * dt_over_h);
+    else
+        hipLaunchKernelGGL(k_velocity_gradient<false>, dim3(row_blocks(g)), dim3(kThreads), 0, stream, g, grad_v,
+                           grad_kappa, v, dt_over_h * dt_over_h);
     return launch_status();
 }
 
@@ -1599,7 +1673,12 @@ int rtm_snapshot_encode(const rtm_grid *grid, const float *u, uint16_t *codes, f
         hipLaunchKernelGGL((k_plane_absmax<false>), dim3(g.nz), dim3(kAbsmaxThreads), 0, stream, g, u, scales);
     st = launch_status();
     if (st != RTM_OK) return st;
-    hipLaunchKernelGGL(k_encode, dim3(blocks_for(n)), dim3(kThreads), 0, stream, g, u, scales, codes, (int)format);
+    if (rows_vec(g) && aligned16(u) && aligned8(codes))
+        hipLaunchKernelGGL(k_encode<true>, dim3(row_blocks(g)), dim3(kThreads), 0, stream, g, u, scales, codes,
+                           (int)format);
+    else
+        hipLaunchKernelGGL(k_encode<false>, dim3(row_blocks(g)), dim3(kThreads), 0, stream, g, u, scales, codes,
+                           (int)format);
     return launch_status();
 }
 
@@ -1618,8 +1697,12 @@ int rtm_image_accumulate_coded(const rtm_grid *grid, float *image, const uint16_
     st = check_device();
     if (st != RTM_OK) return st;
     const Geo g = make_geo(grid);
-    hipLaunchKernelGGL(k_image_coded, dim3(blocks_for(n)), dim3(kThreads), 0, stream, g, image, codes, scales,
-                       (int)format, rcv, weight);
+    if (rows_vec(g) && aligned16(image) && aligned16(rcv) && aligned8(codes))
+        hipLaunchKernelGGL(k_image_coded<true>, dim3(row_blocks(g)), dim3(kThreads), 0, stream, g, image, codes,
+                           scales, (int)format, rcv, weight);
+    else
+        hipLaunchKernelGGL(k_image_coded<false>, dim3(row_blocks(g)), dim3(kThreads), 0, stream, g, image, codes,
+                           scales, (int)format, rcv, weight);
     return launch_status();
 }
 

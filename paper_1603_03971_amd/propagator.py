@@ -62,24 +62,23 @@ class Sources:
         face = shell & ((ijk[:, 0] < R) | (ijk[:, 0] >= grid.nx - R) | (ijk[:, 1] < R) | (ijk[:, 1] >= grid.ny - R)
                         | (ijk[:, 2] < R) | (ijk[:, 2] >= grid.nz - R))
         self.face_idx = torch.from_numpy(grid.index(ijk[face])).to(grid.device) if face.any() else None
-        self.sets = []
-        for mask in (shell, ~shell):
-            sel = np.nonzero(mask)[0]
-            if len(sel) == 0:
-                self.sets.append(None)
-                continue
-            idx = torch.from_numpy(grid.index(ijk[sel])).to(grid.device)
-            ww = torch.from_numpy(w[sel]).to(grid.device)
-            a = amp_t[:, torch.from_numpy(sel).to(grid.device)].contiguous()
-            self.sets.append((idx, ww, a))
+        # one table with the halo-region sources first: set 0 (halo region), set 1 (the rest) and set 2
+        # (all, for a schedule that updates every cell in one launch) are column ranges of it
+        order = np.concatenate([np.nonzero(shell)[0], np.nonzero(~shell)[0]])
+        n0 = int(shell.sum())
+        self.count = len(order)
+        self.idx = torch.from_numpy(grid.index(ijk[order])).to(grid.device)
+        self.w = torch.from_numpy(w[order]).to(grid.device)
+        self.amp = amp_t[:, torch.from_numpy(order).to(grid.device)].contiguous()
+        self.ranges = [(0, n0), (n0, self.count - n0), (0, self.count)]
 
     def inject(self, grid: Grid, u: torch.Tensor, n: int, which: int, stream):
-        s = self.sets[which]
-        if s is None or n >= self.nsteps:
+        """Add row n of the amplitude table at set `which`: 0 = halo region, 1 = the rest, 2 = all."""
+        off, cnt = self.ranges[which]
+        if cnt == 0 or n >= self.nsteps:
             return
-        idx, w, a = s
-        cnt = idx.numel()
-        _abi.rtm_inject(grid.c, u, idx, w, a.data_ptr() + 4 * n * cnt, cnt, stream)
+        _abi.rtm_inject(grid.c, u, self.idx.data_ptr() + 8 * off, self.w.data_ptr() + 4 * off,
+                        self.amp.data_ptr() + 4 * (n * self.count + off), cnt, stream)
 
     def repack(self, grid: Grid, u: torch.Tensor, n: int, faces: torch.Tensor, stream):
         """After the halo-region injection of row n: copy the injected face cells into `faces`."""
@@ -210,8 +209,7 @@ class Propagator:
             st = torch.cuda.current_stream()
             _abi.rtm_step_whole(c, u_nxt, u_cur, u_prv, kap, st)
             for s in self.sources:
-                s.inject(g, u_nxt, n, 0, st)
-                s.inject(g, u_nxt, n, 1, st)
+                s.inject(g, u_nxt, n, 2, st)
             if any(r is not None for r in self.recv):
                 _abi.rtm_pack_halo(c, u_nxt, self.send, st)
                 _abi.rtm_unpack_halo(c, u_nxt, self.recv, st)

@@ -284,6 +284,18 @@ int rtm_cnn_conv3d(int32_t nx, int32_t ny, int32_t nz, const uint16_t *x, const 
 int rtm_cnn_conv3d_wgrad(int32_t nx, int32_t ny, int32_t nz, const uint16_t *x, const float *dz, float *dw, float *db,
                          hipStream_t stream);
 
+/* The same weight gradient with a fixed summation order, so that repeated calls (and trainings) give
+ * the same bits: each workgroup's partial sums go to its own slot of `partials` (caller-owned device
+ * FP32 buffer of at least rtm_cnn_wgrad_partials(nx, ny, nz) elements, contents overwritten), and a
+ * second kernel adds the slots in order into dw and db.  RTM_EINVAL for bad dimensions, a NULL pointer
+ * or a short buffer.  The result differs from rtm_cnn_conv3d_wgrad's only by summation order. */
+int rtm_cnn_conv3d_wgrad_ordered(int32_t nx, int32_t ny, int32_t nz, const uint16_t *x, const float *dz, float *dw,
+                                 float *db, float *partials, int64_t partials_len, hipStream_t stream);
+
+/* Elements of `partials` that rtm_cnn_conv3d_wgrad_ordered needs for this volume (one slot of
+ * 27*16*16 + 16 floats per workgroup of 64 x 4 voxels and one plane), or RTM_EINVAL. */
+int64_t rtm_cnn_wgrad_partials(int32_t nx, int32_t ny, int32_t nz);
+
 /* dz = dy for channels < channels (0 elsewhere), times the ReLU derivative (y > 0) when relu != 0;
  * written compact FP32 (dz32) and BF16 with halo (dz16). */
 int rtm_cnn_relu_backward(int32_t nx, int32_t ny, int32_t nz, const float *y, const float *dy, int32_t relu,

@@ -73,6 +73,8 @@ def _load():
         "rtm_image_accumulate_coded": ([gp, vp, vp, vp, i32, vp, f32, vp], ctypes.c_int),
         "rtm_cnn_conv3d": ([i32, i32, i32, vp, vp, vp, i32, vp, i32, vp, vp], ctypes.c_int),
         "rtm_cnn_conv3d_wgrad": ([i32, i32, i32, vp, vp, vp, vp, vp], ctypes.c_int),
+        "rtm_cnn_conv3d_wgrad_ordered": ([i32, i32, i32, vp, vp, vp, vp, vp, i64, vp], ctypes.c_int),
+        "rtm_cnn_wgrad_partials": ([i32, i32, i32], i64),
         "rtm_cnn_relu_backward": ([i32, i32, i32, vp, vp, i32, i32, vp, vp, vp], ctypes.c_int),
         "rtm_cnn_loss_grad": ([i32, i32, i32, vp, vp, i32, f32, vp, vp, vp, vp, vp], ctypes.c_int),
         "rtm_cnn_weight_flip": ([vp, vp, vp], ctypes.c_int),
@@ -271,6 +273,18 @@ def rtm_cnn_conv3d(nx, ny, nz, x, w, bias, relu, y32, y16, stream=None, y32_chan
 
 def rtm_cnn_conv3d_wgrad(nx, ny, nz, x, dz, dw, db, stream=None):
     _check(_lib.rtm_cnn_conv3d_wgrad(nx, ny, nz, _p(x), _p(dz), _p(dw), _p(db), _s(stream)), "rtm_cnn_conv3d_wgrad")
+
+
+def rtm_cnn_wgrad_partials(nx, ny, nz) -> int:
+    n = int(_lib.rtm_cnn_wgrad_partials(nx, ny, nz))
+    if n < 0:
+        raise RTMError(n, "rtm_cnn_wgrad_partials")
+    return n
+
+
+def rtm_cnn_conv3d_wgrad_ordered(nx, ny, nz, x, dz, dw, db, partials, partials_len, stream=None):
+    _check(_lib.rtm_cnn_conv3d_wgrad_ordered(nx, ny, nz, _p(x), _p(dz), _p(dw), _p(db), _p(partials), partials_len,
+                                             _s(stream)), "rtm_cnn_conv3d_wgrad_ordered")
 
 
 def rtm_cnn_relu_backward(nx, ny, nz, y, dy, relu, channels, dz32, dz16, stream=None):

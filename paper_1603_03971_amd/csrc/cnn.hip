@@ -395,9 +395,16 @@ __global__ __launch_bounds__(64 * TY) void k_conv3d(Vol v, int zc, const uint16_
 // with M = output channel, N = input channel and K = 16 voxels along x.  A wave accumulates a row
 // segment for all 27 taps, the workgroup's four waves add their partial sums in LDS, and one atomic
 // add per weight and workgroup goes to global memory.  db[co] += sum of dz[voxel][co].
+// FIXED: the summation order is fixed.  The four waves add their sums into LDS one after another
+// (instead of all at once), the bias sums of a wave's four lanes per channel meet in a fixed
+// order, and the workgroup writes its partial sums to its own slot of `part` (kWgradSlot floats:
+// the weights, then the biases) for k_wgrad_reduce, instead of adding them with global atomics.
+constexpr int kWgradSlot = kTaps * kC * kC + kC;
+
+template <bool FIXED>
 __global__ __launch_bounds__(256) void k_conv3d_wgrad(Vol v, const uint16_t *__restrict__ x,
                                                       const float *__restrict__ dz, float *__restrict__ dw,
-                                                      float *__restrict__ db)
+                                                      float *__restrict__ db, float *__restrict__ part)
 {
     __shared__ float red[kTaps * kC * kC];
     __shared__ float redb[kC];
@@ -409,11 +416,11 @@ __global__ __launch_bounds__(256) void k_conv3d_wgrad(Vol v, const uint16_t *__r
     const int j = blockIdx.y * 4 + wave;
     const int k = blockIdx.z;
     const int m = lane & 15, q = lane >> 4;
-    if (j < v.ny) {
-        v4f acc[kTaps];
+    v4f acc[kTaps];
 #pragma unroll
-        for (int t = 0; t < kTaps; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
-        float bsum = 0.0f;
+    for (int t = 0; t < kTaps; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.0f;
+    if (j < v.ny) {
         for (int x0 = blockIdx.x * 64; x0 < min(v.nx, blockIdx.x * 64 + 64); x0 += 16) {
             // A[co = m][vox = 4q + i] = dz[x0 + 4q + i][m]
             v4s a;
@@ -434,16 +441,55 @@ __global__ __launch_bounds__(256) void k_conv3d_wgrad(Vol v, const uint16_t *__r
                 acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc[t], 0, 0, 0);
             }
         }
-        // D[co = 4q + i][ci = m]
-#pragma unroll
-        for (int t = 0; t < kTaps; ++t)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) atomicAdd(&red[(t * kC + 4 * q + i) * kC + m], acc[t][i]);
-        atomicAdd(&redb[m], bsum);
     }
-    __syncthreads();
-    for (int t = threadIdx.x; t < kTaps * kC * kC; t += 256) atomicAdd(&dw[t], red[t]);
-    if (threadIdx.x < kC) atomicAdd(&db[threadIdx.x], redb[threadIdx.x]);
+    // D[co = 4q + i][ci = m]: each lane of a wave owns distinct weights
+    if constexpr (FIXED) {
+        // one wave per phase: its lanes own distinct weights, so each LDS address takes exactly one
+        // (uncontended) atomic add per phase, in wave order
+#pragma unroll 1
+        for (int w = 0; w < 4; ++w) {
+            if (wave == w && j < v.ny) {
+#pragma unroll
+                for (int t = 0; t < kTaps; ++t)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) atomicAdd(&red[(t * kC + 4 * q + i) * kC + m], acc[t][i]);
+                const float b = ((__shfl(bsum, m) + __shfl(bsum, m + 16)) + __shfl(bsum, m + 32)) + __shfl(bsum, m + 48);
+                if (q == 0) atomicAdd(&redb[m], b);
+            }
+            __syncthreads();
+        }
+        const long long slot =
+            ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        float *dst = part + slot * kWgradSlot;
+        for (int t = threadIdx.x; t < kTaps * kC * kC; t += 256) dst[t] = red[t];
+        if (threadIdx.x < kC) dst[kTaps * kC * kC + threadIdx.x] = redb[threadIdx.x];
+    } else {
+        if (j < v.ny) {
+#pragma unroll
+            for (int t = 0; t < kTaps; ++t)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) atomicAdd(&red[(t * kC + 4 * q + i) * kC + m], acc[t][i]);
+            atomicAdd(&redb[m], bsum);
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < kTaps * kC * kC; t += 256) atomicAdd(&dw[t], red[t]);
+        if (threadIdx.x < kC) atomicAdd(&db[threadIdx.x], redb[threadIdx.x]);
+    }
+}
+
+// dw += the sum of the slots' weights and db += their biases, each value summed over the slots in
+// slot order by one thread.
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float *__restrict__ part, long long nslot,
+                                                      float *__restrict__ dw, float *__restrict__ db)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= kWgradSlot) return;
+    float s = 0.0f;
+    for (long long b = 0; b < nslot; ++b) s += part[b * kWgradSlot + t];
+    if (t < kTaps * kC * kC)
+        dw[t] += s;
+    else
+        db[t - kTaps * kC * kC] += s;
 }
 
 // dz = dy * (y > 0) for a ReLU layer (relu = 0: dz = dy), over the channels < cmask (others 0);
@@ -816,7 +862,31 @@ int rtm_cnn_conv3d_wgrad(int32_t nx, int32_t ny, int32_t nz, const uint16_t *x, 
     if (!vol_ok(nx, ny, nz) || !x || !dz || !dw || !db) return RTM_EINVAL;
     const Vol v{nx, ny, nz};
     CNN_CHECK_DEVICE();
-    hipLaunchKernelGGL(k_conv3d_wgrad, dim3((nx + 63) / 64, (ny + 3) / 4, nz), dim3(256), 0, stream, v, x, dz, dw, db);
+    hipLaunchKernelGGL(k_conv3d_wgrad<false>, dim3((nx + 63) / 64, (ny + 3) / 4, nz), dim3(256), 0, stream, v, x, dz, dw,
+                       db, nullptr);
+    return status();
+}
+
+int64_t rtm_cnn_wgrad_partials(int32_t nx, int32_t ny, int32_t nz)
+{
+    if (!vol_ok(nx, ny, nz)) return RTM_EINVAL;
+    return (int64_t)((nx + 63) / 64) * ((ny + 3) / 4) * nz * kWgradSlot;
+}
+
+int rtm_cnn_conv3d_wgrad_ordered(int32_t nx, int32_t ny, int32_t nz, const uint16_t *x, const float *dz, float *dw,
+                                 float *db, float *partials, int64_t partials_len, hipStream_t stream)
+{
+    if (!vol_ok(nx, ny, nz) || !x || !dz || !dw || !db || !partials) return RTM_EINVAL;
+    const int64_t need = rtm_cnn_wgrad_partials(nx, ny, nz);
+    if (partials_len < need) return RTM_EINVAL;
+    const Vol v{nx, ny, nz};
+    CNN_CHECK_DEVICE();
+    const dim3 grid((nx + 63) / 64, (ny + 3) / 4, nz);
+    hipLaunchKernelGGL(k_conv3d_wgrad<true>, grid, dim3(256), 0, stream, v, x, dz, dw, db, partials);
+    int st = status();
+    if (st != RTM_OK) return st;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblk(kWgradSlot)), dim3(256), 0, stream, partials,
+                       (long long)grid.x * grid.y * grid.z, dw, db);
     return status();
 }
 

@@ -194,6 +194,9 @@ class Workspace:
             self.dh = torch.zeros(n, dtype=torch.float32, device=dev)
             self.wt = torch.zeros(WEIGHTS, dtype=torch.int16, device=dev)
             self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
+            # per-workgroup partial sums of the weight gradient (fixed summation order: a training
+            # run is reproducible bit for bit)
+            self.wpart = torch.empty(_abi.rtm_cnn_wgrad_partials(nx, ny, nz), dtype=torch.float32, device=dev)
 
 
 def forward(net: CorrectorNet, ws: Workspace, stream=None):
@@ -223,7 +226,8 @@ def backward(net: CorrectorNet, ws: Workspace, stream=None, weight: float = 1.0,
     acts16 = (ws.x, ws.h1, ws.h2)
     acts32 = (None, ws.h1f, ws.h2f)
     for layer in (2, 1, 0):
-        _abi.rtm_cnn_conv3d_wgrad(nx, ny, nz, acts16[layer], ws.dz, net.dw(layer), net.db(layer), st)
+        _abi.rtm_cnn_conv3d_wgrad_ordered(nx, ny, nz, acts16[layer], ws.dz, net.dw(layer), net.db(layer), ws.wpart,
+                                          ws.wpart.numel(), st)
         if layer == 0:
             break
         _abi.rtm_cnn_weight_flip(net.w16(layer), ws.wt, st)

@@ -102,6 +102,20 @@ def test_conv3d_weight_gradient(shape):
     ew, eb = _rel(gw, ref_w), _rel(gb, ref_b)
     _say(f"  dW rel-L2 {ew:.2e}, db rel-L2 {eb:.2e}")
     assert ew <= 1e-5 and eb <= 1e-5
+    # the fixed-order variant: the same sums to the same tolerance, and the same bits on every call
+    npart = _abi.rtm_cnn_wgrad_partials(nx, ny, nz)
+    part = torch.full((npart,), float("nan"), device="cuda")
+    xd, dzd = _dev(_with_halo(xc).reshape(-1)), _dev(dz.reshape(-1))
+    outs = []
+    for _ in range(2):
+        dw2, db2 = _dev(dw0.reshape(-1)), _dev(db0)
+        _abi.rtm_cnn_conv3d_wgrad_ordered(nx, ny, nz, xd, dzd, dw2, db2, part, npart, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        outs.append((dw2.cpu().numpy(), db2.cpu().numpy()))
+    gw2 = outs[0][0].reshape(27, C, C) - dw0.astype(np.float64)
+    gb2 = outs[0][1] - db0.astype(np.float64)
+    assert _rel(gw2, ref_w) <= 1e-5 and _rel(gb2, ref_b) <= 1e-5
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
 @pytest.mark.parametrize("shape", SHAPES[:2])

@@ -34,6 +34,24 @@ def test_training_lowers_the_window_loss(trained):
     assert with_net < 0.7 * zero
 
 
+def test_training_is_reproducible(trained):
+    """Two trainings from the same seed on the same windows end with the same weights, bit for bit
+    (the weight gradient sums in a fixed order)."""
+    import torch
+
+    from paper_1603_03971_amd import learned
+
+    _, pairs, _, _ = trained
+    nets = []
+    for _ in range(2):
+        net = learned.CorrectorNet(seed=3, relu=False)
+        learned.train(net, pairs, epochs=1, seed=4)
+        torch.cuda.synchronize()
+        nets.append(net.p.clone())
+    assert bool(torch.equal(nets[0], nets[1]))
+    assert float((nets[0] - learned.CorrectorNet(seed=3, relu=False).p).abs().max()) > 0
+
+
 def test_corrected_coarse_beats_plain_coarse(trained):
     """Held-out model (seed 6000, point source, 15 Hz): after 300 coarse steps the corrected coarse
     field is closer to the restricted fine field than the plain coarse field."""

@@ -6,8 +6,8 @@
       Run it under `rocprofv3 --pmc FETCH_SIZE` and, separately, `rocprofv3 --pmc WRITE_SIZE`.
 
   python3 -m paper_1603_03971_amd.profile halo [--n 512] [--launches 10]
-      the same for the halo call (rtm_step_halo: the z slabs, y strips and x strips of the halo
-      region), for its counters.
+      the same for the halo call as the serial schedule runs it (rtm_step_halo_pack: the z slabs,
+      y strips and x strips of the halo region, also writing the six faces), for its counters.
 
   python3 -m paper_1603_03971_amd.profile conv [--n 384] [--launches 10]
       runs the corrector network's forward pass (three 3x3x3 convolutions, 16 channels, BF16 MFMA)
@@ -77,9 +77,12 @@ def run_interior(n: int, launches: int, call: str = "interior"):
     g.owned(u).normal_()
     g.owned(up).normal_()
     s = torch.cuda.current_stream()
-    step = _abi.rtm_step_interior if call == "interior" else _abi.rtm_step_halo
+    faces = g.faces()
     for _ in range(launches):
-        step(g.c, up, u, up, kap, s)
+        if call == "interior":
+            _abi.rtm_step_interior(g.c, up, u, up, kap, s)
+        else:                                  # the serial schedule's halo call, which also packs
+            _abi.rtm_step_halo_pack(g.c, up, u, up, kap, faces, s)
     a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     b.copy_(a)
@@ -320,19 +323,21 @@ def summarize(stats_dir, fetch_dir, write_dir, out, n, commands):
         name = r["Name"].replace("(anonymous namespace)::", "")[:60]
         avg = float(r["AverageNs"]) / 1e3
         lines.append(f"    {name:60s} {r['Calls']:>6s} {avg:10.2f} {float(r['Percentage']):8.2f}")
-    # In the halo-first sequence the interior call is the tiled dispatch right after the halo call's;
-    # the other radius-4 tiled dispatches that are not halo calls are one-launch whole steps.
+    # In the halo-first sequence the interior call is the first radius-4 tiled dispatch after a halo
+    # call (injections may come between them); the other radius-4 tiled dispatches that are not halo
+    # calls are one-launch whole steps.
     trace = sorted(_csv(stats_dir, "*kernel_trace.csv"), key=lambda r: int(r["Start_Timestamp"]))
     calls = {"rtm_step_interior": [], "rtm_step_whole (fused schedule)": []}
     grids = {}
-    prev = ""
+    prev = ""                                  # the last radius-4 tiled dispatch
     for r in trace:
         name = r["Kernel_Name"]
         if TILED_R4 in name and HALO_KERNEL not in name:
             what = "rtm_step_interior" if HALO_KERNEL in prev else "rtm_step_whole (fused schedule)"
             calls[what].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
             grids.setdefault(what, set()).add(int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"]))
-        prev = name
+        if TILED_R4 in name:
+            prev = name
     interior_avg_us = None
     if any(calls.values()):
         lines += ["", "Radius-4 tiled launches other than the halo call (kernel trace):",
@@ -382,21 +387,26 @@ def summarize_halo(fetch_dir, write_dir, out, n, commands, stats_dir=None):
     kw = COPY_BYTES / (w_cp * 1024.0)
     rd, wt = f_h * 1024.0 * kf, w_h * 1024.0 * kw
     pts = n**3 - (n - 128) * (n - 32) * (n - 8)
+    fc = 6 * 4 * n * n                         # face cells the call also writes
+    alg_w = 4 * (pts + fc)
     lines = [f"# rocprofv3 summary: HBM traffic of the halo call, {n}^3 layered forward workload", "",
              "Commands:"] + [f"    {c}" for c in commands] + [""]
-    lines += ["Halo call (rtm_step_halo: two 4-plane z slabs, two 16-row y strips, two 64-column x strips):",
-              f"    cells {pts} (the interior call's box is the rest)",
+    lines += ["Halo call as the serial schedule runs it (rtm_step_halo_pack: two 4-plane z slabs, two 16-row",
+              "y strips, two 64-column x strips, and the six 4-wide faces written to the face buffer):",
+              f"    cells {pts} (the interior call's box is the rest), face cells {fc}",
               f"    FETCH_SIZE {f_h:.0f} KiB ({nf} dispatches), WRITE_SIZE {w_h:.0f} KiB ({nw} dispatches)",
               f"    calibration with a plain 1 GiB device copy: FETCH x {kf:.3f}, WRITE x {kw:.3f}",
               f"    read {rd / 1e6:.1f} MB against 12 B x cells = {12 * pts / 1e6:.1f} MB (ratio {rd / (12 * pts):.3f})",
-              f"    written {wt / 1e6:.1f} MB against 4 B x cells = {4 * pts / 1e6:.1f} MB (ratio {wt / (4 * pts):.3f})",
-              f"    total {(rd + wt) / 1e6:.1f} MB per launch, {(rd + wt) / (16 * pts):.3f} x algorithmic"]
+              f"    written {wt / 1e6:.1f} MB against 4 B x (cells + face cells) = {alg_w / 1e6:.1f} MB "
+              f"(ratio {wt / alg_w:.3f})",
+              f"    total {(rd + wt) / 1e6:.1f} MB per launch, {(rd + wt) / (12 * pts + alg_w):.3f} x algorithmic"]
     if stats_dir:
         for r in _csv(stats_dir, "*kernel_stats.csv"):
             if HALO_KERNEL in r["Name"]:
                 us = float(r["AverageNs"]) / 1e3
                 lines.append(f"    kernel trace of the benchmark run: {us:.1f} us per launch -> "
-                             f"{16 * pts / us / 1e6:.2f} TB/s algorithmic, {(rd + wt) / us / 1e6:.2f} TB/s moved")
+                             f"{(12 * pts + alg_w) / us / 1e6:.2f} TB/s algorithmic, "
+                             f"{(rd + wt) / us / 1e6:.2f} TB/s moved")
                 break
     text = "\n".join(lines) + "\n"
     with open(out, "w") as f:

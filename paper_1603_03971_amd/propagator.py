@@ -15,9 +15,8 @@ a pointer swap with no copy).  Time levels rotate by pointer: by default u^{n+1}
 u^{n-1} in place (two buffers), and a level that must outlive the rotation (an RTM snapshot) is
 "pinned" so that the next write goes to a fresh buffer instead of copying it.
 
-The "serial" schedule runs the same phases on one stream (halo, interior, injection, pack, unpack,
-record: on one GPU nothing needs the faces before the interior call); both give bitwise identical
-fields.  The
+The "serial" schedule runs the same phases on one stream (the halo call that packs, shell sources,
+interior call, interior sources, unpack, record); both give bitwise identical fields.  The
 "fused" schedule, for one subdomain with nothing to overlap, updates every owned cell in one launch
 (rtm_step_whole) instead of the halo and interior calls, then injects, refreshes the ghosts and
 records on one stream; it too is bitwise identical.  With no face received (the physical boundary),
@@ -221,11 +220,15 @@ class Propagator:
             if tr_ptr is not None:
                 _abi.rtm_record(c, u_nxt, self.rec_idx, tr_ptr, self.nrec, st)
         elif self.schedule == "serial":
-            # one stream: the interior call right after the halo call, whose reads it shares through
-            # the caches, and the pack after the injections (packing before the interior call, alone
-            # or inside the halo call, made the interior call 16-20 us slower at 512^3)
+            # one stream, in the paper's phase order: the halo call that also writes the faces, the
+            # shell sources (re-copied into the faces they sit in), the interior call, the interior
+            # sources, the unpack (at 512^3: 0.525 ms per step against 0.546 ms with the pack after
+            # the interior call, once each row's owned cells start a cache line)
             st = torch.cuda.current_stream()
-            _abi.rtm_step_halo(c, u_nxt, u_cur, u_prv, kap, st)
+            _abi.rtm_step_halo_pack(c, u_nxt, u_cur, u_prv, kap, self.send, st)
+            for s in self.sources:
+                s.inject(g, u_nxt, n, 0, st)
+                s.repack(g, u_nxt, n, self.send, st)
             if self.interior_events is not None:
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(st)
@@ -235,9 +238,7 @@ class Propagator:
             else:
                 _abi.rtm_step_interior(c, u_nxt, u_cur, u_prv, kap, st)
             for s in self.sources:
-                s.inject(g, u_nxt, n, 0, st)
                 s.inject(g, u_nxt, n, 1, st)
-            _abi.rtm_pack_halo(c, u_nxt, self.send, st)
             _abi.rtm_unpack_halo(c, u_nxt, self.recv, st)
             if tr_ptr is not None:
                 _abi.rtm_record(c, u_nxt, self.rec_idx, tr_ptr, self.nrec, st)

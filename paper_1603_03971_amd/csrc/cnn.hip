@@ -477,19 +477,30 @@ __global__ __launch_bounds__(256) void k_conv3d_wgrad(Vol v, const uint16_t *__r
     }
 }
 
-// dw += the sum of the slots' weights and db += their biases, each value summed over the slots in
-// slot order by one thread.
-__global__ __launch_bounds__(256) void k_wgrad_reduce(const float *__restrict__ part, long long nslot,
-                                                      float *__restrict__ dw, float *__restrict__ db)
+// dw += the sum of the slots' weights and db += their biases, in a fixed order: a workgroup takes 64
+// values; its wave w sums the slots w, w + 16, w + 32, ... in slot order (lane l reads value l: 256
+// contiguous bytes per slot), and the 16 group sums are then added in group order.
+constexpr int kReduceGroups = 16;
+
+__global__ __launch_bounds__(64 * kReduceGroups) void k_wgrad_reduce(const float *__restrict__ part, long long nslot,
+                                                                     float *__restrict__ dw, float *__restrict__ db)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= kWgradSlot) return;
+    __shared__ float grp[kReduceGroups][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int t = blockIdx.x * 64 + lane;
     float s = 0.0f;
-    for (long long b = 0; b < nslot; ++b) s += part[b * kWgradSlot + t];
-    if (t < kTaps * kC * kC)
-        dw[t] += s;
-    else
-        db[t - kTaps * kC * kC] += s;
+    if (t < kWgradSlot)
+        for (long long b = w; b < nslot; b += kReduceGroups) s += part[b * kWgradSlot + t];
+    grp[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && t < kWgradSlot) {
+        float tot = grp[0][lane];
+        for (int i = 1; i < kReduceGroups; ++i) tot += grp[i][lane];
+        if (t < kTaps * kC * kC)
+            dw[t] += tot;
+        else
+            db[t - kTaps * kC * kC] += tot;
+    }
 }
 
 // dz = dy * (y > 0) for a ReLU layer (relu = 0: dz = dy), over the channels < cmask (others 0);
@@ -885,7 +896,7 @@ int rtm_cnn_conv3d_wgrad_ordered(int32_t nx, int32_t ny, int32_t nz, const uint1
     hipLaunchKernelGGL(k_conv3d_wgrad<true>, grid, dim3(256), 0, stream, v, x, dz, dw, db, partials);
     int st = status();
     if (st != RTM_OK) return st;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblk(kWgradSlot)), dim3(256), 0, stream, partials,
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((kWgradSlot + 63) / 64), dim3(64 * kReduceGroups), 0, stream, partials,
                        (long long)grid.x * grid.y * grid.z, dw, db);
     return status();
 }

@@ -336,6 +336,41 @@ def test_image_and_kappa_kernels(torch_cuda):
     np.testing.assert_allclose(g.download(kap), (vel * 7e-4 / 10.0) ** 2, rtol=5e-7)
 
 
+def test_row_kernels_vector_and_scalar_paths_bitwise(torch_cuda):
+    """The owned-row kernels (imaging, coded imaging, snapshot coding, kappa, velocity gradient) give
+    the same bits on a layout that takes their float4 path (aligned rows) and on one that takes the
+    scalar path (row pitch not a multiple of 4)."""
+    torch = torch_cuda
+    from paper_1603_03971_amd import _abi
+    from paper_1603_03971_amd.grid import Grid
+
+    nx, ny, nz = 68, 30, 21
+    rng = np.random.default_rng(14)
+    a, b, i0, gk = rng.standard_normal((4, nz, ny, nx))
+    vel = rng.uniform(1500, 4500, (nz, ny, nx))
+    st = torch.cuda.current_stream()
+    outs = []
+    for x_align, pitch in ((32, None), (1, nx + 9)):
+        g = Grid(nx, ny, nz, 10.0, 7e-4, x_align=x_align, pitch_y=pitch)
+        assert (g.pitch_y % 4 == 0) == (x_align == 32)
+        img = g.upload(i0)
+        _abi.rtm_image_accumulate(g.c, img, g.upload(a), g.upload(b), 0.75, st)
+        kap = g.kappa_from_velocity(vel)
+        codes = torch.empty(nx * ny * nz, dtype=torch.int16, device="cuda")
+        scales = torch.empty(nz, dtype=torch.float32, device="cuda")
+        _abi.rtm_snapshot_encode(g.c, g.upload(a), codes, scales, _abi.RTM_SNAP_BF16, st)
+        img2 = g.upload(i0)
+        _abi.rtm_image_accumulate_coded(g.c, img2, codes, scales, _abi.RTM_SNAP_BF16, g.upload(b), 0.5, st)
+        gv = torch.empty(nx * ny * nz, dtype=torch.float32, device="cuda")
+        vt = torch.from_numpy(vel.astype(np.float32).reshape(-1)).cuda()
+        _abi.rtm_velocity_gradient(g.c, gv, g.upload(gk), vt, 7e-5, st)
+        torch.cuda.synchronize()
+        outs.append([g.download(img), g.download(kap), codes.cpu().numpy(), scales.cpu().numpy(),
+                     g.download(img2), gv.cpu().numpy()])
+    for name, x, y in zip(("image", "kappa", "codes", "scales", "coded image", "velocity gradient"), *outs):
+        assert np.array_equal(x, y), name
+
+
 def test_two_subdomain_split_bitwise(torch_cuda):
     """Domain decomposition on one GPU: the box split in x into two subdomains, each stepping with
     its own halo call, pack, interior call and unpack, whose receive slot for the shared face points

@@ -236,6 +236,15 @@ int rtm_gradient_accumulate(const rtm_grid *grid, float *grad, const float *u, c
  * obs. */
 int rtm_misfit_residual(const float *d, const float *obs, float *resid, int64_t n, double *misfit, hipStream_t stream);
 
+/* The same residual and misfit spread over the whole device: the samples are split into `nchunks`
+ * contiguous chunks of ceil(n / nchunks) (one workgroup each), whose FP64 sums of squares go to
+ * `partials` (caller-owned device buffer of at least nchunks doubles, overwritten) and are then added
+ * in chunk order into *misfit.  The summation order depends only on n and nchunks, so repeated calls
+ * give the same bits (not the same bits as rtm_misfit_residual, whose single workgroup sums in
+ * another order).  RTM_EINVAL for n < 0, nchunks <= 0 or a NULL pointer; n == 0 does nothing. */
+int rtm_misfit_residual_chunks(const float *d, const float *obs, float *resid, int64_t n, double *partials,
+                               int32_t nchunks, double *misfit, hipStream_t stream);
+
 /* Chain rule through kappa = (v dt / h)^2: grad_v = 2 v (dt/h)^2 grad_kappa, with grad_v and v compact
  * x-fastest nz*ny*nx arrays and grad_kappa a padded field. */
 int rtm_velocity_gradient(const rtm_grid *grid, float *grad_v, const float *grad_kappa, const float *v,

@@ -22,6 +22,8 @@ from . import _abi
 from .grid import Grid
 from .propagator import Propagator, Sources
 
+MISFIT_CHUNKS = 1024      # chunks of the residual's FP64 sum (one workgroup each, fixed order)
+
 
 class Shot:
     """One shot: source cells and weights, receiver cells, observed traces (device, (nsteps, nrec))."""
@@ -64,6 +66,14 @@ class MisfitProblem:
         prop.run(self.nsteps, tr)
         return tr
 
+    def _residual(self, tr: torch.Tensor, shot: Shot, resid: torch.Tensor, misfit: torch.Tensor):
+        """resid = traces - observed, misfit += 1/2 |resid|^2 summed in FP64 over MISFIT_CHUNKS chunks
+        of the samples in a fixed order (the same bits on every call)."""
+        if getattr(self, "_partials", None) is None:
+            self._partials = torch.empty(MISFIT_CHUNKS, dtype=torch.float64, device=self.g.device)
+        _abi.rtm_misfit_residual_chunks(tr, shot.observed, resid, tr.numel(), self._partials, MISFIT_CHUNKS, misfit,
+                                        torch.cuda.current_stream())
+
     def forward(self, kappa: torch.Tensor, shot: Shot, misfit: torch.Tensor):
         """Forward run with checkpoints; returns (checkpoints {n: (u^n, u^{n-1})}, residual traces)."""
         g = self.g
@@ -76,7 +86,7 @@ class MisfitProblem:
             prop.step(tr)
         prop.sync()
         resid = torch.empty_like(tr)
-        _abi.rtm_misfit_residual(tr, shot.observed, resid, tr.numel(), misfit, torch.cuda.current_stream())
+        self._residual(tr, shot, resid, misfit)
         return ckpt, resid
 
     def backward(self, kappa: torch.Tensor, shot: Shot, ckpt, resid: torch.Tensor, grad_kappa: torch.Tensor,
@@ -141,7 +151,7 @@ class MisfitProblem:
         for shot in self.shots:
             tr = self.model(kappa, shot)
             resid = torch.empty_like(tr)
-            _abi.rtm_misfit_residual(tr, shot.observed, resid, tr.numel(), misfit, torch.cuda.current_stream())
+            self._residual(tr, shot, resid, misfit)
         return float(misfit.item())
 
 

@@ -744,6 +744,48 @@ __global__ __launch_bounds__(kReduceThreads) void k_residual(const float *__rest
     if (threadIdx.x == 0) *misfit += 0.5 * red[0];
 }
 
+// The same over `nb` contiguous chunks of the samples, one workgroup each: chunk b is
+// [b * chunk, min(n, (b + 1) * chunk)), its threads stride through it in order and meet in a fixed
+// tree, and the chunk's FP64 sum of squares goes to part[b]; k_residual_final adds part[0..nb) in
+// order.  The order depends only on n and nb, so the result is the same on every call.
+constexpr int kChunkThreads = 256;
+__global__ __launch_bounds__(kChunkThreads) void k_residual_chunks(const float *__restrict__ d,
+                                                                   const float *__restrict__ obs,
+                                                                   float *__restrict__ resid, long long n,
+                                                                   long long chunk, double *__restrict__ part)
+{
+    const long long lo = (long long)blockIdx.x * chunk, hi = min(n, lo + chunk);
+    double acc = 0.0;
+    for (long long t = lo + threadIdx.x; t < hi; t += kChunkThreads) {
+        const float r = d[t] - obs[t];
+        resid[t] = r;
+        acc += (double)r * (double)r;
+    }
+    __shared__ double red[kChunkThreads];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kChunkThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kReduceThreads) void k_residual_final(const double *__restrict__ part, int nb,
+                                                                   double *misfit)
+{
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kReduceThreads) acc += part[b];
+    __shared__ double red[kReduceThreads];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kReduceThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *misfit += 0.5 * red[0];
+}
+
 // grad_v (compact, x fastest) = 2 v (dt/h)^2 grad_kappa (the chain rule through kappa = (v dt/h)^2).
 template <bool VEC>
 __global__ __launch_bounds__(kThreads) void k_velocity_gradient(Geo g, float *__restrict__ gv,
@@ -1627,6 +1669,26 @@ int rtm_misfit_residual(const float *d, const float *obs, float *resid, int64_t 
     const int st = check_device();
     if (st != RTM_OK) return st;
     hipLaunchKernelGGL(k_residual, dim3(1), dim3(kReduceThreads), 0, stream, d, obs, resid, (long long)n, misfit);
+    return launch_status();
+}
+
+int rtm_misfit_residual_chunks(const float *d, const float *obs, float *resid, int64_t n, double *partials,
+                               int32_t nchunks, double *misfit, hipStream_t stream)
+{
+    if (n < 0 || nchunks <= 0) return RTM_EINVAL;
+    if (n == 0) return RTM_OK;
+    if (!d || !obs || !resid || !misfit || !partials) return RTM_EINVAL;
+    if ((resid != d && ranges_overlap(resid, n, d, n)) || (resid != obs && ranges_overlap(resid, n, obs, n)))
+        return RTM_EALIAS;
+    const int st = check_device();
+    if (st != RTM_OK) return st;
+    const long long chunk = (n + nchunks - 1) / nchunks;
+    const long long nb = (n + chunk - 1) / chunk;      // chunks that hold samples (<= nchunks)
+    hipLaunchKernelGGL(k_residual_chunks, dim3((unsigned)nb), dim3(kChunkThreads), 0, stream, d, obs, resid,
+                       (long long)n, chunk, partials);
+    const int s1 = launch_status();
+    if (s1 != RTM_OK) return s1;
+    hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(kReduceThreads), 0, stream, partials, (int)nb, misfit);
     return launch_status();
 }
 

@@ -88,6 +88,9 @@ def test_validation_before_device(abi):
     assert L.rtm_inject(gp, 4096, 64, 64, 64, 0, None) == abi.RTM_OK                # nothing to do
     assert L.rtm_record(gp, 4096, 64, 64, -5, None) == abi.RTM_EINVAL
     assert L.rtm_record(gp, None, None, None, 0, None) == abi.RTM_OK               # nothing to do
+    assert L.rtm_misfit_residual_chunks(64, 128, 256, 10, 512, 0, 1024, None) == abi.RTM_EINVAL   # no chunks
+    assert L.rtm_misfit_residual_chunks(64, 128, 256, 10, None, 4, 1024, None) == abi.RTM_EINVAL  # no partials
+    assert L.rtm_misfit_residual_chunks(None, None, None, 0, None, 4, None, None) == abi.RTM_OK    # nothing to do
     assert L.rtm_cnn_wgrad_partials(64, 8, 4) == 1 * 2 * 4 * (27 * 16 * 16 + 16)
     assert L.rtm_cnn_wgrad_partials(60, 8, 4) == abi.RTM_EINVAL                     # nx % 16 != 0
     need = L.rtm_cnn_wgrad_partials(64, 8, 4)

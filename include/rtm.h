@@ -241,7 +241,8 @@ int rtm_misfit_residual(const float *d, const float *obs, float *resid, int64_t 
  * `partials` (caller-owned device buffer of at least nchunks doubles, overwritten) and are then added
  * in chunk order into *misfit.  The summation order depends only on n and nchunks, so repeated calls
  * give the same bits (not the same bits as rtm_misfit_residual, whose single workgroup sums in
- * another order).  RTM_EINVAL for n < 0, nchunks <= 0 or a NULL pointer; n == 0 does nothing. */
+ * another order).  RTM_EINVAL for n < 0, nchunks <= 0 or a NULL pointer; RTM_EALIAS if resid
+ * partly overlaps d or obs, or `partials` overlaps d, obs, resid or misfit; n == 0 does nothing. */
 int rtm_misfit_residual_chunks(const float *d, const float *obs, float *resid, int64_t n, double *partials,
                                int32_t nchunks, double *misfit, hipStream_t stream);
 
@@ -297,7 +298,8 @@ int rtm_cnn_conv3d_wgrad(int32_t nx, int32_t ny, int32_t nz, const uint16_t *x, 
  * the same bits: each workgroup's partial sums go to its own slot of `partials` (caller-owned device
  * FP32 buffer of at least rtm_cnn_wgrad_partials(nx, ny, nz) elements, contents overwritten), and a
  * second kernel adds the slots in order into dw and db.  RTM_EINVAL for bad dimensions, a NULL pointer
- * or a short buffer.  The result differs from rtm_cnn_conv3d_wgrad's only by summation order. */
+ * or a short buffer; RTM_EALIAS if `partials` overlaps x, dz, dw or db.  The result differs from
+ * rtm_cnn_conv3d_wgrad's only by summation order. */
 int rtm_cnn_conv3d_wgrad_ordered(int32_t nx, int32_t ny, int32_t nz, const uint16_t *x, const float *dz, float *dw,
                                  float *db, float *partials, int64_t partials_len, hipStream_t stream);
 

@@ -764,6 +764,13 @@ __global__ __launch_bounds__(256) void k_absmax_cells(G g, const float *__restri
 
 int status() { return hipGetLastError() == hipSuccess ? RTM_OK : RTM_ELAUNCH; }
 
+// Whether the byte ranges [a, a + na) and [b, b + nb) overlap.
+bool bytes_overlap(const void *a, long long na, const void *b, long long nb)
+{
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
+    return a0 < b0 + (uintptr_t)nb && b0 < a0 + (uintptr_t)na;
+}
+
 // The kernels are built for gfx950 only: the current device is checked once per device.
 std::atomic<int> g_cnn_dev[64];   // 0 unknown, 1 gfx950, -1 other
 
@@ -890,6 +897,11 @@ int rtm_cnn_conv3d_wgrad_ordered(int32_t nx, int32_t ny, int32_t nz, const uint1
     if (!vol_ok(nx, ny, nz) || !x || !dz || !dw || !db || !partials) return RTM_EINVAL;
     const int64_t need = rtm_cnn_wgrad_partials(nx, ny, nz);
     if (partials_len < need) return RTM_EINVAL;
+    const long long pb = (long long)need * 4;
+    const long long vox = (long long)nx * ny * nz, pvox = (long long)(nx + 2) * (ny + 2) * (nz + 2);
+    if (bytes_overlap(partials, pb, dw, 4ll * kTaps * kC * kC) || bytes_overlap(partials, pb, db, 4ll * kC) ||
+        bytes_overlap(partials, pb, dz, 4 * vox * kC) || bytes_overlap(partials, pb, x, 2 * pvox * kC))
+        return RTM_EALIAS;
     const Vol v{nx, ny, nz};
     CNN_CHECK_DEVICE();
     const dim3 grid((nx + 63) / 64, (ny + 3) / 4, nz);

@@ -1680,6 +1680,10 @@ int rtm_misfit_residual_chunks(const float *d, const float *obs, float *resid, i
     if (!d || !obs || !resid || !misfit || !partials) return RTM_EINVAL;
     if ((resid != d && ranges_overlap(resid, n, d, n)) || (resid != obs && ranges_overlap(resid, n, obs, n)))
         return RTM_EALIAS;
+    const long long pf = 2ll * nchunks;               // partials in floats
+    if (ranges_overlap(partials, pf, misfit, 2) || ranges_overlap(partials, pf, d, n) ||
+        ranges_overlap(partials, pf, obs, n) || ranges_overlap(partials, pf, resid, n))
+        return RTM_EALIAS;
     const int st = check_device();
     if (st != RTM_OK) return st;
     const long long chunk = (n + nchunks - 1) / nchunks;

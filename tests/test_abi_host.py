@@ -91,11 +91,14 @@ def test_validation_before_device(abi):
     assert L.rtm_misfit_residual_chunks(64, 128, 256, 10, 512, 0, 1024, None) == abi.RTM_EINVAL   # no chunks
     assert L.rtm_misfit_residual_chunks(64, 128, 256, 10, None, 4, 1024, None) == abi.RTM_EINVAL  # no partials
     assert L.rtm_misfit_residual_chunks(None, None, None, 0, None, 4, None, None) == abi.RTM_OK    # nothing to do
+    assert L.rtm_misfit_residual_chunks(1 << 20, 1 << 21, 1 << 22, 10, 1 << 30, 4, 1 << 30, None) == abi.RTM_EALIAS
     assert L.rtm_cnn_wgrad_partials(64, 8, 4) == 1 * 2 * 4 * (27 * 16 * 16 + 16)
     assert L.rtm_cnn_wgrad_partials(60, 8, 4) == abi.RTM_EINVAL                     # nx % 16 != 0
     need = L.rtm_cnn_wgrad_partials(64, 8, 4)
     assert L.rtm_cnn_conv3d_wgrad_ordered(64, 8, 4, 4096, 8192, 16384, 32768, 1 << 20, need - 1, None) == abi.RTM_EINVAL
     assert L.rtm_cnn_conv3d_wgrad_ordered(64, 8, 4, 4096, 8192, 16384, 32768, None, need, None) == abi.RTM_EINVAL
+    assert L.rtm_cnn_conv3d_wgrad_ordered(64, 8, 4, 1 << 30, 1 << 31, 1 << 32, 1 << 33, 1 << 32, need, None) == \
+        abi.RTM_EALIAS                                                               # partials over dw
     assert L.rtm_inject(gp, None, None, None, None, 0, None) == abi.RTM_OK
     assert L.rtm_image_accumulate(gp, 4096, 4096, 1 << 40, 1.0, None) == abi.RTM_EALIAS
     assert L.rtm_set_option(99, 0) == abi.RTM_EINVAL

@@ -73,6 +73,18 @@ int rtm_grid_init(rtm_grid *grid, int32_t nx, int32_t ny, int32_t nz, int32_t ra
  * 2 / sqrt(3 S) with S = |c0| + 2 sum |c_m| (the checkerboard mode).  0 for a bad radius. */
 double rtm_stability_limit(int32_t radius);
 
+/* Time step at `fraction` of the stability limit: *dt = fraction * rtm_stability_limit(radius) * h / vmax
+ * (the workloads run at half the limit, fraction = 0.5; a Courant number of 0.5 taken literally would
+ * exceed the limit of the radius-4 scheme), computed in FP64 into the host double *dt.  RTM_EINVAL for a bad radius, h <= 0, vmax <= 0, fraction <= 0 or a NULL dt. */
+int rtm_stable_dt(int32_t radius, double h, double vmax, double fraction, double *dt);
+
+/* Point-source weights into host memory `out[n]`: out[s] = (v[s] dt)^2 / h^3 in FP64, rounded to
+ * FP32.  A source term f(t) delta(x - x_s) of (1/v^2) p_tt - lap p = f delta discretises, after the
+ * leapfrog update multiplies the right-hand side by (v dt)^2, to adding (v_s dt)^2 f(t_n) / h^3 at
+ * the source cell (the grid delta is 1/h^3).  v: host velocities at the source cells (m/s).
+ * RTM_EINVAL for n < 0, h <= 0, dt <= 0 or a NULL pointer with n > 0. */
+int rtm_injection_weights(int32_t n, const double *v, double dt, double h, float *out);
+
 /* Cerjan taper along one axis into host memory `out[n]`: exp(-(alpha d)^2), with d = the number
  * of cells into a `width`-cell sponge at either end (d = max(0, width - i, i - (n - 1 - width))). */
 int rtm_sponge_profile(int32_t n, int32_t width, double alpha, float *out);

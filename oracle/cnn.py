@@ -2,10 +2,14 @@
 
 A 3x3x3 convolution with zero padding on channel-last volumes x[z, y, x, ci]:
     y[v, co] = bias[co] + sum over taps t and ci of w[t, co, ci] x[v + d_t, ci],
-tap t = 9 (dz+1) + 3 (dy+1) + (dx+1).  The network is three such layers (ReLU after the first two);
-the loss is L = 1/2 sum over the first two output channels of (out - target)^2.  Gradients follow
-the chain rule: dW_t[co, ci] = sum_v dz[v, co] x[v + d_t, ci], db = sum_v dz, and the data gradient
-dx[v, ci] = sum_t sum_co dz[v - d_t, co] w[t, co, ci].  Plain numpy; no code shared with the HIP path.
+tap t = 9 (dz+1) + 3 (dy+1) + (dx+1).  The network is three such layers, with ReLU after the first
+two or none at all (a linear network); the loss is
+    L = 1/2 sum over voxels v and the first two output channels of w_v (out - target)^2,
+    w_v = weight * mask[v]   (mask: None for 1 everywhere, else a per-voxel array >= 0).
+Gradients follow the chain rule: dL/dout = w_v (out - target) on those channels, then per layer
+dW_t[co, ci] = sum_v dz[v, co] x[v + d_t, ci], db = sum_v dz, the data gradient
+dx[v, ci] = sum_t sum_co dz[v - d_t, co] w[t, co, ci], and the ReLU derivative (y > 0) where a
+ReLU follows the layer.  Plain numpy; no code shared with the HIP path.
 """
 from __future__ import annotations
 
@@ -53,26 +57,32 @@ def conv3d_dgrad(dz, w):
     return dx
 
 
-def forward(x, params):
-    """params: [(w1, b1), (w2, b2), (w3, b3)]; returns (out, activations)."""
+def forward(x, params, relu: bool = True):
+    """params: [(w1, b1), (w2, b2), (w3, b3)]; ReLU after the first two layers when relu is True.
+    Returns (out, activations)."""
     acts = [np.asarray(x, dtype=np.float64)]
     h = acts[0]
     for li, (w, b) in enumerate(params):
-        h = conv3d(h, w, b, relu=li < 2)
+        h = conv3d(h, w, b, relu=relu and li < 2)
         acts.append(h)
     return h, acts
 
 
-def loss_and_grads(x, target, params, channels: int = 2):
-    """L = 1/2 sum over the first `channels` outputs of (out - target)^2 and its parameter gradients."""
-    out, acts = forward(x, params)
-    dy = np.zeros_like(out)
-    dy[..., :channels] = out[..., :channels] - np.asarray(target, dtype=np.float64)[..., :channels]
-    loss = 0.5 * float(np.sum(dy * dy))
+def loss_and_grads(x, target, params, channels: int = 2, relu: bool = True, mask=None, weight: float = 1.0):
+    """L = 1/2 sum_v w_v sum over the first `channels` outputs of (out - target)^2, with
+    w_v = weight * mask[v] (mask None: 1), and its parameter gradients."""
+    out, acts = forward(x, params, relu)
+    wv = np.full(out.shape[:3], float(weight))
+    if mask is not None:
+        wv = wv * np.asarray(mask, dtype=np.float64).reshape(out.shape[:3])
+    err = np.zeros_like(out)
+    err[..., :channels] = out[..., :channels] - np.asarray(target, dtype=np.float64)[..., :channels]
+    loss = 0.5 * float(np.sum(wv[..., None] * err * err))
+    dy = wv[..., None] * err
     grads = [None] * 3
     dz = dy
     for li in (2, 1, 0):
-        if li < 2:
+        if li < 2 and relu:
             dz = dz * (acts[li + 1] > 0)
         dw, db = conv3d_wgrad(acts[li], dz)
         grads[li] = (dw, db)

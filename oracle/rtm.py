@@ -19,8 +19,12 @@ a 3-D block each time step) is written out here as
 * adjoint:      the exact transpose of the recursion above (Tarantola 1984) and the
                 adjoint-state gradient of the least-squares misfit with respect to kappa.
 
-Arrays are numpy float64 of shape (nz, ny, nx) (x fastest).  Parity unpinned: the sponge constants
-(alpha, width) have no closed form to pin them; only agreement with the GPU path covers them.
+Arrays are numpy float64 of shape (nz, ny, nx) (x fastest).  Where the sponge acts is pinned in
+closed form (with kappa = 0 each cell obeys a scalar recurrence with the double root g; with
+constant g and kappa a periodic standing wave decays as g^n while it oscillates at the discrete
+dispersion frequency; both for the forward and the transposed step).  Parity unpinned: the sponge
+constants themselves (alpha, width) are a reading with no closed form; only agreement with the GPU
+path covers them.
 """
 from __future__ import annotations
 

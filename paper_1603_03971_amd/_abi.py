@@ -47,6 +47,8 @@ def _load():
         "rtm_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "rtm_grid_init": ([gp, i32, i32, i32, i32, i64, i64, vp, vp, vp], ctypes.c_int),
         "rtm_stability_limit": ([i32], f64),
+        "rtm_stable_dt": ([i32, f64, f64, f64, ctypes.POINTER(f64)], ctypes.c_int),
+        "rtm_injection_weights": ([i32, vp, f64, f64, vp], ctypes.c_int),
         "rtm_sponge_profile": ([i32, i32, f64, vp], ctypes.c_int),
         "rtm_ricker": ([i32, f64, f64, f64, vp], ctypes.c_int),
         "rtm_face_layout": ([gp, ctypes.POINTER(i64)], ctypes.c_int),
@@ -139,6 +141,22 @@ def rtm_grid_init(nx, ny, nz, radius, pitch_y, pitch_z, gx, gy, gz) -> rtm_grid:
 
 def rtm_stability_limit(radius: int) -> float:
     return _lib.rtm_stability_limit(radius)
+
+
+def rtm_stable_dt(radius: int, h: float, vmax: float, fraction: float = 0.5) -> float:
+    dt = ctypes.c_double()
+    _check(_lib.rtm_stable_dt(radius, h, vmax, fraction, ctypes.byref(dt)), "rtm_stable_dt")
+    return dt.value
+
+
+def rtm_injection_weights(v, dt: float, h: float):
+    import numpy as np
+
+    v = np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(-1))
+    out = np.empty(len(v), dtype=np.float32)
+    _check(_lib.rtm_injection_weights(len(v), v.ctypes.data if len(v) else None, dt, h,
+                                      out.ctypes.data if len(v) else None), "rtm_injection_weights")
+    return out
 
 
 def rtm_sponge_profile(n: int, width: int, alpha: float):

@@ -1352,6 +1352,25 @@ double rtm_stability_limit(int32_t radius)
     return 2.0 / std::sqrt(3.0 * s);
 }
 
+int rtm_stable_dt(int32_t radius, double h, double vmax, double fraction, double *dt)
+{
+    const double cstar = rtm_stability_limit(radius);
+    if (!dt || cstar <= 0.0 || !(h > 0.0) || !(vmax > 0.0) || !(fraction > 0.0)) return RTM_EINVAL;
+    *dt = fraction * cstar * h / vmax;
+    return RTM_OK;
+}
+
+int rtm_injection_weights(int32_t n, const double *v, double dt, double h, float *out)
+{
+    if (n < 0 || !(dt > 0.0) || !(h > 0.0)) return RTM_EINVAL;
+    if (n > 0 && (!v || !out)) return RTM_EINVAL;
+    for (int s = 0; s < n; ++s) {
+        const double a = v[s] * dt;
+        out[s] = (float)(a * a / (h * h * h));
+    }
+    return RTM_OK;
+}
+
 int rtm_sponge_profile(int32_t n, int32_t width, double alpha, float *out)
 {
     if (n < 0 || width < 0 || !out) return RTM_EINVAL;

@@ -137,17 +137,17 @@ class Grid:
         return [faces[o:o + s] for o, s in zip(self.face_offsets, self.face_sizes)]
 
     def injection_weights(self, v_at_sources) -> np.ndarray:
-        """Point-source weights (v_s dt)^2 / h^3 (the grid delta is 1/h^3), FP64 then FP32."""
-        v = np.asarray(v_at_sources, dtype=np.float64)
-        return ((v * self.dt) ** 2 / self.h ** 3).astype(np.float32)
+        """Point-source weights of this grid's dt and h for the velocities at the source cells
+        (rtm_injection_weights)."""
+        return _abi.rtm_injection_weights(v_at_sources, self.dt, self.h)
 
     def ricker(self, nsteps: int, fpeak: float, t0: float | None = None) -> np.ndarray:
         return _abi.rtm_ricker(nsteps, self.dt, fpeak, 1.5 / fpeak if t0 is None else t0)
 
     @staticmethod
     def stable_dt(radius: int, h: float, vmax: float, fraction: float = 0.5) -> float:
-        """dt at `fraction` of the 3-D leapfrog stability limit."""
-        return fraction * _abi.rtm_stability_limit(radius) * h / vmax
+        """dt at `fraction` of the 3-D leapfrog stability limit (rtm_stable_dt)."""
+        return _abi.rtm_stable_dt(radius, h, vmax, fraction)
 
     def bytes_per_field(self) -> int:
         return 4 * self.total

@@ -135,6 +135,30 @@ def test_host_helpers_match_oracle(abi):
                                rtol=0, atol=2e-7)
 
 
+def test_stable_dt_and_injection_weights_match_oracle(abi):
+    """dt and the point-source weights come from the library (the C ABI) and agree with the oracle's
+    own formulas; bad arguments are RTM_EINVAL."""
+    for r, h, vmax in ((4, 10.0, 2000.0), (4, 10.0, 4500.0), (2, 20.0, 3000.0)):
+        dt = abi.rtm_stable_dt(r, h, vmax, 0.5)
+        assert abs(dt - oracle.stable_dt(r, h, vmax)) <= 1e-15 * dt
+        assert abs(abi.rtm_stable_dt(r, h, vmax, 0.99) - 0.99 * oracle.stability_limit(r) * h / vmax) <= 1e-15 * dt
+    # C1: dt = 0.5 C* h / v = 1.132139 ms
+    assert abs(abi.rtm_stable_dt(4, 10.0, 2000.0, 0.5) - 1.132139e-3) < 1e-9
+    for bad in ((3, 10.0, 2000.0, 0.5), (4, 0.0, 2000.0, 0.5), (4, 10.0, -1.0, 0.5), (4, 10.0, 2000.0, 0.0)):
+        with pytest.raises(abi.RTMError) as e:
+            abi.rtm_stable_dt(*bad)
+        assert e.value.status == abi.RTM_EINVAL
+    v = np.array([1500.0, 2000.0, 4500.0, 3217.5])
+    dt, h = 5.389e-4, 10.0
+    w = abi.rtm_injection_weights(v, dt, h)
+    ref = oracle.injection_weight(v, dt, h)
+    assert w.dtype == np.float32
+    np.testing.assert_array_equal(w, ref.astype(np.float32))
+    assert len(abi.rtm_injection_weights([], dt, h)) == 0
+    with pytest.raises(abi.RTMError):
+        abi.rtm_injection_weights(v, -dt, h)
+
+
 def test_injection_mask():
     """The corrector's weight: 0 at and near injection cells and in the sponge, 1 in the clear
     interior, a linear ramp between."""

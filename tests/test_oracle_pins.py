@@ -141,6 +141,105 @@ def test_discrete_dispersion_relation():
     assert np.max(np.abs(out["u_prv"] - p0 * math.cos(w * (nsteps - 1) * dt))) < 1e-12
 
 
+def test_sponge_scalar_recurrence_closed_form(oracle_threads):
+    """With kappa = 0 every cell obeys u^{n+1} = g (2 u^n - g u^{n-1}), whose characteristic
+    polynomial (r - g)^2 has the double root g, so u^n = (A + B n) g^n with A = u^0 and
+    B = u^0 - g u^{-1}.  Pins where the sponge enters both time levels, cell by cell, for
+    different per-axis factors."""
+    rng = np.random.default_rng(21)
+    nz, ny, nx = 6, 7, 9
+    gx, gy, gz = rng.uniform(0.6, 1.0, nx), rng.uniform(0.6, 1.0, ny), rng.uniform(0.6, 1.0, nz)
+    gx[0] = 1.0
+    g = gz[:, None, None] * gy[None, :, None] * gx[None, None, :]
+    u0 = rng.standard_normal((nz, ny, nx))
+    um = rng.standard_normal((nz, ny, nx))
+    nsteps = 40
+    out = oracle.forward(np.zeros((nz, ny, nx)), (gx, gy, gz), nsteps, u_cur=u0, u_prv=um, nthreads=oracle_threads)
+    A, B = u0, u0 - g * um
+    for n, key in ((nsteps, "u_cur"), (nsteps - 1, "u_prv")):
+        ref = (A + B * n) * g ** n
+        assert np.max(np.abs(out[key] - ref)) <= 1e-13 * np.max(np.abs(A) + np.abs(B) * n)
+
+
+def test_adjoint_sponge_scalar_recurrence_closed_form():
+    """With kappa = 0 the transposed recursion is mu^m = 2 g mu^{m+1} - g^2 mu^{m+2}: the same double
+    root g, so mu^{N+1-j} = (A + B j) g^j with A = mu^{N+1} and B = mu^{N+1} - g mu^{N+2}.  Pins the
+    -g^2 mu term and the 2 g factor of the adjoint step."""
+    rng = np.random.default_rng(22)
+    nz, ny, nx = 5, 6, 8
+    gx, gy, gz = rng.uniform(0.6, 1.0, nx), rng.uniform(0.6, 1.0, ny), rng.uniform(0.6, 1.0, nz)
+    g = gz[:, None, None] * gy[None, :, None] * gx[None, None, :]
+    a0 = rng.standard_normal((nz, ny, nx))      # mu one level later
+    b0 = rng.standard_normal((nz, ny, nx))      # mu two levels later
+    mu_a, mu_b = a0, b0
+    kap = np.zeros((nz, ny, nx))
+    A, B = a0, a0 - g * b0
+    for j in range(1, 31):
+        mu = oracle.adjoint_step(mu_a, mu_b, kap, (gx, gy, gz))
+        mu_b, mu_a = mu_a, mu
+        ref = (A + B * j) * g ** j
+        assert np.max(np.abs(mu - ref)) <= 1e-13 * np.max(np.abs(A) + np.abs(B) * j), j
+
+
+def _damped_mode(a0, am1, g, c, n):
+    """n-th term of a^{n+1} = g (2 + q) a^n - g^2 a^{n-1} with q = kappa lambda: a^n = g^n (A cos n t
+    + B sin n t), cos t = 1 + q / 2 (an oscillating mode, |1 + q/2| < 1)."""
+    t = math.acos(c)
+    A = a0
+    B = (A * math.cos(t) - g * am1) / math.sin(t)
+    return g ** n * (A * math.cos(n * t) + B * math.sin(n * t))
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_damped_standing_wave_closed_form(adjoint):
+    """A standing wave on a periodic box with constant sponge factor g and constant kappa: L p = lambda p
+    with the exact discrete symbol, so the forward update (and the transposed one, which for constant
+    g and kappa is the same map) multiplies the mode amplitude by the scalar recurrence
+    a^{n+1} = g (2 + kappa lambda) a^n - g^2 a^{n-1}, solved in closed form.  Pins where g sits
+    relative to kappa L (outside both), in both directions of time."""
+    nx, ny, nz = 16, 12, 10
+    h, v = 10.0, 2500.0
+    dt = oracle.stable_dt(4, h, v)
+    modes = (3, 2, 1)
+    kx, ky, kz = (2 * math.pi * m / (n * h) for m, n in zip(modes, (nx, ny, nz)))
+    lam = sum(_textbook_symbol(kd * h) for kd in (kx, ky, kz))
+    kap = oracle.kappa_field(np.full((nz, ny, nx), v), dt, h)
+    q = kap[0, 0, 0] * lam
+    x, y, z = np.arange(nx) * h, np.arange(ny) * h, np.arange(nz) * h
+    p = np.cos(kx * x[None, None, :] + ky * y[None, :, None] + kz * z[:, None, None])
+    gxv, gyv, gzv = 0.99, 0.985, 0.995
+    sponge = (np.full(nx, gxv), np.full(ny, gyv), np.full(nz, gzv))
+    g = gxv * gyv * gzv
+    a0, am1 = 1.0, 0.7
+    nsteps = 120
+    if not adjoint:
+        out = oracle.forward(kap, sponge, nsteps, u_cur=a0 * p, u_prv=am1 * p, periodic=True)
+        got = out["u_cur"]
+    else:
+        mu_a, mu_b = a0 * p, am1 * p
+        for _ in range(nsteps):
+            mu = oracle.adjoint_step(mu_a, mu_b, kap, sponge, periodic=True)
+            mu_b, mu_a = mu_a, mu
+        got = mu_a
+    ref = _damped_mode(a0, am1, g, 1.0 + q / 2.0, nsteps) * p
+    assert np.max(np.abs(got - ref)) <= 1e-12
+    # the damping really acts: the undamped amplitude differs
+    assert np.max(np.abs(got - _damped_mode(a0, am1, 1.0, 1.0 + q / 2.0, nsteps) * p)) > 1e-3
+
+
+def test_kappa_field_values():
+    """kappa = (v dt / h)^2: exact values, and at v_max with dt at half the stability limit
+    kappa = (C*/2)^2 = 1 / (3 S) with S = 2048/315 (radius 4), the squared Courant number."""
+    assert oracle.kappa_field(np.array([2000.0]), 1e-3, 10.0)[0] == pytest.approx(0.04, rel=1e-15)
+    assert oracle.kappa_field(np.array([1500.0]), 2e-3, 20.0)[0] == pytest.approx(0.0225, rel=1e-15)
+    v = np.array([[[3000.0, 1500.0], [4500.0, 2250.0]]])
+    dt = oracle.stable_dt(4, 10.0, 4500.0)
+    kap = oracle.kappa_field(v, dt, 10.0)
+    assert kap.shape == v.shape
+    assert kap[0, 1, 0] == pytest.approx(315.0 / 6144.0, rel=1e-14)
+    np.testing.assert_allclose(kap, (v / 4500.0) ** 2 * 315.0 / 6144.0, rtol=1e-14)
+
+
 def test_stability_threshold():
     """The checkerboard mode grows above the limit and stays bounded just below it."""
     n = 8
@@ -499,7 +598,11 @@ def test_cnn_conv3d_matches_direct_definition():
                     assert abs(y[k, j, i, co] - s) < 1e-12
 
 
-def test_cnn_gradients_match_finite_differences():
+@pytest.mark.parametrize("relu", [True, False])
+@pytest.mark.parametrize("masked", [False, True])
+def test_cnn_gradients_match_finite_differences(relu, masked):
+    """Every parameter group's gradient against central differences of the loss, for the ReLU and
+    the linear network, with and without a per-voxel mask and a loss weight."""
     from oracle import cnn
 
     rng = np.random.default_rng(62)
@@ -508,7 +611,12 @@ def test_cnn_gradients_match_finite_differences():
     params = [(rng.standard_normal((27, 4, 3)) * 0.3, rng.standard_normal(4) * 0.1),
               (rng.standard_normal((27, 4, 4)) * 0.3, rng.standard_normal(4) * 0.1),
               (rng.standard_normal((27, 2, 4)) * 0.3, rng.standard_normal(2) * 0.1)]
-    loss, grads = cnn.loss_and_grads(x, tgt, params)
+    kw = dict(relu=relu)
+    if masked:
+        mask = rng.uniform(0.0, 1.0, (4, 5, 6))
+        mask[rng.uniform(size=mask.shape) < 0.3] = 0.0
+        kw.update(mask=mask, weight=0.37)
+    loss, grads = cnn.loss_and_grads(x, tgt, params, **kw)
     eps = 1e-6
     for li in range(3):
         for which in (0, 1):
@@ -517,10 +625,46 @@ def test_cnn_gradients_match_finite_differences():
                 idx = tuple(int(rng.integers(0, s)) for s in p.shape)
                 old = p[idx]
                 p[idx] = old + eps
-                lp = cnn.loss_and_grads(x, tgt, params)[0]
+                lp = cnn.loss_and_grads(x, tgt, params, **kw)[0]
                 p[idx] = old - eps
-                lm = cnn.loss_and_grads(x, tgt, params)[0]
+                lm = cnn.loss_and_grads(x, tgt, params, **kw)[0]
                 p[idx] = old
                 fd = (lp - lm) / (2 * eps)
                 an = grads[li][which][idx]
                 assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (li, which, idx, fd, an)
+
+
+def test_cnn_masked_loss_brute_force_and_linearity():
+    """The masked, weighted loss equals its definition summed voxel by voxel; a voxel with mask 0
+    does not count; the linear network without biases is linear in its input, the ReLU one is not."""
+    from oracle import cnn
+
+    rng = np.random.default_rng(63)
+    shape = (3, 4, 5)
+    x = rng.standard_normal(shape + (3,))
+    tgt = rng.standard_normal(shape + (2,))
+    params = [(rng.standard_normal((27, 4, 3)) * 0.3, np.zeros(4)),
+              (rng.standard_normal((27, 4, 4)) * 0.3, np.zeros(4)),
+              (rng.standard_normal((27, 3, 4)) * 0.3, np.zeros(3))]
+    mask = rng.uniform(0.0, 1.0, shape)
+    mask[1, 2, 3] = 0.0
+    for relu in (True, False):
+        out, _ = cnn.forward(x, params, relu)
+        loss, _ = cnn.loss_and_grads(x, tgt, params, relu=relu, mask=mask, weight=2.5)
+        brute = 0.0
+        for k in range(shape[0]):
+            for j in range(shape[1]):
+                for i in range(shape[2]):
+                    for c in range(2):       # the third output channel is not in the loss
+                        brute += 0.5 * 2.5 * mask[k, j, i] * (out[k, j, i, c] - tgt[k, j, i, c]) ** 2
+        assert abs(loss - brute) <= 1e-13 * brute
+        t2 = tgt.copy()
+        t2[1, 2, 3] += 10.0
+        l2, g2 = cnn.loss_and_grads(x, t2, params, relu=relu, mask=mask, weight=2.5)
+        _, g1 = cnn.loss_and_grads(x, tgt, params, relu=relu, mask=mask, weight=2.5)
+        assert l2 == loss
+        assert all(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) for a, b in zip(g1, g2))
+    lin, _ = cnn.forward(-2.0 * x, params, relu=False)
+    np.testing.assert_allclose(lin, -2.0 * cnn.forward(x, params, relu=False)[0], rtol=1e-12, atol=1e-12)
+    rel, _ = cnn.forward(-2.0 * x, params, relu=True)
+    assert not np.allclose(rel, -2.0 * cnn.forward(x, params, relu=True)[0])

@@ -216,6 +216,12 @@ int rtm_record(const rtm_grid *grid, const float *u, const int64_t *idx, float *
 int rtm_kappa_from_velocity(const rtm_grid *grid, float *kappa, const float *v, float dt_over_h,
                             hipStream_t stream);
 
+/* Health check of a time level: *count (a device uint32 the caller zeroes) += the number of owned
+ * cells of u that are not finite (NaN or infinite).  A run past the stability limit grows until its
+ * values overflow; checking the newest level every K steps catches it within K steps of the first
+ * non-finite level.  Reads 4 bytes per owned cell. */
+int rtm_count_nonfinite(const rtm_grid *grid, const float *u, uint32_t *count, hipStream_t stream);
+
 /* Zero-lag cross-correlation imaging condition (Claerbout 1971): image += weight * src * rcv on
  * owned cells; src is the source wavefield at a time level and rcv the receiver wavefield at the
  * same level.  image may not overlap src or rcv. */

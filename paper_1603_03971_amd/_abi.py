@@ -67,6 +67,7 @@ def _load():
         "rtm_record": ([gp, vp, vp, vp, i32, vp], ctypes.c_int),
         "rtm_kappa_from_velocity": ([gp, vp, vp, f32, vp], ctypes.c_int),
         "rtm_image_accumulate": ([gp, vp, vp, vp, f32, vp], ctypes.c_int),
+        "rtm_count_nonfinite": ([gp, vp, vp, vp], ctypes.c_int),
         "rtm_snapshot_encode": ([gp, vp, vp, vp, i32, vp], ctypes.c_int),
         "rtm_adjoint_step": ([gp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "rtm_gradient_accumulate": ([gp, vp, vp, vp, vp], ctypes.c_int),
@@ -254,6 +255,10 @@ def rtm_kappa_from_velocity(grid, kappa, v, dt_over_h, stream=None):
 def rtm_image_accumulate(grid, image, src, rcv, weight=1.0, stream=None):
     _check(_lib.rtm_image_accumulate(ctypes.byref(grid), _p(image), _p(src), _p(rcv), weight, _s(stream)),
            "rtm_image_accumulate")
+
+
+def rtm_count_nonfinite(grid, u, count, stream=None):
+    _check(_lib.rtm_count_nonfinite(ctypes.byref(grid), _p(u), _p(count), _s(stream)), "rtm_count_nonfinite")
 
 
 def rtm_snapshot_encode(grid, u, codes, scales, fmt, stream=None):

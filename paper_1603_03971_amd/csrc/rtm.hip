@@ -704,6 +704,27 @@ __global__ __launch_bounds__(kThreads) void k_kappa(Geo g, float *__restrict__ k
     });
 }
 
+// count += the number of owned cells of u that are not finite (NaN or infinite: all exponent bits
+// set), one atomic add per wave.
+template <bool VEC>
+__global__ __launch_bounds__(kThreads) void k_count_nonfinite(Geo g, const float *__restrict__ u,
+                                                              unsigned *__restrict__ count)
+{
+    auto bad = [](float x) -> unsigned { return ((__float_as_uint(x) >> 23) & 0xFFu) == 0xFFu ? 1u : 0u; };
+    unsigned n = 0;
+    owned_rows<VEC>(g, [&](long long p, long long, int) {
+        if constexpr (VEC) {
+            const float4 v = ld4(u + p);
+            n += bad(v.x) + bad(v.y) + bad(v.z) + bad(v.w);
+        } else {
+            n += bad(u[p]);
+        }
+    });
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) n += __shfl_xor(n, off);
+    if ((threadIdx.x & 63) == 0 && n) atomicAdd(count, n);
+}
+
 // ---------------------------------------------------------------------------------------------
 // Adjoint-state gradient helpers
 // ---------------------------------------------------------------------------------------------
@@ -1622,6 +1643,22 @@ int rtm_kappa_from_velocity(const rtm_grid *grid, float *kappa, const float *v, 
         hipLaunchKernelGGL(k_kappa<true>, dim3(row_blocks(g)), dim3(kThreads), 0, stream, g, kappa, v, dt_over_h);
     else
         hipLaunchKernelGGL(k_kappa<false>, dim3(row_blocks(g)), dim3(kThreads), 0, stream, g, kappa, v, dt_over_h);
+    return launch_status();
+}
+
+int rtm_count_nonfinite(const rtm_grid *grid, const float *u, uint32_t *count, hipStream_t stream)
+{
+    int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (!u || !count) return RTM_EINVAL;
+    if (ranges_overlap(count, 1, u, padded_total(grid))) return RTM_EALIAS;
+    st = check_device();
+    if (st != RTM_OK) return st;
+    const Geo g = make_geo(grid);
+    if (rows_vec(g) && aligned16(u))
+        hipLaunchKernelGGL(k_count_nonfinite<true>, dim3(row_blocks(g)), dim3(kThreads), 0, stream, g, u, count);
+    else
+        hipLaunchKernelGGL(k_count_nonfinite<false>, dim3(row_blocks(g)), dim3(kThreads), 0, stream, g, u, count);
     return launch_status();
 }
 

@@ -88,8 +88,15 @@ class Sources:
 
 class Propagator:
     def __init__(self, grid: Grid, kappa: torch.Tensor, *, sources: Sources | list | None = None,
-                 receivers=None, boundary: str = "zero", schedule: str = "overlap", debug: bool = False):
-        """debug: NaN-poison mode.  Buffers taken fresh for a new time level (when a pinned level
+                 receivers=None, boundary: str = "zero", schedule: str = "overlap", debug: bool = False,
+                 check_every: int = 0):
+        """check_every = K > 0: health check of the production path.  After every K-th step the
+        newest level's non-finite owned cells are counted on the device (rtm_count_nonfinite, 4 bytes
+        per cell) and the host reads the count (one synchronisation per K steps); a run that went
+        unstable (e.g. a time step past the stability limit) raises FloatingPointError within K
+        steps of its first non-finite level.
+
+        debug: NaN-poison mode.  Buffers taken fresh for a new time level (when a pinned level
         blocks the in-place rotation) start as NaN, ghost ring included, and after every step the
         owned cells of the new level must be finite; a kernel that read a cell nobody wrote (an unset
         ghost, an edge or corner of the ring, a stale buffer) would carry NaN into them.  The check
@@ -127,6 +134,10 @@ class Propagator:
         self._ev_int = None
         self.interior_events = None   # list of (start, end) timing events around rtm_step_interior
         self.debug = bool(debug)
+        if check_every < 0:
+            raise ValueError("check_every must be >= 0")
+        self.check_every = int(check_every)
+        self._bad = torch.zeros(1, dtype=torch.int32, device=grid.device) if self.check_every else None
 
     # ------------------------------------------------------------------------------------------
     def set_state(self, u_cur_host=None, u_prv_host=None, n: int = 0):
@@ -276,6 +287,18 @@ class Propagator:
         self.n = n + 1
         if self.debug:
             self._check_finite(u_nxt)
+        if self.check_every and self.n % self.check_every == 0:
+            self._health_check(u_nxt)
+
+    def _health_check(self, u: torch.Tensor):
+        st = self.level_stream
+        with torch.cuda.stream(st):
+            self._bad.zero_()
+        _abi.rtm_count_nonfinite(self.grid.c, u, self._bad, st)
+        st.synchronize()
+        bad = int(self._bad.item())
+        if bad:
+            raise FloatingPointError(f"level {self.n}: {bad} owned cells are not finite (unstable run?)")
 
     @property
     def level_stream(self):

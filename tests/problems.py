@@ -3,6 +3,7 @@ coefficients, time step, sponge, wavelet and kappa from the same seeded syntheti
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
 
@@ -10,8 +11,17 @@ import oracle
 from paper_1603_03971_amd import synth
 
 
+def host_threads() -> int:
+    """Threads for the oracle's stencil loops: the cores this process may run on (any count gives
+    the same bits)."""
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        return max(1, os.cpu_count() or 1)
+
+
 def oracle_forward_problem(v, h, nsteps, src_ijk, fpeak=15.0, rec_ijk=None, sponge_width=16, alpha=0.015,
-                           nthreads=8, radius=4, snap_every=0):
+                           nthreads=None, radius=4, snap_every=0):
     """Oracle run of a forward problem: point sources with the Ricker wavelet."""
     nz, ny, nx = v.shape
     dt = oracle.stable_dt(radius, h, float(np.max(v)))
@@ -22,7 +32,7 @@ def oracle_forward_problem(v, h, nsteps, src_ijk, fpeak=15.0, rec_ijk=None, spon
     w = oracle.injection_weight(vs, dt, h)
     amp = np.repeat(oracle.ricker(np.arange(nsteps) * dt, fpeak)[:, None], len(src_ijk), axis=1)
     out = oracle.forward(kap, sponge, nsteps, radius=radius, src_ijk=src_ijk, src_w=w, src_amp=amp, rec_ijk=rec_ijk,
-                         nthreads=nthreads, snap_every=snap_every)
+                         nthreads=nthreads or host_threads(), snap_every=snap_every)
     out["dt"] = dt
     return out
 

@@ -91,6 +91,84 @@ def test_fullsize_sampled_cells_match_oracle(layered):
     _say(f"fullsize sampled: worst {worst:.2e}")
 
 
+def test_c2_final_field_matches_oracle_after_1000_steps(layered, capsys):
+    """The benchmark's workload at its configured length: 512^3, 1000 steps of the halo-first step
+    with the six faces packed and unpacked, the whole final wavefield and the traces of a 32 x 32
+    surface spread against the FP64 oracle run on every host core (about 270 s on 16 cores; the
+    oracle is stepped in chunks of 100 steps so the run reports its progress).  Skipped, with the
+    projected time, on a host too slow to finish within 8 minutes."""
+    import time
+
+    import torch
+
+    from paper_1603_03971_amd.grid import Grid
+    from paper_1603_03971_amd.propagator import Propagator, Sources
+    from tests import problems
+
+    prof = layered
+    nsteps = 1000
+    c = N // 2
+    rec = synth.surface_receivers(N, N, k=20, stride=16)
+    dt = Grid.stable_dt(4, H, float(prof.max()))
+    g = Grid(N, N, N, H, dt)
+    v = torch.from_numpy(np.ascontiguousarray(np.broadcast_to(prof[:, None, None], (N, N, N)), dtype=np.float32))
+    kap = g.kappa_from_velocity(v.cuda())
+    del v
+    src = Sources(g, [(c, c, c)], g.injection_weights([prof[c]]), g.ricker(nsteps, 15.0)[:, None])
+    prop = Propagator(g, kap, sources=src, receivers=rec, schedule="serial")
+    traces = prop.new_traces(nsteps)
+    prop.run(nsteps, traces)
+    torch.cuda.synchronize()
+    u_gpu = g.download(prop.u_cur)
+    tr_gpu = traces.cpu().numpy()
+    del prop, kap, traces
+    torch.cuda.empty_cache()
+
+    threads = problems.host_threads()
+    dto = oracle.stable_dt(4, H, float(prof.max()))
+    v3 = np.broadcast_to(prof[:, None, None], (N, N, N))
+    kap_o = oracle.kappa_field(v3, dto, H)
+    sp = oracle.sponge_profile(N, 16, 0.015)
+    w = oracle.injection_weight([prof[c]], dto, H)
+    wav = oracle.ricker(np.arange(nsteps) * dto, 15.0)
+    u_cur = u_prv = None
+    tr_o = []
+    chunk = 100
+    t0 = time.perf_counter()
+    for n0 in range(0, nsteps, chunk):
+        if n0 == 0:
+            # time a short first chunk to decide whether the host can finish
+            out = oracle.forward(kap_o, (sp, sp, sp), 10, src_ijk=[(c, c, c)], src_w=w, src_amp=wav[:10, None],
+                                 rec_ijk=rec, nthreads=threads)
+            projected = (time.perf_counter() - t0) / 10 * nsteps
+            with capsys.disabled():
+                _say(f"\nc2 oracle: {threads} threads, projected {projected:.0f} s for {nsteps} steps")
+            if projected > 480:
+                pytest.skip(f"the host oracle would take {projected:.0f} s on {threads} threads")
+            tr_o.append(out["traces"])
+            u_cur, u_prv = out["u_cur"], out["u_prv"]
+            out = oracle.forward(kap_o, (sp, sp, sp), chunk - 10, src_ijk=[(c, c, c)], src_w=w,
+                                 src_amp=wav[10:chunk, None], rec_ijk=rec, u_cur=u_cur, u_prv=u_prv, nthreads=threads)
+        else:
+            out = oracle.forward(kap_o, (sp, sp, sp), chunk, src_ijk=[(c, c, c)], src_w=w,
+                                 src_amp=wav[n0:n0 + chunk, None], rec_ijk=rec, u_cur=u_cur, u_prv=u_prv,
+                                 nthreads=threads)
+        tr_o.append(out["traces"])
+        u_cur, u_prv = out["u_cur"], out["u_prv"]
+        del out
+        with capsys.disabled():
+            _say(f"c2 oracle: {n0 + chunk} / {nsteps} steps, {time.perf_counter() - t0:.0f} s")
+    tr_o = np.concatenate(tr_o, axis=0)
+    e_u = oracle.rel_l2(u_gpu, u_cur)
+    e_t = oracle.rel_l2(tr_gpu, tr_o)
+    scale = float(np.max(np.abs(u_cur)))
+    worst = float(np.max(np.abs(u_gpu - u_cur))) / scale
+    with capsys.disabled():
+        _say(f"c2 512^3 x 1000: rel-L2 wavefield {e_u:.2e}, traces {e_t:.2e}, max |diff| / max |u| {worst:.2e}")
+    assert e_u <= 1e-4 and e_t <= 1e-4
+    assert worst <= 1e-5
+
+
 def test_fullsize_mirror_symmetry_after_1000_steps(layered):
     """Centred source, medium layered along z, square x-y extent: u(i, j, k) = u(j, i, k) bitwise
     after the benchmark's 1000 steps (the update is symmetric in its x and y operands)."""

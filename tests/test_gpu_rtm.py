@@ -4,6 +4,7 @@ import pytest
 
 import oracle
 from paper_1603_03971_amd import synth
+from tests import problems
 
 pytestmark = pytest.mark.gpu
 
@@ -85,6 +86,54 @@ def test_rtm_image_parity_reduced(reduced_case):
     assert oracle.rel_l2(d_t, dt_o) <= 1e-4
     assert e_img <= 1e-3
     assert np.max(np.abs(img_o)) > 0
+
+
+def c3_reduced_inputs(seed=3):
+    """The one-shot RTM recipe scaled down four times per axis: 128 x 128 x 64 cells, h = 10 m, the
+    v(z) background with three thin dipping planes (seed 3, depths 15-38 cells), a surface source at
+    the centre and 64 x 64 receivers every 2 cells, both at depth index 10."""
+    shape = (64, 128, 128)
+    v_true, v_bg = synth.dipping_reflector_model(shape, 10.0, seed=seed, z0_cells=(15, 38), max_dip_deg=15.0)
+    src = [(64, 64, 10)]
+    rec = synth.surface_receivers(128, 128, k=10, stride=2)
+    return v_true, v_bg, src, rec
+
+
+@pytest.fixture(scope="module")
+def c3_reduced_case():
+    v_true, v_bg, src, rec = c3_reduced_inputs()
+    nsteps, fpeak, s = 500, 15.0, 4
+    _say("rtm 128x128x64 x 500: oracle")
+    ref = oracle_rtm(v_true, v_bg, src, rec, nsteps, fpeak, s, nthreads=problems.host_threads())
+    return (v_true, v_bg, src, rec, nsteps, fpeak, s), ref
+
+
+@pytest.mark.parametrize("schedule,halo_x", [("serial", None), ("serial", 32), ("fused", None)])
+def test_rtm_image_parity_128x128x64(c3_reduced_case, schedule, halo_x):
+    """Image parity at 128 x 128 x 64 x 500 steps (snapshots every 4 steps): the halo-first schedule,
+    the halo-first schedule with 32-column x strips (so that the interior call updates a 64-column
+    box; with the default 64-column strips it has nothing to do at this width) and the one-launch
+    schedule, each against the FP64 oracle."""
+    from paper_1603_03971_amd import _abi
+
+    args, (img_o, dt_o, db_o, _) = c3_reduced_case
+    old = _abi.rtm_get_option(_abi.RTM_OPT_HALO_X_WIDTH)
+    try:
+        if halo_x is not None:
+            _abi.rtm_set_option(_abi.RTM_OPT_HALO_X_WIDTH, halo_x)
+        _say(f"rtm 128x128x64 {schedule} halo_x={halo_x}: gpu")
+        img, d_t, d_b, _ = gpu_rtm(*args, schedule=schedule)
+    finally:
+        _abi.rtm_set_option(_abi.RTM_OPT_HALO_X_WIDTH, old)
+    e_t = oracle.rel_l2(d_t, dt_o)
+    e_r = oracle.rel_l2(d_t - d_b, dt_o - db_o)
+    e_img = oracle.rel_l2(img, img_o)
+    worst = float(np.max(np.abs(img - img_o)) / np.max(np.abs(img_o)))
+    _say(f"rtm 128x128x64 {schedule} halo_x={halo_x}: traces {e_t:.2e}, residual traces {e_r:.2e}, "
+         f"image rel-L2 {e_img:.2e}, max |diff| / max {worst:.2e}")
+    assert e_t <= 1e-4
+    assert e_img <= 1e-3
+    assert worst <= 1e-3
 
 
 def test_rtm_serial_schedule_bitwise(reduced_case):

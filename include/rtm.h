@@ -264,6 +264,20 @@ int rtm_misfit_residual(const float *d, const float *obs, float *resid, int64_t 
 int rtm_misfit_residual_chunks(const float *d, const float *obs, float *resid, int64_t n, double *partials,
                                int32_t nchunks, double *misfit, hipStream_t stream);
 
+/* rtm_misfit_residual_chunks without the caller's `partials` buffer, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * per-chunk FP64 sums go to a scratch array inside the library, at most 4096 chunks (32 KiB), which
+ * each device that runs this call holds until the process ends.  The call itself allocates nothing
+ * and frees nothing.  Same residual, same fixed summation order and so the same bits as
+ * rtm_misfit_residual_chunks with the same n and nchunks.  Every call on one device shares that
+ * device's scratch: calls that overlap in time on one device (other streams, other host threads)
+ * race and must be ordered by the caller.  Each call writes every slot it reads, so nothing carries
+ * over from the previous call.  RTM_EINVAL for n < 0, nchunks <= 0 or nchunks > 4096, or a NULL
+ * pointer; RTM_EALIAS if resid partly overlaps d or obs; RTM_EDEVICE if the scratch address of the
+ * current device cannot be obtained. */
+int rtm_misfit_residual_chunks_noalloc(const float *d, const float *obs, float *resid, int64_t n, int32_t nchunks,
+                                       double *misfit, hipStream_t stream);
+
 /* Chain rule through kappa = (v dt / h)^2: grad_v = 2 v (dt/h)^2 grad_kappa, with grad_v and v compact
  * x-fastest nz*ny*nx arrays and grad_kappa a padded field. */
 int rtm_velocity_gradient(const rtm_grid *grid, float *grad_v, const float *grad_kappa, const float *v,

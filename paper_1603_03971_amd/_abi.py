@@ -73,6 +73,7 @@ def _load():
         "rtm_gradient_accumulate": ([gp, vp, vp, vp, vp], ctypes.c_int),
         "rtm_misfit_residual": ([vp, vp, vp, i64, vp, vp], ctypes.c_int),
         "rtm_misfit_residual_chunks": ([vp, vp, vp, i64, vp, i32, vp, vp], ctypes.c_int),
+        "rtm_misfit_residual_chunks_noalloc": ([vp, vp, vp, i64, i32, vp, vp], ctypes.c_int),
         "rtm_velocity_gradient": ([gp, vp, vp, vp, f32, vp], ctypes.c_int),
         "rtm_image_accumulate_coded": ([gp, vp, vp, vp, i32, vp, f32, vp], ctypes.c_int),
         "rtm_cnn_conv3d": ([i32, i32, i32, vp, vp, vp, i32, vp, i32, vp, vp], ctypes.c_int),
@@ -288,6 +289,11 @@ def rtm_misfit_residual(d, obs, resid, n, misfit, stream=None):
 def rtm_misfit_residual_chunks(d, obs, resid, n, partials, nchunks, misfit, stream=None):
     _check(_lib.rtm_misfit_residual_chunks(_p(d), _p(obs), _p(resid), n, _p(partials), nchunks, _p(misfit),
                                            _s(stream)), "rtm_misfit_residual_chunks")
+
+
+def rtm_misfit_residual_chunks_noalloc(d, obs, resid, n, nchunks, misfit, stream=None):
+    _check(_lib.rtm_misfit_residual_chunks_noalloc(_p(d), _p(obs), _p(resid), n, nchunks, _p(misfit), _s(stream)),
+           "rtm_misfit_residual_chunks_noalloc")
 
 
 def rtm_velocity_gradient(grid, grad_v, grad_kappa, v, dt_over_h, stream=None):

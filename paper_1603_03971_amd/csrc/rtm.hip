@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <utility>
 
@@ -1311,6 +1312,42 @@ bool ranges_overlap(const void *a, long long na, const void *b, long long nb)
 
 }  // namespace
 
+// ---------------------------------------------------------------------------------------------
+// Library-owned scratch for the entry points that allocate nothing.  Each device that runs them
+// holds one copy of this array until the process ends; host code never passes the array's name to
+// a kernel (on the host it stands for the host-side shadow, not the device copy), only the device
+// address that hipGetSymbolAddress returns for the current device, cached per device.
+// ---------------------------------------------------------------------------------------------
+constexpr int kNoAllocMaxChunks = 4096;       // FP64 partial sums: 32 KiB per device
+static __device__ __align__(256) double scratch[kNoAllocMaxChunks];
+
+namespace {
+
+std::atomic<double *> g_scratch_ptr[kMaxDevices];
+std::mutex g_scratch_mu;
+
+// The current device's address of `scratch` (looked up once per device, with it current).
+int device_scratch(double **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return RTM_EDEVICE;
+    double *p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        p = g_scratch_ptr[dev].load(std::memory_order_relaxed);
+        if (!p) {
+            void *q = nullptr;
+            if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q) return RTM_EDEVICE;
+            p = static_cast<double *>(q);
+            g_scratch_ptr[dev].store(p, std::memory_order_release);
+        }
+    }
+    *out = p;
+    return RTM_OK;
+}
+
+}  // namespace
+
 // =============================================================================================
 // extern "C" entry points
 // =============================================================================================
@@ -1749,6 +1786,31 @@ int rtm_misfit_residual_chunks(const float *d, const float *obs, float *resid, i
     const int s1 = launch_status();
     if (s1 != RTM_OK) return s1;
     hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(kReduceThreads), 0, stream, partials, (int)nb, misfit);
+    return launch_status();
+}
+
+int rtm_misfit_residual_chunks_noalloc(const float *d, const float *obs, float *resid, int64_t n, int32_t nchunks,
+                                       double *misfit, hipStream_t stream)
+{
+    if (n < 0 || nchunks <= 0 || nchunks > kNoAllocMaxChunks) return RTM_EINVAL;
+    if (n == 0) return RTM_OK;
+    if (!d || !obs || !resid || !misfit) return RTM_EINVAL;
+    if ((resid != d && ranges_overlap(resid, n, d, n)) || (resid != obs && ranges_overlap(resid, n, obs, n)))
+        return RTM_EALIAS;
+    int st = check_device();
+    if (st != RTM_OK) return st;
+    double *part = nullptr;
+    st = device_scratch(&part);
+    if (st != RTM_OK) return st;
+    const long long chunk = (n + nchunks - 1) / nchunks;
+    const long long nb = (n + chunk - 1) / chunk;      // chunks that hold samples (<= nchunks)
+    // every slot the final sum reads (part[0..nb)) is written by the first kernel of this call, so the
+    // previous call's contents never leak in and nothing needs clearing
+    hipLaunchKernelGGL(k_residual_chunks, dim3((unsigned)nb), dim3(kChunkThreads), 0, stream, d, obs, resid,
+                       (long long)n, chunk, part);
+    st = launch_status();
+    if (st != RTM_OK) return st;
+    hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(kReduceThreads), 0, stream, part, (int)nb, misfit);
     return launch_status();
 }
 

@@ -123,6 +123,15 @@ const char *rtm_strerror(int status);
  *   RTM_OPT_XCD_REMAP         1 = give each XCD a contiguous range of tiles (default), 0 = hardware order.
  *   RTM_OPT_HALO_X_WIDTH      width of the halo region's x strips (default 64 = one tile);
  *   RTM_OPT_HALO_Y_WIDTH      height of its y strips (default 16); see rtm_halo_region.
+ *   RTM_OPT_UNPACK_LINES      1 = (default) where the layout puts a row's +X ghost, its padding and the
+ *                             next row's -X ghost in one 128-byte line (radius 4, nx % 32 == 0,
+ *                             pitch_y = nx + 32, owned (0,0,0) line-aligned), rtm_unpack_halo writes the
+ *                             x faces as whole lines (zeros in the padding, which holds no cell);
+ *                             0 = 16-byte pieces.  Ghost and owned cells get the same values either way.
+ *   RTM_OPT_TILE_FLAGS        variants of the radius-4 forward tiled launches (halo, interior, whole):
+ *                             bit 0 = non-temporal loads of u_prv and kappa and stores of u_nxt (data
+ *                             used once per step), bit 1 = each thread's x neighbours from the adjacent
+ *                             lanes' registers (DPP lane shifts) instead of LDS; default 0.
  * Returns RTM_EINVAL for an unknown option or value. */
 enum {
     RTM_OPT_INTERIOR_VARIANT = 1,
@@ -132,6 +141,8 @@ enum {
     RTM_OPT_HALO_Y_WIDTH = 5,
     RTM_OPT_HALO_VARIANT = 6,
     RTM_OPT_WHOLE_VARIANT = 7,
+    RTM_OPT_UNPACK_LINES = 8,
+    RTM_OPT_TILE_FLAGS = 9,
 };
 int rtm_set_option(int32_t option, int32_t value);
 /* The current value of an option (>= 0), or RTM_EINVAL for an unknown option. */
@@ -248,6 +259,37 @@ int rtm_adjoint_step(const rtm_grid *grid, float *mu_out, const float *mu_a, con
 /* Gradient of the least-squares misfit with respect to kappa, one term per step:
  * grad += g * mu^{n+1} * L u^n on owned cells (u's ghosts are read, zero for a physical boundary). */
 int rtm_gradient_accumulate(const rtm_grid *grid, float *grad, const float *u, const float *mu, hipStream_t stream);
+
+/* The same recursion in scaled form, which the forward kernel runs.  With w = kappa g mu (kappa, g > 0
+ * and time-independent), multiplying the transposed step by kappa g gives
+ *     w^m = g (2 w^{m+1} - g w^{m+2} + kappa L w^{m+1}) + kappa g R^T y^{m-1},
+ * which is exactly the forward update of rtm_step_whole with u_cur = w^{m+1}, u_prv = w^{m+2} (zero
+ * ghosts: cells outside the owned block are zero in w as in kappa g mu), followed by rtm_inject at
+ * the receivers with the weights kappa_r g_r.  The adjoint step then costs one forward step.  In this
+ * form the gradient is
+ *     dJ/dkappa = sum_n g mu^{n+1} L u^n = (1/kappa) sum_n w^{n+1} L u^n,
+ *     dJ/dv = 2 v (dt/h)^2 dJ/dkappa = (2 / v) sum_n w^{n+1} L u^n,
+ * and the source-side output is w_s mu^{n+1}[s] = w_s w^{n+1}[s] / (kappa_s g_s).  The four calls below
+ * provide the pieces the forward calls do not. */
+
+/* grad += w L u on owned cells (u's ghosts are read): one term of G = sum_n w^{n+1} L u^n. */
+int rtm_gradient_accumulate_scaled(const rtm_grid *grid, float *grad, const float *u, const float *w,
+                                   hipStream_t stream);
+
+/* For the n padded indices idx (int64, device) of owned cells: kg[r] = kappa g at the cell (the receiver
+ * weights of the scaled recursion) and inv_kg[r] = 1 / (kappa g) (its source-side output scale), FP32,
+ * device arrays of n; either may be NULL, not both.  An index that is not an owned cell gives 0 in both. */
+int rtm_scaled_adjoint_factors(const rtm_grid *grid, const float *kappa, const int64_t *idx, int32_t n, float *kg,
+                               float *inv_kg, hipStream_t stream);
+
+/* Weighted recording: out[r] = w[r] * u[idx[r]] for r < n (an index outside the padded block gives 0). */
+int rtm_record_weighted(const rtm_grid *grid, const float *u, const int64_t *idx, const float *w, float *out,
+                        int32_t n, hipStream_t stream);
+
+/* grad_v = 2 G / v (compact x-fastest nz*ny*nx arrays grad_v and v; G a padded field): dJ/dv from the
+ * scaled gradient sum G = sum_n w^{n+1} L u^n. */
+int rtm_velocity_gradient_scaled(const rtm_grid *grid, float *grad_v, const float *G, const float *v,
+                                 hipStream_t stream);
 
 /* resid[i] = d[i] - obs[i] for i < n, and *misfit += 1/2 sum resid^2 accumulated in FP64 in a fixed
  * order (bitwise reproducible; misfit is a device double the caller zeroes).  resid may equal d or
@@ -412,6 +454,14 @@ int rtm_cnn_target(const rtm_grid *grid, const float *ref_cur, const float *ref_
 #define RTM_RESTRICT_FULL 1
 int rtm_restrict(const rtm_grid *fine, const rtm_grid *coarse, const float *u_fine, float *u_coarse, int32_t mode,
                  hipStream_t stream);
+
+/* Prolongation from a coarse grid to one of twice the resolution (owned cells of padded fields of the two
+ * grids), the transpose of RTM_RESTRICT_FULL up to a factor 8: fine (I, J, K) takes, along each axis,
+ * coarse I/2 for even I and the mean of coarse (I-1)/2 and (I+1)/2 for odd I (trilinear interpolation).
+ * Needs n_fine <= 2 n_coarse along every axis; the last odd fine cell reads the coarse ghost layer,
+ * which must hold its boundary values. */
+int rtm_prolong(const rtm_grid *coarse, const rtm_grid *fine, const float *u_coarse, float *u_fine,
+                hipStream_t stream);
 
 /* out[0] = max |u| over the owned cells (device; order-independent). */
 int rtm_field_absmax(const rtm_grid *grid, const float *u, float *out, hipStream_t stream);

@@ -17,7 +17,7 @@ RTM_OK, RTM_EINVAL, RTM_EALIAS, RTM_ELAUNCH, RTM_EDEVICE = 0, -1, -2, -3, -4
 RTM_SNAP_BF16, RTM_SNAP_F16 = 1, 2
 RTM_RESTRICT_INJECT, RTM_RESTRICT_FULL = 0, 1
 RTM_OPT_INTERIOR_VARIANT, RTM_OPT_ZCHUNK, RTM_OPT_XCD_REMAP, RTM_OPT_HALO_X_WIDTH, RTM_OPT_HALO_Y_WIDTH = 1, 2, 3, 4, 5
-RTM_OPT_HALO_VARIANT, RTM_OPT_WHOLE_VARIANT = 6, 7
+RTM_OPT_HALO_VARIANT, RTM_OPT_WHOLE_VARIANT, RTM_OPT_UNPACK_LINES, RTM_OPT_TILE_FLAGS = 6, 7, 8, 9
 
 
 class RTMError(RuntimeError):
@@ -71,6 +71,10 @@ def _load():
         "rtm_snapshot_encode": ([gp, vp, vp, vp, i32, vp], ctypes.c_int),
         "rtm_adjoint_step": ([gp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "rtm_gradient_accumulate": ([gp, vp, vp, vp, vp], ctypes.c_int),
+        "rtm_gradient_accumulate_scaled": ([gp, vp, vp, vp, vp], ctypes.c_int),
+        "rtm_scaled_adjoint_factors": ([gp, vp, vp, i32, vp, vp, vp], ctypes.c_int),
+        "rtm_record_weighted": ([gp, vp, vp, vp, vp, i32, vp], ctypes.c_int),
+        "rtm_velocity_gradient_scaled": ([gp, vp, vp, vp, vp], ctypes.c_int),
         "rtm_misfit_residual": ([vp, vp, vp, i64, vp, vp], ctypes.c_int),
         "rtm_misfit_residual_chunks": ([vp, vp, vp, i64, vp, i32, vp, vp], ctypes.c_int),
         "rtm_misfit_residual_chunks_noalloc": ([vp, vp, vp, i64, i32, vp, vp], ctypes.c_int),
@@ -91,6 +95,7 @@ def _load():
         "rtm_cnn_conv3d_apply": ([gp, vp, vp, vp, i32, vp, vp, vp, vp, vp], ctypes.c_int),
         "rtm_cnn_target": ([gp, vp, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "rtm_restrict": ([gp, gp, vp, vp, i32, vp], ctypes.c_int),
+        "rtm_prolong": ([gp, gp, vp, vp, vp], ctypes.c_int),
         "rtm_field_absmax": ([gp, vp, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
@@ -296,6 +301,26 @@ def rtm_misfit_residual_chunks_noalloc(d, obs, resid, n, nchunks, misfit, stream
            "rtm_misfit_residual_chunks_noalloc")
 
 
+def rtm_gradient_accumulate_scaled(grid, grad, u, w, stream=None):
+    _check(_lib.rtm_gradient_accumulate_scaled(ctypes.byref(grid), _p(grad), _p(u), _p(w), _s(stream)),
+           "rtm_gradient_accumulate_scaled")
+
+
+def rtm_scaled_adjoint_factors(grid, kappa, idx, n, kg, inv_kg, stream=None):
+    _check(_lib.rtm_scaled_adjoint_factors(ctypes.byref(grid), _p(kappa), _p(idx), n, _p(kg), _p(inv_kg),
+                                           _s(stream)), "rtm_scaled_adjoint_factors")
+
+
+def rtm_record_weighted(grid, u, idx, w, out, n, stream=None):
+    _check(_lib.rtm_record_weighted(ctypes.byref(grid), _p(u), _p(idx), _p(w), _p(out), n, _s(stream)),
+           "rtm_record_weighted")
+
+
+def rtm_velocity_gradient_scaled(grid, grad_v, G, v, stream=None):
+    _check(_lib.rtm_velocity_gradient_scaled(ctypes.byref(grid), _p(grad_v), _p(G), _p(v), _s(stream)),
+           "rtm_velocity_gradient_scaled")
+
+
 def rtm_velocity_gradient(grid, grad_v, grad_kappa, v, dt_over_h, stream=None):
     _check(_lib.rtm_velocity_gradient(ctypes.byref(grid), _p(grad_v), _p(grad_kappa), _p(v), dt_over_h, _s(stream)),
            "rtm_velocity_gradient")
@@ -375,6 +400,11 @@ def rtm_restrict(fine, coarse, u_fine, u_coarse, stream=None, mode=None):
     mode = RTM_RESTRICT_INJECT if mode is None else mode
     _check(_lib.rtm_restrict(ctypes.byref(fine), ctypes.byref(coarse), _p(u_fine), _p(u_coarse), mode, _s(stream)),
            "rtm_restrict")
+
+
+def rtm_prolong(coarse, fine, u_coarse, u_fine, stream=None):
+    _check(_lib.rtm_prolong(ctypes.byref(coarse), ctypes.byref(fine), _p(u_coarse), _p(u_fine), _s(stream)),
+           "rtm_prolong")
 
 
 def rtm_field_absmax(grid, u, out, stream=None):

@@ -12,6 +12,13 @@ with mu^{N+1} = mu^{N+2} = 0, and accumulates dJ/dkappa += g mu^m L u^{m-1} (rtm
 rtm_inject, rtm_gradient_accumulate).  The chain rule through kappa = (v dt / h)^2 gives dJ/dv
 (rtm_velocity_gradient).  Injection weights are held at the values of the model they were built
 from (the gradient treats them as constants).
+
+By default the recursion runs in scaled form, on the state w = kappa g mu: multiplying the step above
+by kappa g turns it into w^m = g (2 w^{m+1} - g w^{m+2} + kappa L w^{m+1}) + kappa g R^T r^{m-1}, the
+forward update itself (rtm_step_whole, then rtm_inject with the receiver weights kappa_r g_r from
+rtm_scaled_adjoint_factors), so an adjoint step costs one forward step.  The gradient is then
+G = sum w^m L u^{m-1} (rtm_gradient_accumulate_scaled) and dJ/dv = 2 G / v
+(rtm_velocity_gradient_scaled).  adjoint="direct" runs the mu recursion with rtm_adjoint_step.
 """
 from __future__ import annotations
 
@@ -39,9 +46,14 @@ class MisfitProblem:
     """J(v) = 1/2 sum over shots, steps and receivers of (d - d_obs)^2 on one grid."""
 
     def __init__(self, grid: Grid, nsteps: int, wavelet, shots: list[Shot], checkpoint_every: int = 50,
-                 schedule: str = "fused"):
+                 schedule: str = "fused", adjoint: str = "scaled"):
         """schedule: the propagator schedule of the forward and recomputation runs (all give the
-        same bits; the one-launch schedule is the fastest on one GPU)."""
+        same bits; the one-launch schedule is the fastest on one GPU).  adjoint: "scaled" (the
+        recursion on w = kappa g mu, run by the forward kernel) or "direct" (rtm_adjoint_step on mu);
+        the two agree to FP32 rounding."""
+        if adjoint not in ("scaled", "direct"):
+            raise ValueError(adjoint)
+        self.adjoint = adjoint
         self.g = grid
         self.schedule = schedule
         self.nsteps = int(nsteps)
@@ -91,17 +103,27 @@ class MisfitProblem:
 
     def backward(self, kappa: torch.Tensor, shot: Shot, ckpt, resid: torch.Tensor, grad_kappa: torch.Tensor,
                  y_src: torch.Tensor | None = None):
-        """Adjoint pass of one shot; adds its dJ/dkappa to grad_kappa.  With y_src (device
-        (nsteps, nsrc)), also records the source-side adjoint output mu^{n+1}[s] into it."""
+        """Adjoint pass of one shot; adds its gradient term to grad_kappa (dJ/dkappa, or in the scaled
+        form G = kappa dJ/dkappa).  With y_src (device (nsteps, nsrc)), also records the source-side
+        adjoint state mu^{n+1}[s] into it."""
         g, N, C = self.g, self.nsteps, self.C
         st = torch.cuda.current_stream()
-        if self._work is None:
+        scaled = self.adjoint == "scaled"
+        if self._work is None and not scaled:
             self._work = g.field()
         work = self._work
+        nrec, nsrc = len(shot.rec_ijk), len(shot.src_ijk)
         rec_idx = torch.from_numpy(g.index(shot.rec_ijk)).to(g.device)
-        ones = torch.ones(len(shot.rec_ijk), dtype=torch.float32, device=g.device)
         src_idx = torch.from_numpy(g.index(shot.src_ijk)).to(g.device)
-        mu_a, mu_b = g.field(), g.field()           # mu^{m+1}, mu^{m+2}
+        if scaled:
+            # receiver weights kappa_r g_r, and 1 / (kappa_s g_s) to turn w back into mu at the sources
+            rec_w = torch.empty(nrec, dtype=torch.float32, device=g.device)
+            src_scale = torch.empty(nsrc, dtype=torch.float32, device=g.device)
+            _abi.rtm_scaled_adjoint_factors(g.c, kappa, rec_idx, nrec, rec_w, None, st)
+            _abi.rtm_scaled_adjoint_factors(g.c, kappa, src_idx, nsrc, None, src_scale, st)
+        else:
+            rec_w = torch.ones(nrec, dtype=torch.float32, device=g.device)
+        mu_a, mu_b = g.field(), g.field()           # mu^{m+1}, mu^{m+2} (or w); zero ghost rings
         prop = Propagator(g, kappa, sources=self._sources(shot), schedule=self.schedule)
         nseg = (N + C - 1) // C
         for seg in range(nseg - 1, -1, -1):
@@ -116,14 +138,22 @@ class MisfitProblem:
                 levels[n + 1] = prop.pin_current()
             prop.sync()
             for m in range(n1, n0, -1):
-                # mu^m from mu^{m+1}, mu^{m+2}; in place over mu^{m+2}
-                _abi.rtm_adjoint_step(g.c, mu_b, mu_a, mu_b, kappa, work, st)
-                _abi.rtm_inject(g.c, mu_b, rec_idx, ones, resid.data_ptr() + 4 * (m - 1) * len(shot.rec_ijk),
-                                len(shot.rec_ijk), st)
-                _abi.rtm_gradient_accumulate(g.c, grad_kappa, levels[m - 1], mu_b, st)
+                # mu^m (or w^m) from the two later levels, in place over the older one
+                if scaled:
+                    _abi.rtm_step_whole(g.c, mu_b, mu_a, mu_b, kappa, st)
+                else:
+                    _abi.rtm_adjoint_step(g.c, mu_b, mu_a, mu_b, kappa, work, st)
+                _abi.rtm_inject(g.c, mu_b, rec_idx, rec_w, resid.data_ptr() + 4 * (m - 1) * nrec, nrec, st)
+                if scaled:
+                    _abi.rtm_gradient_accumulate_scaled(g.c, grad_kappa, levels[m - 1], mu_b, st)
+                else:
+                    _abi.rtm_gradient_accumulate(g.c, grad_kappa, levels[m - 1], mu_b, st)
                 if y_src is not None:
-                    _abi.rtm_record(g.c, mu_b, src_idx, y_src.data_ptr() + 4 * (m - 1) * len(shot.src_ijk),
-                                    len(shot.src_ijk), st)
+                    out = y_src.data_ptr() + 4 * (m - 1) * nsrc
+                    if scaled:
+                        _abi.rtm_record_weighted(g.c, mu_b, src_idx, src_scale, out, nsrc, st)
+                    else:
+                        _abi.rtm_record(g.c, mu_b, src_idx, out, nsrc, st)
                 mu_a, mu_b = mu_b, mu_a
             for t in levels.values():
                 prop.unpin(t)
@@ -141,7 +171,10 @@ class MisfitProblem:
             ckpt, resid = self.forward(kappa, shot, misfit)
             self.backward(kappa, shot, ckpt, resid, grad_k)
         gv = torch.empty(g.shape, dtype=torch.float32, device=g.device)
-        _abi.rtm_velocity_gradient(g.c, gv, grad_k, v, g.dt / g.h, torch.cuda.current_stream())
+        if self.adjoint == "scaled":
+            _abi.rtm_velocity_gradient_scaled(g.c, gv, grad_k, v, torch.cuda.current_stream())
+        else:
+            _abi.rtm_velocity_gradient(g.c, gv, grad_k, v, g.dt / g.h, torch.cuda.current_stream())
         return float(misfit.item()), gv
 
     def misfit(self, v: torch.Tensor) -> float:

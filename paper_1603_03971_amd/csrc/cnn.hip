@@ -719,6 +719,31 @@ __global__ __launch_bounds__(256) void k_restrict(G f, G c, const float *__restr
     }
 }
 
+// Prolongation, the transpose of full weighting up to a factor 8: fine cell (I, J, K) takes, along each
+// axis, coarse cell I/2 for even I and the mean of coarse cells (I-1)/2 and (I+1)/2 for odd I (trilinear
+// interpolation between coincident cells; the last odd fine cell reads the coarse ghost layer).
+__global__ __launch_bounds__(256) void k_prolong(G c, G f, const float *__restrict__ uc, float *__restrict__ uf)
+{
+    const long long n = (long long)f.nx * f.ny * f.nz;
+    for (long long t = first_item(); t < n; t += item_stride()) {
+        const int I = (int)(t % f.nx);
+        const int J = (int)((t / f.nx) % f.ny);
+        const int K = (int)(t / ((long long)f.nx * f.ny));
+        const int i0 = I >> 1, j0 = J >> 1, k0 = K >> 1;
+        const int ni = (I & 1) ? 2 : 1, nj = (J & 1) ? 2 : 1, nk = (K & 1) ? 2 : 1;
+        float acc = 0.0f;
+        for (int a = 0; a < nk; ++a) {
+            float sy = 0.0f;
+            for (int b = 0; b < nj; ++b) {
+                const float *r = uc + c.idx(i0, j0 + b, k0 + a);
+                sy += (ni == 2) ? 0.5f * (r[0] + r[1]) : r[0];
+            }
+            acc += (nj == 2) ? 0.5f * sy : sy;
+        }
+        uf[f.idx(I, J, K)] = (nk == 2) ? 0.5f * acc : acc;
+    }
+}
+
 // max |u| over owned cells into out[0] (the corrector's per-application scale): workgroups stride
 // over the rows, each thread over a row's cells, and the workgroup maxima are combined with an
 // integer atomic max on the bit patterns (non-negative floats order like their bits), so the result
@@ -1023,6 +1048,18 @@ int rtm_restrict(const rtm_grid *fine, const rtm_grid *coarse, const float *u_fi
     CNN_CHECK_DEVICE();
     hipLaunchKernelGGL(k_restrict, dim3(nblk(n)), dim3(256), 0, stream, f, c, u_fine, u_coarse,
                        (int)(mode == RTM_RESTRICT_FULL));
+    return status();
+}
+
+int rtm_prolong(const rtm_grid *coarse, const rtm_grid *fine, const float *u_coarse, float *u_fine, hipStream_t stream)
+{
+    if (!grid_ok(fine) || !grid_ok(coarse) || !u_fine || !u_coarse) return RTM_EINVAL;
+    // every fine cell's coarse neighbours are owned or in the first ghost layer
+    if (fine->nx > 2 * coarse->nx || fine->ny > 2 * coarse->ny || fine->nz > 2 * coarse->nz) return RTM_EINVAL;
+    const G f = make_g(fine), c = make_g(coarse);
+    const long long n = (long long)f.nx * f.ny * f.nz;
+    CNN_CHECK_DEVICE();
+    hipLaunchKernelGGL(k_prolong, dim3(nblk(n)), dim3(256), 0, stream, c, f, u_coarse, u_fine);
     return status();
 }
 

@@ -50,7 +50,8 @@ __device__ __forceinline__ float axis_sum(float xm, float xp, float ym, float yp
 //   OP_ADJOINT   u = kappa g mu_a,   a = mu_a,    b = mu_b:    2 g mu_a + L(kappa g mu_a) - g^2 mu_b
 //                (the tiled kernel forms u itself from mu_a and kappa as it loads each plane)
 //   OP_GRADIENT  u = u^n,            a = mu,      b = grad:    grad + g mu L u^n
-enum { OP_FORWARD = 0, OP_ADJOINT = 1, OP_GRADIENT = 2 };
+//   OP_GRADIENT_SCALED u = u^n,      a = w,       b = grad:    grad + w L u^n   (w = kappa g mu)
+enum { OP_FORWARD = 0, OP_ADJOINT = 1, OP_GRADIENT = 2, OP_GRADIENT_SCALED = 3 };
 
 // The per-point operation.  s[m-1] = axis_sum at distance m.  The centre weight is 3 c0 (one c0 per
 // axis).
@@ -69,13 +70,46 @@ __device__ __forceinline__ float point_op(float u0, const float (&s)[R], float a
     } else if constexpr (OP == OP_ADJOINT) {
         const float t = __builtin_fmaf(2.0f * g, a, lap);
         return __builtin_fmaf(-(g * g), b, t);
-    } else {
+    } else if constexpr (OP == OP_GRADIENT) {
         return __builtin_fmaf(g * a, lap, b);
+    } else {
+        return __builtin_fmaf(a, lap, b);
     }
 }
 
 __device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
 __device__ __forceinline__ void st4(float *p, float4 v) { *reinterpret_cast<float4 *>(p) = v; }
+
+// Non-temporal (streaming) forms, for data used once per step (u^{n-1}, kappa, u^{n+1}).
+typedef float f4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld4_nt(const float *p)
+{
+    const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st4_nt(float *p, float4 v)
+{
+    const f4v w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<f4v *>(p));
+}
+
+// Cross-lane moves of a float4 by one lane (DPP wave_shr:1 / wave_shl:1): lane l receives lane l - 1's
+// (shr) or lane l + 1's (shl) value; the lane with no source receives 0.  Every lane of the wave must
+// be active.
+__device__ __forceinline__ float dpp_shr1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float dpp_shl1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float4 dpp_shr1(float4 v) { return make_float4(dpp_shr1(v.x), dpp_shr1(v.y), dpp_shr1(v.z), dpp_shr1(v.w)); }
+__device__ __forceinline__ float4 dpp_shl1(float4 v) { return make_float4(dpp_shl1(v.x), dpp_shl1(v.y), dpp_shl1(v.z), dpp_shl1(v.w)); }
+
+// Variants of the tiled kernel (template flags): streaming hints on the once-used streams, and the
+// x neighbours of a thread's float4 taken from the adjacent lanes' registers instead of LDS.
+enum { FL_NT = 1, FL_XSHUF = 2 };
 __device__ __forceinline__ float el(const float4 &v, int e)
 {
     return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
@@ -196,11 +230,14 @@ __device__ __forceinline__ float4 weight4(float4 mu, float4 kp, const float (&gx
     return w;
 }
 
-template <int R, int BX, int BY, int OP, bool PACK = false>
+template <int R, int BX, int BY, int OP, bool PACK = false, int FL = 0>
 __global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(BX * BY >= 512 ? 4 : 1)))
 void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, const float *kap, BoxList bl,
              PackOut po, const float *__restrict__ rk)
 {
+    constexpr bool STREAM = (FL & FL_NT) != 0;
+    constexpr bool XS = (FL & FL_XSHUF) != 0;
+    auto ldo = [](const float *p) { return STREAM ? ld4_nt(p) : ld4(p); };   // u_prv / kappa operands
     // OP_ADJOINT: the stencil field is kappa g mu_a, formed here from two loads per ring element (uc =
     // mu_a, rk = kappa) instead of being read from a field written by a separate pass; the ring
     // elements of cells outside the owned block are zero, as the ghosts of such a field would be.
@@ -379,8 +416,8 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
     // batch of loads, so waiting for them never waits for the loads issued for later planes
     float4 pv[2], kv[2];
     float gzv[2];
-    pv[0] = ld4(up + pca);
-    kv[0] = ld4(kap + pca);
+    pv[0] = ldo(up + pca);
+    kv[0] = ldo(kap + pca);
     gzv[0] = g.gz[zs];
 
     int k0_ = zs;                           // first plane of the current ring revolution
@@ -437,15 +474,30 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
 #pragma unroll
                 for (int h = 0; h < HPT; ++h) hv[h] = ld4(uc + hoff[h] + kh * pz);
             }
-            pv[b ^ 1] = ld4(up + pca + kn * pz);
-            kv[b ^ 1] = ld4(kap + pca + kn * pz);
+            pv[b ^ 1] = ldo(up + pca + kn * pz);
+            kv[b ^ 1] = ldo(kap + pca + kn * pz);
             gzv[b ^ 1] = g.gz[zs + kn];
         }
 
+        // XS: the neighbouring float4s of the row from the adjacent lanes (all lanes active here; lanes
+        // of one row are consecutive), the tile's edge lanes from the LDS halo columns
+        float4 xls = zero4, xrs = zero4;
+        if constexpr (XS) {
+            xls = dpp_shr1(q[(s + R) % QR]);
+            xrs = dpp_shl1(q[(s + R) % QR]);
+        }
         if (active) {
-            const float4 xl = lds[sk][R + ly][lx];
             const float4 xc = q[(s + R) % QR];
-            const float4 xr = lds[sk][R + ly][2 + lx];
+            float4 xl, xr;
+            if constexpr (XS) {
+                xl = xls;
+                xr = xrs;
+                if (lx == 0) xl = lds[sk][R + ly][0];
+                if (lx == BX - 1) xr = lds[sk][R + ly][BX + 1];
+            } else {
+                xl = lds[sk][R + ly][lx];
+                xr = lds[sk][R + ly][2 + lx];
+            }
             float4 ym[R], yp[R];
 #pragma unroll
             for (int m = 1; m <= R; ++m) {
@@ -467,7 +519,10 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
             float *dst = un + pc + dz;
             if (full) {
                 const float4 o4 = make_float4(out[0], out[1], out[2], out[3]);
-                st4(dst, o4);
+                if constexpr (STREAM)
+                    st4_nt(dst, o4);
+                else
+                    st4(dst, o4);
                 if constexpr (PACK) {
                     // the float4 is one row of a face's R-thick layer (R = 4, nx % 4 == 0): copy it into
                     // each face slot that holds it, in the slot order of rtm_pack_halo
@@ -621,6 +676,52 @@ __global__ __launch_bounds__(kThreads) void k_unpack4(Geo g, float *__restrict__
         const int j = s.oy + (int)(row % (I)s.wy);
         const int k = s.oz + (int)(row / (I)s.wy);
         st4(u + pidx(g, i, j, k), p ? ld4(p + 4 * (long long)t) : make_float4(0.f, 0.f, 0.f, 0.f));
+    }
+}
+
+// The unpack for the line-aligned layout (R = 4, nx % 32 == 0, pitch_y = nx + 32, owned (0, 0, 0) on a
+// 128-byte line, pitch_z a multiple of 32): the +X ghost of row j (padded x = nx+4 .. nx+7), the row's
+// 24 floats of padding and the -X ghost of row j + 1 (padded x = 0 .. 3 of the next row) are exactly
+// one 128-byte line, so the two x faces are written as whole lines (eight float4 per line: slot 1's
+// cells, zeros in the padding, slot 0's cells) instead of two 16-byte pieces of it.  The lines that
+// also hold an edge ghost (before row 0 and after row ny - 1) write only their face cells, so edges
+// and corners stay untouched.  blockIdx.y = 0: the x faces (line by line); 1..4: the y and z faces
+// as in k_unpack4.
+template <typename I>
+__global__ __launch_bounds__(kThreads) void k_unpack_lines(Geo g, float *__restrict__ u, FacePtrs src)
+{
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (blockIdx.y == 0) {
+        const I lines = (I)(g.ny + 1) * (I)g.nz;
+        const float *s0 = src.p[0], *s1 = src.p[1];
+        for (I t = (I)first_item(); t < 8 * lines; t += (I)item_stride()) {
+            const I line = t >> 3;
+            const int q = (int)(t & 7);
+            const int jj = (int)(line % (I)(g.ny + 1));
+            const int k = (int)(line / (I)(g.ny + 1));
+            // the line starts at the +X ghost of row jj - 1
+            float *dst = u + pidx(g, g.nx, jj - 1, k) + 4 * q;
+            if (q == 0) {
+                if (jj >= 1) st4(dst, s1 ? ld4(s1 + 4 * ((long long)k * g.ny + (jj - 1))) : zero4);
+            } else if (q == 7) {
+                if (jj < g.ny) st4(dst, s0 ? ld4(s0 + 4 * ((long long)k * g.ny + jj)) : zero4);
+            } else if (jj >= 1 && jj < g.ny) {
+                st4(dst, zero4);      // padding, not a cell: written only to complete the line
+            }
+        }
+        return;
+    }
+    const int f = blockIdx.y + 1;
+    const Slab s = face_ghost(g, f);
+    const I w4 = (I)(s.wx >> 2);
+    const I cnt = w4 * (I)s.wy * (I)s.wz;
+    const float *p = src.p[f];
+    for (I t = (I)first_item(); t < cnt; t += (I)item_stride()) {
+        const I row = t / w4;
+        const int i = s.ox + 4 * (int)(t - row * w4);
+        const int j = s.oy + (int)(row % (I)s.wy);
+        const int k = s.oz + (int)(row / (I)s.wy);
+        st4(u + pidx(g, i, j, k), p ? ld4(p + 4 * (long long)t) : zero4);
     }
 }
 
@@ -826,6 +927,59 @@ __global__ __launch_bounds__(kThreads) void k_velocity_gradient(Geo g, float *__
     });
 }
 
+// kg[r] = kappa g and inv_kg[r] = 1 / (kappa g) at the owned cell of padded index idx[r] (the factor
+// kappa (gxy gz) in the order the adjoint kernel forms kappa g mu); 0 for an index that is not an owned
+// cell.  Either output may be NULL.
+__global__ __launch_bounds__(kThreads) void k_scaled_factors(Geo g, const float *__restrict__ kap,
+                                                             const long long *__restrict__ idx, int n,
+                                                             float *__restrict__ kg, float *__restrict__ inv_kg)
+{
+    const int R = g.R;
+    for (long long r = first_item(); r < n; r += item_stride()) {
+        const long long p = idx[r];
+        const long long kk = p / g.pz, rem = p - kk * g.pz;
+        const long long jj = rem / g.py, ii = rem - jj * g.py;
+        float f = 0.0f, fi = 0.0f;
+        if (p >= 0 && kk >= R && kk < (long long)g.nz + R && jj >= R && jj < (long long)g.ny + R && ii >= R &&
+            ii < (long long)g.nx + R) {
+            const int i = (int)ii - R, j = (int)jj - R, k = (int)kk - R;
+            f = kap[p] * ((g.gx[i] * g.gy[j]) * g.gz[k]);
+            fi = 1.0f / f;
+        }
+        if (kg) kg[r] = f;
+        if (inv_kg) inv_kg[r] = fi;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_record_weighted(const float *__restrict__ u, long long total,
+                                                              const int64_t *__restrict__ idx,
+                                                              const float *__restrict__ w, float *__restrict__ out,
+                                                              int n)
+{
+    for (long long r = first_item(); r < n; r += item_stride()) {
+        const long long p = idx[r];
+        out[r] = (p >= 0 && p < total) ? w[r] * u[p] : 0.0f;
+    }
+}
+
+// grad_v (compact) = 2 G / v: the chain rule for the gradient accumulated from the scaled adjoint state
+// w = kappa g mu (G = sum w L u = kappa dJ/dkappa, and dkappa/dv = 2 kappa / v).
+template <bool VEC>
+__global__ __launch_bounds__(kThreads) void k_velocity_gradient_scaled(Geo g, float *__restrict__ gv,
+                                                                       const float *__restrict__ G,
+                                                                       const float *__restrict__ v)
+{
+    owned_rows<VEC>(g, [&](long long p, long long c, int) {
+        if constexpr (VEC) {
+            const float4 v4 = ld4(v + c), k4 = ld4(G + p);
+            st4(gv + c, make_float4((2.0f * k4.x) / v4.x, (2.0f * k4.y) / v4.y, (2.0f * k4.z) / v4.z,
+                                    (2.0f * k4.w) / v4.w));
+        } else {
+            gv[c] = (2.0f * G[p]) / v[c];
+        }
+    });
+}
+
 // ---------------------------------------------------------------------------------------------
 // Reduced-precision snapshots: one FP32 scale per z plane (slab) and 16-bit codes
 // ---------------------------------------------------------------------------------------------
@@ -967,6 +1121,8 @@ struct Options {
     std::atomic<int> halo_x_width{64};     // x strips of the halo region
     std::atomic<int> halo_y_width{16};     // y strips of the halo region
     std::atomic<int> halo_variant{0};      // tile shape of the halo call (as interior_variant; 5: 16x32)
+    std::atomic<int> unpack_lines{1};      // 1: x-face ghosts unpacked as whole lines where the layout allows
+    std::atomic<int> tile_flags{0};        // FL_NT | FL_XSHUF for the radius-4 forward tiled launches
 };
 Options g_opt;
 
@@ -1076,7 +1232,7 @@ int balanced_zchunk(int tiles, int wz, int R, int cus)
 
 // Launch the tiled kernel over up to kMaxBoxes boxes {x0, x1, y0, y1, z0, z1} (empty ones skipped).
 // rk: kappa for OP_ADJOINT (see k_tiled), unused otherwise.
-template <int R, int BX, int BY, int OP, bool PACK = false>
+template <int R, int BX, int BY, int OP, bool PACK = false, int FL = 0>
 int launch_tiled(const Geo &g, float *un, const float *uc, const float *up, const float *kap, const int (*boxes)[6],
                  int nbox, hipStream_t st, const PackOut *po = nullptr, const float *rk = nullptr)
 {
@@ -1119,7 +1275,7 @@ int launch_tiled(const Geo &g, float *un, const float *uc, const float *up, cons
         int occ = resident.load(std::memory_order_relaxed);
         if (occ == 0) {
             int per_cu = 0, cus = 0, dev = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tiled<R, BX, BY, OP, PACK>, BX * BY, 0) !=
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tiled<R, BX, BY, OP, PACK, FL>, BX * BY, 0) !=
                 hipSuccess)
                 per_cu = 2;
             if (hipGetDevice(&dev) != hipSuccess ||
@@ -1147,9 +1303,22 @@ int launch_tiled(const Geo &g, float *un, const float *uc, const float *up, cons
     PackOut pk;
     std::memset(&pk, 0, sizeof(pk));
     if (po) pk = *po;
-    hipLaunchKernelGGL((k_tiled<R, BX, BY, OP, PACK>), dim3((unsigned)nb), dim3(BX * BY), 0, st, g, un, uc, up, kap,
+    hipLaunchKernelGGL((k_tiled<R, BX, BY, OP, PACK, FL>), dim3((unsigned)nb), dim3(BX * BY), 0, st, g, un, uc, up, kap,
                        bl, pk, rk);
     return launch_status();
+}
+
+template <int R, int OP, bool PACK = false, int FL = 0>
+int launch_tiled_flags(int var, const Geo &g, float *un, const float *uc, const float *up, const float *kap,
+                       const int (*boxes)[6], int nbox, hipStream_t st, const PackOut *po, const float *rk)
+{
+    switch (var) {
+    case 1: return launch_tiled<R, 32, 8, OP, PACK, FL>(g, un, uc, up, kap, boxes, nbox, st, po, rk);
+    case 2: return launch_tiled<R, 16, 8, OP, PACK, FL>(g, un, uc, up, kap, boxes, nbox, st, po, rk);
+    case 4: return launch_tiled<R, 32, 16, OP, PACK, FL>(g, un, uc, up, kap, boxes, nbox, st, po, rk);
+    case 5: return launch_tiled<R, 16, 32, OP, PACK, FL>(g, un, uc, up, kap, boxes, nbox, st, po, rk);
+    default: return launch_tiled<R, 16, 16, OP, PACK, FL>(g, un, uc, up, kap, boxes, nbox, st, po, rk);
+    }
 }
 
 template <int R, int OP, bool PACK = false>
@@ -1157,6 +1326,17 @@ int launch_tiled_variant(int var, const Geo &g, float *un, const float *uc, cons
                          const int (*boxes)[6], int nbox, hipStream_t st, const PackOut *po = nullptr,
                          const float *rk = nullptr)
 {
+    // the kernel flags (streaming hints, lane shuffles) are built for the radius-4 forward update
+    if constexpr (R == 4 && OP == OP_FORWARD && !PACK) {
+        switch (g_opt.tile_flags.load(std::memory_order_relaxed)) {
+        case FL_NT: return launch_tiled_flags<R, OP, PACK, FL_NT>(var, g, un, uc, up, kap, boxes, nbox, st, po, rk);
+        case FL_XSHUF:
+            return launch_tiled_flags<R, OP, PACK, FL_XSHUF>(var, g, un, uc, up, kap, boxes, nbox, st, po, rk);
+        case FL_NT | FL_XSHUF:
+            return launch_tiled_flags<R, OP, PACK, FL_NT | FL_XSHUF>(var, g, un, uc, up, kap, boxes, nbox, st, po, rk);
+        default: break;
+        }
+    }
     switch (var) {
     case 1: return launch_tiled<R, 32, 8, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po, rk);
     case 2: return launch_tiled<R, 16, 8, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po, rk);
@@ -1605,7 +1785,19 @@ int rtm_unpack_halo(const rtm_grid *grid, float *u, const float *const faces[6],
     bool vec = faces_vec(g, u);
     for (int f = 0; f < 6; ++f) vec = vec && (fp.p[f] == nullptr || aligned16(fp.p[f]));
     const bool narrow = mx < (1ll << 31);     // 32-bit face counters suffice
-    if (vec) {
+    const bool lines = vec && g.nx % 32 == 0 && g.py == (long long)g.nx + 32 && g.pz % 32 == 0 &&
+                       (reinterpret_cast<uintptr_t>(u + (4ll * g.pz + 4ll * g.py + 4)) & 127u) == 0 &&
+                       g_opt.unpack_lines.load(std::memory_order_relaxed);
+    if (lines) {
+        // the x faces as (ny + 1) nz lines of eight float4 each; the y / z faces as before
+        const long long items = std::max(8ll * (g.ny + 1) * g.nz, mx / 4);
+        if (items < (1ll << 31))
+            hipLaunchKernelGGL(k_unpack_lines<unsigned>, dim3(blocks_for(items), 5), dim3(kThreads), 0, stream, g, u,
+                               fp);
+        else
+            hipLaunchKernelGGL(k_unpack_lines<long long>, dim3(blocks_for(items), 5), dim3(kThreads), 0, stream, g,
+                               u, fp);
+    } else if (vec) {
         if (narrow)
             hipLaunchKernelGGL(k_unpack4<unsigned>, dim3(blocks_for(mx / 4), 6), dim3(kThreads), 0, stream, g, u, fp);
         else
@@ -1750,6 +1942,75 @@ int rtm_gradient_accumulate(const rtm_grid *grid, float *grad, const float *u, c
     if (st != RTM_OK) return st;
     const Geo g = make_geo(grid);
     return launch_whole<OP_GRADIENT>(g, grad, u, mu, grad, stream);
+}
+
+int rtm_gradient_accumulate_scaled(const rtm_grid *grid, float *grad, const float *u, const float *w,
+                                   hipStream_t stream)
+{
+    int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (!grad || !u || !w) return RTM_EINVAL;
+    const long long tot = padded_total(grid);
+    if (ranges_overlap(grad, tot, u, tot) || ranges_overlap(grad, tot, w, tot)) return RTM_EALIAS;
+    st = check_device();
+    if (st != RTM_OK) return st;
+    const Geo g = make_geo(grid);
+    return launch_whole<OP_GRADIENT_SCALED>(g, grad, u, w, grad, stream);
+}
+
+int rtm_scaled_adjoint_factors(const rtm_grid *grid, const float *kappa, const int64_t *idx, int32_t n, float *kg,
+                               float *inv_kg, hipStream_t stream)
+{
+    int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (n < 0) return RTM_EINVAL;
+    if (n == 0) return RTM_OK;
+    if (!kappa || !idx || (!kg && !inv_kg)) return RTM_EINVAL;
+    const long long tot = padded_total(grid);
+    if ((kg && ranges_overlap(kg, n, kappa, tot)) || (inv_kg && ranges_overlap(inv_kg, n, kappa, tot)) ||
+        (kg && inv_kg && ranges_overlap(kg, n, inv_kg, n)))
+        return RTM_EALIAS;
+    st = check_device();
+    if (st != RTM_OK) return st;
+    const Geo g = make_geo(grid);
+    hipLaunchKernelGGL(k_scaled_factors, dim3(blocks_for(n)), dim3(kThreads), 0, stream, g, kappa,
+                       reinterpret_cast<const long long *>(idx), (int)n, kg, inv_kg);
+    return launch_status();
+}
+
+int rtm_record_weighted(const rtm_grid *grid, const float *u, const int64_t *idx, const float *w, float *out,
+                        int32_t n, hipStream_t stream)
+{
+    int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (n < 0) return RTM_EINVAL;
+    if (n == 0) return RTM_OK;
+    if (!u || !idx || !w || !out) return RTM_EINVAL;
+    st = check_device();
+    if (st != RTM_OK) return st;
+    hipLaunchKernelGGL(k_record_weighted, dim3(blocks_for(n)), dim3(kThreads), 0, stream, u, padded_total(grid), idx,
+                       w, out, (int)n);
+    return launch_status();
+}
+
+int rtm_velocity_gradient_scaled(const rtm_grid *grid, float *grad_v, const float *G, const float *v,
+                                 hipStream_t stream)
+{
+    int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (!grad_v || !G || !v) return RTM_EINVAL;
+    const long long n = (long long)grid->nx * grid->ny * grid->nz;
+    if (ranges_overlap(grad_v, n, G, padded_total(grid)) || ranges_overlap(grad_v, n, v, n)) return RTM_EALIAS;
+    st = check_device();
+    if (st != RTM_OK) return st;
+    const Geo g = make_geo(grid);
+    if (rows_vec(g) && aligned16(grad_v) && aligned16(G) && aligned16(v))
+        hipLaunchKernelGGL(k_velocity_gradient_scaled<true>, dim3(row_blocks(g)), dim3(kThreads), 0, stream, g, grad_v,
+                           G, v);
+    else
+        hipLaunchKernelGGL(k_velocity_gradient_scaled<false>, dim3(row_blocks(g)), dim3(kThreads), 0, stream, g,
+                           grad_v, G, v);
+    return launch_status();
 }
 
 int rtm_misfit_residual(const float *d, const float *obs, float *resid, int64_t n, double *misfit, hipStream_t stream)
@@ -1920,6 +2181,13 @@ int rtm_set_option(int32_t option, int32_t value)
         if (value < 0 || value > 5 || value == 3) return RTM_EINVAL;
         g_opt.whole_variant.store(value);
         return RTM_OK;
+    case RTM_OPT_UNPACK_LINES:
+        g_opt.unpack_lines.store(value ? 1 : 0);
+        return RTM_OK;
+    case RTM_OPT_TILE_FLAGS:
+        if (value < 0 || value > 3) return RTM_EINVAL;
+        g_opt.tile_flags.store(value);
+        return RTM_OK;
     default: return RTM_EINVAL;
     }
 }
@@ -1934,6 +2202,8 @@ int rtm_get_option(int32_t option)
     case RTM_OPT_HALO_Y_WIDTH: return g_opt.halo_y_width.load();
     case RTM_OPT_HALO_VARIANT: return g_opt.halo_variant.load();
     case RTM_OPT_WHOLE_VARIANT: return g_opt.whole_variant.load();
+    case RTM_OPT_UNPACK_LINES: return g_opt.unpack_lines.load();
+    case RTM_OPT_TILE_FLAGS: return g_opt.tile_flags.load();
     default: return RTM_EINVAL;
     }
 }

@@ -18,7 +18,7 @@ from __future__ import annotations
 
 import math
 import time
-from dataclasses import asdict, dataclass
+from dataclasses import asdict, dataclass, replace
 
 import numpy as np
 import torch
@@ -57,6 +57,25 @@ def coarse_grid(fine: Grid) -> Grid:
              sponge_width=max(fine.sponge_width // 2, 1), sponge_alpha=fine.sponge_alpha * 2.0 * math.sqrt(2.0),
              device=fine.device)
     return g
+
+
+def plain_grid(fine: Grid, spacing: int, radius: int, step: int) -> Grid:
+    """A plain (uncorrected) solver for the time-versus-error comparison: spacing `spacing` h (1 or 2),
+    stencil radius 2 or 4, time step `step` dt (1 or 2).  On the 2h grid the sponge is W/2 cells
+    with alpha 2 sqrt(step): one step then damps, at the same distance, like `step` fine steps
+    (exp(-(alpha_c d/2)^2) = exp(-step (alpha d)^2)).  Every combination keeps the Courant number at
+    or below the fine one, so each is stable when the fine grid is."""
+    if spacing not in (1, 2) or step not in (1, 2) or radius not in (2, 4):
+        raise ValueError("spacing and step must be 1 or 2, radius 2 or 4")
+    if spacing == 1:
+        return Grid(fine.nx, fine.ny, fine.nz, fine.h, step * fine.dt, radius=radius,
+                    sponge_width=fine.sponge_width, sponge_alpha=fine.sponge_alpha * math.sqrt(step),
+                    device=fine.device)
+    if fine.nx % 2 or fine.ny % 2 or fine.nz % 2:
+        raise ValueError("fine grid dimensions must be even")
+    return Grid(fine.nx // 2, fine.ny // 2, fine.nz // 2, 2.0 * fine.h, step * fine.dt, radius=radius,
+                sponge_width=max(fine.sponge_width // 2, 1), sponge_alpha=fine.sponge_alpha * 2.0 * math.sqrt(step),
+                device=fine.device)
 
 
 def coarse_velocity(v_fine: np.ndarray) -> np.ndarray:
@@ -609,16 +628,31 @@ def _timed(fn, repeats: int = 1):
     return out, best
 
 
+PLAIN_VARIANTS = {
+    # name: (spacing factor, radius, step factor)
+    "2h_r2_2dt": (2, 2, 2),      # the coarse grid the corrector works on, uncorrected
+    "2h_r4_2dt": (2, 4, 2),
+    "2h_r2_dt": (2, 2, 1),
+    "2h_r4_dt": (2, 4, 1),
+    "h_r2_dt": (1, 2, 1),
+}
+
+
 def compare_rtm(fine: Grid, v_true, v_bg, src_f, rec_f, nsteps_f: int, fpeak: float, net: CorrectorNet | None,
                 every: int, image_every_f: int = 4, repeats: int = 2, schedule: str = "fused",
-                snapshots_fine: str | None = None, log=None):
+                snapshots_fine: str | None = None, log=None, plain_variants=(), prolonged: bool = False):
     """Migrate one shot on the fine grid (the reference) and on the coarse grid without and with the
     learned corrector.  The recorded data are modelled on the fine grid (d_true in v_true, d_bg in
     v_bg) and decimated in time for the coarse runs; sources and receivers sit on even fine cells,
     i.e. on coarse cells.  Returns a dict of images (host arrays on the coarse grid), relative L2
     errors against the fine image (decimated, and full-weighted; over the whole volume and over the
     target zone below the acquisition plane and outside the sponge), and migration wall times.
-    snapshots_fine: None (FP32 levels) or "bf16"/"f16" coded snapshots for the fine run (memory)."""
+    snapshots_fine: None (FP32 levels) or "bf16"/"f16" coded snapshots for the fine run (memory).
+    plain_variants: names from PLAIN_VARIANTS, further uncorrected solvers timed and scored the same
+    way (an image on the fine spacing is restricted to the coarse grid like the reference), the
+    points of a time-versus-error curve on which the corrected coarse solver is placed.
+    prolonged: also form the plain and corrected coarse images on the fine grid from prolonged
+    coarse wavefields (migrate_prolonged) and score them against the fine image on the fine grid."""
     from . import snapshots as snapcodec
     from .rtm import migrate_shot, model_shot
 
@@ -645,6 +679,7 @@ def compare_rtm(fine: Grid, v_true, v_bg, src_f, rec_f, nsteps_f: int, fpeak: fl
     img_f, t_fine = _timed(lambda: migrate_shot(fine, kb, v_bg, src_f, wav_f, rec_f, d_true, d_bg, nsteps_f,
                                                 image_every_f, schedule, snaps_f), repeats)
     say(f"fine migration {t_fine:.3f} s")
+    ref_full = fine.download(img_f).astype(np.float64) if prolonged else None
     ref_dec = fine.download(img_f)[::2, ::2, ::2].astype(np.float64)
     fw = coarse.field()
     _abi.rtm_restrict(fine.c, coarse.c, img_f, fw, _cur(), mode=_abi.RTM_RESTRICT_FULL)
@@ -681,7 +716,91 @@ def compare_rtm(fine: Grid, v_true, v_bg, src_f, rec_f, nsteps_f: int, fpeak: fl
         out[f"err_{name}_zone_full_weighted"] = float(np.linalg.norm((im - ref_fw)[zone]) /
                                                       np.linalg.norm(ref_fw[zone]))
         say(f"coarse migration ({name}) {t:.3f} s")
+        if prolonged:
+            zf = tuple(slice(2 * z.start, 2 * z.stop) for z in zone)
+            imgp, tp = _timed(lambda: migrate_prolonged(fine, coarse, kbc, vbc, src_c, wav_c, rec_c, dc_true, dc_bg,
+                                                        nsteps_c, image_every_f // 2, schedule, corr), repeats)
+            imf = fine.download(imgp).astype(np.float64)
+            del imgp
+            out[f"t_{name}_prolonged"] = tp
+            out[f"err_{name}_prolonged_zone"] = float(np.linalg.norm((imf - ref_full)[zf]) /
+                                                      np.linalg.norm(ref_full[zf]))
+            out[f"err_{name}_prolonged"] = float(np.linalg.norm(imf - ref_full) / np.linalg.norm(ref_full))
+            say(f"coarse migration ({name}) imaged on the fine grid: {tp:.3f} s, target-zone error "
+                f"{out[f'err_{name}_prolonged_zone']:.3f}")
+    for name in plain_variants:
+        spacing, radius, step = PLAIN_VARIANTS[name]
+        pg = plain_grid(fine, spacing, radius, step)
+        vp = coarse_velocity(v_bg) if spacing == 2 else np.ascontiguousarray(v_bg, dtype=np.float32)
+        kp = pg.kappa_from_velocity(vp)
+        sp, rp = src_f // spacing, rec_f // spacing
+        # a step of `step` fine steps records u^{n+1} at fine trace row step (n + 1) - 1
+        dp_true = d_true[step - 1::step].contiguous()
+        dp_bg = d_bg[step - 1::step].contiguous()
+        # on the fine spacing the snapshots take the fine run's format (FP32 ones may not fit)
+        sn = codec(pg) if (spacing == 1 and codec is not None) else None
+        img, t = _timed(lambda: migrate_shot(pg, kp, vp, sp, pg.ricker(nsteps_f // step, fpeak), rp, dp_true, dp_bg,
+                                             nsteps_f // step, image_every_f // step, schedule, sn), repeats)
+        if spacing == 1:
+            fwp = coarse.field()
+            _abi.rtm_restrict(pg.c, coarse.c, img, fwp, _cur(), mode=_abi.RTM_RESTRICT_FULL)
+            im_fw = coarse.download(fwp).astype(np.float64)
+            im_dec = pg.download(img)[::2, ::2, ::2].astype(np.float64)
+            del fwp
+        else:
+            im_fw = im_dec = pg.download(img).astype(np.float64)
+        del img, kp
+        out[f"t_{name}"] = t
+        out[f"err_{name}_zone_full_weighted"] = float(np.linalg.norm((im_fw - ref_fw)[zone]) /
+                                                      np.linalg.norm(ref_fw[zone]))
+        out[f"err_{name}_zone_decimated"] = float(np.linalg.norm((im_dec - ref_dec)[zone]) /
+                                                  np.linalg.norm(ref_dec[zone]))
+        say(f"plain {name}: {t:.3f} s, target-zone error {out[f'err_{name}_zone_full_weighted']:.3f} (full-weighted) "
+            f"{out[f'err_{name}_zone_decimated']:.3f} (decimated)")
     return out
+
+
+def migrate_prolonged(fine: Grid, coarse: Grid, kappa_c, v_c, src_c, wav_c, rec_c, d_true, d_bg, nsteps_c: int,
+                      image_every_c: int, schedule: str = "fused", corrector=None) -> torch.Tensor:
+    """Migrate on the coarse grid but form the image on the fine one: at each imaging level the coarse
+    source snapshot and receiver level are prolonged to the fine grid (rtm_prolong, trilinear) and
+    correlated there (rtm_image_accumulate).  Returns the fine image field."""
+    from .rtm import ShotImager
+
+    imager = ShotImager(coarse, kappa_c, v_c, src_c, wav_c, rec_c, nsteps_c, image_every_c, schedule, None, corrector)
+    snaps = imager.forward()
+    image = fine.field()
+    fa, fb = fine.field(), fine.field()
+
+    def image_fine(snap, r, st):
+        _abi.rtm_prolong(coarse.c, fine.c, snap, fa, st)
+        _abi.rtm_prolong(coarse.c, fine.c, r, fb, st)
+        _abi.rtm_image_accumulate(fine.c, image, fa, fb, 1.0, st)
+
+    imager.backward(snaps, d_true, d_bg, image_fn=image_fine)
+    return image
+
+
+def time_at_error(points, err: float):
+    """Time a plain solver needs for image error `err`, read off the time-versus-error curve of
+    plain solvers: `points` are (time, error) pairs; the curve is their lower-left frontier (each
+    point faster or more accurate than the ones before), interpolated linearly in log error between
+    the two frontier points that bracket `err`.  None when err is below every plain error (no plain
+    solver measured reaches it); the fastest time when err is above every plain error."""
+    pts = sorted((float(t), float(e)) for t, e in points)
+    front = []
+    for t, e in pts:
+        if not front or e < front[-1][1]:
+            front.append((t, e))
+    if err >= front[0][1]:
+        return front[0][0]
+    for (t0, e0), (t1, e1) in zip(front, front[1:]):
+        if e1 <= err <= e0:
+            if e1 <= 0.0:
+                return t1
+            w = (math.log(e0) - math.log(err)) / (math.log(e0) - math.log(e1))
+            return t0 + w * (t1 - t0)
+    return None
 
 
 # -------------------------------------------------------------------------------------------------
@@ -704,6 +823,11 @@ class CorrectorSpec:
     fp_high: float
     every: int
     relu: bool
+    # the fine grid judges the corrector: the target-zone image error of the corrected coarse shot
+    # against the plain fine shot, as measured by `compare` (NaN: never measured), and the largest
+    # error at which the corrected coarse grid may stand in for the fine one
+    image_error: float = float("nan")
+    error_bar: float = 1e-2
 
 
 def save_corrector(path: str, net: CorrectorNet, spec: CorrectorSpec):
@@ -718,7 +842,7 @@ def load_corrector(path: str, device="cuda"):
     else:
         with np.load(path) as f:
             params = f["params"]
-            spec = CorrectorSpec(**{k: (f[k].item()) for k in CorrectorSpec.__dataclass_fields__})
+            spec = CorrectorSpec(**{k: (f[k].item()) for k in CorrectorSpec.__dataclass_fields__ if k in f})
     net = CorrectorNet(device=device, relu=bool(spec.relu) if spec is not None else DEFAULTS["relu"])
     net.load(params)
     return net, spec
@@ -728,9 +852,15 @@ def applicable(spec: CorrectorSpec | None, fine, v, fpeak: float, rtol: float = 
     """(ok, reason): may this corrector stand in for the fine grid on this problem?  The grid must
     have the trained spacing and step, radius 4 and even sizes whose halves suit the network
     (multiple of 16 along x); the velocities must lie in the trained range (within vslack) and the
-    peak frequency in the trained band.  Otherwise the fine grid is used."""
+    peak frequency in the trained band; and the corrector's measured image error against the fine
+    solve must lie within its error bar.  Otherwise the fine grid is used."""
     if spec is None:
         return False, "no validity record"
+    if not float(spec.image_error) <= float(spec.error_bar):
+        if math.isnan(float(spec.image_error)):
+            return False, "the corrector's image error against the fine grid was never measured"
+        return False, (f"measured image error {float(spec.image_error):.3g} against the fine grid is above the "
+                       f"bar {float(spec.error_bar):.3g}")
     if fine.radius != 4:
         return False, "fine grid radius is not 4"
     if abs(fine.h - spec.h) > rtol * spec.h or abs(fine.dt - spec.dt) > rtol * spec.dt:
@@ -830,6 +960,12 @@ def main(argv=None):
     c.add_argument("--image-every", type=int, default=4, help="fine steps between imaging levels")
     c.add_argument("--snapshots", default=None, help="fine snapshot format: bf16 or f16 (default FP32)")
     c.add_argument("--repeats", type=int, default=2)
+    c.add_argument("--plain", nargs="*", default=[], choices=sorted(PLAIN_VARIANTS),
+                   help="further plain solvers for the time-versus-error curve")
+    c.add_argument("--prolonged", action="store_true",
+                   help="also image the coarse runs on the fine grid from prolonged wavefields")
+    c.add_argument("--record", default=None,
+                   help="save the corrector with the measured target-zone image error in its record (.npz)")
     a = ap.parse_args(argv)
 
     def say(msg):
@@ -867,8 +1003,23 @@ def main(argv=None):
         say(f"fallback rule: corrector {'applies' if ok else 'does not apply'} ({why})")
     say(f"compare: fine {n}^3, {a.steps} steps, {a.fp} Hz, corrector every {every} coarse steps")
     r = compare_rtm(fine, v_true, v_bg, src, rec, a.steps, a.fp, net, every, image_every_f=a.image_every,
-                    repeats=a.repeats, snapshots_fine=a.snapshots, log=say)
+                    repeats=a.repeats, snapshots_fine=a.snapshots, log=say, plain_variants=a.plain,
+                    prolonged=a.prolonged)
+    if a.plain and "err_learned_zone_full_weighted" in r:
+        # the plain curve: the fine solve (error 0 by definition), the plain coarse grid, the variants
+        pts = [(r["t_fine"], 0.0), (r["t_plain"], r["err_plain_zone_full_weighted"])]
+        pts += [(r[f"t_{n}"], r[f"err_{n}_zone_full_weighted"]) for n in a.plain]
+        t_eq = time_at_error(pts, r["err_learned_zone_full_weighted"])
+        r["plain_time_at_learned_error"] = t_eq
+        say(f"learned: {r['t_learned']:.3f} s at target-zone error {r['err_learned_zone_full_weighted']:.3f}; "
+            f"plain solvers reach that error in {t_eq if t_eq is None else round(t_eq, 3)} s")
     say(json.dumps({k: v for k, v in r.items() if not k.startswith(("img", "ref"))}))
+    if a.record is not None and spec is not None and "err_learned_zone_full_weighted" in r:
+        spec = replace(spec, image_error=float(r["err_learned_zone_full_weighted"]))
+        save_corrector(a.record, net, spec)
+        ok, why = applicable(spec, fine, v_bg, a.fp)
+        say(f"recorded image error {spec.image_error:.4g} in {a.record}; fallback rule now: "
+            f"{'corrected coarse grid' if ok else 'fine grid'} ({why})")
     return 0
 
 

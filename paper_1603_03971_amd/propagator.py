@@ -54,6 +54,16 @@ class Sources:
         if reverse_time:
             amp_t = torch.flip(amp_t, dims=[0])
         self.nsteps = amp_t.shape[0]
+        self._ijk, self._w = ijk, w
+        self._order = np.arange(len(w))
+        self.amp = amp_t.contiguous()
+        self._split(grid)
+
+    def _split(self, grid: Grid):
+        """Order the sources as halo region first, then the rest, for the halo region of the current
+        options (rtm_halo_region); self.amp's columns follow the order."""
+        ijk, w = self._ijk, self._w
+        self.widths = _abi.rtm_halo_region(grid.c)
         shell = grid.in_halo(ijk)
         # halo-region cells within R of a face: packed by the halo call before their injection, so
         # re-copied into the face buffer after it (rtm_pack_cells)
@@ -68,8 +78,20 @@ class Sources:
         self.count = len(order)
         self.idx = torch.from_numpy(grid.index(ijk[order])).to(grid.device)
         self.w = torch.from_numpy(w[order]).to(grid.device)
-        self.amp = amp_t[:, torch.from_numpy(order).to(grid.device)].contiguous()
+        # the table's columns are in self._order; re-order them to `order`
+        pos = np.empty(len(order), dtype=np.int64)
+        pos[self._order] = np.arange(len(order))
+        self.amp = self.amp[:, torch.from_numpy(pos[order]).to(grid.device)].contiguous()
+        self._order = order
         self.ranges = [(0, n0), (n0, self.count - n0), (0, self.count)]
+
+    def ensure_split(self, grid: Grid):
+        """Re-split when the halo region changed since the split (an option set between steps), so
+        every source is still added by the call that owns its cell.  Rare: it waits for the device,
+        so that no kernel still reads the tables it replaces."""
+        if _abi.rtm_halo_region(grid.c) != self.widths:
+            torch.cuda.synchronize(grid.device)
+            self._split(grid)
 
     def inject(self, grid: Grid, u: torch.Tensor, n: int, which: int, stream):
         """Add row n of the amplitude table at set `which`: 0 = halo region, 1 = the rest, 2 = all."""
@@ -110,7 +132,7 @@ class Propagator:
         if receivers is not None and len(np.asarray(receivers).reshape(-1, 3)):
             self.rec_idx = torch.from_numpy(grid.index(receivers)).to(grid.device)
         self.nrec = 0 if self.rec_idx is None else self.rec_idx.numel()
-        if boundary not in ("zero", "periodic"):
+        if boundary not in ("zero", "zero_faces", "periodic"):
             raise ValueError(boundary)
         self.boundary = boundary
         if schedule not in ("overlap", "serial", "fused"):
@@ -127,7 +149,18 @@ class Propagator:
         self.pool: list[torch.Tensor] = []
         self.send = grid.faces()
         slots = grid.face_slots(self.send)
-        self.recv = [None] * 6 if boundary == "zero" else [slots[OPPOSITE[f]] for f in range(6)]
+        # what face f of each new level receives: NULL slots for the physical boundary (the unpack
+        # writes zero ghosts and reads nothing); "zero_faces": the same zeros received through six
+        # real slots of a zero-filled receive buffer, as a subdomain whose neighbours all sent zero
+        # faces (the unpack reads them); "periodic": the opposite face's send slot (a pointer swap)
+        self.recv_buf = None
+        if boundary == "zero":
+            self.recv = [None] * 6
+        elif boundary == "zero_faces":
+            self.recv_buf = grid.faces()
+            self.recv = grid.face_slots(self.recv_buf)
+        else:
+            self.recv = [slots[OPPOSITE[f]] for f in range(6)]
         self.n = 0
         self.sH = torch.cuda.Stream(device=grid.device)
         self.sI = torch.cuda.Stream(device=grid.device)
@@ -231,6 +264,8 @@ class Propagator:
             if tr_ptr is not None:
                 _abi.rtm_record(c, u_nxt, self.rec_idx, tr_ptr, self.nrec, st)
         elif self.schedule == "serial":
+            for s in self.sources:
+                s.ensure_split(g)
             # one stream, in the paper's phase order: the halo call that also writes the faces, the
             # shell sources (re-copied into the faces they sit in), the interior call, the interior
             # sources, the unpack (at 512^3: 0.525 ms per step against 0.546 ms with the pack after
@@ -254,6 +289,8 @@ class Propagator:
             if tr_ptr is not None:
                 _abi.rtm_record(c, u_nxt, self.rec_idx, tr_ptr, self.nrec, st)
         else:
+            for s in self.sources:
+                s.ensure_split(g)
             sH, sI = self.sH, self.sI
             if self._ev_int is not None:
                 sH.wait_event(self._ev_int)

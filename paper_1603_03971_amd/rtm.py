@@ -80,8 +80,11 @@ class ShotImager:
         prop.run(self.nsteps, on_level=keep)
         return snaps
 
-    def backward(self, snaps, data_true: torch.Tensor, data_bg: torch.Tensor | None = None) -> torch.Tensor:
-        """Receiver wavefield and image.  data_*: device traces (nsteps, nrec) at the receivers."""
+    def backward(self, snaps, data_true: torch.Tensor, data_bg: torch.Tensor | None = None,
+                 image_fn=None) -> torch.Tensor:
+        """Receiver wavefield and image.  data_*: device traces (nsteps, nrec) at the receivers.
+        image_fn(snapshot, receiver level, stream), if given, replaces the imaging of each pair
+        (e.g. to form the image on another grid); the returned field is then left zero."""
         g = self.g
         N = self.nsteps
         wr = g.injection_weights(_cells_velocity(self.v_bg, self.rec_ijk))
@@ -96,7 +99,9 @@ class ShotImager:
                 self.corrector[1](level, p)
             k = N + 1 - level                 # forward level this receiver level pairs with
             if k in snaps:
-                if self.snapshots is None:
+                if image_fn is not None:
+                    image_fn(snaps[k], p.u_cur, p.level_stream)
+                elif self.snapshots is None:
                     _abi.rtm_image_accumulate(g.c, image, snaps[k], p.u_cur, 1.0, p.level_stream)
                 else:
                     self.snapshots.image_accumulate(image, snaps[k], p.u_cur, 1.0, p.level_stream)

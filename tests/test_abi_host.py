@@ -187,14 +187,37 @@ def test_corrector_fallback_rule():
 
     from paper_1603_03971_amd.learned import CorrectorSpec, applicable
 
+    from dataclasses import replace
+
     spec = CorrectorSpec(h=10.0, dt=7.5e-4, vmin=1500.0, vmax=3000.0, fp_low=6.0, fp_high=16.0, every=16,
-                         relu=False)
+                         relu=False, image_error=0.008)
     fine = SimpleNamespace(h=10.0, dt=7.5e-4, radius=4, nx=96, ny=64, nz=70)
     v = np.full((70, 64, 96), 2000.0)
     assert applicable(spec, fine, v, 15.0) == (True, "ok")
+    # the fine grid judges the corrector: no measured error, or one above the bar, means the fine grid
+    ok, why = applicable(replace(spec, image_error=float("nan")), fine, v, 15.0)
+    assert not ok and "never measured" in why
+    ok, why = applicable(replace(spec, image_error=0.21), fine, v, 15.0)
+    assert not ok and "above the bar" in why
+    assert applicable(replace(spec, image_error=0.21, error_bar=0.25), fine, v, 15.0)[0]
     assert not applicable(None, fine, v, 15.0)[0]
     assert not applicable(spec, fine, v, 20.0)[0]                                   # frequency
     assert not applicable(spec, fine, np.full_like(v, 4000.0), 15.0)[0]             # velocity
     assert not applicable(spec, SimpleNamespace(**{**vars(fine), "dt": 5e-4}), v, 15.0)[0]
     assert not applicable(spec, SimpleNamespace(**{**vars(fine), "nx": 80}), v, 15.0)[0]   # 40 % 16
     assert not applicable(spec, SimpleNamespace(**{**vars(fine), "radius": 2}), v, 15.0)[0]
+
+
+def test_time_at_error_reads_the_plain_frontier():
+    """The plain solvers' time at a given image error: the lower-left frontier of (time, error)
+    points, interpolated in log error; dominated points do not count."""
+    from paper_1603_03971_amd.learned import time_at_error
+
+    pts = [(3.2, 0.0), (0.25, 0.29), (0.26, 0.12), (0.30, 0.2), (0.5, 0.05), (0.9, 0.02)]
+    assert time_at_error(pts, 0.5) == 0.25            # above every error: the fastest solver
+    assert time_at_error(pts, 0.12) == 0.26
+    t = time_at_error(pts, 0.2)                       # between 0.29 and 0.12 on the frontier
+    w = (np.log(0.29) - np.log(0.2)) / (np.log(0.29) - np.log(0.12))
+    assert abs(t - (0.25 + w * 0.01)) < 1e-12
+    assert time_at_error(pts, 0.01) == 3.2            # only the fine solve reaches it
+    assert time_at_error([(0.2, 0.3), (0.4, 0.1)], 0.05) is None

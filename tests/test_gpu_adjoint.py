@@ -146,7 +146,58 @@ def test_gradient_kernel_matches_oracle():
     assert oracle.rel_l2(g.download(grad), ref) <= 1e-6
 
 
-def _problem(shape, nsteps, nshots, seed, C=50, nrec_stride=3, true_model=None):
+def test_scaled_adjoint_kernels():
+    """The pieces of the scaled recursion: grad += w L u against the oracle's Laplacian; the receiver
+    factors kappa g and 1 / (kappa g) bit for bit against the same FP32 products on the host (0 for an
+    index that is not an owned cell); the weighted gather; dJ/dv = 2 G / v bit for bit."""
+    import torch
+
+    from paper_1603_03971_amd import _abi
+
+    shape = (21, 30, 37)
+    nz, ny, nx = shape
+    g = _grid(shape)
+    st = torch.cuda.current_stream()
+    u, w, g0 = (synth.random_field(shape, s) for s in (84, 85, 86))
+    grad = g.upload(g0)
+    _abi.rtm_gradient_accumulate_scaled(g.c, grad, g.upload(u), g.upload(w), st)
+    torch.cuda.synchronize()
+    u32, w32 = u.astype(np.float32).astype(np.float64), w.astype(np.float32).astype(np.float64)
+    ref = g0.astype(np.float32) + w32 * oracle.laplacian(u32, 4)
+    assert oracle.rel_l2(g.download(grad), ref) <= 1e-6
+
+    v = synth.random_smooth_velocity(shape, seed=87, vmin=1500, vmax=3000).astype(np.float32)
+    kap = g.kappa_from_velocity(v)
+    cells = np.array([(0, 0, 0), (36, 29, 20), (5, 7, 3), (18, 1, 19), (2, 28, 10)])
+    idx = np.concatenate([g.index(cells), [0, g.total - 1]])           # two indices of ghost cells
+    idx_d = torch.from_numpy(idx).cuda()
+    kg = torch.full((len(idx),), float("nan"), device="cuda")
+    inv = torch.full((len(idx),), float("nan"), device="cuda")
+    _abi.rtm_scaled_adjoint_factors(g.c, kap, idx_d, len(idx), kg, inv, st)
+    gx, gy, gz = (t.cpu().numpy() for t in (g.gx, g.gy, g.gz))
+    kh = g.download(kap)
+    want = np.array([kh[k, j, i] * ((gx[i] * gy[j]) * gz[k]) for i, j, k in cells], dtype=np.float32)
+    got_kg, got_inv = kg.cpu().numpy(), inv.cpu().numpy()
+    np.testing.assert_array_equal(got_kg[:len(cells)], want)
+    np.testing.assert_array_equal(got_inv[:len(cells)], (np.float32(1.0) / want).astype(np.float32))
+    assert np.all(got_kg[len(cells):] == 0) and np.all(got_inv[len(cells):] == 0)
+
+    field = g.upload(w)
+    out = torch.empty(len(cells), device="cuda")
+    wt = torch.from_numpy(np.linspace(-2, 3, len(cells)).astype(np.float32)).cuda()
+    _abi.rtm_record_weighted(g.c, field, idx_d, wt, out, len(cells), st)
+    wh = w.astype(np.float32)
+    np.testing.assert_array_equal(out.cpu().numpy(),
+                                  wt.cpu().numpy() * np.array([wh[k, j, i] for i, j, k in cells], dtype=np.float32))
+
+    G = g.upload(g0)
+    gv = torch.empty(shape, device="cuda")
+    _abi.rtm_velocity_gradient_scaled(g.c, gv, G, torch.from_numpy(v).cuda(), st)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(gv.cpu().numpy(), (np.float32(2.0) * g0.astype(np.float32)) / v)
+
+
+def _problem(shape, nsteps, nshots, seed, C=50, nrec_stride=3, true_model=None, adjoint="scaled"):
     """Shots at seeded surface positions with receivers every `nrec_stride` cells at depth 4."""
     import torch
 
@@ -162,7 +213,7 @@ def _problem(shape, nsteps, nshots, seed, C=50, nrec_stride=3, true_model=None):
     for s in src:
         w = g.injection_weights([v_true[s[2], s[1], s[0]]])
         shots.append(Shot([s], w, rec))
-    prob = MisfitProblem(g, nsteps, wav, shots, checkpoint_every=C)
+    prob = MisfitProblem(g, nsteps, wav, shots, checkpoint_every=C, adjoint=adjoint)
     kt = g.kappa_from_velocity(v_true)
     for sh in shots:
         sh.observed = prob.model(kt, sh)
@@ -170,13 +221,15 @@ def _problem(shape, nsteps, nshots, seed, C=50, nrec_stride=3, true_model=None):
     return prob, v_true, src, rec, wav
 
 
-def test_dot_product_fp32():
-    """<F x, y> = <x, F^T y> for the GPU forward map (source series -> traces) and its transpose."""
+@pytest.mark.parametrize("adjoint", ["scaled", "direct"])
+def test_dot_product_fp32(adjoint):
+    """<F x, y> = <x, F^T y> for the GPU forward map (source series -> traces) and its transpose, run
+    as the scaled recursion (the forward kernel on w = kappa g mu) and as the direct one."""
     import torch
 
     shape = (40, 36, 44)
     nsteps = 90
-    prob, v, src, rec, _ = _problem(shape, nsteps, 1, seed=90, C=25)
+    prob, v, src, rec, _ = _problem(shape, nsteps, 1, seed=90, C=25, adjoint=adjoint)
     g = prob.g
     kap = prob.kappa(torch.from_numpy(v.astype(np.float32)).cuda())
     shot = prob.shots[0]
@@ -195,7 +248,7 @@ def test_dot_product_fp32():
     lhs = float(np.sum(fx.cpu().numpy().astype(np.float64) * y.cpu().numpy()))
     rhs = float(np.sum(x.astype(np.float64) * fty))
     rel = abs(lhs - rhs) / max(abs(lhs), abs(rhs))
-    _say(f"dot product: <Fx,y> {lhs:.9e} <x,F^T y> {rhs:.9e} rel {rel:.2e}")
+    _say(f"dot product ({adjoint}): <Fx,y> {lhs:.9e} <x,F^T y> {rhs:.9e} rel {rel:.2e}")
     assert rel <= 1e-5
 
 
@@ -268,6 +321,23 @@ def test_gradient_matches_finite_differences(grad64):
     rel = abs(fd - an) / abs(an)
     _say(f"FD: {fd:.6e} adjoint {an:.6e} rel {rel:.2e}")
     assert rel <= 1e-2
+
+
+def test_scaled_and_direct_gradients_agree():
+    """The scaled recursion (forward kernel on w) and the direct one (rtm_adjoint_step on mu) give the
+    same misfit bits (same forward runs) and the same gradient to FP32 rounding."""
+    import torch
+
+    shape = (36, 32, 40)
+    a = _problem(shape, 80, 2, seed=140, C=20, adjoint="scaled")
+    b = _problem(shape, 80, 2, seed=140, C=20, adjoint="direct")
+    v0 = torch.from_numpy(synth.smooth(a[1], 4.0).astype(np.float32)).cuda()
+    Ja, ga = a[0].misfit_and_gradient(v0)
+    Jb, gb = b[0].misfit_and_gradient(v0)
+    e = oracle.rel_l2(ga.cpu().numpy(), gb.cpu().numpy())
+    _say(f"scaled vs direct gradient rel-L2 {e:.2e}")
+    assert Ja == Jb
+    assert e <= 1e-5
 
 
 def test_checkpoint_interval_invariance():

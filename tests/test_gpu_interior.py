@@ -31,12 +31,15 @@ def _interior_box(shape):
 @pytest.fixture(scope="module")
 def wide_case():
     """256 x 192 x 160 layered medium (seed 7), sources in the interior box, in an x strip, in a
-    z slab, and one on the seam between the interior box and an x strip."""
+    z slab, and one on the seam between the interior box and an x strip; 300 steps (0.15 s, past
+    the 15 Hz wavelet's peak at 0.1 s), receivers 8-25 cells from the sources, on both sides of
+    the seams."""
     shape = (160, 192, 256)
     v = np.array(synth.layered_velocity(shape, 10.0, seed=7))
     src = [(150, 100, 80), (20, 90, 70), (200, 50, 2), (64, 96, 90)]
-    rec = [(130, 96, 8), (64, 16, 40), (63, 15, 40), (191, 176, 151), (10, 10, 10)]
-    nsteps = 100
+    rec = [(150, 100, 62), (130, 96, 80), (64, 110, 90), (63, 110, 90), (20, 90, 55), (200, 40, 12),
+           (200, 66, 4)]
+    nsteps = 300
     _say("wide 256x192x160: oracle")
     ref = problems.oracle_forward_problem(v, 10.0, nsteps, src, rec_ijk=rec)
     return v, src, rec, nsteps, ref

@@ -106,7 +106,12 @@ def test_saved_corrector_and_fallback_rule(trained, tmp_path):
     from paper_1603_03971_amd.grid import Grid
     from paper_1603_03971_amd.rtm import model_shot
 
+    from dataclasses import replace
+
     net, _, _, spec = trained
+    # a corrector whose measured image error (0.2) is within an explicitly loosened bar (0.3); with
+    # the default bar of 1e-2 the fine grid runs
+    spec = replace(spec, image_error=0.2, error_bar=0.3)
     path = str(tmp_path / "corrector.npz")
     learned.save_corrector(path, net, spec)
     net2, spec2 = learned.load_corrector(path)
@@ -127,5 +132,10 @@ def test_saved_corrector_and_fallback_rule(trained, tmp_path):
         out = learned.migrate(fine, v_bg, src, rec, fp, d_t, d_b, nsteps, corrector=(net2, spec2))
         _say(f"migrate at {fp} Hz: {out['solver']} ({out['reason']})")
         assert out["solver"] == expect
+        if fp == 15.0:
+            strict = learned.migrate(fine, v_bg, src, rec, fp, d_t, d_b, nsteps,
+                                     corrector=(net2, replace(spec2, error_bar=1e-2)))
+            _say(f"migrate at {fp} Hz with the 1e-2 bar: {strict['solver']} ({strict['reason']})")
+            assert strict["solver"] == "fine" and "above the bar" in strict["reason"]
         img = out["grid"].download(out["image"])
         assert np.isfinite(img).all() and np.abs(img).max() > 0

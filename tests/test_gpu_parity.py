@@ -183,6 +183,38 @@ def test_pack_unpack_bitwise(torch_cuda):
     assert np.all(padz[R:R + nz, R:R + ny, 0:R] == 0.0)
 
 
+@pytest.mark.parametrize("shape", [(64, 40, 36), (96, 9, 8), (32, 8, 12)])
+def test_unpack_whole_lines(torch_cuda, shape):
+    """On the line-aligned layout the x faces are unpacked as whole 128-byte lines (a row's +X ghost,
+    its padding, the next row's -X ghost).  Every ghost and owned cell gets the bits of the 16-byte
+    unpack; edge and corner ghosts stay untouched (NaN here), with real slots and with NULL ones."""
+    torch = torch_cuda
+    from paper_1603_03971_amd import _abi
+    from paper_1603_03971_amd.grid import Grid
+
+    nx, ny, nz = shape
+    g = Grid(nx, ny, nz, 10.0, 1e-3)
+    assert g.pitch_y == nx + 32                       # the layout the whole-line path needs
+    s = torch.cuda.current_stream()
+    host = np.random.default_rng(5).standard_normal((nz, ny, nx)).astype(np.float32)
+    slots = [torch.from_numpy(np.random.default_rng(20 + f).standard_normal(g.face_sizes[f]).astype(np.float32)).cuda()
+             for f in range(6)]
+    for recv in (slots, [None] * 6, [slots[0], None, None, slots[3], slots[4], None]):
+        out = {}
+        for lines in (1, 0):
+            _abi.rtm_set_option(_abi.RTM_OPT_UNPACK_LINES, lines)
+            try:
+                u = g.field(fill=float("nan"))
+                g.upload(host, u)
+                _abi.rtm_unpack_halo(g.c, u, recv, s)
+                torch.cuda.synchronize()
+            finally:
+                _abi.rtm_set_option(_abi.RTM_OPT_UNPACK_LINES, 1)
+            out[lines] = g.padded(u).cpu().numpy()
+        assert np.array_equal(out[1], out[0], equal_nan=True)
+        assert np.isnan(out[1][0, 0, 0]) and np.isnan(out[1][4, 3, 2]) and np.isnan(out[1][4, 4 + ny, 2])
+
+
 def test_periodic_standing_wave(torch_cuda):
     """Periodic self-exchange (slot swap): the discrete dispersion relation's closed form and the
     oracle's periodic mode."""
@@ -607,3 +639,42 @@ def synth_layered(shape):
     from paper_1603_03971_amd import synth
 
     return synth.layered_velocity(shape, 20.0, seed=12, vmin=1500.0, vmax=3000.0)
+
+
+@pytest.mark.parametrize("schedule", ["serial", "overlap"])
+def test_sources_follow_a_halo_width_change(torch_cuda, schedule):
+    """A source whose cell moves from the halo region to the interior when the x-strip width changes
+    between steps (64 -> 32 columns) is still added by the call that owns its cell: the run gives the
+    one-launch schedule's bits."""
+    from paper_1603_03971_amd import _abi, synth
+    from paper_1603_03971_amd.grid import Grid
+    from paper_1603_03971_amd.propagator import Propagator, Sources
+
+    torch = torch_cuda
+    shape = (36, 40, 200)
+    nz, ny, nx = shape
+    v = np.array(synth.layered_velocity(shape, 10.0, seed=14))
+    src = [(40, 20, 18), (150, 30, 10)]
+    g = Grid(nx, ny, nz, 10.0, Grid.stable_dt(4, 10.0, float(v.max())))
+    kap = g.kappa_from_velocity(v)
+    vs = np.array([v[k, j, i] for i, j, k in src])
+    amp = np.repeat(g.ricker(60, 15.0)[:, None], 2, axis=1)
+
+    def prop_for(sched):
+        return Propagator(g, kap, sources=Sources(g, src, g.injection_weights(vs), amp), schedule=sched)
+
+    ref = prop_for("fused")
+    ref.run(60)
+    prop = prop_for(schedule)
+    old = _abi.rtm_get_option(_abi.RTM_OPT_HALO_X_WIDTH)
+    try:
+        assert bool(g.in_halo([src[0]])[0])
+        prop.run(30)
+        _abi.rtm_set_option(_abi.RTM_OPT_HALO_X_WIDTH, 32)
+        assert not bool(g.in_halo([src[0]])[0])
+        prop.run(30)
+        torch.cuda.synchronize()
+    finally:
+        _abi.rtm_set_option(_abi.RTM_OPT_HALO_X_WIDTH, old)
+    assert np.any(g.download(ref.u_cur) != 0)
+    assert np.array_equal(g.download(prop.u_cur), g.download(ref.u_cur))

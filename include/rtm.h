@@ -128,10 +128,13 @@ const char *rtm_strerror(int status);
  *                             pitch_y = nx + 32, owned (0,0,0) line-aligned), rtm_unpack_halo writes the
  *                             x faces as whole lines (zeros in the padding, which holds no cell);
  *                             0 = 16-byte pieces.  Ghost and owned cells get the same values either way.
- *   RTM_OPT_TILE_FLAGS        variants of the radius-4 forward tiled launches (halo, interior, whole):
- *                             bit 0 = non-temporal loads of u_prv and kappa and stores of u_nxt (data
- *                             used once per step), bit 1 = each thread's x neighbours from the adjacent
- *                             lanes' registers (DPP lane shifts) instead of LDS; default 0.
+ *   RTM_OPT_TILE_FLAGS        kernel variants.  Bit 0 (default on): non-temporal (streaming) loads of the
+ *                             operands every stencil kernel uses once per cell (u_prv and kappa; mu and
+ *                             grad; the adjoint's mu_b) and stores of its output, and the same for the
+ *                             imaging kernels' operands; the stencil field itself stays cached, since
+ *                             neighbouring tiles read it again.  Bit 1: in the radius-4 forward launches,
+ *                             each thread's x neighbours from the adjacent lanes' registers (DPP lane
+ *                             shifts) instead of LDS (measured: no change).  Default 1.
  * Returns RTM_EINVAL for an unknown option or value. */
 enum {
     RTM_OPT_INTERIOR_VARIANT = 1,

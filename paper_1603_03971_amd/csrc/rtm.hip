@@ -771,19 +771,22 @@ __device__ __forceinline__ void owned_rows(const Geo &g, F &&f)
     }
 }
 
-template <bool VEC>
+template <bool VEC, bool NT = false>
 __global__ __launch_bounds__(kThreads) void k_image(Geo g, float *image, const float *__restrict__ src,
                                                     const float *__restrict__ rcv, float weight)
 {
     owned_rows<VEC>(g, [&](long long p, long long, int) {
         if constexpr (VEC) {
-            const float4 s4 = ld4(src + p), r4 = ld4(rcv + p);
-            float4 o = ld4(image + p);
+            const float4 s4 = NT ? ld4_nt(src + p) : ld4(src + p), r4 = NT ? ld4_nt(rcv + p) : ld4(rcv + p);
+            float4 o = NT ? ld4_nt(image + p) : ld4(image + p);
             o.x = __builtin_fmaf(weight * s4.x, r4.x, o.x);
             o.y = __builtin_fmaf(weight * s4.y, r4.y, o.y);
             o.z = __builtin_fmaf(weight * s4.z, r4.z, o.z);
             o.w = __builtin_fmaf(weight * s4.w, r4.w, o.w);
-            st4(image + p, o);
+            if constexpr (NT)
+                st4_nt(image + p, o);
+            else
+                st4(image + p, o);
         } else {
             image[p] = __builtin_fmaf(weight * src[p], rcv[p], image[p]);
         }
@@ -1081,7 +1084,7 @@ __global__ __launch_bounds__(kThreads) void k_encode(Geo g, const float *__restr
 }
 
 // image += weight * (decode(code) * scale) * rcv on owned cells.
-template <bool VEC>
+template <bool VEC, bool NT = false>
 __global__ __launch_bounds__(kThreads) void k_image_coded(Geo g, float *image, const uint16_t *__restrict__ codes,
                                                           const float *__restrict__ scales, int fmt,
                                                           const float *__restrict__ rcv, float weight)
@@ -1092,14 +1095,24 @@ __global__ __launch_bounds__(kThreads) void k_image_coded(Geo g, float *image, c
     owned_rows<VEC>(g, [&](long long p, long long c, int k) {
         const float sc = scales[k];
         if constexpr (VEC) {
-            const uint2 w = *reinterpret_cast<const uint2 *>(codes + c);
-            const float4 r4 = ld4(rcv + p);
-            float4 o = ld4(image + p);
+            typedef unsigned u2v __attribute__((ext_vector_type(2)));
+            uint2 w;
+            if constexpr (NT) {
+                const u2v t = __builtin_nontemporal_load(reinterpret_cast<const u2v *>(codes + c));
+                w = make_uint2(t.x, t.y);
+            } else {
+                w = *reinterpret_cast<const uint2 *>(codes + c);
+            }
+            const float4 r4 = NT ? ld4_nt(rcv + p) : ld4(rcv + p);
+            float4 o = NT ? ld4_nt(image + p) : ld4(image + p);
             o.x = __builtin_fmaf(weight * value(w.x & 0xFFFFu, sc), r4.x, o.x);
             o.y = __builtin_fmaf(weight * value(w.x >> 16, sc), r4.y, o.y);
             o.z = __builtin_fmaf(weight * value(w.y & 0xFFFFu, sc), r4.z, o.z);
             o.w = __builtin_fmaf(weight * value(w.y >> 16, sc), r4.w, o.w);
-            st4(image + p, o);
+            if constexpr (NT)
+                st4_nt(image + p, o);
+            else
+                st4(image + p, o);
         } else {
             image[p] = __builtin_fmaf(weight * value(codes[c], sc), rcv[p], image[p]);
         }
@@ -1122,7 +1135,7 @@ struct Options {
     std::atomic<int> halo_y_width{16};     // y strips of the halo region
     std::atomic<int> halo_variant{0};      // tile shape of the halo call (as interior_variant; 5: 16x32)
     std::atomic<int> unpack_lines{1};      // 1: x-face ghosts unpacked as whole lines where the layout allows
-    std::atomic<int> tile_flags{0};        // FL_NT | FL_XSHUF for the radius-4 forward tiled launches
+    std::atomic<int> tile_flags{FL_NT};    // FL_NT (streaming hints, default) | FL_XSHUF (lane shifts)
 };
 Options g_opt;
 
@@ -1326,9 +1339,10 @@ int launch_tiled_variant(int var, const Geo &g, float *un, const float *uc, cons
                          const int (*boxes)[6], int nbox, hipStream_t st, const PackOut *po = nullptr,
                          const float *rk = nullptr)
 {
-    // the kernel flags (streaming hints, lane shuffles) are built for the radius-4 forward update
+    // kernel flags: streaming hints for every operation; lane shifts for the radius-4 forward update
+    const int fl = g_opt.tile_flags.load(std::memory_order_relaxed);
     if constexpr (R == 4 && OP == OP_FORWARD && !PACK) {
-        switch (g_opt.tile_flags.load(std::memory_order_relaxed)) {
+        switch (fl) {
         case FL_NT: return launch_tiled_flags<R, OP, PACK, FL_NT>(var, g, un, uc, up, kap, boxes, nbox, st, po, rk);
         case FL_XSHUF:
             return launch_tiled_flags<R, OP, PACK, FL_XSHUF>(var, g, un, uc, up, kap, boxes, nbox, st, po, rk);
@@ -1336,6 +1350,8 @@ int launch_tiled_variant(int var, const Geo &g, float *un, const float *uc, cons
             return launch_tiled_flags<R, OP, PACK, FL_NT | FL_XSHUF>(var, g, un, uc, up, kap, boxes, nbox, st, po, rk);
         default: break;
         }
+    } else {
+        if (fl & FL_NT) return launch_tiled_flags<R, OP, PACK, FL_NT>(var, g, un, uc, up, kap, boxes, nbox, st, po, rk);
     }
     switch (var) {
     case 1: return launch_tiled<R, 32, 8, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po, rk);
@@ -1851,7 +1867,11 @@ int rtm_image_accumulate(const rtm_grid *grid, float *image, const float *src, c
     st = check_device();
     if (st != RTM_OK) return st;
     const Geo g = make_geo(grid);
-    if (rows_vec(g) && aligned16(image) && aligned16(src) && aligned16(rcv))
+    const bool nt = (g_opt.tile_flags.load(std::memory_order_relaxed) & FL_NT) != 0;
+    if (rows_vec(g) && aligned16(image) && aligned16(src) && aligned16(rcv) && nt)
+        hipLaunchKernelGGL((k_image<true, true>), dim3(row_blocks(g)), dim3(kThreads), 0, stream, g, image, src, rcv,
+                           weight);
+    else if (rows_vec(g) && aligned16(image) && aligned16(src) && aligned16(rcv))
         hipLaunchKernelGGL(k_image<true>, dim3(row_blocks(g)), dim3(kThreads), 0, stream, g, image, src, rcv, weight);
     else
         hipLaunchKernelGGL(k_image<false>, dim3(row_blocks(g)), dim3(kThreads), 0, stream, g, image, src, rcv, weight);
@@ -2142,7 +2162,11 @@ int rtm_image_accumulate_coded(const rtm_grid *grid, float *image, const uint16_
     st = check_device();
     if (st != RTM_OK) return st;
     const Geo g = make_geo(grid);
-    if (rows_vec(g) && aligned16(image) && aligned16(rcv) && aligned8(codes))
+    const bool nt = (g_opt.tile_flags.load(std::memory_order_relaxed) & FL_NT) != 0;
+    if (rows_vec(g) && aligned16(image) && aligned16(rcv) && aligned8(codes) && nt)
+        hipLaunchKernelGGL((k_image_coded<true, true>), dim3(row_blocks(g)), dim3(kThreads), 0, stream, g, image,
+                           codes, scales, (int)format, rcv, weight);
+    else if (rows_vec(g) && aligned16(image) && aligned16(rcv) && aligned8(codes))
         hipLaunchKernelGGL(k_image_coded<true>, dim3(row_blocks(g)), dim3(kThreads), 0, stream, g, image, codes,
                            scales, (int)format, rcv, weight);
     else

@@ -528,11 +528,12 @@ def _windows(pairs):
 
 
 def train(net: CorrectorNet, pairs, epochs: int, lr: float = 1e-3, seed: int = 0, lr_final: float | None = None,
-          noise: float = 0.0, remove_noise: bool = False, weighted: bool = True, log=None):
+          noise: float = 0.0, remove_noise: bool = False, weighted: bool = True, log=None, validate=None):
     """Adam over the windows of one PairSet or a list of them, in a seeded random order; returns the
     mean loss per epoch (normalised by the number of voxels and output channels).  noise > 0 adds
     N(0, noise^2) to the normalised wavefield inputs; with remove_noise the target asks the network to
-    take it out again, otherwise the target ignores it."""
+    take it out again, otherwise the target ignores it.  validate(net) -> float, if given, scores the
+    network after every epoch (lower is better) and the parameters of the best epoch are kept."""
     g, index = _windows(pairs)
     ws = Workspace(g.nx, g.ny, g.nz, train=True, device=g.device)
     scale = torch.zeros(1, dtype=torch.float32, device=g.device)
@@ -542,6 +543,7 @@ def train(net: CorrectorNet, pairs, epochs: int, lr: float = 1e-3, seed: int = 0
     rng = np.random.default_rng(seed)
     st = _cur()
     hist = []
+    best = None
     total = epochs * len(index)
     it = 0
     norm = 1.0 / (g.points * OUT_CHANNELS)
@@ -564,6 +566,15 @@ def train(net: CorrectorNet, pairs, epochs: int, lr: float = 1e-3, seed: int = 0
         hist.append(float(ws.loss.item()) * norm / len(index))
         if log is not None:
             log(ep, hist[-1])
+        if validate is not None:
+            score = float(validate(net))
+            if log is not None:
+                log(ep, hist[-1], score)
+            if best is None or score < best[0]:
+                best = (score, ep, net.state())
+    if validate is not None and best is not None:
+        net.load(best[2])
+        net.selected_epoch, net.validation_score = best[1], best[0]
     return hist
 
 
@@ -912,13 +923,40 @@ def migrate(fine: Grid, v_bg, src_f, rec_f, wavelet_fpeak: float, data_true, dat
 # -------------------------------------------------------------------------------------------------
 
 
+def rollout_validator(fine: Grid, coarse: Grid, every: int, nsteps_coarse: int, band, seeds):
+    """A validation score for training: held-out models (seeds outside the training set, alternating
+    point-source and receiver-plane problems, peak frequencies across `band`), each rolled out for
+    nsteps_coarse corrected coarse steps and compared with its restricted fine solution, where the
+    corrector acts (relative L2 weighted by the injection mask).  The fine solutions are computed
+    once.  Returns score(net) = the mean of the models' errors."""
+    seeds = list(seeds)
+    freqs = np.linspace(band[0], band[1], len(seeds)) if len(seeds) > 1 else [0.5 * (band[0] + band[1])]
+    probs, refs, masks = [], [], []
+    for i, (sd, fp) in enumerate(zip(seeds, freqs)):
+        prob = Problem(fine, coarse, sd, float(fp), kind="source" if i % 2 == 0 else "receivers")
+        probs.append(prob)
+        refs.append(coarse.owned(fine_final_restricted(fine, coarse, prob, nsteps_coarse)).double().clone())
+        masks.append(torch.from_numpy(prob.mask(coarse)).to(coarse.device).double())
+
+    def score(net: CorrectorNet) -> float:
+        errs = []
+        for prob, ref, m in zip(probs, refs, masks):
+            corr = Corrector(net, coarse, prob.vc, every)
+            u = coarse.owned(coarse_final(coarse, prob, nsteps_coarse, corr)).double()
+            errs.append(float(torch.linalg.norm(m * (u - ref)) / torch.linalg.norm(m * ref)))
+        return float(np.mean(errs))
+
+    return score
+
+
 def train_corrector(n: int = 96, models: int = 200, first_seed: int = 5000, every: int = DEFAULTS["every"],
                     fpeak=DEFAULTS["fpeak"], nsteps_coarse: int = 300, epochs: int = 10, lr: float = 1e-3,
-                    relu: bool = DEFAULTS["relu"], seed: int = 1, log=None):
+                    relu: bool = DEFAULTS["relu"], seed: int = 1, log=None, validation_models: int = 4):
     """Train a corrector on `models` seeded fine/coarse pairs (fine n^3, h = 10 m, v in [1500, 3000]
     m/s, alternating point-source and receiver-plane problems).  fpeak: one peak frequency, or a
-    (low, high) band from which each model draws its own (seeded).  Returns (net, pairs, losses,
-    spec)."""
+    (low, high) band from which each model draws its own (seeded).  With validation_models > 0 the
+    epoch whose parameters give the lowest rollout error on that many held-out models is kept
+    (rollout_validator).  Returns (net, pairs, losses, spec)."""
     fine = Grid(n, n, n, TRAIN_H, Grid.stable_dt(4, TRAIN_H, TRAIN_VMAX))
     coarse = coarse_grid(fine)
     band = (float(fpeak[0]), float(fpeak[1])) if isinstance(fpeak, (tuple, list)) else (float(fpeak), float(fpeak))
@@ -927,7 +965,9 @@ def train_corrector(n: int = 96, models: int = 200, first_seed: int = 5000, ever
     pairs = PairSet(fine, coarse, every, nsteps_coarse, fpeak, range(first_seed, first_seed + models),
                     kinds=("source", "receivers"))
     net = CorrectorNet(seed=seed, relu=relu)
-    hist = train(net, pairs, epochs, lr=lr, lr_final=lr / 5, log=log)
+    validate = rollout_validator(fine, coarse, every, nsteps_coarse, band, seeds=range(7000, 7000 + validation_models)) \
+        if validation_models > 0 else None
+    hist = train(net, pairs, epochs, lr=lr, lr_final=lr / 5, log=log, validate=validate)
     spec = CorrectorSpec(h=fine.h, dt=fine.dt, vmin=TRAIN_VMIN, vmax=TRAIN_VMAX, fp_low=band[0], fp_high=band[1],
                          every=int(every), relu=bool(relu))
     return net, pairs, hist, spec
@@ -949,6 +989,9 @@ def main(argv=None):
     t.add_argument("--steps", type=int, default=300, help="coarse steps per training model")
     t.add_argument("--epochs", type=int, default=10)
     t.add_argument("--relu", action="store_true")
+    t.add_argument("--validation-models", type=int, default=4,
+                   help="held-out models whose rollout error selects the epoch (0: keep the last epoch)")
+    t.add_argument("--seed", type=int, default=1, help="seed of the initial weights")
     t.add_argument("--out", required=True)
     c = sub.add_parser("compare", help="one RTM shot: fine vs plain coarse vs corrected coarse")
     c.add_argument("--weights", required=True)
@@ -973,10 +1016,15 @@ def main(argv=None):
 
     if a.cmd == "train":
         t0 = time.perf_counter()
+        def logger(e, loss, score=None):
+            say(f"epoch {e}: loss {loss:.4e}" if score is None else f"epoch {e}: held-out rollout error {score:.4f}")
+
         net, pairs, hist, spec = train_corrector(a.n, a.models, every=a.every,
                                                  fpeak=a.fp if a.fp is not None else tuple(a.fp_band),
-                                                 nsteps_coarse=a.steps, epochs=a.epochs, relu=a.relu,
-                                                 log=lambda e, l: say(f"epoch {e}: loss {l:.4e}"))
+                                                 nsteps_coarse=a.steps, epochs=a.epochs, relu=a.relu, seed=a.seed,
+                                                 log=logger, validation_models=a.validation_models)
+        if getattr(net, "selected_epoch", None) is not None:
+            say(f"kept epoch {net.selected_epoch} (held-out rollout error {net.validation_score:.4f})")
         with_net, zero = window_loss(net, pairs)
         save_corrector(a.out, net, spec)
         say(json.dumps({"windows": len(pairs), "generation_s": round(pairs.gen_seconds, 2),

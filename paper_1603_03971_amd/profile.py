@@ -92,6 +92,115 @@ def run_interior(n: int, launches: int, call: str = "interior"):
     print(json.dumps({f"{call}_points": interior if call == "interior" else n**3 - interior, "copy_bytes": COPY_BYTES}))
 
 
+# The hot kernels of the forward, RTM and gradient paths, each launched `launches` times on the n^3
+# layered workload (radius 4, line-aligned fields), for counter runs: name -> (kernel-name substring,
+# algorithmic bytes per launch as a function of n, what the bytes are).
+def kernel_table(n: int):
+    cells = n ** 3
+    interior = (n - 128) * (n - 32) * (n - 8)
+    halo = cells - interior
+    faces = 6 * 4 * n * n
+    return {
+        "interior": ("k_tiled<4, 16, 8, 0, false", 16 * interior, "16 B per interior cell"),
+        "halo_pack": ("k_tiled<4, 16, 16, 0, true", 16 * halo + 4 * faces, "16 B per halo cell + 4 B per face cell"),
+        "whole": ("k_tiled<4, 32, 16, 0, false", 16 * cells, "16 B per cell (also the scaled adjoint step)"),
+        "adjoint_direct": ("k_tiled<4, 16, 16, 1, false", 16 * cells, "16 B per cell: mu_a, kappa, mu_b in, mu out"),
+        "gradient": ("k_tiled<4, 32, 16, 2, false", 16 * cells, "16 B per cell: u, mu, grad in, grad out"),
+        "gradient_scaled": ("k_tiled<4, 32, 16, 3, false", 16 * cells, "16 B per cell: u, w, grad in, grad out"),
+        "unpack": ("k_unpack_lines", 8 * faces, "8 B per face cell: slot in, ghost out"),
+        "image": ("k_image<true>", 16 * cells, "16 B per cell: S, R, I in, I out"),
+        "absmax": ("k_plane_absmax<true>", 4 * cells, "4 B per cell"),
+        "encode": ("k_encode<true>", 6 * cells, "6 B per cell: u in, 16-bit code out"),
+        "image_coded": ("k_image_coded<true>", 14 * cells, "14 B per cell: code, R, I in, I out"),
+    }
+
+
+def run_kernels(n: int, launches: int):
+    import numpy as np
+    import torch
+
+    from . import _abi, synth
+    from .grid import Grid
+    from .snapshots import CodedSnapshots
+
+    h = 10.0
+    prof = synth.layered_profile(n, h, seed=2)
+    g = Grid(n, n, n, h, Grid.stable_dt(4, h, float(prof.max())))
+    v = torch.from_numpy(np.ascontiguousarray(np.broadcast_to(prof[:, None, None], (n, n, n)), dtype=np.float32))
+    kap = g.kappa_from_velocity(v.cuda())
+    del v
+    a, b, c = g.field(), g.field(), g.field()
+    for f in (a, b, c):
+        g.owned(f).normal_()
+    s = torch.cuda.current_stream()
+    send, recv = g.faces(), g.faces()
+    slots = g.face_slots(recv)
+    work = g.field()
+    codes = torch.empty(n ** 3, dtype=torch.int16, device="cuda")
+    scales = torch.empty(n, dtype=torch.float32, device="cuda")
+    calls = {
+        "interior": lambda: _abi.rtm_step_interior(g.c, c, a, b, kap, s),
+        "halo_pack": lambda: _abi.rtm_step_halo_pack(g.c, c, a, b, kap, send, s),
+        "whole": lambda: _abi.rtm_step_whole(g.c, c, a, b, kap, s),
+        "adjoint_direct": lambda: _abi.rtm_adjoint_step(g.c, c, a, b, kap, work, s),
+        "gradient": lambda: _abi.rtm_gradient_accumulate(g.c, c, a, b, s),
+        "gradient_scaled": lambda: _abi.rtm_gradient_accumulate_scaled(g.c, c, a, b, s),
+        "unpack": lambda: _abi.rtm_unpack_halo(g.c, c, slots, s),
+        "image": lambda: _abi.rtm_image_accumulate(g.c, c, a, b, 1.0, s),
+        "encode": lambda: _abi.rtm_snapshot_encode(g.c, a, codes, scales, _abi.RTM_SNAP_BF16, s),
+        "image_coded": lambda: _abi.rtm_image_accumulate_coded(g.c, c, codes, scales, _abi.RTM_SNAP_BF16, b, 1.0, s),
+    }
+    for name, fn in calls.items():
+        for _ in range(launches):
+            fn()
+        torch.cuda.synchronize()
+        print(f"{name}: {launches} launches", flush=True)
+    x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"n": n, "launches": launches, "copy_bytes": COPY_BYTES}), flush=True)
+
+
+def summarize_kernels(fetch_dir, write_dir, stats_dir, out, n, commands):
+    """Per-kernel HBM traffic (FETCH_SIZE + WRITE_SIZE, calibrated by the 1 GiB copy) against the
+    algorithmic bytes of kernel_table, and the kernel-trace duration of the same run."""
+    fr, wr = _csv(fetch_dir, "*counter_collection.csv"), _csv(write_dir, "*counter_collection.csv")
+    f_cp, _ = _counter(fr, "opy", "FETCH_SIZE", largest=True)
+    w_cp, _ = _counter(wr, "opy", "WRITE_SIZE", largest=True)
+    kf = COPY_BYTES / (f_cp * 1024.0)
+    kw = COPY_BYTES / (w_cp * 1024.0)
+    stats = _csv(stats_dir, "*kernel_stats.csv") if stats_dir else []
+    lines = [f"# rocprofv3 summary: HBM traffic of the hot kernels, {n}^3 layered workload (radius 4)", "",
+             "Commands:"] + [f"    {c}" for c in commands] + [""]
+    lines += [f"Counter calibration with a plain 1 GiB device copy: FETCH_SIZE x {kf:.3f}, WRITE_SIZE x {kw:.3f}", "",
+              f"    {'call':16s} {'alg MB':>9s} {'read MB':>9s} {'write MB':>9s} {'ratio':>6s} {'avg us':>8s} "
+              f"{'alg TB/s':>8s} {'moved TB/s':>10s}  algorithmic bytes"]
+    record = {"n": n, "kernel_source_sha256_16": kernel_source_hash(), "fetch_factor": kf, "write_factor": kw,
+              "kernels": {}}
+    for name, (sub, alg, what) in kernel_table(n).items():
+        f, nf = _counter(fr, sub, "FETCH_SIZE")
+        w, nw = _counter(wr, sub, "WRITE_SIZE")
+        if f is None or w is None:
+            continue
+        rd, wt = f * 1024.0 * kf, w * 1024.0 * kw
+        us = None
+        for r in stats:
+            if sub in r["Name"]:
+                us = float(r["AverageNs"]) / 1e3
+                break
+        tb_alg = f"{alg / us / 1e6:8.2f}" if us else f"{'-':>8s}"
+        tb_mv = f"{(rd + wt) / us / 1e6:10.2f}" if us else f"{'-':>10s}"
+        lines.append(f"    {name:16s} {alg / 1e6:9.1f} {rd / 1e6:9.1f} {wt / 1e6:9.1f} {(rd + wt) / alg:6.3f} "
+                     f"{(us or 0):8.1f} {tb_alg} {tb_mv}  {what}")
+        record["kernels"][name] = {"kernel": sub, "algorithmic_bytes": alg, "read_bytes": rd, "write_bytes": wt,
+                                   "avg_us": us, "dispatches": [nf, nw]}
+    text = "\n".join(lines) + "\n"
+    with open(out, "w") as fo:
+        fo.write(text)
+    print(text)
+
+
 def run_conv(n: int, launches: int):
     import torch
 
@@ -134,8 +243,8 @@ def run_corrected(n: int, steps: int, every: int):
 # The radius-4 tiled kernels under the default options: the interior call's (16 x 8-thread tiles),
 # the halo call's (16 x 16) and the one-launch whole step's (32 x 16).
 # (name prefixes: the demangled names go on with the kernel's last template argument, e.g. ", false>")
-INTERIOR_KERNEL = "k_tiled<4, 16, 8, 0"
-HALO_KERNEL = "k_tiled<4, 16, 16, 0"
+INTERIOR_KERNEL = "k_tiled<4, 16, 8, 0, false"
+HALO_KERNEL = "k_tiled<4, 16, 16, 0, true"
 TILED_R4 = "k_tiled<4, "
 
 
@@ -503,6 +612,16 @@ def main(argv=None):
     bh.add_argument("--out", required=True)
     bh.add_argument("--n", type=int, default=512)
     bh.add_argument("--command", action="append", default=[])
+    kn = sub.add_parser("kernels")
+    kn.add_argument("--n", type=int, default=512)
+    kn.add_argument("--launches", type=int, default=10)
+    sk = sub.add_parser("summarize-kernels")
+    sk.add_argument("--fetch", required=True)
+    sk.add_argument("--write", required=True)
+    sk.add_argument("--stats")
+    sk.add_argument("--out", required=True)
+    sk.add_argument("--n", type=int, default=512)
+    sk.add_argument("--command", action="append", default=[])
     cv = sub.add_parser("conv")
     cv.add_argument("--n", type=int, default=384)
     cv.add_argument("--launches", type=int, default=10)
@@ -552,6 +671,10 @@ def main(argv=None):
         run_interior(args.n, args.launches, call="halo")
     elif args.cmd == "summarize-halo":
         summarize_halo(args.fetch, args.write, args.out, args.n, args.command, args.stats)
+    elif args.cmd == "kernels":
+        run_kernels(args.n, args.launches)
+    elif args.cmd == "summarize-kernels":
+        summarize_kernels(args.fetch, args.write, args.stats, args.out, args.n, args.command)
     elif args.cmd == "conv":
         run_conv(args.n, args.launches)
     elif args.cmd == "corrected":

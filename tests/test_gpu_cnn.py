@@ -251,6 +251,53 @@ def test_network_gradient_matches_oracle():
         assert ew <= 2e-2 and eb <= 2e-2 and cos >= 0.999
 
 
+@pytest.mark.parametrize("relu,masked", [(False, True), (False, False), (True, True)])
+def test_trained_network_loss_and_gradients_match_oracle(relu, masked):
+    """The network the corrector trains (linear by default) with its masked, weighted window loss:
+    forward, loss and every parameter group's gradient through the library against the FP64 oracle
+    (oracle/cnn.py with the same relu flag, mask and weight), at the BF16-level tolerance of the
+    whole network (activations rounded to BF16 between layers)."""
+    import torch
+
+    from paper_1603_03971_amd import learned
+
+    nz, ny, nx = 6, 9, 32
+    net = learned.CorrectorNet(seed=5, out_init=1.0, bias=False, relu=relu)
+    rng = np.random.default_rng(801)
+    xin = np.zeros((nz, ny, nx, C), dtype=np.float32)
+    xin[..., :4] = rng.standard_normal((nz, ny, nx, 4))
+    xc, xv = _q(xin)
+    tgt = np.zeros((nz, ny, nx, C), dtype=np.float32)
+    tgt[..., :2] = rng.standard_normal((nz, ny, nx, 2)) * 0.5
+    weight = 0.37
+    mask = None
+    if masked:
+        mask = rng.uniform(0.0, 1.0, (nz, ny, nx)).astype(np.float32)
+        mask[:, :2] = 0.0                                   # a masked-off band, as near injection cells
+    ws = learned.Workspace(nx, ny, nz, train=True)
+    ws.x.copy_(_dev(_with_halo(xc).reshape(-1)))
+    ws.target.copy_(_dev(tgt.reshape(-1)))
+    learned.forward(net, ws)
+    learned.backward(net, ws, weight=weight, mask=None if mask is None else _dev(mask.reshape(-1)))
+    torch.cuda.synchronize()
+    params = [(oracle.bf16_to_f32(oracle.bf16_rne(w.astype(np.float32))).astype(np.float64), b)
+              for w, b in net.layers_host()]
+    loss, grads = ocnn.loss_and_grads(xv, tgt, params, relu=relu, mask=mask, weight=weight)
+    out_ref, _ = ocnn.forward(xv, params, relu=relu)
+    out = ws.out.cpu().numpy().reshape(nz, ny, nx, C)
+    eo = _rel(out[..., :2], out_ref[..., :2])
+    el = abs(float(ws.loss.item()) - loss) / loss
+    _say(f"network relu={relu} masked={masked}: out rel-L2 {eo:.2e}, loss rel {el:.2e}")
+    assert eo <= 1e-2 and el <= 1e-2
+    g = net.grad.cpu().numpy().astype(np.float64)
+    for layer in range(3):
+        gw = g[layer * learned.LAYER:layer * learned.LAYER + learned.WEIGHTS].reshape(27, C, C)
+        ew = _rel(gw, grads[layer][0])
+        cos = float(np.sum(gw * grads[layer][0]) / (np.linalg.norm(gw) * np.linalg.norm(grads[layer][0])))
+        _say(f"  layer {layer}: dW rel-L2 {ew:.2e} (cos {cos:.6f})")
+        assert ew <= 2e-2 and cos >= 0.999
+
+
 def test_restrict_absmax_pack_target_apply():
     import torch
 

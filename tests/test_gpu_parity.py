@@ -90,6 +90,11 @@ def test_schedules_and_variants_bitwise(torch_cuda):
         _abi.rtm_set_option(_abi.RTM_OPT_XCD_REMAP, 0)
         runs["noremap"] = problems.gpu_forward_problem(v, h, nsteps, src)["u_cur"]
         _abi.rtm_set_option(_abi.RTM_OPT_XCD_REMAP, 1)
+        for fl in (0, 1, 2, 3):
+            _abi.rtm_set_option(_abi.RTM_OPT_TILE_FLAGS, fl)
+            runs[f"tile_flags{fl}"] = problems.gpu_forward_problem(v, h, nsteps, src)["u_cur"]
+            runs[f"tile_flags{fl}_fused"] = problems.gpu_forward_problem(v, h, nsteps, src, schedule="fused")["u_cur"]
+        _abi.rtm_set_option(_abi.RTM_OPT_TILE_FLAGS, 1)
         runs["x_align4"] = problems.gpu_forward_problem(v, h, nsteps, src, x_align=4)["u_cur"]
         runs["unaligned_pitch"] = problems.gpu_forward_problem(v, h, nsteps, src, x_align=1)["u_cur"]
     finally:
@@ -98,6 +103,7 @@ def test_schedules_and_variants_bitwise(torch_cuda):
         _abi.rtm_set_option(_abi.RTM_OPT_WHOLE_VARIANT, 4)
         _abi.rtm_set_option(_abi.RTM_OPT_ZCHUNK, 0)
         _abi.rtm_set_option(_abi.RTM_OPT_XCD_REMAP, 1)
+        _abi.rtm_set_option(_abi.RTM_OPT_TILE_FLAGS, 1)
     assert np.any(base != 0)
     for name, u in runs.items():
         assert np.array_equal(u, base), name

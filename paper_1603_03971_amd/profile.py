@@ -108,10 +108,10 @@ def kernel_table(n: int):
         "gradient": ("k_tiled<4, 32, 16, 2, false", 16 * cells, "16 B per cell: u, mu, grad in, grad out"),
         "gradient_scaled": ("k_tiled<4, 32, 16, 3, false", 16 * cells, "16 B per cell: u, w, grad in, grad out"),
         "unpack": ("k_unpack_lines", 8 * faces, "8 B per face cell: slot in, ghost out"),
-        "image": ("k_image<true>", 16 * cells, "16 B per cell: S, R, I in, I out"),
+        "image": ("k_image<true", 16 * cells, "16 B per cell: S, R, I in, I out"),
         "absmax": ("k_plane_absmax<true>", 4 * cells, "4 B per cell"),
         "encode": ("k_encode<true>", 6 * cells, "6 B per cell: u in, 16-bit code out"),
-        "image_coded": ("k_image_coded<true>", 14 * cells, "14 B per cell: code, R, I in, I out"),
+        "image_coded": ("k_image_coded<true", 14 * cells, "14 B per cell: code, R, I in, I out"),
     }
 
 

@@ -45,15 +45,17 @@ def _cur():
 # -------------------------------------------------------------------------------------------------
 # Coarse grid
 # -------------------------------------------------------------------------------------------------
-def coarse_grid(fine: Grid) -> Grid:
-    """The coarse companion of `fine`: half the cells per axis, spacing 2h, step 2dt, radius 2.  Its
-    Courant number v (2dt) / (2h) equals the fine one, which is below the radius-4 limit and hence
-    below the larger radius-2 limit, so the coarse grid is stable whenever the fine one is."""
+def coarse_grid(fine: Grid, radius: int = 2) -> Grid:
+    """The coarse companion of `fine`: half the cells per axis, spacing 2h, step 2dt, radius 2 (or 4).
+    Its Courant number v (2dt) / (2h) equals the fine one, which is below the radius-4 limit and
+    hence below the larger radius-2 limit, so the coarse grid is stable whenever the fine one is."""
     if fine.nx % 2 or fine.ny % 2 or fine.nz % 2:
         raise ValueError("fine grid dimensions must be even")
     if fine.radius != 4:
         raise ValueError("the fine grid uses the radius-4 stencil")
-    g = Grid(fine.nx // 2, fine.ny // 2, fine.nz // 2, 2.0 * fine.h, 2.0 * fine.dt, radius=2,
+    if radius not in (2, 4):
+        raise ValueError("coarse radius 2 or 4")
+    g = Grid(fine.nx // 2, fine.ny // 2, fine.nz // 2, 2.0 * fine.h, 2.0 * fine.dt, radius=radius,
              sponge_width=max(fine.sponge_width // 2, 1), sponge_alpha=fine.sponge_alpha * 2.0 * math.sqrt(2.0),
              device=fine.device)
     return g
@@ -651,7 +653,8 @@ PLAIN_VARIANTS = {
 
 def compare_rtm(fine: Grid, v_true, v_bg, src_f, rec_f, nsteps_f: int, fpeak: float, net: CorrectorNet | None,
                 every: int, image_every_f: int = 4, repeats: int = 2, schedule: str = "fused",
-                snapshots_fine: str | None = None, log=None, plain_variants=(), prolonged: bool = False):
+                snapshots_fine: str | None = None, log=None, plain_variants=(), prolonged: bool = False,
+                coarse_radius: int = 2):
     """Migrate one shot on the fine grid (the reference) and on the coarse grid without and with the
     learned corrector.  The recorded data are modelled on the fine grid (d_true in v_true, d_bg in
     v_bg) and decimated in time for the coarse runs; sources and receivers sit on even fine cells,
@@ -669,7 +672,7 @@ def compare_rtm(fine: Grid, v_true, v_bg, src_f, rec_f, nsteps_f: int, fpeak: fl
 
     say = log if log is not None else (lambda msg: None)
 
-    coarse = coarse_grid(fine)
+    coarse = coarse_grid(fine, coarse_radius)
     src_f = np.asarray(src_f, dtype=np.int64).reshape(-1, 3)
     rec_f = np.asarray(rec_f, dtype=np.int64).reshape(-1, 3)
     if (src_f % 2).any() or (rec_f % 2).any():
@@ -834,6 +837,7 @@ class CorrectorSpec:
     fp_high: float
     every: int
     relu: bool
+    coarse_radius: int = 2       # stencil radius of the coarse grid the corrector was trained on
     # the fine grid judges the corrector: the target-zone image error of the corrected coarse shot
     # against the plain fine shot, as measured by `compare` (NaN: never measured), and the largest
     # error at which the corrected coarse grid may stand in for the fine one
@@ -901,7 +905,7 @@ def migrate(fine: Grid, v_bg, src_f, rec_f, wavelet_fpeak: float, data_true, dat
     if ok and ((src_f % 2).any() or (rec_f % 2).any() or nsteps_f % 2 or image_every_f % 2):
         ok, reason = False, "sources, receivers, step count and imaging interval must be even"
     if ok:
-        coarse = coarse_grid(fine)
+        coarse = coarse_grid(fine, int(spec.coarse_radius))
         vbc = coarse_velocity(v_bg)
         cf, cb = Corrector(net, coarse, vbc, spec.every), Corrector(net, coarse, vbc, spec.every)
         cf.set_mask(injection_mask(coarse, src_f // 2))
@@ -951,14 +955,15 @@ def rollout_validator(fine: Grid, coarse: Grid, every: int, nsteps_coarse: int, 
 
 def train_corrector(n: int = 96, models: int = 200, first_seed: int = 5000, every: int = DEFAULTS["every"],
                     fpeak=DEFAULTS["fpeak"], nsteps_coarse: int = 300, epochs: int = 10, lr: float = 1e-3,
-                    relu: bool = DEFAULTS["relu"], seed: int = 1, log=None, validation_models: int = 4):
+                    relu: bool = DEFAULTS["relu"], seed: int = 1, log=None, validation_models: int = 4,
+                    coarse_radius: int = 2):
     """Train a corrector on `models` seeded fine/coarse pairs (fine n^3, h = 10 m, v in [1500, 3000]
     m/s, alternating point-source and receiver-plane problems).  fpeak: one peak frequency, or a
     (low, high) band from which each model draws its own (seeded).  With validation_models > 0 the
     epoch whose parameters give the lowest rollout error on that many held-out models is kept
     (rollout_validator).  Returns (net, pairs, losses, spec)."""
     fine = Grid(n, n, n, TRAIN_H, Grid.stable_dt(4, TRAIN_H, TRAIN_VMAX))
-    coarse = coarse_grid(fine)
+    coarse = coarse_grid(fine, coarse_radius)
     band = (float(fpeak[0]), float(fpeak[1])) if isinstance(fpeak, (tuple, list)) else (float(fpeak), float(fpeak))
     if isinstance(fpeak, (tuple, list)):
         fpeak = np.random.default_rng(first_seed).uniform(band[0], band[1], models)
@@ -969,7 +974,7 @@ def train_corrector(n: int = 96, models: int = 200, first_seed: int = 5000, ever
         if validation_models > 0 else None
     hist = train(net, pairs, epochs, lr=lr, lr_final=lr / 5, log=log, validate=validate)
     spec = CorrectorSpec(h=fine.h, dt=fine.dt, vmin=TRAIN_VMIN, vmax=TRAIN_VMAX, fp_low=band[0], fp_high=band[1],
-                         every=int(every), relu=bool(relu))
+                         every=int(every), relu=bool(relu), coarse_radius=int(coarse_radius))
     return net, pairs, hist, spec
 
 
@@ -992,6 +997,7 @@ def main(argv=None):
     t.add_argument("--validation-models", type=int, default=4,
                    help="held-out models whose rollout error selects the epoch (0: keep the last epoch)")
     t.add_argument("--seed", type=int, default=1, help="seed of the initial weights")
+    t.add_argument("--coarse-radius", type=int, default=2, choices=[2, 4], help="stencil radius of the coarse grid")
     t.add_argument("--out", required=True)
     c = sub.add_parser("compare", help="one RTM shot: fine vs plain coarse vs corrected coarse")
     c.add_argument("--weights", required=True)
@@ -1022,7 +1028,8 @@ def main(argv=None):
         net, pairs, hist, spec = train_corrector(a.n, a.models, every=a.every,
                                                  fpeak=a.fp if a.fp is not None else tuple(a.fp_band),
                                                  nsteps_coarse=a.steps, epochs=a.epochs, relu=a.relu, seed=a.seed,
-                                                 log=logger, validation_models=a.validation_models)
+                                                 log=logger, validation_models=a.validation_models,
+                                                 coarse_radius=a.coarse_radius)
         if getattr(net, "selected_epoch", None) is not None:
             say(f"kept epoch {net.selected_epoch} (held-out rollout error {net.validation_score:.4f})")
         with_net, zero = window_loss(net, pairs)
@@ -1052,15 +1059,20 @@ def main(argv=None):
     say(f"compare: fine {n}^3, {a.steps} steps, {a.fp} Hz, corrector every {every} coarse steps")
     r = compare_rtm(fine, v_true, v_bg, src, rec, a.steps, a.fp, net, every, image_every_f=a.image_every,
                     repeats=a.repeats, snapshots_fine=a.snapshots, log=say, plain_variants=a.plain,
-                    prolonged=a.prolonged)
+                    prolonged=a.prolonged, coarse_radius=int(spec.coarse_radius) if spec is not None else 2)
     if a.plain and "err_learned_zone_full_weighted" in r:
-        # the plain curve: the fine solve (error 0 by definition), the plain coarse grid, the variants
+        # the plain curve: the fine solve (error 0 by definition), the uncorrected coarse grid, the variants
         pts = [(r["t_fine"], 0.0), (r["t_plain"], r["err_plain_zone_full_weighted"])]
         pts += [(r[f"t_{n}"], r[f"err_{n}_zone_full_weighted"]) for n in a.plain]
         t_eq = time_at_error(pts, r["err_learned_zone_full_weighted"])
         r["plain_time_at_learned_error"] = t_eq
-        say(f"learned: {r['t_learned']:.3f} s at target-zone error {r['err_learned_zone_full_weighted']:.3f}; "
-            f"plain solvers reach that error in {t_eq if t_eq is None else round(t_eq, 3)} s")
+        pts_d = [(r["t_fine"], 0.0), (r["t_plain"], r["err_plain_zone_decimated"])]
+        pts_d += [(r[f"t_{n}"], r[f"err_{n}_zone_decimated"]) for n in a.plain]
+        t_eq_d = time_at_error(pts_d, r["err_learned_zone_decimated"])
+        r["plain_time_at_learned_error_decimated"] = t_eq_d
+        say(f"learned: {r['t_learned']:.3f} s at target-zone error {r['err_learned_zone_full_weighted']:.3f} "
+            f"(full-weighted), {r['err_learned_zone_decimated']:.3f} (decimated); plain solvers reach those errors "
+            f"in {t_eq if t_eq is None else round(t_eq, 3)} s and {t_eq_d if t_eq_d is None else round(t_eq_d, 3)} s")
     say(json.dumps({k: v for k, v in r.items() if not k.startswith(("img", "ref"))}))
     if a.record is not None and spec is not None and "err_learned_zone_full_weighted" in r:
         spec = replace(spec, image_error=float(r["err_learned_zone_full_weighted"]))

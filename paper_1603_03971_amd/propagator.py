@@ -111,8 +111,12 @@ class Sources:
 class Propagator:
     def __init__(self, grid: Grid, kappa: torch.Tensor, *, sources: Sources | list | None = None,
                  receivers=None, boundary: str = "zero", schedule: str = "overlap", debug: bool = False,
-                 check_every: int = 0):
-        """check_every = K > 0: health check of the production path.  After every K-th step the
+                 check_every: int = 0, unpack_aside: bool = False):
+        """unpack_aside (serial schedule): the unpack runs on a second stream as soon as the halo call
+        and the shell sources are done, concurrently with the interior call (it writes ghost cells
+        only, the interior call owned cells only); the next step waits for it.  Same bits.
+
+        check_every = K > 0: health check of the production path.  After every K-th step the
         newest level's non-finite owned cells are counted on the device (rtm_count_nonfinite, 4 bytes
         per cell) and the host reads the count (one synchronisation per K steps); a run that went
         unstable (e.g. a time step past the stability limit) raises FloatingPointError within K
@@ -170,6 +174,8 @@ class Propagator:
         if check_every < 0:
             raise ValueError("check_every must be >= 0")
         self.check_every = int(check_every)
+        self.unpack_aside = bool(unpack_aside)
+        self._ev_unpack = None
         self._bad = torch.zeros(1, dtype=torch.int32, device=grid.device) if self.check_every else None
 
     # ------------------------------------------------------------------------------------------
@@ -271,10 +277,20 @@ class Propagator:
             # sources, the unpack (at 512^3: 0.525 ms per step against 0.546 ms with the pack after
             # the interior call, once each row's owned cells start a cache line)
             st = torch.cuda.current_stream()
+            if self._ev_unpack is not None:
+                st.wait_event(self._ev_unpack)          # the ghosts of u^n are complete
+                self._ev_unpack = None
             _abi.rtm_step_halo_pack(c, u_nxt, u_cur, u_prv, kap, self.send, st)
             for s in self.sources:
                 s.inject(g, u_nxt, n, 0, st)
                 s.repack(g, u_nxt, n, self.send, st)
+            if self.unpack_aside:
+                ev = torch.cuda.Event()
+                ev.record(st)
+                self.sH.wait_event(ev)
+                _abi.rtm_unpack_halo(c, u_nxt, self.recv, self.sH)
+                self._ev_unpack = torch.cuda.Event()
+                self._ev_unpack.record(self.sH)
             if self.interior_events is not None:
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(st)
@@ -285,7 +301,8 @@ class Propagator:
                 _abi.rtm_step_interior(c, u_nxt, u_cur, u_prv, kap, st)
             for s in self.sources:
                 s.inject(g, u_nxt, n, 1, st)
-            _abi.rtm_unpack_halo(c, u_nxt, self.recv, st)
+            if not self.unpack_aside:
+                _abi.rtm_unpack_halo(c, u_nxt, self.recv, st)
             if tr_ptr is not None:
                 _abi.rtm_record(c, u_nxt, self.rec_idx, tr_ptr, self.nrec, st)
         else:
@@ -344,6 +361,9 @@ class Propagator:
 
     def sync(self):
         """Make the caller's current stream wait for everything enqueued so far."""
+        if self._ev_unpack is not None:
+            torch.cuda.current_stream().wait_event(self._ev_unpack)
+            self._ev_unpack = None
         if self.schedule == "overlap":
             cur = torch.cuda.current_stream()
             cur.wait_stream(self.sH)

@@ -1,4 +1,6 @@
 """GPU one-shot RTM against the oracle: reflection data, back-propagation and the zero-lag image."""
+import os
+
 import numpy as np
 import pytest
 
@@ -134,6 +136,32 @@ def test_rtm_image_parity_128x128x64(c3_reduced_case, schedule, halo_x):
     assert e_t <= 1e-4
     assert e_img <= 1e-3
     assert worst <= 1e-3
+
+
+@pytest.mark.skipif(not os.environ.get("RTM_LONG_CHECKS"), reason="about 2 minutes of host time; RTM_LONG_CHECKS=1")
+def test_rtm_image_parity_half_size(capsys):
+    """The one-shot RTM recipe at half size per axis: 256 x 256 x 128 cells, 1000 steps, 128 x 128
+    receivers every 2 cells and the source at depth index 10, reflectors at depths 30-75 cells,
+    snapshots every 4 steps, halo-first schedule; the image against the FP64 oracle (whose
+    snapshots take 17 GB of host memory)."""
+    import time
+
+    shape = (128, 256, 256)
+    v_true, v_bg = synth.dipping_reflector_model(shape, 10.0, seed=3, z0_cells=(30, 75), max_dip_deg=15.0)
+    src = [(128, 128, 10)]
+    rec = synth.surface_receivers(256, 256, k=10, stride=2)
+    nsteps, fpeak, every = 1000, 15.0, 4
+    img, d_t, d_b, _ = gpu_rtm(v_true, v_bg, src, rec, nsteps, fpeak, every, sponge_width=16, schedule="serial")
+    t0 = time.perf_counter()
+    img_o, dt_o, db_o, _ = oracle_rtm(v_true, v_bg, src, rec, nsteps, fpeak, every, sponge_width=16,
+                                      nthreads=problems.host_threads())
+    e_t = oracle.rel_l2(d_t, dt_o)
+    e_img = oracle.rel_l2(img, img_o)
+    worst = float(np.max(np.abs(img - img_o)) / np.max(np.abs(img_o)))
+    with capsys.disabled():
+        _say(f"\nrtm 256x256x128 x {nsteps}: traces {e_t:.2e}, image rel-L2 {e_img:.2e}, max |diff| / max "
+             f"{worst:.2e} (oracle {time.perf_counter() - t0:.0f} s)")
+    assert e_t <= 1e-4 and e_img <= 1e-3 and worst <= 1e-3
 
 
 def test_rtm_serial_schedule_bitwise(reduced_case):

@@ -112,14 +112,15 @@ const char *rtm_strerror(int status);
  *                             3 = scalar per-cell kernels for every call, 4 = 32x16 (128x16 cells,
  *                             two workgroups per CU), 5 = 16x32 (64x32 cells).
  *   RTM_OPT_HALO_VARIANT      the halo call's workgroup shape, numbered as above (not 3); default 0.
- *   RTM_OPT_WHOLE_VARIANT     rtm_step_whole's workgroup shape, numbered as above (not 3); default 4.
- *                             The one-launch adjoint and gradient calls take it too, except that the
- *                             adjoint runs 4 and 5 (tiles held to 128 registers) as 0.
+ *   RTM_OPT_WHOLE_VARIANT     rtm_step_whole's workgroup shape, numbered as above (not 3), or 6 (the
+ *                             default): 1 (32x8) at radius 4, 4 (32x16) at radius 2.  The one-launch
+ *                             adjoint and gradient calls take it too, except that the adjoint runs 4
+ *                             and 5 (tiles held to 128 registers) as 0.
  *   RTM_OPT_ZCHUNK            z planes per workgroup of the tiled kernels; 0 = automatic: at radius 4,
  *                             for one-box launches (interior, whole step, adjoint, gradient) the
- *                             chunking that balances the work of the busiest CU with the fewest
- *                             workgroups, for the halo call at most one wave of resident workgroups
- *                             over the whole chip; at radius 2 chunks of 16 planes.
+ *                             chunking that balances the work of the busiest CU (a CU counted as
+ *                             enough workgroups for about 8 wavefronts) with the fewest workgroups,
+ *                             for the halo call chunks of 12 planes; at radius 2 chunks of 16 planes.
  *   RTM_OPT_XCD_REMAP         1 = give each XCD a contiguous range of tiles (default), 0 = hardware order.
  *   RTM_OPT_HALO_X_WIDTH      width of the halo region's x strips (default 64 = one tile);
  *   RTM_OPT_HALO_Y_WIDTH      height of its y strips (default 16); see rtm_halo_region.

@@ -1128,7 +1128,7 @@ std::atomic<int> g_dev_ok[kMaxDevices];   // 0 unknown, 1 gfx950, -1 other
 struct Options {
     std::atomic<int> interior_variant{2};  // 0: 16x16 threads (64 x 16 cells), 1: 32x8, 2: 16x8, 3: scalar,
                                            // 4: 32x16 (128 x 16 cells, two workgroups per CU), 5: 16x32
-    std::atomic<int> whole_variant{4};     // tile shape of the one-launch whole step (not 3)
+    std::atomic<int> whole_variant{6};     // tile shape of the one-launch whole step (not 3); 6 = by radius
     std::atomic<int> zchunk{0};            // 0: automatic
     std::atomic<int> xcd_remap{1};
     std::atomic<int> halo_x_width{64};     // x strips of the halo region
@@ -1220,26 +1220,33 @@ int cu_count()
     return n;
 }
 
-// z chunk of a launch over one deep box of `tiles` XY tiles and depth wz.  Each chunk re-reads 2R
-// planes it does not write, and the launch lasts about as long as its busiest CU:
-//     cost(nzc) = ceil(tiles * nzc / CUs) * (wz / nzc + 2R)    (in tile-planes).
+// z chunk of a launch over one deep box of `tiles` XY tiles and depth wz, for workgroups of
+// `waves` wavefronts.  Each chunk re-reads 2R planes it does not write, and the launch lasts about as
+// long as its busiest CU, which holds k = ceil(tiles * nzc / CUs) workgroups.  A CU streams at full
+// rate only once it holds about 6 wavefronts (one 32x8 workgroup, 4 waves, runs at about 3/4 of it),
+// so the cost counts at least 6 / waves workgroups per CU:
+//     cost(nzc) = max(k, 6 / waves) * (wz / nzc + 2R)    (in tile-planes).
 // Among chunkings within 3% of the least cost the one with the fewest workgroups wins: fewer,
-// longer streams use HBM better (512^3 whole step with 32x16 tiles: 2 chunks, one workgroup per
-// CU, 454 us; 4 chunks 501 us; 3 chunks, 384 workgroups on 256 CUs, 559 us).
-int balanced_zchunk(int tiles, int wz, int R, int cus)
+// longer streams use HBM better.  At 512^3 this gives 2 chunks for the interior call (720
+// workgroups of 16x8: 269-276 us; 1 chunk 313 us, 3 chunks 301 us), for every tile shape of the
+// one-launch call (32x8 threads: 343 us against 462 us for 1 chunk; 32x16: 376 us, 1 chunk 597 us,
+// 3 chunks 427 us) and for the direct adjoint step (500 against 643 us for 1 chunk).
+int balanced_zchunk(int tiles, int wz, int R, int cus, int waves)
 {
+    const double min_k = 6.0 / std::max(1, waves);
     const int max_nzc = std::max(1, wz / 16);
-    long long best = -1;
-    long long cost[64 + 1];
+    double best = -1;
+    double cost[64 + 1];
     const int n_try = std::min(max_nzc, 64);
     for (int nzc = 1; nzc <= n_try; ++nzc) {
         const int zc = (wz + nzc - 1) / nzc;
         const long long blocks = (long long)tiles * ((wz + zc - 1) / zc);
-        cost[nzc] = ((blocks + cus - 1) / cus) * (long long)(zc + 2 * R);
+        const double k = (double)((blocks + cus - 1) / cus);
+        cost[nzc] = std::max(k, min_k) * (double)(zc + 2 * R);
         if (best < 0 || cost[nzc] < best) best = cost[nzc];
     }
     for (int nzc = 1; nzc <= n_try; ++nzc)   // fewest workgroups first
-        if (cost[nzc] * 100 <= best * 103) return (wz + nzc - 1) / nzc;
+        if (cost[nzc] <= best * 1.03) return (wz + nzc - 1) / nzc;
     return wz;
 }
 
@@ -1279,27 +1286,13 @@ int launch_tiled(const Geo &g, float *un, const float *uc, const float *up, cons
         // one (384^3 whole step: 237 us at 16 planes against 266 us for one wave).
         zc = 16;
     } else if (zc <= 0 && tiles > 0 && bl.nbox == 1) {
-        zc = balanced_zchunk(tiles, wz, R, cu_count());
+        zc = balanced_zchunk(tiles, wz, R, cu_count(), (BX * BY + 63) / 64);
     } else if (zc <= 0 && tiles > 0) {
-        // One wave of workgroups: split z so that tiles x chunks is at most the number of workgroups
-        // the whole chip holds at once (CUs x resident workgroups per CU), with chunks of >= 16
-        // planes; rounding down keeps a second, nearly empty wave from doubling the time.
-        static std::atomic<int> resident{0};
-        int occ = resident.load(std::memory_order_relaxed);
-        if (occ == 0) {
-            int per_cu = 0, cus = 0, dev = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tiled<R, BX, BY, OP, PACK, FL>, BX * BY, 0) !=
-                hipSuccess)
-                per_cu = 2;
-            if (hipGetDevice(&dev) != hipSuccess ||
-                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-                cus = 256;
-            occ = std::max(1, per_cu) * std::max(1, cus);
-            resident.store(occ, std::memory_order_relaxed);
-        }
-        int nzc = occ / tiles;
-        nzc = std::max(1, std::min(nzc, std::max(1, wz / 16)));
-        zc = (wz + nzc - 1) / nzc;
+        // The halo call's mix of thin slabs and deep strips: short chunks of 12 planes for its deep
+        // strips, many small workgroups that fill the chip evenly (512^3 halo call with the pack:
+        // 155 us, against 174 us with one wave of resident workgroups, about 51-plane chunks;
+        // 8 planes 160, 16 planes 157, 24 planes 167 us).
+        zc = 12;
     }
     if (zc <= 0) zc = 1 << 30;
     long long nb = 0;
@@ -1451,12 +1444,21 @@ int launch_interior(const Geo &g, float *un, const float *uc, const float *up, c
 
 // Every owned cell in one launch: a single box of the tiled kernel (its own tile option) over the
 // whole owned block; like the halo call it reads the ghost ring.
+// The one-launch call's tile shape: the option, or by radius (6, the default): at radius 4 the 32x8
+// tiles (128x8 cells; 343 us for the 512^3 step, 32x16 376 us, 16x16 356 us), at radius 2 the 32x16
+// tiles (384^3 coarse step: 216 us, the other shapes 219-258 us).
+int whole_variant(int R)
+{
+    const int v = g_opt.whole_variant.load(std::memory_order_relaxed);
+    return v == 6 ? (R == 4 ? 1 : 4) : v;
+}
+
 template <int R, int OP = OP_FORWARD>
 int launch_all(const Geo &g, float *un, const float *uc, const float *up, const float *kap, hipStream_t st)
 {
     const int boxes[1][6] = {{0, g.nx, 0, g.ny, 0, g.nz}};
     if (vector_path(g, un, uc, up, kap)) {
-        const int var = g_opt.whole_variant.load(std::memory_order_relaxed);
+        const int var = whole_variant(R);
         return launch_tiled_variant<R, OP>(var, g, un, uc, up, kap, boxes, 1, st);
     }
     return launch_box_scalar<R, OP>(g, un, uc, up, kap, boxes[0], st);
@@ -1480,7 +1482,7 @@ int launch_adjoint(const Geo &g, float *mu_out, const float *mu_a, const float *
                    hipStream_t st)
 {
     const int boxes[1][6] = {{0, g.nx, 0, g.ny, 0, g.nz}};
-    int var = g_opt.whole_variant.load(std::memory_order_relaxed);
+    int var = whole_variant(R);
     if (var == 4 || var == 5) var = 0;
     return launch_tiled_variant<R, OP_ADJOINT>(var, g, mu_out, mu_a, mu_a, mu_b, boxes, 1, st, nullptr, kappa);
 }
@@ -2202,7 +2204,7 @@ int rtm_set_option(int32_t option, int32_t value)
         g_opt.halo_variant.store(value);
         return RTM_OK;
     case RTM_OPT_WHOLE_VARIANT:
-        if (value < 0 || value > 5 || value == 3) return RTM_EINVAL;
+        if (value < 0 || value > 6 || value == 3) return RTM_EINVAL;
         g_opt.whole_variant.store(value);
         return RTM_OK;
     case RTM_OPT_UNPACK_LINES:

@@ -105,7 +105,7 @@ def test_validation_before_device(abi):
     assert L.rtm_set_option(abi.RTM_OPT_INTERIOR_VARIANT, 7) == abi.RTM_EINVAL
     assert L.rtm_get_option(99) == abi.RTM_EINVAL
     assert L.rtm_get_option(abi.RTM_OPT_INTERIOR_VARIANT) == 2          # the 16x8 tile by default
-    assert L.rtm_get_option(abi.RTM_OPT_WHOLE_VARIANT) == 4             # the 32x16 tile by default
+    assert L.rtm_get_option(abi.RTM_OPT_WHOLE_VARIANT) == 6             # the tile shape chosen by radius
     assert L.rtm_set_option(abi.RTM_OPT_WHOLE_VARIANT, 3) == abi.RTM_EINVAL
     assert L.rtm_get_option(abi.RTM_OPT_ZCHUNK) == 0
     assert L.rtm_get_option(abi.RTM_OPT_HALO_VARIANT) == 0

@@ -83,10 +83,10 @@ def test_schedules_and_variants_bitwise(torch_cuda):
             _abi.rtm_set_option(_abi.RTM_OPT_HALO_VARIANT, var)
             runs[f"halo_variant{var}"] = problems.gpu_forward_problem(v, h, nsteps, src)["u_cur"]
         _abi.rtm_set_option(_abi.RTM_OPT_HALO_VARIANT, 0)
-        for var in (0, 1, 2, 5):
+        for var in (0, 1, 2, 4, 5):
             _abi.rtm_set_option(_abi.RTM_OPT_WHOLE_VARIANT, var)
             runs[f"whole_variant{var}"] = problems.gpu_forward_problem(v, h, nsteps, src, schedule="fused")["u_cur"]
-        _abi.rtm_set_option(_abi.RTM_OPT_WHOLE_VARIANT, 4)
+        _abi.rtm_set_option(_abi.RTM_OPT_WHOLE_VARIANT, 6)
         for zc in (1, 7, 1000):
             _abi.rtm_set_option(_abi.RTM_OPT_ZCHUNK, zc)
             runs[f"zchunk{zc}"] = problems.gpu_forward_problem(v, h, nsteps, src)["u_cur"]
@@ -104,7 +104,7 @@ def test_schedules_and_variants_bitwise(torch_cuda):
     finally:
         _abi.rtm_set_option(_abi.RTM_OPT_INTERIOR_VARIANT, default_variant)
         _abi.rtm_set_option(_abi.RTM_OPT_HALO_VARIANT, 0)
-        _abi.rtm_set_option(_abi.RTM_OPT_WHOLE_VARIANT, 4)
+        _abi.rtm_set_option(_abi.RTM_OPT_WHOLE_VARIANT, 6)
         _abi.rtm_set_option(_abi.RTM_OPT_ZCHUNK, 0)
         _abi.rtm_set_option(_abi.RTM_OPT_XCD_REMAP, 1)
         _abi.rtm_set_option(_abi.RTM_OPT_TILE_FLAGS, 1)

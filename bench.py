@@ -3,11 +3,12 @@
 Workload: 512^3 cells, h = 10 m, seeded layered medium (20 layers, 1500-4500 m/s, Gaussian-smoothed
 with sigma = 3 cells, seed 2), radius-4 star stencil with leapfrog, dt at half the stability limit,
 15 Hz Ricker point source at the centre, 16-cell sponge, and the halo-first step schedule with all
-six 4-wide faces packed and unpacked on the device (one subdomain's share: the faces go out to a
-send buffer, and the ghosts come in from six receive slots of a zero-filled receive buffer, which the
-unpack reads, as from neighbours that sent zero faces).  A step is one pass of the whole per-step
-sequence: halo stencil (writing the faces as it goes), source injection, interior stencil, unpack,
-receiver recording.
+six 4-wide faces exchanged on the device (one subdomain's share: the faces go out to a send buffer,
+and the ghosts come in from six receive slots of a zero-filled receive buffer, as from neighbours
+that sent zero faces).  A step is one pass of the whole per-step sequence: halo stencil (reading the
+ghosts from the receive slots and writing the faces to the send buffer as it goes), source
+injection, interior stencil, receiver recording.  With --ghosts ring the received faces are instead
+unpacked into the ghost ring by a pass of their own after the interior stencil.
 
 Prints one JSON line: G point-updates/s over the timed steps, the interior kernel's achieved HBM
 bandwidth against the 8 TB/s peak (algorithmic bytes / HIP-event kernel time), and the FP64 CPU
@@ -40,6 +41,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--phases", action="store_true", help="also time each phase separately (serial)")
+    ap.add_argument("--ghosts", default="slots", choices=["slots", "ring"],
+                    help="slots: the halo call reads the ghosts from the receive slots; ring: an unpack pass")
     return ap.parse_args()
 
 
@@ -133,7 +136,8 @@ def main():
     c = n // 2
     src = Sources(g, [(c, c, c)], g.injection_weights([prof[c]]), g.ricker(total_steps, 15.0)[:, None])
     rec = synth.surface_receivers(n, n, k=20, stride=16)           # a sparse 32 x 32 surface spread
-    prop = Propagator(g, kap, sources=src, receivers=rec, schedule=args.schedule, boundary="zero_faces")
+    prop = Propagator(g, kap, sources=src, receivers=rec, schedule=args.schedule, boundary="zero_faces",
+                      ghosts=args.ghosts)
     traces = prop.new_traces(total_steps)
     torch.cuda.synchronize()
 
@@ -153,6 +157,8 @@ def main():
     finite = bool(torch.isfinite(traces).all().item())
     pts = g.points
     value = pts * args.steps / wall / 1e9
+    exchange = ("read by the next halo call from zero-filled receive slots (no unpack pass)" if args.ghosts == "slots"
+                else "unpacked from zero-filled receive slots")
     result = {
         "metric": "Gpoint-updates/s", "value": round(value, 3), "unit": "Gpts/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 4),
@@ -160,9 +166,8 @@ def main():
         "config": {"workload": f"forward {n}^3 layered (20 layers 1500-4500 m/s, sigma 3, seed 2), radius-4 "
                                f"8th-order star, leapfrog, dt at half the stability limit, 15 Hz Ricker at the "
                                f"centre, 16-cell sponge, halo-first with 6 x 4-wide faces packed to a send buffer and "
-                               f"unpacked from zero-filled receive slots, "
-                               f"{args.steps} timed steps",
-                   "grid": [n, n, n], "h_m": h, "dt_s": dt, "schedule": args.schedule,
+                               f"{exchange}, {args.steps} timed steps",
+                   "grid": [n, n, n], "h_m": h, "dt_s": dt, "schedule": args.schedule, "ghosts": args.ghosts,
                    "receivers": int(len(rec))},
         "finite": finite,
     }
@@ -185,10 +190,11 @@ def main():
                               "algorithmic_bytes_per_launch": BYTES_PER_POINT * interior_pts}
         # whole-step roofline with the halo phases, counting the bytes each phase must move: the
         # stencil 16 B per cell; per face cell, the halo call stores the computed value into its
-        # send slot (4 B; the value is in registers, not read back) and the unpack reads the
-        # receive slot and writes the ghost (8 B)
+        # send slot (4 B; the value is in registers, not read back) and the received ghost is read
+        # from its slot by the next halo call (4 B), or read and written into the ring by the
+        # unpack (8 B, ghosts="ring")
         face_cells = 6 * 4 * n * n
-        step_bytes = BYTES_PER_POINT * pts + 12 * face_cells
+        step_bytes = BYTES_PER_POINT * pts + (8 if args.ghosts == "slots" else 12) * face_cells
         result["step_hbm_frac"] = round(step_bytes / (wall / args.steps) / 1e9 / HBM_PEAK_GBS, 4)
     if args.phases:
         result["phases_us"] = time_phases(g, prop, traces)
@@ -228,6 +234,8 @@ def time_phases(g, prop, traces, reps: int = 20):
         "halo": lambda: _abi.rtm_step_halo(c, u_nxt, u_cur, u_prv, prop.kappa, st),
         "pack": lambda: _abi.rtm_pack_halo(c, u_nxt, prop.send, st),
         "halo_pack": lambda: _abi.rtm_step_halo_pack(c, u_nxt, u_cur, u_prv, prop.kappa, prop.send, st),
+        "halo_pack_slots": lambda: _abi.rtm_step_halo_pack_slots(c, u_nxt, u_cur, u_prv, prop.kappa, prop.recv,
+                                                                 prop.send, st),
         "unpack": lambda: _abi.rtm_unpack_halo(c, u_nxt, prop.recv, st),
         "interior": lambda: _abi.rtm_step_interior(c, u_nxt, u_cur, u_prv, prop.kappa, st),
         "record": lambda: _abi.rtm_record(c, u_nxt, prop.rec_idx, traces, prop.nrec, st),

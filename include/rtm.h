@@ -200,6 +200,21 @@ int rtm_pack_halo(const rtm_grid *grid, const float *u, float *faces, hipStream_
 int rtm_step_halo_pack(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv,
                        const float *kappa, float *faces, hipStream_t stream);
 
+/* Phases 1 and 2 of a step with the previous step's phase 5 (section II) folded in: the result of
+ * rtm_unpack_halo(u_cur, recv) followed by rtm_step_halo_pack, bitwise (u_nxt's halo-region cells
+ * and `faces`), except that u_cur's ghost ring is neither written nor read: the halo call loads
+ * each ghost cell it needs from its receive slot.  recv[f] (device) is the receive slot of ghost
+ * face f in the layout rtm_unpack_halo reads (what arrived for u_cur's faces); a zero-filled slot
+ * stands for a physical boundary.  rtm_step_interior reads no ghost cell, so a step built on this
+ * call needs no unpack pass; code that reads u_cur's ghost ring afterwards (rtm_step_whole, the
+ * adjoint and gradient calls) must unpack first.  Requires radius 4 with the vectorised layout,
+ * nx % 4 == 0, six non-NULL 16-byte aligned slots and a 16-byte aligned `faces`: RTM_EINVAL
+ * otherwise.  `faces` must not overlap any field, and no slot may overlap `faces` or u_nxt
+ * (RTM_EALIAS): an exchange that hands one step's face buffer to the next step as its receive slots
+ * alternates between two face buffers. */
+int rtm_step_halo_pack_slots(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv,
+                             const float *kappa, const float *const recv[6], float *faces, hipStream_t stream);
+
 /* For each of the n padded indices idx (int64, device) of owned cells, copy u[idx] into every face
  * slot that holds that cell (as rtm_pack_halo would); indices of cells outside every face, or not
  * owned, are skipped.  Used after injecting sources into face cells of a level packed by

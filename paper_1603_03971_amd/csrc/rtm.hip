@@ -107,9 +107,10 @@ __device__ __forceinline__ float dpp_shl1(float v)
 __device__ __forceinline__ float4 dpp_shr1(float4 v) { return make_float4(dpp_shr1(v.x), dpp_shr1(v.y), dpp_shr1(v.z), dpp_shr1(v.w)); }
 __device__ __forceinline__ float4 dpp_shl1(float4 v) { return make_float4(dpp_shl1(v.x), dpp_shl1(v.y), dpp_shl1(v.z), dpp_shl1(v.w)); }
 
-// Variants of the tiled kernel (template flags): streaming hints on the once-used streams, and the
-// x neighbours of a thread's float4 taken from the adjacent lanes' registers instead of LDS.
-enum { FL_NT = 1, FL_XSHUF = 2 };
+// Variants of the tiled kernel (template flags): streaming hints on the once-used streams, the
+// x neighbours of a thread's float4 taken from the adjacent lanes' registers instead of LDS, and (the
+// radius-4 halo call) the ghost cells of u_cur read from the receive slots instead of the ghost ring.
+enum { FL_NT = 1, FL_XSHUF = 2, FL_SLOTS = 4 };
 __device__ __forceinline__ float el(const float4 &v, int e)
 {
     return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
@@ -213,9 +214,11 @@ struct BoxList {
 
 // Where a halo launch with PACK also writes the face cells it computes: the face buffer and the six
 // slot offsets of rtm_face_layout.
+// With FL_SLOTS, recv[f] is the receive slot of ghost face f (the layout rtm_unpack_halo reads).
 struct PackOut {
     float *faces;
     long long off[6];
+    const float *recv[6];
 };
 
 // kappa g mu for the four cells of a float4, in the order (kappa (gxy gz)) mu, and exactly zero for
@@ -237,11 +240,13 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
 {
     constexpr bool STREAM = (FL & FL_NT) != 0;
     constexpr bool XS = (FL & FL_XSHUF) != 0;
+    constexpr bool GS = (FL & FL_SLOTS) != 0;
     auto ldo = [](const float *p) { return STREAM ? ld4_nt(p) : ld4(p); };   // u_prv / kappa operands
     // OP_ADJOINT: the stencil field is kappa g mu_a, formed here from two loads per ring element (uc =
     // mu_a, rk = kappa) instead of being read from a field written by a separate pass; the ring
     // elements of cells outside the owned block are zero, as the ghosts of such a field would be.
     constexpr bool WR = (OP == OP_ADJOINT);
+    static_assert(!GS || (R == 4 && PACK && !WR), "ghosts from slots: the radius-4 forward halo call only");
     constexpr int NT = BX * BY;
     constexpr int TX = 4 * BX;
     constexpr int TY = BY;
@@ -290,11 +295,54 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
     const long long pcl = cload ? pc : p0;
     const long long pca = active ? pc : p0;
 
+    // GS: where a float4 of u_cur at column xx, row yy lives, as a pointer at plane zs and a plane
+    // stride: owned cells in uc, ghost cells in the receive slot of their face, float4s that are
+    // ghosts in both x and y (no active cell reads them) at the tile origin.  With R = 4 and
+    // nx % 4 == 0 no float4 mixes owned and ghost cells.
+    auto where = [&](int xx, int yy, const float *&base, long long &stride) {
+        const long long nx = g.nx, ny = g.ny;
+        const bool xin = xx >= 0 && xx < g.nx, yin = yy >= 0 && yy < g.ny;
+        if (xin && yin) {
+            base = uc + pidx(g, xx, yy, zs);
+            stride = pz;
+        } else if (yin) {           // x ghost: slot 0 or 1, one float4 per row
+            base = (xx < 0 ? po.recv[0] : po.recv[1]) + ((long long)zs * ny + yy) * R;
+            stride = ny * R;
+        } else if (xin) {           // y ghost: slot 2 or 3, R rows per plane
+            base = (yy < 0 ? po.recv[2] + ((long long)zs * R + (yy + R)) * nx
+                           : po.recv[3] + ((long long)zs * R + (yy - g.ny)) * nx) + xx;
+            stride = R * nx;
+        } else {
+            base = uc + p0;
+            stride = pz;
+        }
+    };
+    // GS: the centre column's source on owned planes (cb, cs) and in the z ghost slots (planes -R ..
+    // -1 in slot 4, nz .. nz + R - 1 in slot 5; zst = 0 for a column that is not owned)
+    const float *cb = uc + pcl, *zlo = uc + p0, *zhi = uc + p0;
+    long long cs = pz, zst = 0;
+    if constexpr (GS) {
+        if (cload) where(x, y, cb, cs);
+        if (cload && x < g.nx && y < g.ny) {
+            const long long o = (long long)y * g.nx + x;
+            zlo = po.recv[4] + o;
+            zhi = po.recv[5] + o;
+            zst = (long long)g.nx * g.ny;
+        }
+    }
+    auto ldc = [&](int p) -> float4 {       // GS: centre column at plane p (uniform over the block)
+        if (p < 0) return ld4(zlo + (long long)(p + R) * zst);
+        if (p >= g.nz) return ld4(zhi + (long long)(p - g.nz) * zst);
+        return ld4(cb + (long long)(p - zs) * cs);
+    };
+
     // halo items owned by this thread: global offset at plane zs and LDS slot (row, float4 column)
     long long hoff[HPT];
     int hrow[HPT], hcol[HPT];
     bool hok[HPT];
     int hxx[HPT], hyy[HPT];
+    const float *hb[HPT];                   // GS: the item's source at plane zs and its plane stride
+    long long hs[HPT];
 #pragma unroll
     for (int h = 0; h < HPT; ++h) {
         const int t = tid + h * NT;
@@ -326,6 +374,10 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
             hxx[h] = xx;
             hyy[h] = row;
         }
+        hb[h] = uc + hoff[h];
+        hs[h] = pz;
+        if constexpr (GS)
+            if (hok[h]) where(hxx[h], hyy[h], hb[h], hs[h]);
     }
     // WR: the x-y sponge factors of each halo item's four cells and which of them are owned cells
     float hg[HPT][4];
@@ -378,6 +430,9 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
         qm = ld4(uc + pcl + (long long)R * pz);
         qk = ld4(rk + pcl + (long long)R * pz);
         q[2 * R] = zero4;
+    } else if constexpr (GS) {
+#pragma unroll
+        for (int m = 0; m < 2 * R + 1; ++m) q[m] = ldc(zs - R + m);
     } else {
 #pragma unroll
         for (int m = 0; m < 2 * R + 1; ++m) q[m] = ld4(uc + pcl + (long long)(m - R) * pz);
@@ -396,6 +451,10 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
             }
             const long long o = pcl + (long long)d * pz;
             lds[d][R + ly][1 + lx] = weight4(ld4(uc + o), ld4(rk + o), gxy, gz, cin & zm);
+        } else if constexpr (GS) {
+#pragma unroll
+            for (int h = 0; h < HPT; ++h) hv[h] = ld4(hb[h] + (long long)d * hs[h]);
+            lds[d][R + ly][1 + lx] = ld4(cb + (long long)d * cs);
         } else {
 #pragma unroll
             for (int h = 0; h < HPT; ++h) hv[h] = ld4(uc + hoff[h] + (long long)d * pz);
@@ -409,7 +468,10 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
     float4 hv[HPT], hk[HPT];
 #pragma unroll
     for (int h = 0; h < HPT; ++h) {
-        hv[h] = ld4(uc + hoff[h] + (long long)R * pz);
+        if constexpr (GS)   // a chunk shorter than R + 1 planes never stages this plane: clamped into it
+            hv[h] = ld4(hb[h] + (long long)(min(zs + R, ze - 1) - zs) * hs[h]);
+        else
+            hv[h] = ld4(uc + hoff[h] + (long long)R * pz);
         if constexpr (WR) hk[h] = ld4(rk + hoff[h] + (long long)R * pz);
     }
     // operands of plane k (u_prv, kappa and the z sponge factor) arrive one plane ahead, in the same
@@ -469,6 +531,10 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
                     hv[h] = ld4(uc + hoff[h] + kh * pz);
                     hk[h] = ld4(rk + hoff[h] + kh * pz);
                 }
+            } else if constexpr (GS) {
+                q[(s + 2 * R + 1) % QR] = ldc(zs + (int)kn + R);
+#pragma unroll
+                for (int h = 0; h < HPT; ++h) hv[h] = ld4(hb[h] + kh * hs[h]);
             } else {
                 q[(s + 2 * R + 1) % QR] = ld4(uc + pcl + (kn + R) * pz);
 #pragma unroll
@@ -1330,10 +1396,20 @@ int launch_tiled_flags(int var, const Geo &g, float *un, const float *uc, const 
 template <int R, int OP, bool PACK = false>
 int launch_tiled_variant(int var, const Geo &g, float *un, const float *uc, const float *up, const float *kap,
                          const int (*boxes)[6], int nbox, hipStream_t st, const PackOut *po = nullptr,
-                         const float *rk = nullptr)
+                         const float *rk = nullptr, bool slots = false)
 {
-    // kernel flags: streaming hints for every operation; lane shifts for the radius-4 forward update
+    // kernel flags: streaming hints for every operation; lane shifts for the radius-4 forward update;
+    // ghosts from the receive slots for the radius-4 halo call that packs
     const int fl = g_opt.tile_flags.load(std::memory_order_relaxed);
+    if constexpr (R == 4 && OP == OP_FORWARD && PACK) {
+        if (slots) {
+            if (fl & FL_NT)
+                return launch_tiled_flags<R, OP, PACK, FL_NT | FL_SLOTS>(var, g, un, uc, up, kap, boxes, nbox, st, po,
+                                                                         rk);
+            return launch_tiled_flags<R, OP, PACK, FL_SLOTS>(var, g, un, uc, up, kap, boxes, nbox, st, po, rk);
+        }
+    }
+    if (slots) return RTM_EINVAL;
     if constexpr (R == 4 && OP == OP_FORWARD && !PACK) {
         switch (fl) {
         case FL_NT: return launch_tiled_flags<R, OP, PACK, FL_NT>(var, g, un, uc, up, kap, boxes, nbox, st, po, rk);
@@ -1419,15 +1495,16 @@ int launch_halo(const Geo &g, float *un, const float *uc, const float *up, const
     return RTM_OK;
 }
 
-// The halo call that also writes the six faces (radius 4, float4 layout; see rtm_step_halo_pack).
+// The halo call that also writes the six faces (radius 4, float4 layout; see rtm_step_halo_pack);
+// with `slots`, it reads the ghosts of u_cur from po.recv (rtm_step_halo_pack_slots).
 int launch_halo_pack(const Geo &g, float *un, const float *uc, const float *up, const float *kap, const PackOut &po,
-                     hipStream_t st)
+                     hipStream_t st, bool slots = false)
 {
     const Region r = halo_region(g.nx, g.ny, 4);
     int boxes[6][6];
     const int nb = halo_boxes(g, r, boxes);
     return launch_tiled_variant<4, OP_FORWARD, true>(g_opt.halo_variant.load(std::memory_order_relaxed), g, un, uc,
-                                                     up, kap, boxes, nb, st, &po);
+                                                     up, kap, boxes, nb, st, &po, nullptr, slots);
 }
 
 template <int R, int OP = OP_FORWARD>
@@ -1755,6 +1832,7 @@ int rtm_step_halo_pack(const rtm_grid *grid, float *u_nxt, const float *u_cur, c
     const Geo g = make_geo(grid);
     if (g.R == 4 && vector_path(g, u_nxt, u_cur, u_prv, kappa) && faces_vec(g, u_nxt) && aligned16(faces)) {
         PackOut po;
+        std::memset(&po, 0, sizeof(po));
         po.faces = faces;
         for (int f = 0; f < 6; ++f) po.off[f] = off[f];
         return launch_halo_pack(g, u_nxt, u_cur, u_prv, kappa, po, stream);
@@ -1762,6 +1840,38 @@ int rtm_step_halo_pack(const rtm_grid *grid, float *u_nxt, const float *u_cur, c
     st = rtm_step_halo(grid, u_nxt, u_cur, u_prv, kappa, stream);
     if (st != RTM_OK) return st;
     return rtm_pack_halo(grid, u_nxt, faces, stream);
+}
+
+int rtm_step_halo_pack_slots(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv,
+                             const float *kappa, const float *const recv[6], float *faces, hipStream_t stream)
+{
+    int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (!faces || !recv) return RTM_EINVAL;
+    for (int f = 0; f < 6; ++f)
+        if (!recv[f] || !aligned16(recv[f])) return RTM_EINVAL;
+    long long off[7];
+    fill_face_offsets(grid, off);
+    const long long tot = padded_total(grid);
+    if (ranges_overlap(faces, off[6], u_nxt, tot) || ranges_overlap(faces, off[6], u_cur, tot) ||
+        ranges_overlap(faces, off[6], u_prv, tot) || ranges_overlap(faces, off[6], kappa, tot))
+        return RTM_EALIAS;
+    for (int f = 0; f < 6; ++f)   // what this call writes must not be what it reads
+        if (ranges_overlap(recv[f], off[f + 1] - off[f], faces, off[6]) ||
+            ranges_overlap(recv[f], off[f + 1] - off[f], u_nxt, tot))
+            return RTM_EALIAS;
+    const Geo g = make_geo(grid);
+    if (!(g.R == 4 && vector_path(g, u_nxt, u_cur, u_prv, kappa) && faces_vec(g, u_nxt) && aligned16(faces)))
+        return RTM_EINVAL;
+    st = step_common(grid, u_nxt, u_cur, u_prv, kappa);
+    if (st != RTM_OK) return st;
+    PackOut po;
+    po.faces = faces;
+    for (int f = 0; f < 6; ++f) {
+        po.off[f] = off[f];
+        po.recv[f] = recv[f];
+    }
+    return launch_halo_pack(g, u_nxt, u_cur, u_prv, kappa, po, stream, true);
 }
 
 int rtm_pack_cells(const rtm_grid *grid, const float *u, const int64_t *idx, int32_t n, float *faces,

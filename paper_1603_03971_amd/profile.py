@@ -77,12 +77,13 @@ def run_interior(n: int, launches: int, call: str = "interior"):
     g.owned(u).normal_()
     g.owned(up).normal_()
     s = torch.cuda.current_stream()
-    faces = g.faces()
+    faces, recv = g.faces(), g.faces()
+    slots = g.face_slots(recv)
     for _ in range(launches):
         if call == "interior":
             _abi.rtm_step_interior(g.c, up, u, up, kap, s)
-        else:                                  # the serial schedule's halo call, which also packs
-            _abi.rtm_step_halo_pack(g.c, up, u, up, kap, faces, s)
+        else:                                  # the benchmark's halo call: ghosts from the slots, packs
+            _abi.rtm_step_halo_pack_slots(g.c, up, u, up, kap, slots, faces, s)
     a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     b.copy_(a)
@@ -102,11 +103,13 @@ def kernel_table(n: int):
     faces = 6 * 4 * n * n
     return {
         "interior": ("k_tiled<4, 16, 8, 0, false", 16 * interior, "16 B per interior cell"),
-        "halo_pack": ("k_tiled<4, 16, 16, 0, true", 16 * halo + 4 * faces, "16 B per halo cell + 4 B per face cell"),
-        "whole": ("k_tiled<4, 32, 16, 0, false", 16 * cells, "16 B per cell (also the scaled adjoint step)"),
-        "adjoint_direct": ("k_tiled<4, 16, 16, 1, false", 16 * cells, "16 B per cell: mu_a, kappa, mu_b in, mu out"),
-        "gradient": ("k_tiled<4, 32, 16, 2, false", 16 * cells, "16 B per cell: u, mu, grad in, grad out"),
-        "gradient_scaled": ("k_tiled<4, 32, 16, 3, false", 16 * cells, "16 B per cell: u, w, grad in, grad out"),
+        "halo_pack": ("k_tiled<4, 16, 16, 0, true, 1>", 16 * halo + 4 * faces, "16 B per halo cell + 4 B per face cell"),
+        "halo_pack_slots": ("k_tiled<4, 16, 16, 0, true, 5>", 16 * halo + 8 * faces,
+                            "16 B per halo cell + 4 B per face cell out + 4 B per ghost cell in"),
+        "whole": ("k_tiled<4, 32, 8, 0, false", 16 * cells, "16 B per cell (also the scaled adjoint step)"),
+        "adjoint_direct": ("k_tiled<4, 32, 8, 1, false", 16 * cells, "16 B per cell: mu_a, kappa, mu_b in, mu out"),
+        "gradient": ("k_tiled<4, 32, 8, 2, false", 16 * cells, "16 B per cell: u, mu, grad in, grad out"),
+        "gradient_scaled": ("k_tiled<4, 32, 8, 3, false", 16 * cells, "16 B per cell: u, w, grad in, grad out"),
         "unpack": ("k_unpack_lines", 8 * faces, "8 B per face cell: slot in, ghost out"),
         "image": ("k_image<true", 16 * cells, "16 B per cell: S, R, I in, I out"),
         "absmax": ("k_plane_absmax<true>", 4 * cells, "4 B per cell"),
@@ -141,6 +144,7 @@ def run_kernels(n: int, launches: int):
     calls = {
         "interior": lambda: _abi.rtm_step_interior(g.c, c, a, b, kap, s),
         "halo_pack": lambda: _abi.rtm_step_halo_pack(g.c, c, a, b, kap, send, s),
+        "halo_pack_slots": lambda: _abi.rtm_step_halo_pack_slots(g.c, c, a, b, kap, slots, send, s),
         "whole": lambda: _abi.rtm_step_whole(g.c, c, a, b, kap, s),
         "adjoint_direct": lambda: _abi.rtm_adjoint_step(g.c, c, a, b, kap, work, s),
         "gradient": lambda: _abi.rtm_gradient_accumulate(g.c, c, a, b, s),
@@ -241,7 +245,7 @@ def run_corrected(n: int, steps: int, every: int):
 
 
 # The radius-4 tiled kernels under the default options: the interior call's (16 x 8-thread tiles),
-# the halo call's (16 x 16) and the one-launch whole step's (32 x 16).
+# the halo call's (16 x 16) and the one-launch whole step's (32 x 8).
 # (name prefixes: the demangled names go on with the kernel's last template argument, e.g. ", false>")
 INTERIOR_KERNEL = "k_tiled<4, 16, 8, 0, false"
 HALO_KERNEL = "k_tiled<4, 16, 16, 0, true"
@@ -496,25 +500,28 @@ def summarize_halo(fetch_dir, write_dir, out, n, commands, stats_dir=None):
     kw = COPY_BYTES / (w_cp * 1024.0)
     rd, wt = f_h * 1024.0 * kf, w_h * 1024.0 * kw
     pts = n**3 - (n - 128) * (n - 32) * (n - 8)
-    fc = 6 * 4 * n * n                         # face cells the call also writes
+    fc = 6 * 4 * n * n                         # face cells the call also writes, ghost cells it reads
+    alg_r = 12 * pts + 4 * fc
     alg_w = 4 * (pts + fc)
     lines = [f"# rocprofv3 summary: HBM traffic of the halo call, {n}^3 layered forward workload", "",
              "Commands:"] + [f"    {c}" for c in commands] + [""]
-    lines += ["Halo call as the serial schedule runs it (rtm_step_halo_pack: two 4-plane z slabs, two 16-row",
-              "y strips, two 64-column x strips, and the six 4-wide faces written to the face buffer):",
-              f"    cells {pts} (the interior call's box is the rest), face cells {fc}",
+    lines += ["Halo call as the benchmark's serial schedule runs it (rtm_step_halo_pack_slots: two 4-plane z",
+              "slabs, two 16-row y strips, two 64-column x strips; the ghosts read from six receive slots,",
+              "the six 4-wide faces written to the face buffer):",
+              f"    cells {pts} (the interior call's box is the rest), face cells {fc} (as many ghost cells)",
               f"    FETCH_SIZE {f_h:.0f} KiB ({nf} dispatches), WRITE_SIZE {w_h:.0f} KiB ({nw} dispatches)",
               f"    calibration with a plain 1 GiB device copy: FETCH x {kf:.3f}, WRITE x {kw:.3f}",
-              f"    read {rd / 1e6:.1f} MB against 12 B x cells = {12 * pts / 1e6:.1f} MB (ratio {rd / (12 * pts):.3f})",
+              f"    read {rd / 1e6:.1f} MB against 12 B x cells + 4 B x ghost cells = {alg_r / 1e6:.1f} MB "
+              f"(ratio {rd / alg_r:.3f})",
               f"    written {wt / 1e6:.1f} MB against 4 B x (cells + face cells) = {alg_w / 1e6:.1f} MB "
               f"(ratio {wt / alg_w:.3f})",
-              f"    total {(rd + wt) / 1e6:.1f} MB per launch, {(rd + wt) / (12 * pts + alg_w):.3f} x algorithmic"]
+              f"    total {(rd + wt) / 1e6:.1f} MB per launch, {(rd + wt) / (alg_r + alg_w):.3f} x algorithmic"]
     if stats_dir:
         for r in _csv(stats_dir, "*kernel_stats.csv"):
             if HALO_KERNEL in r["Name"]:
                 us = float(r["AverageNs"]) / 1e3
                 lines.append(f"    kernel trace of the benchmark run: {us:.1f} us per launch -> "
-                             f"{(12 * pts + alg_w) / us / 1e6:.2f} TB/s algorithmic, "
+                             f"{(alg_r + alg_w) / us / 1e6:.2f} TB/s algorithmic, "
                              f"{(rd + wt) / us / 1e6:.2f} TB/s moved")
                 break
     text = "\n".join(lines) + "\n"

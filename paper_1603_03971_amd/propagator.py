@@ -16,7 +16,14 @@ u^{n-1} in place (two buffers), and a level that must outlive the rotation (an R
 "pinned" so that the next write goes to a fresh buffer instead of copying it.
 
 The "serial" schedule runs the same phases on one stream (the halo call that packs, shell sources,
-interior call, interior sources, unpack, record); both give bitwise identical fields.  The
+interior call, interior sources, unpack, record); both give bitwise identical fields.
+
+With ghosts="slots" (serial and overlap schedules, radius 4, nx % 4 == 0) the unpack pass goes away:
+the ghosts of level n stay in the receive slots that the exchange filled, and step n's halo call reads
+them there (rtm_step_halo_pack_slots); the interior call reads no ghost cell.  The level buffers'
+ghost rings are then not kept (fill_ghosts() writes the newest level's from its slots), and the face
+buffer alternates between two buffers, since step n + 1 packs while a periodic exchange still has
+step n's faces in use as its receive slots.  Same bits as ghosts="ring".  The
 "fused" schedule, for one subdomain with nothing to overlap, updates every owned cell in one launch
 (rtm_step_whole) instead of the halo and interior calls, then injects, refreshes the ghosts and
 records on one stream; it too is bitwise identical.  With no face received (the physical boundary),
@@ -111,7 +118,7 @@ class Sources:
 class Propagator:
     def __init__(self, grid: Grid, kappa: torch.Tensor, *, sources: Sources | list | None = None,
                  receivers=None, boundary: str = "zero", schedule: str = "overlap", debug: bool = False,
-                 check_every: int = 0, unpack_aside: bool = False):
+                 check_every: int = 0, unpack_aside: bool = False, ghosts: str = "ring"):
         """unpack_aside (serial schedule): the unpack runs on a second stream as soon as the halo call
         and the shell sources are done, concurrently with the interior call (it writes ghost cells
         only, the interior call owned cells only); the next step waits for it.  Same bits.
@@ -151,20 +158,37 @@ class Propagator:
         self._mark_zero_ghosts(self.u_cur)
         self.pinned: set[int] = set()
         self.pool: list[torch.Tensor] = []
+        if ghosts not in ("ring", "slots"):
+            raise ValueError(ghosts)
+        self.ghosts = ghosts
+        if ghosts == "slots":
+            if schedule == "fused" or unpack_aside:
+                raise ValueError("ghosts='slots' is for the serial and overlap schedules (no unpack pass)")
+            if grid.radius != 4 or grid.nx % 4:
+                raise ValueError("ghosts='slots' needs radius 4 and nx % 4 == 0")
         self.send = grid.faces()
+        # ghosts="slots": step n packs into send_bufs[n % 2]
+        self.send_bufs = [self.send, grid.faces()] if ghosts == "slots" else [self.send]
         slots = grid.face_slots(self.send)
         # what face f of each new level receives: NULL slots for the physical boundary (the unpack
         # writes zero ghosts and reads nothing); "zero_faces": the same zeros received through six
         # real slots of a zero-filled receive buffer, as a subdomain whose neighbours all sent zero
         # faces (the unpack reads them); "periodic": the opposite face's send slot (a pointer swap)
         self.recv_buf = None
-        if boundary == "zero":
+        if boundary == "zero" and ghosts == "slots":
+            self.recv_buf = grid.faces()        # the physical boundary's zeros, read by the halo call
+            self.recv = grid.face_slots(self.recv_buf)
+        elif boundary == "zero":
             self.recv = [None] * 6
         elif boundary == "zero_faces":
             self.recv_buf = grid.faces()
             self.recv = grid.face_slots(self.recv_buf)
         else:
             self.recv = [slots[OPPOSITE[f]] for f in range(6)]
+        # ghosts="slots", periodic: the receive slots of a level made by a step that packed into
+        # send_bufs[b] (a pointer swap, as above)
+        self._recv_periodic = [[self.grid.face_slots(b)[OPPOSITE[f]].data_ptr() for f in range(6)]
+                               for b in self.send_bufs]
         self.n = 0
         self.sH = torch.cuda.Stream(device=grid.device)
         self.sI = torch.cuda.Stream(device=grid.device)
@@ -192,12 +216,34 @@ class Propagator:
         self.exchange_ghosts(self.u_cur)
 
     def exchange_ghosts(self, u: torch.Tensor, stream=None):
-        """Pack, exchange and unpack the faces of an existing level (used to prime u^0)."""
+        """Pack, exchange and unpack the faces of an existing level (used to prime u^0).  With
+        ghosts="slots", u must be the newest level: its faces are packed where the next step's halo
+        call reads them, and its ghost ring is written from there too."""
         st = stream if stream is not None else torch.cuda.current_stream()
+        if self.ghosts == "slots":
+            _abi.rtm_pack_halo(self.grid.c, u, self.send_bufs[(self.n - 1) % 2], st)
+            _abi.rtm_unpack_halo(self.grid.c, u, self._recv_for(self.n), st)
+            return
         _abi.rtm_pack_halo(self.grid.c, u, self.send, st)
         _abi.rtm_unpack_halo(self.grid.c, u, self.recv, st)
         if all(r is None for r in self.recv):
             self._mark_zero_ghosts(u)
+
+    def _recv_for(self, m: int):
+        """ghosts="slots": the six receive slots that hold level m's ghost faces (the faces packed by
+        the step that made level m, or by exchange_ghosts)."""
+        if self.boundary != "periodic":
+            return self.recv
+        return self._recv_periodic[(m - 1) % 2]
+
+    def fill_ghosts(self, stream=None):
+        """Write the newest level's ghost ring (kept in the receive slots with ghosts="slots", for code
+        that reads the ring: rtm_step_whole, the adjoint and gradient calls); a no-op otherwise."""
+        if self.ghosts != "slots":
+            return
+        self.sync()
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _abi.rtm_unpack_halo(self.grid.c, self.u_cur, self._recv_for(self.n), st)
 
     def _mark_zero_ghosts(self, u: torch.Tensor):
         self._zero_ghosts[u.data_ptr()] = weakref.ref(u)
@@ -222,6 +268,9 @@ class Propagator:
         self.sync()
         self._zero_ghosts.pop(u_prv.data_ptr(), None)     # its ghosts are the caller's: refreshed on reuse
         self.u_cur, self.u_prv, self.n = u_cur, u_prv, n
+        if self.ghosts == "slots" and self.boundary == "periodic":
+            # the next halo call reads u^n's ghosts from the slots: the faces they are copies of
+            _abi.rtm_pack_halo(self.grid.c, u_cur, self.send_bufs[(n - 1) % 2], torch.cuda.current_stream())
 
     def unpin(self, t: torch.Tensor, recycle: bool = True):
         self.pinned.discard(t.data_ptr())
@@ -253,6 +302,9 @@ class Propagator:
         u_nxt = self._next_buffer()
         u_cur, u_prv, kap = self.u_cur, self.u_prv, self.kappa
         n = self.n
+        slots = self.ghosts == "slots"
+        if slots:
+            self.send = self.send_bufs[n % 2]
         tr_ptr = None if traces is None or self.nrec == 0 else traces.data_ptr() + 4 * n * self.nrec
         if self.schedule == "fused":
             st = torch.cuda.current_stream()
@@ -280,7 +332,10 @@ class Propagator:
             if self._ev_unpack is not None:
                 st.wait_event(self._ev_unpack)          # the ghosts of u^n are complete
                 self._ev_unpack = None
-            _abi.rtm_step_halo_pack(c, u_nxt, u_cur, u_prv, kap, self.send, st)
+            if slots:
+                _abi.rtm_step_halo_pack_slots(c, u_nxt, u_cur, u_prv, kap, self._recv_for(n), self.send, st)
+            else:
+                _abi.rtm_step_halo_pack(c, u_nxt, u_cur, u_prv, kap, self.send, st)
             for s in self.sources:
                 s.inject(g, u_nxt, n, 0, st)
                 s.repack(g, u_nxt, n, self.send, st)
@@ -301,7 +356,7 @@ class Propagator:
                 _abi.rtm_step_interior(c, u_nxt, u_cur, u_prv, kap, st)
             for s in self.sources:
                 s.inject(g, u_nxt, n, 1, st)
-            if not self.unpack_aside:
+            if not self.unpack_aside and not slots:
                 _abi.rtm_unpack_halo(c, u_nxt, self.recv, st)
             if tr_ptr is not None:
                 _abi.rtm_record(c, u_nxt, self.rec_idx, tr_ptr, self.nrec, st)
@@ -314,13 +369,17 @@ class Propagator:
             else:
                 sH.wait_stream(torch.cuda.current_stream())
                 sI.wait_stream(torch.cuda.current_stream())
-            _abi.rtm_step_halo_pack(c, u_nxt, u_cur, u_prv, kap, self.send, sH)
+            if slots:
+                _abi.rtm_step_halo_pack_slots(c, u_nxt, u_cur, u_prv, kap, self._recv_for(n), self.send, sH)
+            else:
+                _abi.rtm_step_halo_pack(c, u_nxt, u_cur, u_prv, kap, self.send, sH)
             for s in self.sources:
                 s.inject(g, u_nxt, n, 0, sH)
                 s.repack(g, u_nxt, n, self.send, sH)
             ev_halo = torch.cuda.Event()
             ev_halo.record(sH)
-            _abi.rtm_unpack_halo(c, u_nxt, self.recv, sH)
+            if not slots:
+                _abi.rtm_unpack_halo(c, u_nxt, self.recv, sH)
             if self.interior_events is not None:
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(sI)

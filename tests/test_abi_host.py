@@ -80,6 +80,22 @@ def test_validation_before_device(abi):
     assert L.rtm_step_halo_pack(gp, 4096, 1 << 36, 1 << 37, 1 << 38, None, None) == abi.RTM_EINVAL
     assert L.rtm_step_halo_pack(gp, 4096, 1 << 36, 1 << 37, 1 << 38, 4096 + 4 * total - 64, None) == abi.RTM_EALIAS
     assert L.rtm_step_halo_pack(gp, None, 1 << 36, 1 << 37, 1 << 38, 1 << 39, None) == abi.RTM_EINVAL
+    # the halo call that reads u_cur's ghosts from six receive slots
+    slots = (ctypes.c_void_p * 6)(*[(1 << 40) + 4096 * f for f in range(6)])
+    one_null = (ctypes.c_void_p * 6)(*([1 << 40] * 5 + [None]))
+    odd = (ctypes.c_void_p * 6)(*([1 << 40] * 5 + [(1 << 40) + 8]))              # not 16-byte aligned
+    hps = L.rtm_step_halo_pack_slots
+    assert hps(gp, 4096, 1 << 36, 1 << 37, 1 << 38, one_null, 1 << 39, None) == abi.RTM_EINVAL
+    assert hps(gp, 4096, 1 << 36, 1 << 37, 1 << 38, odd, 1 << 39, None) == abi.RTM_EINVAL
+    assert hps(gp, 4096, 1 << 36, 1 << 37, 1 << 38, None, 1 << 39, None) == abi.RTM_EINVAL
+    assert hps(gp, 4096, 1 << 36, 1 << 37, 1 << 38, slots, None, None) == abi.RTM_EINVAL
+    assert hps(gp, 4096, 1 << 36, 1 << 37, 1 << 38, slots, (1 << 40) + 8192, None) == abi.RTM_EALIAS  # slot 2
+    assert hps(gp, (1 << 40) + 4096 * 5, 1 << 36, 1 << 37, 1 << 38, slots, 1 << 39, None) == abi.RTM_EALIAS
+    assert hps(gp, 4096, 1 << 36, 1 << 37, 1 << 38, slots, 4096 + 64, None) == abi.RTM_EALIAS   # faces over u_nxt
+    g2 = _grid(abi, radius=2)
+    assert hps(ctypes.byref(g2), 4096, 1 << 36, 1 << 37, 1 << 38, slots, 1 << 39, None) == abi.RTM_EINVAL
+    g3 = _grid(abi, nx=18, pitch_y=28)                                                  # nx % 4 != 0
+    assert hps(ctypes.byref(g3), 4096, 1 << 36, 1 << 37, 1 << 38, slots, 1 << 39, None) == abi.RTM_EINVAL
     assert L.rtm_pack_cells(gp, 4096, 64, -1, 1 << 39, None) == abi.RTM_EINVAL
     assert L.rtm_pack_cells(gp, 4096, 64, 0, 1 << 39, None) == abi.RTM_OK             # nothing to do
     assert L.rtm_pack_cells(gp, 4096, 64, 3, None, None) == abi.RTM_EINVAL

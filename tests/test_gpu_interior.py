@@ -57,11 +57,13 @@ def test_wide_box_exercises_full_interior_tiles(wide_case):
     assert inner >= 0.3 * np.max(np.abs(ref))       # the wavefield is really there
 
 
-@pytest.mark.parametrize("schedule", ["serial", "overlap", "fused"])
+@pytest.mark.parametrize("schedule", ["serial", "overlap", "fused", "serial-slots", "overlap-slots"])
 def test_wide_box_parity(wide_case, schedule):
+    """-slots: the steps with no unpack pass, whose halo calls read the ghosts from the receive slots."""
     v, src, rec, nsteps, ref = wide_case
     _say(f"wide {schedule}: gpu")
-    gpu = problems.gpu_forward_problem(v, 10.0, nsteps, src, rec_ijk=rec, schedule=schedule)
+    sched, _, ghosts = schedule.partition("-")
+    gpu = problems.gpu_forward_problem(v, 10.0, nsteps, src, rec_ijk=rec, schedule=sched, ghosts=ghosts or "ring")
     e_u = problems.rel_l2(gpu["u_cur"], ref["u_cur"])
     e_p = problems.rel_l2(gpu["u_prv"], ref["u_prv"])
     e_t = problems.rel_l2(gpu["traces"], ref["traces"])

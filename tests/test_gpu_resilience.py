@@ -59,8 +59,9 @@ def test_stable_run_is_not_flagged():
     assert prop.n == 800
 
 
-@pytest.mark.parametrize("schedule", ["serial", "fused"])
+@pytest.mark.parametrize("schedule", ["serial", "fused", "serial-slots"])
 def test_kill_and_resume_is_bitwise(tmp_path, schedule):
+    """-slots: ghosts read from the receive slots; the resumed run primes them from the saved level."""
     import torch
 
     from paper_1603_03971_amd.grid import Grid
@@ -78,7 +79,9 @@ def test_kill_and_resume_is_bitwise(tmp_path, schedule):
     rec = [(10, 10, 3), (70, 35, 39)]
 
     def fresh():
-        return Propagator(g, kap, sources=Sources(g, src_ijk, w, amp), receivers=rec, schedule=schedule)
+        sched, _, ghosts = schedule.partition("-")
+        return Propagator(g, kap, sources=Sources(g, src_ijk, w, amp), receivers=rec, schedule=sched,
+                          ghosts=ghosts or "ring")
 
     ref = fresh()
     tr_ref = ref.new_traces(nsteps)

@@ -123,7 +123,7 @@ const char *rtm_strerror(int status);
  *                             for the halo call chunks of 12 planes; at radius 2 chunks of 16 planes.
  *   RTM_OPT_XCD_REMAP         1 = give each XCD a contiguous range of tiles (default), 0 = hardware order.
  *   RTM_OPT_HALO_X_WIDTH      width of the halo region's x strips (default 64 = one tile);
- *   RTM_OPT_HALO_Y_WIDTH      height of its y strips (default 16); see rtm_halo_region.
+ *   RTM_OPT_HALO_Y_WIDTH      height of its y strips (default 8); see rtm_halo_region.
  *   RTM_OPT_UNPACK_LINES      1 = (default) where the layout puts a row's +X ghost, its padding and the
  *                             next row's -X ghost in one 128-byte line (radius 4, nx % 32 == 0,
  *                             pitch_y = nx + 32, owned (0,0,0) line-aligned), rtm_unpack_halo writes the

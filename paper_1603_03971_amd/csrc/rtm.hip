@@ -1198,7 +1198,9 @@ struct Options {
     std::atomic<int> zchunk{0};            // 0: automatic
     std::atomic<int> xcd_remap{1};
     std::atomic<int> halo_x_width{64};     // x strips of the halo region
-    std::atomic<int> halo_y_width{16};     // y strips of the halo region
+    std::atomic<int> halo_y_width{8};      // y strips of the halo region (8 rows: the 512^3 interior box
+                                           // is 62 rows of 16x8 tiles, 744 workgroups in 2 chunks on 256
+                                           // CUs; 16 rows gave 720, and a 1% slower step)
     std::atomic<int> halo_variant{0};      // tile shape of the halo call (as interior_variant; 5: 16x32)
     std::atomic<int> unpack_lines{1};      // 1: x-face ghosts unpacked as whole lines where the layout allows
     std::atomic<int> tile_flags{FL_NT};    // FL_NT (streaming hints, default) | FL_XSHUF (lane shifts)

@@ -96,9 +96,15 @@ def run_interior(n: int, launches: int, call: str = "interior"):
 # The hot kernels of the forward, RTM and gradient paths, each launched `launches` times on the n^3
 # layered workload (radius 4, line-aligned fields), for counter runs: name -> (kernel-name substring,
 # algorithmic bytes per launch as a function of n, what the bytes are).
+def interior_cells(n: int) -> int:
+    """Cells of the interior call's box on an n^3 grid under the default halo region (64-column x
+    strips, 8-row y strips, 4-plane z slabs)."""
+    return (n - 2 * 64) * (n - 2 * 8) * (n - 8)
+
+
 def kernel_table(n: int):
     cells = n ** 3
-    interior = (n - 128) * (n - 32) * (n - 8)
+    interior = interior_cells(n)
     halo = cells - interior
     faces = 6 * 4 * n * n
     return {
@@ -472,7 +478,7 @@ def summarize(stats_dir, fetch_dir, write_dir, out, n, commands):
         kf = COPY_BYTES / (f_cp * 1024.0)
         kw = COPY_BYTES / (w_cp * 1024.0)
         traffic = f_int * 1024.0 * kf + w_int * 1024.0 * kw
-        pts = (n - 128) * (n - 32) * (n - 8)
+        pts = interior_cells(n)
         lines += ["", "HBM traffic of the interior stencil launch (counters, KiB per dispatch):",
                   f"    FETCH_SIZE {f_int:.0f} KiB ({nf} dispatches), WRITE_SIZE {w_int:.0f} KiB ({nw} dispatches)",
                   f"    calibration with a plain 1 GiB device copy: FETCH x {kf:.3f}, WRITE x {kw:.3f}",
@@ -499,14 +505,14 @@ def summarize_halo(fetch_dir, write_dir, out, n, commands, stats_dir=None):
     kf = COPY_BYTES / (f_cp * 1024.0)
     kw = COPY_BYTES / (w_cp * 1024.0)
     rd, wt = f_h * 1024.0 * kf, w_h * 1024.0 * kw
-    pts = n**3 - (n - 128) * (n - 32) * (n - 8)
+    pts = n**3 - interior_cells(n)
     fc = 6 * 4 * n * n                         # face cells the call also writes, ghost cells it reads
     alg_r = 12 * pts + 4 * fc
     alg_w = 4 * (pts + fc)
     lines = [f"# rocprofv3 summary: HBM traffic of the halo call, {n}^3 layered forward workload", "",
              "Commands:"] + [f"    {c}" for c in commands] + [""]
     lines += ["Halo call as the benchmark's serial schedule runs it (rtm_step_halo_pack_slots: two 4-plane z",
-              "slabs, two 16-row y strips, two 64-column x strips; the ghosts read from six receive slots,",
+              "slabs, two 8-row y strips, two 64-column x strips; the ghosts read from six receive slots,",
               "the six 4-wide faces written to the face buffer):",
               f"    cells {pts} (the interior call's box is the rest), face cells {fc} (as many ghost cells)",
               f"    FETCH_SIZE {f_h:.0f} KiB ({nf} dispatches), WRITE_SIZE {w_h:.0f} KiB ({nw} dispatches)",

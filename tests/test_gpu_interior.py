@@ -1,7 +1,7 @@
 """Parity where the interior call really runs: boxes wide enough that rtm_step_interior has full
 64 x 8 tiles, several z chunks and the XCD remap, checked against the FP64 oracle cell by cell.
 
-The halo region is x strips of 64 columns and y strips of 16 rows (rtm_halo_region), so any box at
+The halo region is x strips of 64 columns and y strips of 8 rows (rtm_halo_region), so any box at
 most 128 cells wide in x leaves the interior call nothing to do; the boxes here are wider.
 """
 import numpy as np

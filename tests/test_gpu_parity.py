@@ -135,8 +135,8 @@ def test_halo_and_interior_partition_owned_cells(torch_cuda):
         own = g.owned(out)
         assert torch.isfinite(own).all(), (nx, ny, nz)
         # the halo call wrote the R-shell widened to x strips of min(64, nx // 2) cells and y strips
-        # of min(16, ny // 2) rows
-        R, wx, hy = 4, max(4, min(64, nx // 2)), max(4, min(16, ny // 2))
+        # of min(8, ny // 2) rows
+        R, wx, hy = 4, max(4, min(64, nx // 2)), max(4, min(8, ny // 2))
         assert _abi.rtm_halo_region(g.c) == (wx, hy, R)
         shell = torch.zeros((nz, ny, nx), dtype=torch.bool, device=out.device)
         shell[:R] = True

@@ -118,12 +118,13 @@ const char *rtm_strerror(int status);
  *                             and 5 (tiles held to 128 registers) as 0.
  *   RTM_OPT_ZCHUNK            z planes per workgroup of the tiled kernels; 0 = automatic: at radius 4,
  *                             for one-box launches (interior, whole step, adjoint, gradient) the
- *                             chunking that balances the work of the busiest CU (a CU counted as
- *                             enough workgroups for about 8 wavefronts) with the fewest workgroups,
- *                             for the halo call chunks of 12 planes; at radius 2 chunks of 16 planes.
+ *                             chunking that balances the work of the busiest CU (counted as at least
+ *                             the workgroups that hold 6 wavefronts) with the fewest workgroups, for
+ *                             the halo call chunks of 12 planes; at radius 2 chunks of 16 planes.
  *   RTM_OPT_XCD_REMAP         1 = give each XCD a contiguous range of tiles (default), 0 = hardware order.
  *   RTM_OPT_HALO_X_WIDTH      width of the halo region's x strips (default 64 = one tile);
- *   RTM_OPT_HALO_Y_WIDTH      height of its y strips (default 8); see rtm_halo_region.
+ *   RTM_OPT_HALO_Y_WIDTH      height of its y strips (default 8);
+ *   RTM_OPT_HALO_Z_WIDTH      depth of its z slabs (default 0 = R); see rtm_halo_region.
  *   RTM_OPT_UNPACK_LINES      1 = (default) where the layout puts a row's +X ghost, its padding and the
  *                             next row's -X ghost in one 128-byte line (radius 4, nx % 32 == 0,
  *                             pitch_y = nx + 32, owned (0,0,0) line-aligned), rtm_unpack_halo writes the
@@ -147,14 +148,16 @@ enum {
     RTM_OPT_WHOLE_VARIANT = 7,
     RTM_OPT_UNPACK_LINES = 8,
     RTM_OPT_TILE_FLAGS = 9,
+    RTM_OPT_HALO_Z_WIDTH = 10,
 };
 int rtm_set_option(int32_t option, int32_t value);
 /* The current value of an option (>= 0), or RTM_EINVAL for an unknown option. */
 int rtm_get_option(int32_t option);
 
-/* The halo region of a grid under the current options: widths = {wx, hy, R} with
- * wx = max(R, min(RTM_OPT_HALO_X_WIDTH, nx / 2)) and hy = max(R, min(RTM_OPT_HALO_Y_WIDTH, ny / 2)).
- * rtm_step_halo updates exactly the owned cells with k < R or k >= nz - R or j < hy or j >= ny - hy
+/* The halo region of a grid under the current options: widths = {wx, hy, hz} with
+ * wx = max(R, min(RTM_OPT_HALO_X_WIDTH, nx / 2)), hy = max(R, min(RTM_OPT_HALO_Y_WIDTH, ny / 2)) and
+ * hz = max(R, min(RTM_OPT_HALO_Z_WIDTH, nz / 2)) (hz = R when that option is 0).
+ * rtm_step_halo updates exactly the owned cells with k < hz or k >= nz - hz or j < hy or j >= ny - hy
  * or i < wx or i >= nx - wx (a superset of the R-shell that neighbours need, widened so that the
  * tiled kernel reads whole cache lines); rtm_step_interior updates the rest.  The region depends
  * only on the grid and the options, never on pointers, so a caller can route each source to the

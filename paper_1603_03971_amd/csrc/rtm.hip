@@ -1198,6 +1198,7 @@ struct Options {
     std::atomic<int> zchunk{0};            // 0: automatic
     std::atomic<int> xcd_remap{1};
     std::atomic<int> halo_x_width{64};     // x strips of the halo region
+    std::atomic<int> halo_z_width{0};      // z slabs of the halo region (0: R planes)
     std::atomic<int> halo_y_width{8};      // y strips of the halo region (8 rows: the 512^3 interior box
                                            // is 62 rows of 16x8 tiles, 744 workgroups in 2 chunks on 256
                                            // CUs; 16 rows gave 720, and a 1% slower step)
@@ -1437,28 +1438,30 @@ int launch_tiled_variant(int var, const Geo &g, float *un, const float *uc, cons
 // x strips between those.  The widths depend only on the grid and the options (never on pointers),
 // so callers can tell which call updates a given cell (rtm_halo_region).
 struct Region {
-    int wx, hy, R;
+    int wx, hy, hz, R;
 };
 
-Region halo_region(int nx, int ny, int R)
+Region halo_region(int nx, int ny, int nz, int R)
 {
     Region r;
     r.R = R;
     r.wx = std::max(R, std::min(g_opt.halo_x_width.load(std::memory_order_relaxed), nx / 2));
     r.hy = std::max(R, std::min(g_opt.halo_y_width.load(std::memory_order_relaxed), ny / 2));
+    const int hz = g_opt.halo_z_width.load(std::memory_order_relaxed);
+    r.hz = hz > 0 ? std::max(R, std::min(hz, nz / 2)) : R;
     return r;
 }
 
 int halo_boxes(const Geo &g, const Region &r, int boxes[6][6])
 {
-    const int nx = g.nx, ny = g.ny, nz = g.nz, R = r.R;
+    const int nx = g.nx, ny = g.ny, nz = g.nz, hz = r.hz;
     const int b[6][6] = {
-        {0, nx, 0, ny, 0, R},                        // -Z slab
-        {0, nx, 0, ny, nz - R, nz},                  // +Z slab
-        {0, nx, 0, r.hy, R, nz - R},                 // -Y strip
-        {0, nx, ny - r.hy, ny, R, nz - R},           // +Y strip
-        {0, r.wx, r.hy, ny - r.hy, R, nz - R},       // -X strip
-        {nx - r.wx, nx, r.hy, ny - r.hy, R, nz - R}, // +X strip
+        {0, nx, 0, ny, 0, hz},                         // -Z slab
+        {0, nx, 0, ny, nz - hz, nz},                   // +Z slab
+        {0, nx, 0, r.hy, hz, nz - hz},                 // -Y strip
+        {0, nx, ny - r.hy, ny, hz, nz - hz},           // +Y strip
+        {0, r.wx, r.hy, ny - r.hy, hz, nz - hz},       // -X strip
+        {nx - r.wx, nx, r.hy, ny - r.hy, hz, nz - hz}, // +X strip
     };
     std::memcpy(boxes, b, sizeof(b));
     return 6;
@@ -1484,7 +1487,7 @@ int launch_box_scalar(const Geo &g, float *un, const float *uc, const float *up,
 template <int R, int OP = OP_FORWARD>
 int launch_halo(const Geo &g, float *un, const float *uc, const float *up, const float *kap, hipStream_t st)
 {
-    const Region r = halo_region(g.nx, g.ny, R);
+    const Region r = halo_region(g.nx, g.ny, g.nz, R);
     int boxes[6][6];
     const int nb = halo_boxes(g, r, boxes);
     if (vector_path(g, un, uc, up, kap))
@@ -1502,7 +1505,7 @@ int launch_halo(const Geo &g, float *un, const float *uc, const float *up, const
 int launch_halo_pack(const Geo &g, float *un, const float *uc, const float *up, const float *kap, const PackOut &po,
                      hipStream_t st, bool slots = false)
 {
-    const Region r = halo_region(g.nx, g.ny, 4);
+    const Region r = halo_region(g.nx, g.ny, g.nz, 4);
     int boxes[6][6];
     const int nb = halo_boxes(g, r, boxes);
     return launch_tiled_variant<4, OP_FORWARD, true>(g_opt.halo_variant.load(std::memory_order_relaxed), g, un, uc,
@@ -1512,8 +1515,8 @@ int launch_halo_pack(const Geo &g, float *un, const float *uc, const float *up, 
 template <int R, int OP = OP_FORWARD>
 int launch_interior(const Geo &g, float *un, const float *uc, const float *up, const float *kap, hipStream_t st)
 {
-    const Region r = halo_region(g.nx, g.ny, R);
-    const int boxes[1][6] = {{r.wx, g.nx - r.wx, r.hy, g.ny - r.hy, R, g.nz - R}};
+    const Region r = halo_region(g.nx, g.ny, g.nz, R);
+    const int boxes[1][6] = {{r.wx, g.nx - r.wx, r.hy, g.ny - r.hy, r.hz, g.nz - r.hz}};
     if (vector_path(g, un, uc, up, kap)) {
         const int var = g_opt.interior_variant.load(std::memory_order_relaxed);
         return launch_tiled_variant<R, OP>(var, g, un, uc, up, kap, boxes, 1, st);
@@ -2030,10 +2033,10 @@ int rtm_halo_region(const rtm_grid *grid, int32_t widths[3])
     const int st = check_grid(grid);
     if (st != RTM_OK) return st;
     if (!widths) return RTM_EINVAL;
-    const Region r = halo_region(grid->nx, grid->ny, grid->radius);
+    const Region r = halo_region(grid->nx, grid->ny, grid->nz, grid->radius);
     widths[0] = r.wx;
     widths[1] = r.hy;
-    widths[2] = r.R;
+    widths[2] = r.hz;
     return RTM_OK;
 }
 
@@ -2311,6 +2314,10 @@ int rtm_set_option(int32_t option, int32_t value)
         if (value < 1) return RTM_EINVAL;
         g_opt.halo_y_width.store(value);
         return RTM_OK;
+    case RTM_OPT_HALO_Z_WIDTH:
+        if (value < 0) return RTM_EINVAL;
+        g_opt.halo_z_width.store(value);
+        return RTM_OK;
     case RTM_OPT_HALO_VARIANT:
         if (value < 0 || value > 5 || value == 3) return RTM_EINVAL;
         g_opt.halo_variant.store(value);
@@ -2338,6 +2345,7 @@ int rtm_get_option(int32_t option)
     case RTM_OPT_XCD_REMAP: return g_opt.xcd_remap.load();
     case RTM_OPT_HALO_X_WIDTH: return g_opt.halo_x_width.load();
     case RTM_OPT_HALO_Y_WIDTH: return g_opt.halo_y_width.load();
+    case RTM_OPT_HALO_Z_WIDTH: return g_opt.halo_z_width.load();
     case RTM_OPT_HALO_VARIANT: return g_opt.halo_variant.load();
     case RTM_OPT_WHOLE_VARIANT: return g_opt.whole_variant.load();
     case RTM_OPT_UNPACK_LINES: return g_opt.unpack_lines.load();

@@ -125,6 +125,8 @@ def test_validation_before_device(abi):
     assert L.rtm_set_option(abi.RTM_OPT_WHOLE_VARIANT, 3) == abi.RTM_EINVAL
     assert L.rtm_get_option(abi.RTM_OPT_ZCHUNK) == 0
     assert L.rtm_get_option(abi.RTM_OPT_HALO_VARIANT) == 0
+    assert L.rtm_get_option(abi.RTM_OPT_HALO_Z_WIDTH) == 0              # z slabs of R planes
+    assert L.rtm_set_option(abi.RTM_OPT_HALO_Z_WIDTH, -1) == abi.RTM_EINVAL
     assert L.rtm_set_option(abi.RTM_OPT_HALO_VARIANT, 3) == abi.RTM_EINVAL   # no scalar halo variant
 
 

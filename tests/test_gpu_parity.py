@@ -113,13 +113,22 @@ def test_schedules_and_variants_bitwise(torch_cuda):
         assert np.array_equal(u, base), name
 
 
-def test_halo_and_interior_partition_owned_cells(torch_cuda):
+@pytest.mark.parametrize("hz", [0, 8])
+def test_halo_and_interior_partition_owned_cells(torch_cuda, hz):
     """NaN-poisoned output: halo then interior write every owned cell exactly once (all finite), and
-    neither touches a ghost cell."""
+    neither touches a ghost cell; with the default z slabs (R planes) and with 8-plane slabs."""
     torch = torch_cuda
     from paper_1603_03971_amd import _abi
     from paper_1603_03971_amd.grid import Grid
 
+    _abi.rtm_set_option(_abi.RTM_OPT_HALO_Z_WIDTH, hz)
+    try:
+        _partition_cases(torch, _abi, Grid, hz)
+    finally:
+        _abi.rtm_set_option(_abi.RTM_OPT_HALO_Z_WIDTH, 0)
+
+
+def _partition_cases(torch, _abi, Grid, hz):
     for (nx, ny, nz) in ((150, 41, 70), (8, 8, 8), (9, 21, 13), (64, 64, 64), (200, 19, 12)):
         g = Grid(nx, ny, nz, 10.0, 1e-3)
         rng = np.random.default_rng(nx)
@@ -134,13 +143,14 @@ def test_halo_and_interior_partition_owned_cells(torch_cuda):
         torch.cuda.synchronize()
         own = g.owned(out)
         assert torch.isfinite(own).all(), (nx, ny, nz)
-        # the halo call wrote the R-shell widened to x strips of min(64, nx // 2) cells and y strips
-        # of min(8, ny // 2) rows
+        # the halo call wrote the R-shell widened to x strips of min(64, nx // 2) cells, y strips
+        # of min(8, ny // 2) rows and z slabs of R or min(hz, nz // 2) planes
         R, wx, hy = 4, max(4, min(64, nx // 2)), max(4, min(8, ny // 2))
-        assert _abi.rtm_halo_region(g.c) == (wx, hy, R)
+        zs = max(R, min(hz, nz // 2)) if hz else R
+        assert _abi.rtm_halo_region(g.c) == (wx, hy, zs)
         shell = torch.zeros((nz, ny, nx), dtype=torch.bool, device=out.device)
-        shell[:R] = True
-        shell[-R:] = True
+        shell[:zs] = True
+        shell[-zs:] = True
         shell[:, :hy] = True
         shell[:, -hy:] = True
         shell[:, :, :wx] = True

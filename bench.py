@@ -198,6 +198,7 @@ def main():
         result["step_hbm_frac"] = round(step_bytes / (wall / args.steps) / 1e9 / HBM_PEAK_GBS, 4)
     if args.phases:
         result["phases_us"] = time_phases(g, prop, traces)
+    result["device_copy"] = device_copy_rate()
     # the same steps in one launch each (rtm_step_whole, bitwise the same fields): what one GPU with
     # nothing to overlap can do; reported beside the halo-first value, not as it
     del prop
@@ -219,6 +220,28 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(n, h, prof, args.cpu_seconds)
     print(json.dumps(result), flush=True)
+
+
+def device_copy_rate(nbytes: int = 1 << 30, reps: int = 10):
+    """Context for the roofline: a plain device-to-device copy (torch's copy, 1 GiB), bytes read plus
+    bytes written per second."""
+    import torch
+
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(st)
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"GBs": round(2 * nbytes / s / 1e9, 1), "what": "torch device-to-device copy of 1 GiB, read + written "
+            "bytes per second (context, not a ceiling)"}
 
 
 def time_phases(g, prop, traces, reps: int = 20):

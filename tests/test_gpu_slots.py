@@ -32,9 +32,12 @@ def _poison_ring(g, t):
     g.owned(t).copy_(owned)
 
 
-# (nz, ny, nx): a box the halo region covers whole; ragged x tiles whose last lane loads the +X ghost
-# and y strips whose last tile rows are ghost rows (10-row strips); interior boxes with full tiles
+# (nz, ny, nx): the smallest grids (4-wide x strips, z slabs that meet, odd ny and nz); a box the halo
+# region covers whole; ragged x tiles whose last lane loads the +X ghost and y strips whose last tile
+# rows are ghost rows (10-row strips); interior boxes with full tiles
 @pytest.mark.parametrize("shape,halo_variant,flags", [
+    ((8, 8, 8), 0, 1),
+    ((13, 9, 20), 0, 1),
     ((40, 36, 64), 0, 1),
     ((30, 20, 100), 0, 1),
     ((30, 20, 100), 2, 0),

@@ -119,7 +119,13 @@ class Propagator:
     def __init__(self, grid: Grid, kappa: torch.Tensor, *, sources: Sources | list | None = None,
                  receivers=None, boundary: str = "zero", schedule: str = "overlap", debug: bool = False,
                  check_every: int = 0, unpack_aside: bool = False, ghosts: str = "ring"):
-        """unpack_aside (serial schedule): the unpack runs on a second stream as soon as the halo call
+        """ghosts: "ring" (default) keeps every level's ghost ring current with an unpack pass after
+        each step; "slots" (serial and overlap schedules, radius 4, nx % 4 == 0) leaves the ghosts of
+        each level in the receive slots, where the next halo call reads them (rtm_step_halo_pack_slots),
+        so a step has no unpack pass and the level buffers' rings are not kept (fill_ghosts() writes
+        the newest level's).
+
+        unpack_aside (serial schedule): the unpack runs on a second stream as soon as the halo call
         and the shell sources are done, concurrently with the interior call (it writes ghost cells
         only, the interior call owned cells only); the next step waits for it.  Same bits.
 

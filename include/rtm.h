@@ -24,9 +24,9 @@
  * multiples of 4 selects the vectorised kernels; other layouts are accepted and take a scalar path.
  *
  * Ownership and ordering.  All field, index and weight arguments are DEVICE pointers owned by the
- * caller; the library never allocates, frees, copies to the host or synchronises.  Each compute call
- * only enqueues work on `stream` (NULL = the null stream) and returns at once; ordering across
- * streams is the caller's.  The library keeps no pointer after a call returns.  Calls are
+ * caller; the library never allocates, frees, copies to the host or synchronises, except
+ * rtm_tune_step, which times its settings and waits for them.  Each compute call only enqueues work
+ * on `stream` (NULL = the null stream) and returns at once; ordering across streams is the caller's.  The library keeps no pointer after a call returns.  Calls are
  * thread-safe and re-entrant.
  *
  * Errors.  Every call returns RTM_OK or a negative status and enqueues nothing on error.  No C++
@@ -186,6 +186,20 @@ int rtm_step_interior(const rtm_grid *grid, float *u_nxt, const float *u_cur, co
  * arguments and status codes as rtm_step_halo. */
 int rtm_step_whole(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv,
                    const float *kappa, hipStream_t stream);
+
+/* Measure which tile shape and workgroup order run rtm_step_whole fastest for grids of this shape on
+ * the current device, and use them from then on for the one-launch calls on such grids
+ * (rtm_step_whole, rtm_adjoint_step, the gradient calls) while RTM_OPT_WHOLE_VARIANT is 6 (its
+ * default).  Results never change (every variant evaluates the same per-point expression); only the
+ * time does.  Times `reps` launches (1..1000) of each of ten settings on `stream` and WAITS for
+ * them: call it once per grid shape, before timing anything.  u_nxt is overwritten and must not be
+ * u_prv (RTM_EALIAS); u_cur, u_prv and kappa are read.  choice (host, may be NULL) receives the
+ * chosen {tile variant as numbered for RTM_OPT_WHOLE_VARIANT, 1 = contiguous tiles per XCD or 0 =
+ * hardware order}, or {-1, -1} when the grid takes the per-cell path (nothing to tune).  Keeps up to
+ * 32 shapes (then the oldest is replaced).  Chosen for grids larger than 512^3, where the defaults
+ * leave up to 20% (workgroup counts that do not divide evenly over the 256 CUs). */
+int rtm_tune_step(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv, const float *kappa,
+                  int32_t reps, int32_t choice[2], hipStream_t stream);
 
 /* Phase 2 (section II): copy the R outermost owned layers of u on each face into `faces` (one
  * buffer of rtm_face_layout()[6] elements, slots as described there).  Bitwise copy.  Any slot size

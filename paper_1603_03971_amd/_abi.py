@@ -60,6 +60,7 @@ def _load():
         "rtm_step_halo": ([gp, vp, vp, vp, vp, vp], ctypes.c_int),
         "rtm_step_interior": ([gp, vp, vp, vp, vp, vp], ctypes.c_int),
         "rtm_step_whole": ([gp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "rtm_tune_step": ([gp, vp, vp, vp, vp, i32, ctypes.POINTER(i32), vp], ctypes.c_int),
         "rtm_pack_halo": ([gp, vp, vp, vp], ctypes.c_int),
         "rtm_step_halo_pack": ([gp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "rtm_step_halo_pack_slots": ([gp, vp, vp, vp, vp, ctypes.POINTER(vp), vp, vp], ctypes.c_int),
@@ -225,6 +226,15 @@ def rtm_step_interior(grid, u_nxt, u_cur, u_prv, kappa, stream=None):
 def rtm_step_whole(grid, u_nxt, u_cur, u_prv, kappa, stream=None):
     _check(_lib.rtm_step_whole(ctypes.byref(grid), _p(u_nxt), _p(u_cur), _p(u_prv), _p(kappa), _s(stream)),
            "rtm_step_whole")
+
+
+def rtm_tune_step(grid, u_nxt, u_cur, u_prv, kappa, reps=3, stream=None):
+    """Tune the one-launch call for this grid shape (waits for the device); returns the chosen
+    (tile variant, workgroup order), or (-1, -1) when there is nothing to tune."""
+    choice = (ctypes.c_int32 * 2)()
+    _check(_lib.rtm_tune_step(ctypes.byref(grid), _p(u_nxt), _p(u_cur), _p(u_prv), _p(kappa), int(reps), choice,
+                              _s(stream)), "rtm_tune_step")
+    return int(choice[0]), int(choice[1])
 
 
 def rtm_pack_halo(grid, u, faces, stream=None):

@@ -1323,7 +1323,7 @@ int balanced_zchunk(int tiles, int wz, int R, int cus, int waves)
 // rk: kappa for OP_ADJOINT (see k_tiled), unused otherwise.
 template <int R, int BX, int BY, int OP, bool PACK = false, int FL = 0>
 int launch_tiled(const Geo &g, float *un, const float *uc, const float *up, const float *kap, const int (*boxes)[6],
-                 int nbox, hipStream_t st, const PackOut *po = nullptr, const float *rk = nullptr)
+                 int nbox, hipStream_t st, const PackOut *po = nullptr, const float *rk = nullptr, int remap = -1)
 {
     constexpr int TX = 4 * BX;
     BoxList bl;
@@ -1374,7 +1374,7 @@ int launch_tiled(const Geo &g, float *un, const float *uc, const float *up, cons
     }
     if (nb >= (1ll << 31)) return RTM_EINVAL;
     bl.nblk = (int)nb;
-    bl.remap = g_opt.xcd_remap.load(std::memory_order_relaxed);
+    bl.remap = remap >= 0 ? remap : g_opt.xcd_remap.load(std::memory_order_relaxed);
     PackOut pk;
     std::memset(&pk, 0, sizeof(pk));
     if (po) pk = *po;
@@ -1385,21 +1385,22 @@ int launch_tiled(const Geo &g, float *un, const float *uc, const float *up, cons
 
 template <int R, int OP, bool PACK = false, int FL = 0>
 int launch_tiled_flags(int var, const Geo &g, float *un, const float *uc, const float *up, const float *kap,
-                       const int (*boxes)[6], int nbox, hipStream_t st, const PackOut *po, const float *rk)
+                       const int (*boxes)[6], int nbox, hipStream_t st, const PackOut *po, const float *rk,
+                       int remap)
 {
     switch (var) {
-    case 1: return launch_tiled<R, 32, 8, OP, PACK, FL>(g, un, uc, up, kap, boxes, nbox, st, po, rk);
-    case 2: return launch_tiled<R, 16, 8, OP, PACK, FL>(g, un, uc, up, kap, boxes, nbox, st, po, rk);
-    case 4: return launch_tiled<R, 32, 16, OP, PACK, FL>(g, un, uc, up, kap, boxes, nbox, st, po, rk);
-    case 5: return launch_tiled<R, 16, 32, OP, PACK, FL>(g, un, uc, up, kap, boxes, nbox, st, po, rk);
-    default: return launch_tiled<R, 16, 16, OP, PACK, FL>(g, un, uc, up, kap, boxes, nbox, st, po, rk);
+    case 1: return launch_tiled<R, 32, 8, OP, PACK, FL>(g, un, uc, up, kap, boxes, nbox, st, po, rk, remap);
+    case 2: return launch_tiled<R, 16, 8, OP, PACK, FL>(g, un, uc, up, kap, boxes, nbox, st, po, rk, remap);
+    case 4: return launch_tiled<R, 32, 16, OP, PACK, FL>(g, un, uc, up, kap, boxes, nbox, st, po, rk, remap);
+    case 5: return launch_tiled<R, 16, 32, OP, PACK, FL>(g, un, uc, up, kap, boxes, nbox, st, po, rk, remap);
+    default: return launch_tiled<R, 16, 16, OP, PACK, FL>(g, un, uc, up, kap, boxes, nbox, st, po, rk, remap);
     }
 }
 
 template <int R, int OP, bool PACK = false>
 int launch_tiled_variant(int var, const Geo &g, float *un, const float *uc, const float *up, const float *kap,
                          const int (*boxes)[6], int nbox, hipStream_t st, const PackOut *po = nullptr,
-                         const float *rk = nullptr, bool slots = false)
+                         const float *rk = nullptr, bool slots = false, int remap = -1)
 {
     // kernel flags: streaming hints for every operation; lane shifts for the radius-4 forward update;
     // ghosts from the receive slots for the radius-4 halo call that packs
@@ -1408,29 +1409,29 @@ int launch_tiled_variant(int var, const Geo &g, float *un, const float *uc, cons
         if (slots) {
             if (fl & FL_NT)
                 return launch_tiled_flags<R, OP, PACK, FL_NT | FL_SLOTS>(var, g, un, uc, up, kap, boxes, nbox, st, po,
-                                                                         rk);
-            return launch_tiled_flags<R, OP, PACK, FL_SLOTS>(var, g, un, uc, up, kap, boxes, nbox, st, po, rk);
+                                                                         rk, remap);
+            return launch_tiled_flags<R, OP, PACK, FL_SLOTS>(var, g, un, uc, up, kap, boxes, nbox, st, po, rk, remap);
         }
     }
     if (slots) return RTM_EINVAL;
     if constexpr (R == 4 && OP == OP_FORWARD && !PACK) {
         switch (fl) {
-        case FL_NT: return launch_tiled_flags<R, OP, PACK, FL_NT>(var, g, un, uc, up, kap, boxes, nbox, st, po, rk);
+        case FL_NT: return launch_tiled_flags<R, OP, PACK, FL_NT>(var, g, un, uc, up, kap, boxes, nbox, st, po, rk, remap);
         case FL_XSHUF:
-            return launch_tiled_flags<R, OP, PACK, FL_XSHUF>(var, g, un, uc, up, kap, boxes, nbox, st, po, rk);
+            return launch_tiled_flags<R, OP, PACK, FL_XSHUF>(var, g, un, uc, up, kap, boxes, nbox, st, po, rk, remap);
         case FL_NT | FL_XSHUF:
-            return launch_tiled_flags<R, OP, PACK, FL_NT | FL_XSHUF>(var, g, un, uc, up, kap, boxes, nbox, st, po, rk);
+            return launch_tiled_flags<R, OP, PACK, FL_NT | FL_XSHUF>(var, g, un, uc, up, kap, boxes, nbox, st, po, rk, remap);
         default: break;
         }
     } else {
-        if (fl & FL_NT) return launch_tiled_flags<R, OP, PACK, FL_NT>(var, g, un, uc, up, kap, boxes, nbox, st, po, rk);
+        if (fl & FL_NT) return launch_tiled_flags<R, OP, PACK, FL_NT>(var, g, un, uc, up, kap, boxes, nbox, st, po, rk, remap);
     }
     switch (var) {
-    case 1: return launch_tiled<R, 32, 8, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po, rk);
-    case 2: return launch_tiled<R, 16, 8, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po, rk);
-    case 4: return launch_tiled<R, 32, 16, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po, rk);
-    case 5: return launch_tiled<R, 16, 32, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po, rk);
-    default: return launch_tiled<R, 16, 16, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po, rk);
+    case 1: return launch_tiled<R, 32, 8, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po, rk, remap);
+    case 2: return launch_tiled<R, 16, 8, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po, rk, remap);
+    case 4: return launch_tiled<R, 32, 16, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po, rk, remap);
+    case 5: return launch_tiled<R, 16, 32, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po, rk, remap);
+    default: return launch_tiled<R, 16, 16, OP, PACK>(g, un, uc, up, kap, boxes, nbox, st, po, rk, remap);
     }
 }
 
@@ -1535,13 +1536,67 @@ int whole_variant(int R)
     return v == 6 ? (R == 4 ? 1 : 4) : v;
 }
 
+// Settings that rtm_tune_step measured fastest for the one-launch call on grids of one shape on one
+// device (tile variant and workgroup order); used while RTM_OPT_WHOLE_VARIANT is 6.  A small table:
+// when full, the oldest entry goes.
+struct Tuned {
+    int dev, nx, ny, nz, R;
+    long long py, pz;
+    int var, remap;
+};
+constexpr int kMaxTuned = 32;
+std::mutex g_tuned_mu;
+Tuned g_tuned[kMaxTuned];
+int g_ntuned = 0, g_tuned_next = 0;
+
+bool same_shape(const Tuned &t, int dev, const Geo &g)
+{
+    return t.dev == dev && t.nx == g.nx && t.ny == g.ny && t.nz == g.nz && t.R == g.R && t.py == g.py && t.pz == g.pz;
+}
+
+// The one-launch call's tile variant and workgroup order (-1: the option) for grid g.
+void whole_settings(const Geo &g, int R, int &var, int &remap)
+{
+    var = whole_variant(R);
+    remap = -1;
+    if (g_opt.whole_variant.load(std::memory_order_relaxed) != 6) return;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    for (int i = 0; i < g_ntuned; ++i)
+        if (same_shape(g_tuned[i], dev, g)) {
+            var = g_tuned[i].var;
+            remap = g_tuned[i].remap;
+            return;
+        }
+}
+
+void tuned_store(int dev, const Geo &g, int var, int remap)
+{
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    for (int i = 0; i < g_ntuned; ++i)
+        if (same_shape(g_tuned[i], dev, g)) {
+            g_tuned[i].var = var;
+            g_tuned[i].remap = remap;
+            return;
+        }
+    const Tuned t = {dev, g.nx, g.ny, g.nz, g.R, g.py, g.pz, var, remap};
+    if (g_ntuned < kMaxTuned) {
+        g_tuned[g_ntuned++] = t;
+    } else {
+        g_tuned[g_tuned_next] = t;
+        g_tuned_next = (g_tuned_next + 1) % kMaxTuned;
+    }
+}
+
 template <int R, int OP = OP_FORWARD>
 int launch_all(const Geo &g, float *un, const float *uc, const float *up, const float *kap, hipStream_t st)
 {
     const int boxes[1][6] = {{0, g.nx, 0, g.ny, 0, g.nz}};
     if (vector_path(g, un, uc, up, kap)) {
-        const int var = whole_variant(R);
-        return launch_tiled_variant<R, OP>(var, g, un, uc, up, kap, boxes, 1, st);
+        int var, remap;
+        whole_settings(g, R, var, remap);
+        return launch_tiled_variant<R, OP>(var, g, un, uc, up, kap, boxes, 1, st, nullptr, nullptr, false, remap);
     }
     return launch_box_scalar<R, OP>(g, un, uc, up, kap, boxes[0], st);
 }
@@ -1564,9 +1619,11 @@ int launch_adjoint(const Geo &g, float *mu_out, const float *mu_a, const float *
                    hipStream_t st)
 {
     const int boxes[1][6] = {{0, g.nx, 0, g.ny, 0, g.nz}};
-    int var = whole_variant(R);
+    int var, remap;
+    whole_settings(g, R, var, remap);
     if (var == 4 || var == 5) var = 0;
-    return launch_tiled_variant<R, OP_ADJOINT>(var, g, mu_out, mu_a, mu_a, mu_b, boxes, 1, st, nullptr, kappa);
+    return launch_tiled_variant<R, OP_ADJOINT>(var, g, mu_out, mu_a, mu_a, mu_b, boxes, 1, st, nullptr, kappa, false,
+                                               remap);
 }
 
 bool faces_vec(const Geo &g, const float *u)
@@ -1624,6 +1681,43 @@ int device_scratch(double **out)
     }
     *out = p;
     return RTM_OK;
+}
+
+template <int R>
+int tune_whole(const Geo &g, float *un, const float *uc, const float *up, const float *kap, int reps, hipStream_t st,
+               int &best_var, int &best_remap)
+{
+    const int boxes[1][6] = {{0, g.nx, 0, g.ny, 0, g.nz}};
+    const int vars[5] = {1, 0, 2, 4, 5};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return RTM_ELAUNCH;
+    }
+    float best = -1.0f;
+    int rc = RTM_OK;
+    for (int iv = 0; iv < 5 && rc == RTM_OK; ++iv)
+        for (int remap = 1; remap >= 0 && rc == RTM_OK; --remap) {
+            auto launch = [&] {
+                return launch_tiled_variant<R, OP_FORWARD>(vars[iv], g, un, uc, up, kap, boxes, 1, st, nullptr, nullptr,
+                                                           false, remap);
+            };
+            rc = launch();   // warm-up
+            if (rc == RTM_OK && hipEventRecord(e0, st) != hipSuccess) rc = RTM_ELAUNCH;
+            for (int r = 0; r < reps && rc == RTM_OK; ++r) rc = launch();
+            if (rc == RTM_OK && hipEventRecord(e1, st) != hipSuccess) rc = RTM_ELAUNCH;
+            float ms = 0.0f;
+            if (rc == RTM_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = RTM_ELAUNCH;
+            if (rc == RTM_OK && (best < 0.0f || ms < best)) {
+                best = ms;
+                best_var = vars[iv];
+                best_remap = remap;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
 }
 
 }  // namespace
@@ -1789,6 +1883,32 @@ int rtm_step_whole(const rtm_grid *grid, float *u_nxt, const float *u_cur, const
     const Geo g = make_geo(grid);
     return g.R == 4 ? launch_all<4>(g, u_nxt, u_cur, u_prv, kappa, stream)
                     : launch_all<2>(g, u_nxt, u_cur, u_prv, kappa, stream);
+}
+
+int rtm_tune_step(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv, const float *kappa,
+                  int32_t reps, int32_t choice[2], hipStream_t stream)
+{
+    int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (reps < 1 || reps > 1000) return RTM_EINVAL;
+    if (u_nxt && u_nxt == u_prv) return RTM_EALIAS;     // u_nxt is overwritten: it must be scratch
+    st = step_common(grid, u_nxt, u_cur, u_prv, kappa);
+    if (st != RTM_OK) return st;
+    const Geo g = make_geo(grid);
+    int var = -1, remap = -1;
+    if (vector_path(g, u_nxt, u_cur, u_prv, kappa)) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return RTM_EDEVICE;
+        st = g.R == 4 ? tune_whole<4>(g, u_nxt, u_cur, u_prv, kappa, reps, stream, var, remap)
+                      : tune_whole<2>(g, u_nxt, u_cur, u_prv, kappa, reps, stream, var, remap);
+        if (st != RTM_OK) return st;
+        tuned_store(dev, g, var, remap);
+    }
+    if (choice) {
+        choice[0] = var;
+        choice[1] = remap;
+    }
+    return RTM_OK;
 }
 
 int rtm_pack_halo(const rtm_grid *grid, const float *u, float *faces, hipStream_t stream)

@@ -25,7 +25,7 @@ import torch
 
 from . import _abi, synth
 from .grid import Grid
-from .propagator import Propagator, Sources
+from .propagator import Propagator, Sources, tune_grid
 
 C = 16                          # channels of every layer
 TAPS = 27
@@ -654,7 +654,7 @@ PLAIN_VARIANTS = {
 def compare_rtm(fine: Grid, v_true, v_bg, src_f, rec_f, nsteps_f: int, fpeak: float, net: CorrectorNet | None,
                 every: int, image_every_f: int = 4, repeats: int = 2, schedule: str = "fused",
                 snapshots_fine: str | None = None, log=None, plain_variants=(), prolonged: bool = False,
-                coarse_radius: int = 2):
+                coarse_radius: int = 2, tune: bool = True):
     """Migrate one shot on the fine grid (the reference) and on the coarse grid without and with the
     learned corrector.  The recorded data are modelled on the fine grid (d_true in v_true, d_bg in
     v_bg) and decimated in time for the coarse runs; sources and receivers sit on even fine cells,
@@ -666,13 +666,17 @@ def compare_rtm(fine: Grid, v_true, v_bg, src_f, rec_f, nsteps_f: int, fpeak: fl
     way (an image on the fine spacing is restricted to the coarse grid like the reference), the
     points of a time-versus-error curve on which the corrected coarse solver is placed.
     prolonged: also form the plain and corrected coarse images on the fine grid from prolonged
-    coarse wavefields (migrate_prolonged) and score them against the fine image on the fine grid."""
+    coarse wavefields (migrate_prolonged) and score them against the fine image on the fine grid.
+    tune: first pick the one-launch call's settings for the fine and the coarse grid's shapes
+    (tune_grid), so that every solver is timed with its fastest settings."""
     from . import snapshots as snapcodec
     from .rtm import migrate_shot, model_shot
 
     say = log if log is not None else (lambda msg: None)
 
     coarse = coarse_grid(fine, coarse_radius)
+    if tune:
+        say(f"one-launch step tuned: fine {tune_grid(fine)}, coarse {tune_grid(coarse)}")
     src_f = np.asarray(src_f, dtype=np.int64).reshape(-1, 3)
     rec_f = np.asarray(rec_f, dtype=np.int64).reshape(-1, 3)
     if (src_f % 2).any() or (rec_f % 2).any():
@@ -745,6 +749,8 @@ def compare_rtm(fine: Grid, v_true, v_bg, src_f, rec_f, nsteps_f: int, fpeak: fl
     for name in plain_variants:
         spacing, radius, step = PLAIN_VARIANTS[name]
         pg = plain_grid(fine, spacing, radius, step)
+        if tune:
+            tune_grid(pg)
         vp = coarse_velocity(v_bg) if spacing == 2 else np.ascontiguousarray(v_bg, dtype=np.float32)
         kp = pg.kappa_from_velocity(vp)
         sp, rp = src_f // spacing, rec_f // spacing

@@ -266,6 +266,7 @@ def run_shot(nx: int, ny: int, nz: int, steps: int, every: int, repeats: int, sc
 
     from . import rtm, snapshots, synth
     from .grid import Grid
+    from .propagator import tune_grid
 
     def say(msg):
         print(msg, flush=True)
@@ -280,6 +281,8 @@ def run_shot(nx: int, ny: int, nz: int, steps: int, every: int, repeats: int, sc
     kap_true, kap_bg = g.kappa_from_velocity(v_true), g.kappa_from_velocity(v_bg)
     vs = v_bg[src[:, 2], src[:, 1], src[:, 0]]
     del v_true
+    choice = tune_grid(g)
+    say(f"one-launch step tuned for {nx}x{ny}x{nz}: tile variant {choice[0]}, workgroup order {choice[1]}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     d_true = rtm.model_shot(g, kap_true, vs, src, wav, rec, steps, schedule)
@@ -289,7 +292,7 @@ def run_shot(nx: int, ny: int, nz: int, steps: int, every: int, repeats: int, sc
     del kap_true
     say(f"data modelled: {len(rec)} receivers x {steps} steps, two propagations in {t_model:.3f} s")
     out = {"grid": [nx, ny, nz], "steps": steps, "image_every": every, "receivers": int(len(rec)),
-           "schedule": schedule, "t_model_two_shots_s": round(t_model, 4)}
+           "schedule": schedule, "tuned": list(choice), "t_model_two_shots_s": round(t_model, 4)}
     images = {}
     for fmt in ("f32", "bf16", "f16"):
         best = None
@@ -328,6 +331,7 @@ def run_gradient(n: int, nshots: int, steps: int, every: int, eps: float, cells:
     from . import synth
     from .adjoint import MisfitProblem, Shot
     from .grid import Grid
+    from .propagator import tune_grid
 
     def say(msg):
         print(msg, flush=True)
@@ -343,6 +347,8 @@ def run_gradient(n: int, nshots: int, steps: int, every: int, eps: float, cells:
     shots = [Shot([s], g.injection_weights([v0[s[2], s[1], s[0]]]), rec) for s in src]
     prob = MisfitProblem(g, steps, wav, shots, checkpoint_every=every)
     kt = g.kappa_from_velocity(v_true)
+    choice = tune_grid(g)
+    say(f"one-launch step tuned for {n}^3: tile variant {choice[0]}, workgroup order {choice[1]}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for sh in shots:

@@ -115,6 +115,17 @@ class Sources:
         _abi.rtm_pack_cells(grid.c, u, self.face_idx, self.face_idx.numel(), faces, stream)
 
 
+def tune_grid(grid: Grid, reps: int = 3):
+    """Pick the fastest tile shape and workgroup order of the one-launch call for grids of this
+    grid's shape on the current device (rtm_tune_step on scratch fields; the results of every call
+    stay the same).  Waits for the device; returns the choice."""
+    st = torch.cuda.current_stream()
+    u_nxt, u_cur, u_prv, kap = grid.field(), grid.field(), grid.field(), grid.field(0.05)
+    choice = _abi.rtm_tune_step(grid.c, u_nxt, u_cur, u_prv, kap, reps, st)
+    st.synchronize()
+    return choice
+
+
 class Propagator:
     def __init__(self, grid: Grid, kappa: torch.Tensor, *, sources: Sources | list | None = None,
                  receivers=None, boundary: str = "zero", schedule: str = "overlap", debug: bool = False,

@@ -94,6 +94,11 @@ def test_validation_before_device(abi):
     assert hps(gp, 4096, 1 << 36, 1 << 37, 1 << 38, slots, 4096 + 64, None) == abi.RTM_EALIAS   # faces over u_nxt
     g2 = _grid(abi, radius=2)
     assert hps(ctypes.byref(g2), 4096, 1 << 36, 1 << 37, 1 << 38, slots, 1 << 39, None) == abi.RTM_EINVAL
+    # the tuning call: reps in 1..1000, and u_nxt is scratch, never u_prv
+    assert L.rtm_tune_step(gp, 4096, 1 << 36, 1 << 37, 1 << 38, 0, None, None) == abi.RTM_EINVAL
+    assert L.rtm_tune_step(gp, 4096, 1 << 36, 1 << 37, 1 << 38, 1001, None, None) == abi.RTM_EINVAL
+    assert L.rtm_tune_step(gp, 1 << 37, 1 << 36, 1 << 37, 1 << 38, 3, None, None) == abi.RTM_EALIAS
+    assert L.rtm_tune_step(None, 4096, 1 << 36, 1 << 37, 1 << 38, 3, None, None) == abi.RTM_EINVAL
     g3 = _grid(abi, nx=18, pitch_y=28)                                                  # nx % 4 != 0
     assert hps(ctypes.byref(g3), 4096, 1 << 36, 1 << 37, 1 << 38, slots, 1 << 39, None) == abi.RTM_EINVAL
     assert L.rtm_pack_cells(gp, 4096, 64, -1, 1 << 39, None) == abi.RTM_EINVAL

@@ -726,3 +726,41 @@ def test_unpack_aside_bitwise(torch_cuda, boundary):
         out.append((g.download(p.u_cur), tr.cpu().numpy()))
     assert np.any(out[0][0] != 0)
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("radius", [4, 2])
+def test_tuned_one_launch_step_is_bitwise(torch_cuda, radius):
+    """rtm_tune_step picks a tile shape and workgroup order for a grid shape; the one-launch step and
+    the adjoint step run with it afterwards and give the same bits as before tuning (and as the halo
+    and interior calls)."""
+    torch = torch_cuda
+    from paper_1603_03971_amd import _abi, synth
+    from paper_1603_03971_amd.grid import Grid
+
+    nx, ny, nz = 136, 72, 60
+    v = np.array(synth.layered_velocity((nz, ny, nx), 10.0, seed=17))
+    g = Grid(nx, ny, nz, 10.0, Grid.stable_dt(radius, 10.0, float(v.max())), radius=radius)
+    kap = g.kappa_from_velocity(v)
+    uc = g.upload(synth.random_field((nz, ny, nx), seed=41))
+    up = g.upload(synth.random_field((nz, ny, nx), seed=42))
+    work = g.field()
+    st = torch.cuda.current_stream()
+
+    def run():
+        whole, split, adj = g.field(), g.field(), g.field()
+        _abi.rtm_step_whole(g.c, whole, uc, up, kap, st)
+        _abi.rtm_step_halo(g.c, split, uc, up, kap, st)
+        _abi.rtm_step_interior(g.c, split, uc, up, kap, st)
+        _abi.rtm_adjoint_step(g.c, adj, uc, up, kap, work, st)
+        torch.cuda.synchronize()
+        return g.download(whole), g.download(split), g.download(adj)
+
+    before = run()
+    var, remap = _abi.rtm_tune_step(g.c, g.field(), uc, up, kap, reps=2, stream=st)
+    _say(f"tuned radius {radius}: variant {var}, workgroup order {remap}")
+    assert var in (0, 1, 2, 4, 5) and remap in (0, 1)
+    after = run()
+    assert np.abs(before[0]).max() > 0
+    assert np.array_equal(before[0], before[1])
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)

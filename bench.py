@@ -29,6 +29,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_POINT = 16          # read u^n, u^{n-1}, kappa; write u^{n+1} (FP32)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "forward_512_layered_traffic.txt")
+# the interior call is timed with HIP events on every EVENT_EVERY-th timed step (100 launches of 1000):
+# each event pair makes the step it brackets about 11 us longer (an event waits for the kernel before
+# it and writes back the caches), which the other steps then do not pay
+EVENT_EVERY = 10
 
 
 def parse():
@@ -41,6 +45,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--phases", action="store_true", help="also time each phase separately (serial)")
+    ap.add_argument("--markers", action="store_true",
+                    help="roctx ranges around every per-step call (for rocprofv3 --marker-trace)")
     ap.add_argument("--ghosts", default="slots", choices=["slots", "ring"],
                     help="slots: the halo call reads the ghosts from the receive slots; ring: an unpack pass")
     return ap.parse_args()
@@ -123,6 +129,8 @@ def main():
     from paper_1603_03971_amd.propagator import Propagator, Sources
 
     assert torch.cuda.is_available(), "needs a GPU"
+    if args.markers:
+        _abi.rtm_set_option(_abi.RTM_OPT_MARKERS, 1)
     n, h = args.n, 10.0
     shape = (n, n, n)
     prof = synth.layered_profile(n, h, seed=2)
@@ -147,6 +155,7 @@ def main():
     torch.cuda.synchronize()
 
     prop.interior_events = []
+    prop.interior_event_every = EVENT_EVERY
     t0 = time.perf_counter()
     for _ in range(args.steps):
         prop.step(traces)
@@ -187,6 +196,7 @@ def main():
         result["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                               "kernel": "rtm_step_interior", "avg_us": round(avg_s * 1e6, 2),
+                              "launches_timed": len(ms),
                               "algorithmic_bytes_per_launch": BYTES_PER_POINT * interior_pts}
         # whole-step roofline with the halo phases, counting the bytes each phase must move: the
         # stencil 16 B per cell; per face cell, the halo call stores the computed value into its

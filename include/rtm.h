@@ -137,6 +137,11 @@ const char *rtm_strerror(int status);
  *                             neighbouring tiles read it again.  Bit 1: in the radius-4 forward launches,
  *                             each thread's x neighbours from the adjacent lanes' registers (DPP lane
  *                             shifts) instead of LDS (measured: no change).  Default 1.
+ *   RTM_OPT_MARKERS           1 = a roctx range named after the call around each per-step call (the
+ *                             phase calls, injection, recording, imaging, coding, the adjoint and
+ *                             gradient calls), so that a marker trace (rocprofv3 --marker-trace) shows
+ *                             each step's phase sequence; RTM_EINVAL when the roctx library cannot
+ *                             be opened.  Default 0.
  * Returns RTM_EINVAL for an unknown option or value. */
 enum {
     RTM_OPT_INTERIOR_VARIANT = 1,
@@ -149,6 +154,7 @@ enum {
     RTM_OPT_UNPACK_LINES = 8,
     RTM_OPT_TILE_FLAGS = 9,
     RTM_OPT_HALO_Z_WIDTH = 10,
+    RTM_OPT_MARKERS = 11,
 };
 int rtm_set_option(int32_t option, int32_t value);
 /* The current value of an option (>= 0), or RTM_EINVAL for an unknown option. */

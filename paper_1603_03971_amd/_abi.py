@@ -18,7 +18,7 @@ RTM_SNAP_BF16, RTM_SNAP_F16 = 1, 2
 RTM_RESTRICT_INJECT, RTM_RESTRICT_FULL = 0, 1
 RTM_OPT_INTERIOR_VARIANT, RTM_OPT_ZCHUNK, RTM_OPT_XCD_REMAP, RTM_OPT_HALO_X_WIDTH, RTM_OPT_HALO_Y_WIDTH = 1, 2, 3, 4, 5
 RTM_OPT_HALO_VARIANT, RTM_OPT_WHOLE_VARIANT, RTM_OPT_UNPACK_LINES, RTM_OPT_TILE_FLAGS = 6, 7, 8, 9
-RTM_OPT_HALO_Z_WIDTH = 10
+RTM_OPT_HALO_Z_WIDTH, RTM_OPT_MARKERS = 10, 11
 
 
 class RTMError(RuntimeError):

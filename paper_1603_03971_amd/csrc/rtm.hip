@@ -7,6 +7,7 @@
 // Every stencil kernel evaluates the same per-point expression (point_op) on the same operands
 // in the same order, with explicit FMAs and FP contraction disabled at compile time, so any split of
 // a step between the halo and interior calls produces bitwise identical wavefields.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -1205,8 +1206,47 @@ struct Options {
     std::atomic<int> halo_variant{0};      // tile shape of the halo call (as interior_variant; 5: 16x32)
     std::atomic<int> unpack_lines{1};      // 1: x-face ghosts unpacked as whole lines where the layout allows
     std::atomic<int> tile_flags{FL_NT};    // FL_NT (streaming hints, default) | FL_XSHUF (lane shifts)
+    std::atomic<int> markers{0};           // roctx ranges around the per-step calls
 };
 Options g_opt;
+
+// Phase markers (RTM_OPT_MARKERS): a roctx range named after the call around each per-step call, so
+// a trace (rocprofv3 --marker-trace) shows every step's phase sequence on the host timeline.  The
+// roctx library is opened when the option is first set; nothing links against it.
+struct Roctx {
+    int (*push)(const char *) = nullptr;
+    int (*pop)() = nullptr;
+};
+
+const Roctx &roctx()
+{
+    static const Roctx api = [] {
+        Roctx r;
+        void *h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_GLOBAL);
+        if (!h) h = dlopen("libroctx64.so.4", RTLD_NOW | RTLD_GLOBAL);
+        if (h) {
+            r.push = reinterpret_cast<int (*)(const char *)>(dlsym(h, "roctxRangePushA"));
+            r.pop = reinterpret_cast<int (*)()>(dlsym(h, "roctxRangePop"));
+            if (!r.push || !r.pop) r.push = nullptr, r.pop = nullptr;
+        }
+        return r;
+    }();
+    return api;
+}
+
+struct Marker {
+    bool on;
+    explicit Marker(const char *name) : on(g_opt.markers.load(std::memory_order_relaxed) != 0)
+    {
+        if (on) roctx().push(name);
+    }
+    ~Marker()
+    {
+        if (on) roctx().pop();
+    }
+    Marker(const Marker &) = delete;
+    Marker &operator=(const Marker &) = delete;
+};
 
 int check_device()
 {
@@ -1858,6 +1898,7 @@ static int step_common(const rtm_grid *grid, float *u_nxt, const float *u_cur, c
 int rtm_step_halo(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv, const float *kappa,
                   hipStream_t stream)
 {
+    const Marker mark("rtm_step_halo");
     const int st = step_common(grid, u_nxt, u_cur, u_prv, kappa);
     if (st != RTM_OK) return st;
     const Geo g = make_geo(grid);
@@ -1868,6 +1909,7 @@ int rtm_step_halo(const rtm_grid *grid, float *u_nxt, const float *u_cur, const 
 int rtm_step_interior(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv,
                       const float *kappa, hipStream_t stream)
 {
+    const Marker mark("rtm_step_interior");
     const int st = step_common(grid, u_nxt, u_cur, u_prv, kappa);
     if (st != RTM_OK) return st;
     const Geo g = make_geo(grid);
@@ -1878,6 +1920,7 @@ int rtm_step_interior(const rtm_grid *grid, float *u_nxt, const float *u_cur, co
 int rtm_step_whole(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv, const float *kappa,
                    hipStream_t stream)
 {
+    const Marker mark("rtm_step_whole");
     const int st = step_common(grid, u_nxt, u_cur, u_prv, kappa);
     if (st != RTM_OK) return st;
     const Geo g = make_geo(grid);
@@ -1913,6 +1956,7 @@ int rtm_tune_step(const rtm_grid *grid, float *u_nxt, const float *u_cur, const 
 
 int rtm_pack_halo(const rtm_grid *grid, const float *u, float *faces, hipStream_t stream)
 {
+    const Marker mark("rtm_pack_halo");
     int st = check_grid(grid);
     if (st != RTM_OK) return st;
     if (!u || !faces) return RTM_EINVAL;
@@ -1942,6 +1986,7 @@ int rtm_pack_halo(const rtm_grid *grid, const float *u, float *faces, hipStream_
 int rtm_step_halo_pack(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv,
                        const float *kappa, float *faces, hipStream_t stream)
 {
+    const Marker mark("rtm_step_halo_pack");
     // the face buffer's own checks first: every argument error is reported before the device check
     int st = check_grid(grid);
     if (st != RTM_OK) return st;
@@ -1970,6 +2015,7 @@ int rtm_step_halo_pack(const rtm_grid *grid, float *u_nxt, const float *u_cur, c
 int rtm_step_halo_pack_slots(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv,
                              const float *kappa, const float *const recv[6], float *faces, hipStream_t stream)
 {
+    const Marker mark("rtm_step_halo_pack_slots");
     int st = check_grid(grid);
     if (st != RTM_OK) return st;
     if (!faces || !recv) return RTM_EINVAL;
@@ -2002,6 +2048,7 @@ int rtm_step_halo_pack_slots(const rtm_grid *grid, float *u_nxt, const float *u_
 int rtm_pack_cells(const rtm_grid *grid, const float *u, const int64_t *idx, int32_t n, float *faces,
                    hipStream_t stream)
 {
+    const Marker mark("rtm_pack_cells");
     int st = check_grid(grid);
     if (st != RTM_OK) return st;
     if (n < 0 || (n > 0 && (!u || !idx || !faces))) return RTM_EINVAL;
@@ -2019,6 +2066,7 @@ int rtm_pack_cells(const rtm_grid *grid, const float *u, const int64_t *idx, int
 
 int rtm_unpack_halo(const rtm_grid *grid, float *u, const float *const faces[6], hipStream_t stream)
 {
+    const Marker mark("rtm_unpack_halo");
     int st = check_grid(grid);
     if (st != RTM_OK) return st;
     if (!u || !faces) return RTM_EINVAL;
@@ -2067,6 +2115,7 @@ int rtm_unpack_halo(const rtm_grid *grid, float *u, const float *const faces[6],
 int rtm_inject(const rtm_grid *grid, float *u, const int64_t *idx, const float *w, const float *amp, int32_t n,
                hipStream_t stream)
 {
+    const Marker mark("rtm_inject");
     int st = check_grid(grid);
     if (st != RTM_OK) return st;
     if (n < 0) return RTM_EINVAL;
@@ -2081,6 +2130,7 @@ int rtm_inject(const rtm_grid *grid, float *u, const int64_t *idx, const float *
 
 int rtm_record(const rtm_grid *grid, const float *u, const int64_t *idx, float *out, int32_t n, hipStream_t stream)
 {
+    const Marker mark("rtm_record");
     int st = check_grid(grid);
     if (st != RTM_OK) return st;
     if (n < 0) return RTM_EINVAL;
@@ -2096,6 +2146,7 @@ int rtm_record(const rtm_grid *grid, const float *u, const int64_t *idx, float *
 int rtm_image_accumulate(const rtm_grid *grid, float *image, const float *src, const float *rcv, float weight,
                          hipStream_t stream)
 {
+    const Marker mark("rtm_image_accumulate");
     int st = check_grid(grid);
     if (st != RTM_OK) return st;
     if (!image || !src || !rcv) return RTM_EINVAL;
@@ -2163,6 +2214,7 @@ int rtm_halo_region(const rtm_grid *grid, int32_t widths[3])
 int rtm_adjoint_step(const rtm_grid *grid, float *mu_out, const float *mu_a, const float *mu_b, const float *kappa,
                      float *work, hipStream_t stream)
 {
+    const Marker mark("rtm_adjoint_step");
     int st = check_grid(grid);
     if (st != RTM_OK) return st;
     if (!mu_out || !mu_a || !mu_b || !kappa || !work) return RTM_EINVAL;
@@ -2190,6 +2242,7 @@ int rtm_adjoint_step(const rtm_grid *grid, float *mu_out, const float *mu_a, con
 
 int rtm_gradient_accumulate(const rtm_grid *grid, float *grad, const float *u, const float *mu, hipStream_t stream)
 {
+    const Marker mark("rtm_gradient_accumulate");
     int st = check_grid(grid);
     if (st != RTM_OK) return st;
     if (!grad || !u || !mu) return RTM_EINVAL;
@@ -2204,6 +2257,7 @@ int rtm_gradient_accumulate(const rtm_grid *grid, float *grad, const float *u, c
 int rtm_gradient_accumulate_scaled(const rtm_grid *grid, float *grad, const float *u, const float *w,
                                    hipStream_t stream)
 {
+    const Marker mark("rtm_gradient_accumulate_scaled");
     int st = check_grid(grid);
     if (st != RTM_OK) return st;
     if (!grad || !u || !w) return RTM_EINVAL;
@@ -2238,6 +2292,7 @@ int rtm_scaled_adjoint_factors(const rtm_grid *grid, const float *kappa, const i
 int rtm_record_weighted(const rtm_grid *grid, const float *u, const int64_t *idx, const float *w, float *out,
                         int32_t n, hipStream_t stream)
 {
+    const Marker mark("rtm_record_weighted");
     int st = check_grid(grid);
     if (st != RTM_OK) return st;
     if (n < 0) return RTM_EINVAL;
@@ -2356,6 +2411,7 @@ int rtm_velocity_gradient(const rtm_grid *grid, float *grad_v, const float *grad
 int rtm_snapshot_encode(const rtm_grid *grid, const float *u, uint16_t *codes, float *scales, int32_t format,
                         hipStream_t stream)
 {
+    const Marker mark("rtm_snapshot_encode");
     int st = check_grid(grid);
     if (st != RTM_OK) return st;
     if (!u || !codes || !scales) return RTM_EINVAL;
@@ -2387,6 +2443,7 @@ int rtm_snapshot_encode(const rtm_grid *grid, const float *u, uint16_t *codes, f
 int rtm_image_accumulate_coded(const rtm_grid *grid, float *image, const uint16_t *codes, const float *scales,
                                int32_t format, const float *rcv, float weight, hipStream_t stream)
 {
+    const Marker mark("rtm_image_accumulate_coded");
     int st = check_grid(grid);
     if (st != RTM_OK) return st;
     if (!image || !codes || !scales || !rcv) return RTM_EINVAL;
@@ -2453,6 +2510,11 @@ int rtm_set_option(int32_t option, int32_t value)
         if (value < 0 || value > 3) return RTM_EINVAL;
         g_opt.tile_flags.store(value);
         return RTM_OK;
+    case RTM_OPT_MARKERS:
+        if (value < 0 || value > 1) return RTM_EINVAL;
+        if (value == 1 && !roctx().push) return RTM_EINVAL;
+        g_opt.markers.store(value);
+        return RTM_OK;
     default: return RTM_EINVAL;
     }
 }
@@ -2470,6 +2532,7 @@ int rtm_get_option(int32_t option)
     case RTM_OPT_WHOLE_VARIANT: return g_opt.whole_variant.load();
     case RTM_OPT_UNPACK_LINES: return g_opt.unpack_lines.load();
     case RTM_OPT_TILE_FLAGS: return g_opt.tile_flags.load();
+    case RTM_OPT_MARKERS: return g_opt.markers.load();
     default: return RTM_EINVAL;
     }
 }

@@ -542,6 +542,53 @@ def summarize_halo(fetch_dir, write_dir, out, n, commands, stats_dir=None):
     print(text)
 
 
+def summarize_markers(trace_dir, out, commands):
+    """Phase sequence of the benchmark's steps from a marker trace (RTM_OPT_MARKERS): the calls of
+    one halo-first step in order, host time per call, and the GPU time of the kernels each step
+    launched, from the first kernel after the step's first call to the last before the next step."""
+    marks = sorted(_csv(trace_dir, "*marker_api_trace.csv"), key=lambda r: int(r["Start_Timestamp"]))
+    kern = sorted(_csv(trace_dir, "*kernel_trace.csv"), key=lambda r: int(r["Start_Timestamp"]))
+    first = "rtm_step_halo_pack_slots"
+    starts = [i for i, r in enumerate(marks) if r["Function"] == first]
+    lines = ["# rocprofv3 summary: phase markers of the 512^3 halo-first benchmark step", "", "Commands:"]
+    lines += [f"    {c}" for c in commands] + [""]
+    if len(starts) < 3:
+        lines.append("fewer than three halo-first steps in the trace")
+    else:
+        seq = [marks[i]["Function"] for i in range(starts[1], starts[2])]
+        lines += ["Calls of one halo-first step, in order (host side, each a roctx range):",
+                  "    " + " -> ".join(seq), ""]
+        stats = {}
+        for r in marks[starts[0]:starts[-1]]:
+            stats.setdefault(r["Function"], []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        lines.append(f"    {'call':30s} {'calls':>6s} {'host us per call':>17s}")
+        for name, d in sorted(stats.items(), key=lambda kv: -sum(kv[1])):
+            lines.append(f"    {name:30s} {len(d):6d} {sum(d) / len(d):17.1f}")
+        # the GPU side from the kernel trace alone: a step's kernels run from its halo call's kernel
+        # to the next step's (the host enqueues ahead, so host and GPU times do not line up)
+        halo = [i for i, k in enumerate(kern) if HALO_KERNEL in k["Kernel_Name"]]
+        per, rows = [], {}
+        for a, b in zip(halo[:-1], halo[1:]):
+            per.append((int(kern[b]["Start_Timestamp"]) - int(kern[a]["Start_Timestamp"])) / 1e3)
+            prev_end = None
+            for pos, k in enumerate(kern[a:b]):
+                name = k["Kernel_Name"].replace("(anonymous namespace)::", "").split("(")[0][:44]
+                t0, t1 = int(k["Start_Timestamp"]), int(k["End_Timestamp"])
+                gap = (t0 - prev_end) / 1e3 if prev_end is not None else 0.0
+                rows.setdefault((pos, name), []).append(((t1 - t0) / 1e3, gap))
+                prev_end = t1
+        if per:
+            med = lambda v: sorted(v)[len(v) // 2]
+            lines += ["", f"GPU side, from the kernel trace ({len(per)} steps): median step period {med(per):.1f} us",
+                      f"    {'kernel (in launch order)':46s} {'median us':>10s} {'gap before':>11s}"]
+            for (pos, name), d in sorted(rows.items()):
+                lines.append(f"    {name:46s} {med([x[0] for x in d]):10.1f} {med([x[1] for x in d]):11.1f}")
+    text = "\n".join(lines) + "\n"
+    with open(out, "w") as f:
+        f.write(text)
+    print(text)
+
+
 def summarize_corrected(stats_dir, out, n, steps, every, commands):
     """Per-step and per-correction costs of the `corrected` run from its kernel statistics."""
     rows = _csv(stats_dir, "*kernel_stats.csv")
@@ -634,6 +681,10 @@ def main(argv=None):
     kn = sub.add_parser("kernels")
     kn.add_argument("--n", type=int, default=512)
     kn.add_argument("--launches", type=int, default=10)
+    sm = sub.add_parser("summarize-markers")
+    sm.add_argument("--dir", required=True)
+    sm.add_argument("--out", required=True)
+    sm.add_argument("--command", action="append", default=[])
     sk = sub.add_parser("summarize-kernels")
     sk.add_argument("--fetch", required=True)
     sk.add_argument("--write", required=True)
@@ -692,6 +743,8 @@ def main(argv=None):
         summarize_halo(args.fetch, args.write, args.out, args.n, args.command, args.stats)
     elif args.cmd == "kernels":
         run_kernels(args.n, args.launches)
+    elif args.cmd == "summarize-markers":
+        summarize_markers(args.dir, args.out, args.command)
     elif args.cmd == "summarize-kernels":
         summarize_kernels(args.fetch, args.write, args.stats, args.out, args.n, args.command)
     elif args.cmd == "conv":

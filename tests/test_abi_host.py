@@ -132,6 +132,12 @@ def test_validation_before_device(abi):
     assert L.rtm_get_option(abi.RTM_OPT_HALO_VARIANT) == 0
     assert L.rtm_get_option(abi.RTM_OPT_HALO_Z_WIDTH) == 0              # z slabs of R planes
     assert L.rtm_set_option(abi.RTM_OPT_HALO_Z_WIDTH, -1) == abi.RTM_EINVAL
+    assert L.rtm_get_option(abi.RTM_OPT_MARKERS) == 0
+    assert L.rtm_set_option(abi.RTM_OPT_MARKERS, 2) == abi.RTM_EINVAL
+    assert L.rtm_set_option(abi.RTM_OPT_MARKERS, 1) == abi.RTM_OK       # roctx is installed here
+    g0 = _grid(abi)
+    assert L.rtm_step_halo(ctypes.byref(g0), None, 32, 48, 64, None) == abi.RTM_EINVAL   # marked, still checked
+    assert L.rtm_set_option(abi.RTM_OPT_MARKERS, 0) == abi.RTM_OK
     assert L.rtm_set_option(abi.RTM_OPT_HALO_VARIANT, 3) == abi.RTM_EINVAL   # no scalar halo variant
 
 

@@ -5,12 +5,15 @@ with sigma = 3 cells, seed 2), radius-4 star stencil with leapfrog, dt at half t
 15 Hz Ricker point source at the centre, 16-cell sponge, and the halo-first step schedule with all
 six 4-wide faces exchanged on the device (one subdomain's share: the faces go out to a send buffer,
 and the ghosts come in from six receive slots of a zero-filled receive buffer, as from neighbours
-that sent zero faces).  A step is one pass of the whole per-step sequence: halo stencil (reading the
-ghosts from the receive slots and writing the faces to the send buffer as it goes), source
-injection, interior stencil, receiver recording.  With --ghosts ring the received faces are instead
-unpacked into the ghost ring by a pass of their own after the interior stencil.
+that sent zero faces).  A step is one pass of the whole per-step sequence.  By default (--halo shell):
+the shell call (the owned cells within 4 of a face computed into the send buffer, reading the ghosts
+from the receive slots), the call over every owned cell (the shell again included, full-width tiles,
+the same ghosts), source injection, receiver recording.  With --halo region: the halo call over the
+halo region (writing the faces to the send buffer as it goes), source injection, the interior stencil,
+recording; with --ghosts ring (and --halo region) the received faces are also unpacked into the ghost
+ring by a pass of their own after the interior stencil.
 
-Prints one JSON line: G point-updates/s over the timed steps, the interior kernel's achieved HBM
+Prints one JSON line: G point-updates/s over the timed steps, the dominant kernel's achieved HBM
 bandwidth against the 8 TB/s peak (algorithmic bytes / HIP-event kernel time), and the FP64 CPU
 oracle timed on the host on a bounded sample of the same workload.
 """
@@ -29,7 +32,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_POINT = 16          # read u^n, u^{n-1}, kappa; write u^{n+1} (FP32)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "forward_512_layered_traffic.txt")
-# the interior call is timed with HIP events on every EVENT_EVERY-th timed step (100 launches of 1000):
+# the dominant call (the whole-block call, or the interior call with --halo region) is timed with HIP
+# events on every EVENT_EVERY-th timed step (100 launches of 1000):
 # each event pair makes the step it brackets about 11 us longer (an event waits for the kernel before
 # it and writes back the caches), which the other steps then do not pay
 EVENT_EVERY = 10
@@ -49,7 +53,15 @@ def parse():
                     help="roctx ranges around every per-step call (for rocprofv3 --marker-trace)")
     ap.add_argument("--ghosts", default="slots", choices=["slots", "ring"],
                     help="slots: the halo call reads the ghosts from the receive slots; ring: an unpack pass")
-    return ap.parse_args()
+    ap.add_argument("--halo", default=None, choices=["shell", "region"],
+                    help="shell (default with --ghosts slots): the halo call computes only the faces and the "
+                         "second call every owned cell; region: the halo region, then the interior")
+    args = ap.parse_args()
+    if args.halo is None:
+        args.halo = "shell" if args.ghosts == "slots" else "region"
+    if args.halo == "shell" and args.ghosts != "slots":
+        ap.error("--halo shell reads the ghosts from the receive slots (--ghosts slots)")
+    return args
 
 
 def kernel_source_hash() -> str:
@@ -145,7 +157,7 @@ def main():
     src = Sources(g, [(c, c, c)], g.injection_weights([prof[c]]), g.ricker(total_steps, 15.0)[:, None])
     rec = synth.surface_receivers(n, n, k=20, stride=16)           # a sparse 32 x 32 surface spread
     prop = Propagator(g, kap, sources=src, receivers=rec, schedule=args.schedule, boundary="zero_faces",
-                      ghosts=args.ghosts)
+                      ghosts=args.ghosts, halo=args.halo)
     traces = prop.new_traces(total_steps)
     torch.cuda.synchronize()
 
@@ -166,43 +178,55 @@ def main():
     finite = bool(torch.isfinite(traces).all().item())
     pts = g.points
     value = pts * args.steps / wall / 1e9
-    exchange = ("read by the next halo call from zero-filled receive slots (no unpack pass)" if args.ghosts == "slots"
-                else "unpacked from zero-filled receive slots")
+    if args.halo == "shell":
+        step_text = ("halo-first: a shell call computing the 6 x 4-wide faces into a send buffer, then one call "
+                     "over every owned cell (the shell again included), both reading the ghosts from "
+                     "zero-filled receive slots (no unpack pass)")
+    elif args.ghosts == "slots":
+        step_text = ("halo-first with 6 x 4-wide faces packed to a send buffer and read by the next halo call "
+                     "from zero-filled receive slots (no unpack pass)")
+    else:
+        step_text = "halo-first with 6 x 4-wide faces packed to a send buffer and unpacked from zero-filled receive slots"
     result = {
         "metric": "Gpoint-updates/s", "value": round(value, 3), "unit": "Gpts/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"forward {n}^3 layered (20 layers 1500-4500 m/s, sigma 3, seed 2), radius-4 "
                                f"8th-order star, leapfrog, dt at half the stability limit, 15 Hz Ricker at the "
-                               f"centre, 16-cell sponge, halo-first with 6 x 4-wide faces packed to a send buffer and "
-                               f"{exchange}, {args.steps} timed steps",
+                               f"centre, 16-cell sponge, {step_text}, {args.steps} timed steps",
                    "grid": [n, n, n], "h_m": h, "dt_s": dt, "schedule": args.schedule, "ghosts": args.ghosts,
+                   "halo": args.halo,
                    "receivers": int(len(rec))},
         "finite": finite,
     }
-    # roofline of the dominant kernel (interior stencil), timed with HIP events on its own stream
+    # roofline of the dominant kernel (the whole-block call, or the interior call with --halo region),
+    # timed with HIP events on the stream it runs on
     if prop.interior_events:
         ms = [a.elapsed_time(b) for a, b in prop.interior_events]
         avg_s = sum(ms) / len(ms) / 1e3
-        wx, hy, R = _abi.rtm_halo_region(g.c)
-        interior_pts = (n - 2 * wx) * (n - 2 * hy) * (n - 2 * R)
-        achieved = BYTES_PER_POINT * interior_pts / avg_s / 1e9
+        if args.halo == "shell":
+            kernel, cells = "rtm_step_whole_slots", pts
+        else:
+            wx, hy, R = _abi.rtm_halo_region(g.c)
+            kernel, cells = "rtm_step_interior", (n - 2 * wx) * (n - 2 * hy) * (n - 2 * R)
+        achieved = BYTES_PER_POINT * cells / avg_s / 1e9
         traffic = None
         if os.path.exists(TRAFFIC_FILE):
             with open(TRAFFIC_FILE) as f:
                 t = json.load(f)
-            if t.get("kernel_source_sha256_16") == kernel_source_hash() and t.get("n") == n:
+            if (t.get("kernel_source_sha256_16") == kernel_source_hash() and t.get("n") == n
+                    and t.get("kernel") == kernel):
                 traffic = t.get("hbm_bytes_per_launch")
         result["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                              "kernel": "rtm_step_interior", "avg_us": round(avg_s * 1e6, 2),
+                              "kernel": kernel, "avg_us": round(avg_s * 1e6, 2),
                               "launches_timed": len(ms),
-                              "algorithmic_bytes_per_launch": BYTES_PER_POINT * interior_pts}
+                              "algorithmic_bytes_per_launch": BYTES_PER_POINT * cells}
         # whole-step roofline with the halo phases, counting the bytes each phase must move: the
         # stencil 16 B per cell; per face cell, the halo call stores the computed value into its
         # send slot (4 B; the value is in registers, not read back) and the received ghost is read
-        # from its slot by the next halo call (4 B), or read and written into the ring by the
-        # unpack (8 B, ghosts="ring")
+        # from its slot by the next step (4 B), or read and written into the ring by the unpack (8 B,
+        # ghosts="ring"); the shell form's second computation of the face cells is not counted
         face_cells = 6 * 4 * n * n
         step_bytes = BYTES_PER_POINT * pts + (8 if args.ghosts == "slots" else 12) * face_cells
         result["step_hbm_frac"] = round(step_bytes / (wall / args.steps) / 1e9 / HBM_PEAK_GBS, 4)
@@ -263,14 +287,23 @@ def time_phases(g, prop, traces, reps: int = 20):
     st = torch.cuda.current_stream()
     c = g.c
     u_nxt, u_cur, u_prv = prop.u_prv, prop.u_cur, prop.u_prv
+    recv = prop._recv_for(prop.n) if prop.ghosts == "slots" else prop.recv
+    dense, shell_out = None, prop.send
+    if prop.kappa_faces is not None:         # as the next step would run it: its own send buffer
+        nb = len(prop.send_bufs)
+        dense = (prop.send_bufs[(prop.n - 1) % nb], prop.send_bufs[(prop.n - 2) % nb], prop.kappa_faces)
+        shell_out = prop.send_bufs[prop.n % nb]
     phases = {
         "halo": lambda: _abi.rtm_step_halo(c, u_nxt, u_cur, u_prv, prop.kappa, st),
         "pack": lambda: _abi.rtm_pack_halo(c, u_nxt, prop.send, st),
         "halo_pack": lambda: _abi.rtm_step_halo_pack(c, u_nxt, u_cur, u_prv, prop.kappa, prop.send, st),
-        "halo_pack_slots": lambda: _abi.rtm_step_halo_pack_slots(c, u_nxt, u_cur, u_prv, prop.kappa, prop.recv,
+        "halo_pack_slots": lambda: _abi.rtm_step_halo_pack_slots(c, u_nxt, u_cur, u_prv, prop.kappa, recv,
                                                                  prop.send, st),
         "unpack": lambda: _abi.rtm_unpack_halo(c, u_nxt, prop.recv, st),
         "interior": lambda: _abi.rtm_step_interior(c, u_nxt, u_cur, u_prv, prop.kappa, st),
+        "shell_pack": lambda: _abi.rtm_step_shell_pack(c, u_cur, u_prv, prop.kappa, recv, shell_out, st,
+                                                       dense=dense),
+        "whole_slots": lambda: _abi.rtm_step_whole_slots(c, u_nxt, u_cur, u_prv, prop.kappa, recv, st),
         "record": lambda: _abi.rtm_record(c, u_nxt, prop.rec_idx, traces, prop.nrec, st),
     }
     out = {}

@@ -238,6 +238,38 @@ int rtm_step_halo_pack(const rtm_grid *grid, float *u_nxt, const float *u_cur, c
 int rtm_step_halo_pack_slots(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv,
                              const float *kappa, const float *const recv[6], float *faces, hipStream_t stream);
 
+/* Phases 1 and 2 (section II) as a shell call: the new values of the owned cells within R of a face
+ * (u^{n+1} from u_cur = u^n, u_prv = u^{n-1}, kappa), written to `faces` only (the slots of
+ * rtm_face_layout, bitwise what rtm_pack_halo would copy out of a u^{n+1} computed by any other
+ * step call).  No field is written: the cells are computed again by rtm_step_whole_slots, which
+ * writes u^{n+1}.  The shell call reads u_prv, so a schedule that runs the two calls concurrently
+ * must not let rtm_step_whole_slots overwrite u_prv in place.  The ghosts of u_cur come from the
+ * receive slots recv[f] (device; the layout rtm_unpack_halo reads; a zero-filled slot is a
+ * physical boundary); u_cur's ghost ring is not read.  faces_cur, faces_prv, faces_kappa (device,
+ * all three or none): face buffers holding what rtm_pack_halo copies out of u_cur, u_prv and kappa
+ * (a schedule has the first two as the face buffers of its last two steps); with them the cells of
+ * the x faces read u^n, u^{n-1} and kappa densely from there instead of one 16-byte piece per row of
+ * each field (the result is the same bits; wrong copies give wrong faces).  Radius 4 with the
+ * vectorised layout, nx % 4 == 0, six non-NULL 16-byte aligned slots and 16-byte aligned face
+ * buffers: RTM_EINVAL otherwise.  `faces` must not overlap u_cur, u_prv, kappa or a face copy, and
+ * no slot may overlap `faces` (RTM_EALIAS).  Injected sources in face cells must be re-copied
+ * afterwards (rtm_pack_cells). */
+int rtm_step_shell_pack(const rtm_grid *grid, const float *u_cur, const float *u_prv, const float *kappa,
+                        const float *faces_cur, const float *faces_prv, const float *faces_kappa,
+                        const float *const recv[6], float *faces, hipStream_t stream);
+
+/* Phase 4 (section II) over every owned cell, with the previous step's phase 5 folded in: the result
+ * of rtm_unpack_halo(u_cur, recv) followed by rtm_step_whole, bitwise (u_nxt's owned cells), except
+ * that u_cur's ghost ring is neither written nor read: the ghosts come from the receive slots, as in
+ * rtm_step_halo_pack_slots.  With rtm_step_shell_pack it forms a halo-first step whose halo call only
+ * produces the faces for the exchange (cells within R of a face computed twice, about 5% of the
+ * cells at 512^3) and whose second call covers the whole block in full-width tiles.  u_nxt may be
+ * u_prv (in place) unless a shell call of the same step may still read u_prv.  Requires radius 4
+ * with the vectorised layout, nx % 4 == 0 and six non-NULL 16-byte aligned slots: RTM_EINVAL
+ * otherwise; no slot may overlap u_nxt (RTM_EALIAS); the field rules of rtm_step_whole apply. */
+int rtm_step_whole_slots(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv,
+                         const float *kappa, const float *const recv[6], hipStream_t stream);
+
 /* For each of the n padded indices idx (int64, device) of owned cells, copy u[idx] into every face
  * slot that holds that cell (as rtm_pack_halo would); indices of cells outside every face, or not
  * owned, are skipped.  Used after injecting sources into face cells of a level packed by

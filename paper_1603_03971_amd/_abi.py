@@ -64,6 +64,8 @@ def _load():
         "rtm_pack_halo": ([gp, vp, vp, vp], ctypes.c_int),
         "rtm_step_halo_pack": ([gp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "rtm_step_halo_pack_slots": ([gp, vp, vp, vp, vp, ctypes.POINTER(vp), vp, vp], ctypes.c_int),
+        "rtm_step_shell_pack": ([gp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp), vp, vp], ctypes.c_int),
+        "rtm_step_whole_slots": ([gp, vp, vp, vp, vp, ctypes.POINTER(vp), vp], ctypes.c_int),
         "rtm_pack_cells": ([gp, vp, vp, i32, vp, vp], ctypes.c_int),
         "rtm_unpack_halo": ([gp, vp, ctypes.POINTER(vp), vp], ctypes.c_int),
         "rtm_inject": ([gp, vp, vp, vp, vp, i32, vp], ctypes.c_int),
@@ -251,6 +253,22 @@ def rtm_step_halo_pack_slots(grid, u_nxt, u_cur, u_prv, kappa, recv, faces, stre
     arr = (ctypes.c_void_p * 6)(*[_p(f) for f in recv])
     _check(_lib.rtm_step_halo_pack_slots(ctypes.byref(grid), _p(u_nxt), _p(u_cur), _p(u_prv), _p(kappa), arr,
                                          _p(faces), _s(stream)), "rtm_step_halo_pack_slots")
+
+
+def rtm_step_shell_pack(grid, u_cur, u_prv, kappa, recv, faces, stream=None, dense=None):
+    """`recv`: six receive-slot addresses (tensor or int) holding u_cur's ghost faces.  `dense`: None or
+    the face buffers (faces_cur, faces_prv, faces_kappa) of u_cur, u_prv and kappa."""
+    arr = (ctypes.c_void_p * 6)(*[_p(f) for f in recv])
+    fc, fp, fk = dense if dense is not None else (None, None, None)
+    _check(_lib.rtm_step_shell_pack(ctypes.byref(grid), _p(u_cur), _p(u_prv), _p(kappa), _p(fc), _p(fp), _p(fk),
+                                    arr, _p(faces), _s(stream)), "rtm_step_shell_pack")
+
+
+def rtm_step_whole_slots(grid, u_nxt, u_cur, u_prv, kappa, recv, stream=None):
+    """`recv`: six receive-slot addresses (tensor or int) holding u_cur's ghost faces."""
+    arr = (ctypes.c_void_p * 6)(*[_p(f) for f in recv])
+    _check(_lib.rtm_step_whole_slots(ctypes.byref(grid), _p(u_nxt), _p(u_cur), _p(u_prv), _p(kappa), arr,
+                                     _s(stream)), "rtm_step_whole_slots")
 
 
 def rtm_pack_cells(grid, u, idx, n, faces, stream=None):

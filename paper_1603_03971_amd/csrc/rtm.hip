@@ -109,9 +109,10 @@ __device__ __forceinline__ float4 dpp_shr1(float4 v) { return make_float4(dpp_sh
 __device__ __forceinline__ float4 dpp_shl1(float4 v) { return make_float4(dpp_shl1(v.x), dpp_shl1(v.y), dpp_shl1(v.z), dpp_shl1(v.w)); }
 
 // Variants of the tiled kernel (template flags): streaming hints on the once-used streams, the
-// x neighbours of a thread's float4 taken from the adjacent lanes' registers instead of LDS, and (the
-// radius-4 halo call) the ghost cells of u_cur read from the receive slots instead of the ghost ring.
-enum { FL_NT = 1, FL_XSHUF = 2, FL_SLOTS = 4 };
+// x neighbours of a thread's float4 taken from the adjacent lanes' registers instead of LDS, (radius-4
+// forward launches) the ghost cells of u_cur read from the receive slots instead of the ghost ring, and
+// (the shell call) the computed cells written to the face buffer only, not to u_nxt.
+enum { FL_NT = 1, FL_XSHUF = 2, FL_SLOTS = 4, FL_PONLY = 8 };
 __device__ __forceinline__ float el(const float4 &v, int e)
 {
     return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
@@ -242,12 +243,14 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
     constexpr bool STREAM = (FL & FL_NT) != 0;
     constexpr bool XS = (FL & FL_XSHUF) != 0;
     constexpr bool GS = (FL & FL_SLOTS) != 0;
+    constexpr bool PONLY = (FL & FL_PONLY) != 0;
     auto ldo = [](const float *p) { return STREAM ? ld4_nt(p) : ld4(p); };   // u_prv / kappa operands
     // OP_ADJOINT: the stencil field is kappa g mu_a, formed here from two loads per ring element (uc =
     // mu_a, rk = kappa) instead of being read from a field written by a separate pass; the ring
     // elements of cells outside the owned block are zero, as the ghosts of such a field would be.
     constexpr bool WR = (OP == OP_ADJOINT);
-    static_assert(!GS || (R == 4 && PACK && !WR), "ghosts from slots: the radius-4 forward halo call only");
+    static_assert(!GS || (R == 4 && !WR), "ghosts from slots: radius-4 forward launches only");
+    static_assert(!PONLY || (PACK && GS), "face buffer only: the shell call");
     constexpr int NT = BX * BY;
     constexpr int TX = 4 * BX;
     constexpr int TY = BY;
@@ -586,10 +589,13 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
             float *dst = un + pc + dz;
             if (full) {
                 const float4 o4 = make_float4(out[0], out[1], out[2], out[3]);
-                if constexpr (STREAM)
+                if constexpr (PONLY) {
+                    // the shell call: u_nxt is written by the call that updates every owned cell
+                } else if constexpr (STREAM) {
                     st4_nt(dst, o4);
-                else
+                } else {
                     st4(dst, o4);
+                }
                 if constexpr (PACK) {
                     // the float4 is one row of a face's R-thick layer (R = 4, nx % 4 == 0): copy it into
                     // each face slot that holds it, in the slot order of rtm_pack_halo
@@ -601,7 +607,7 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
                     if (k < R) st4(po.faces + po.off[4] + ((long long)k * ny + y) * nx + x, o4);
                     if (k >= g.nz - R) st4(po.faces + po.off[5] + ((long long)(k - (g.nz - R)) * ny + y) * nx + x, o4);
                 }
-            } else {
+            } else if constexpr (!PONLY) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
                     if (e >= elo && e < ehi) dst[e] = out[e];
@@ -612,6 +618,59 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
     };
 #pragma unroll 1
     for (k0_ = zs; k0_ < ze; k0_ += QR) unroll_seq(plane, std::make_integer_sequence<int, QR>{});
+}
+
+
+// The shell call's x strips (radius 4: the float4 at x = 0 or x = nx - 4 of the rows y in [4, ny - 4),
+// z in [4, nz - 4)) from dense face copies: one thread per row and side.  u^n at the strip and its y and
+// z neighbours come from fc (u^n's face buffer), u^{n-1} from fp and kappa from fk (the same layout:
+// the face slots 0 and 1 at off0 and off1), the x ghosts from gl / gr (the receive slots 0 and 1), and
+// only the float4 on the inside (x = 4 or nx - 8) from the field uc.  The result goes to the face
+// buffer `faces` only.  Same arithmetic, in the same order, as k_tiled.
+__global__ __launch_bounds__(kThreads) void k_xface(Geo g, const float *__restrict__ uc, const float *__restrict__ fc,
+                                                    const float *__restrict__ fp, const float *__restrict__ fk,
+                                                    const float *__restrict__ gl, const float *__restrict__ gr,
+                                                    float *__restrict__ faces, long long off0, long long off1)
+{
+    constexpr int R = 4;
+    const long long ny = g.ny, wy = g.ny - 2 * R, per = wy * (g.nz - 2 * R);
+    float c[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) c[m] = g.c[m];
+    for (long long t = first_item(); t < 2 * per; t += item_stride()) {
+        const int side = t >= per ? 1 : 0;
+        const long long r = t - side * per;
+        const int y = R + (int)(r % wy), z = R + (int)(r / wy);
+        const long long off = side ? off1 : off0;
+        auto at = [&](int yy, int zz) { return off + ((long long)zz * ny + yy) * R; };
+        const float4 xc = ld4(fc + at(y, z));
+        const float4 xl = side ? ld4(uc + pidx(g, g.nx - 2 * R, y, z)) : ld4(gl + (at(y, z) - off));
+        const float4 xr = side ? ld4(gr + (at(y, z) - off)) : ld4(uc + pidx(g, R, y, z));
+        float4 ym[R], yp[R], zm[R], zp[R];
+#pragma unroll
+        for (int m = 1; m <= R; ++m) {
+            ym[m - 1] = ld4(fc + at(y - m, z));
+            yp[m - 1] = ld4(fc + at(y + m, z));
+            zm[m - 1] = ld4(fc + at(y, z - m));
+            zp[m - 1] = ld4(fc + at(y, z + m));
+        }
+        const float4 pv = ld4(fp + at(y, z)), kv = ld4(fk + at(y, z));
+        const int x0 = side ? g.nx - R : 0;
+        const float gz = g.gz[z];
+        const float xs[12] = {xl.x, xl.y, xl.z, xl.w, xc.x, xc.y, xc.z, xc.w, xr.x, xr.y, xr.z, xr.w};
+        float out[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            float sm[R];
+#pragma unroll
+            for (int m = 1; m <= R; ++m)
+                sm[m - 1] = axis_sum(xs[4 + e - m], xs[4 + e + m], el(ym[m - 1], e), el(yp[m - 1], e),
+                                     el(zm[m - 1], e), el(zp[m - 1], e));
+            const float gxy = g.gx[x0 + e] * g.gy[y];
+            out[e] = point_op<R, OP_FORWARD>(xs[4 + e], sm, el(pv, e), el(kv, e), gxy * gz, c);
+        }
+        st4(faces + at(y, z), make_float4(out[0], out[1], out[2], out[3]));
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1359,14 +1418,13 @@ int balanced_zchunk(int tiles, int wz, int R, int cus, int waves)
     return wz;
 }
 
-// Launch the tiled kernel over up to kMaxBoxes boxes {x0, x1, y0, y1, z0, z1} (empty ones skipped).
-// rk: kappa for OP_ADJOINT (see k_tiled), unused otherwise.
-template <int R, int BX, int BY, int OP, bool PACK = false, int FL = 0>
-int launch_tiled(const Geo &g, float *un, const float *uc, const float *up, const float *kap, const int (*boxes)[6],
-                 int nbox, hipStream_t st, const PackOut *po = nullptr, const float *rk = nullptr, int remap = -1)
+// The box list of a tiled launch over up to kMaxBoxes boxes {x0, x1, y0, y1, z0, z1} (empty ones
+// skipped), its z chunking and workgroup order; zc_hint > 0: the z chunk when RTM_OPT_ZCHUNK is
+// automatic.  RTM_EINVAL when the launch would need 2^31 workgroups or more.
+template <int R, int BX, int BY>
+int make_boxlist(const Geo &g, const int (*boxes)[6], int nbox, int remap, int zc_hint, BoxList &bl)
 {
     constexpr int TX = 4 * BX;
-    BoxList bl;
     std::memset(&bl, 0, sizeof(bl));
     int tiles = 0, wz = 0;
     for (int i = 0; i < nbox; ++i) {
@@ -1388,8 +1446,11 @@ int launch_tiled(const Geo &g, float *un, const float *uc, const float *up, cons
         }
     }
     if (bl.nbox == 0) return RTM_OK;
+    (void)g;
     int zc = g_opt.zchunk.load(std::memory_order_relaxed);
-    if (zc <= 0 && tiles > 0 && R <= 2) {
+    if (zc <= 0 && zc_hint > 0) {
+        zc = zc_hint;
+    } else if (zc <= 0 && tiles > 0 && R <= 2) {
         // Narrow stencils: short chunks.  A chunk re-reads 2R planes it does not write, only 25% at
         // 16 planes for R = 2, and several short waves of workgroups balance better than one long
         // one (384^3 whole step: 237 us at 16 planes against 266 us for one wave).
@@ -1415,11 +1476,24 @@ int launch_tiled(const Geo &g, float *un, const float *uc, const float *up, cons
     if (nb >= (1ll << 31)) return RTM_EINVAL;
     bl.nblk = (int)nb;
     bl.remap = remap >= 0 ? remap : g_opt.xcd_remap.load(std::memory_order_relaxed);
+    return RTM_OK;
+}
+
+// Launch the tiled kernel over up to kMaxBoxes boxes (make_boxlist).
+// rk: kappa for OP_ADJOINT (see k_tiled), unused otherwise.
+template <int R, int BX, int BY, int OP, bool PACK = false, int FL = 0>
+int launch_tiled(const Geo &g, float *un, const float *uc, const float *up, const float *kap, const int (*boxes)[6],
+                 int nbox, hipStream_t st, const PackOut *po = nullptr, const float *rk = nullptr, int remap = -1,
+                 int zc_hint = 0)
+{
+    BoxList bl;
+    const int rc = make_boxlist<R, BX, BY>(g, boxes, nbox, remap, zc_hint, bl);
+    if (rc != RTM_OK || bl.nblk == 0) return rc;
     PackOut pk;
     std::memset(&pk, 0, sizeof(pk));
     if (po) pk = *po;
-    hipLaunchKernelGGL((k_tiled<R, BX, BY, OP, PACK, FL>), dim3((unsigned)nb), dim3(BX * BY), 0, st, g, un, uc, up, kap,
-                       bl, pk, rk);
+    hipLaunchKernelGGL((k_tiled<R, BX, BY, OP, PACK, FL>), dim3((unsigned)bl.nblk), dim3(BX * BY), 0, st, g, un, uc, up,
+                       kap, bl, pk, rk);
     return launch_status();
 }
 
@@ -1446,6 +1520,14 @@ int launch_tiled_variant(int var, const Geo &g, float *un, const float *uc, cons
     // ghosts from the receive slots for the radius-4 halo call that packs
     const int fl = g_opt.tile_flags.load(std::memory_order_relaxed);
     if constexpr (R == 4 && OP == OP_FORWARD && PACK) {
+        if (slots) {
+            if (fl & FL_NT)
+                return launch_tiled_flags<R, OP, PACK, FL_NT | FL_SLOTS>(var, g, un, uc, up, kap, boxes, nbox, st, po,
+                                                                         rk, remap);
+            return launch_tiled_flags<R, OP, PACK, FL_SLOTS>(var, g, un, uc, up, kap, boxes, nbox, st, po, rk, remap);
+        }
+    }
+    if constexpr (R == 4 && OP == OP_FORWARD && !PACK) {
         if (slots) {
             if (fl & FL_NT)
                 return launch_tiled_flags<R, OP, PACK, FL_NT | FL_SLOTS>(var, g, un, uc, up, kap, boxes, nbox, st, po,
@@ -1551,6 +1633,46 @@ int launch_halo_pack(const Geo &g, float *un, const float *uc, const float *up, 
     const int nb = halo_boxes(g, r, boxes);
     return launch_tiled_variant<4, OP_FORWARD, true>(g_opt.halo_variant.load(std::memory_order_relaxed), g, un, uc,
                                                      up, kap, boxes, nb, st, &po, nullptr, slots);
+}
+
+// The shell call (radius 4, ghosts from po.recv): the owned cells within R of a face, written to the
+// face buffer only.  The two z slabs and the two y strips between them: one launch of 32x8-thread
+// tiles in 16-plane z chunks (27 us at 512^3).  The two 4-column x strips between those: with dense
+// face copies of u_cur, u_prv and kappa (fc, fp, fk), k_xface, which reads one float4 per row from the
+// field; otherwise 2x32-thread tiles (8 columns: the centre float4 and its inside neighbour) in
+// 32-plane chunks, which read three float4s of separate lines per row and plane from the fields
+// (38 us at 512^3).
+int launch_shell_pack(const Geo &g, const float *uc, const float *up, const float *kap, const float *fc,
+                      const float *fp, const float *fk, const PackOut &po, hipStream_t st)
+{
+    constexpr int R = 4;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int zl = std::min(R, nz), zh = std::max(R, nz - R), yl = std::min(R, ny), yh = std::max(R, ny - R);
+    const int slabs[4][6] = {
+        {0, nx, 0, ny, 0, zl},                 // -Z slab
+        {0, nx, 0, ny, zh, nz},                // +Z slab
+        {0, nx, 0, yl, R, nz - R},             // -Y strip
+        {0, nx, yh, ny, R, nz - R},            // +Y strip
+    };
+    const int cols[2][6] = {
+        {0, std::min(R, nx), R, ny - R, R, nz - R},          // -X strip
+        {std::max(R, nx - R), nx, R, ny - R, R, nz - R},     // +X strip
+    };
+    // u_nxt is never written (FL_PONLY); the tile code forms its addresses from uc
+    float *un = const_cast<float *>(uc);
+    const bool nt = (g_opt.tile_flags.load(std::memory_order_relaxed) & FL_NT) != 0;
+    constexpr int F1 = FL_NT | FL_SLOTS | FL_PONLY, F0 = FL_SLOTS | FL_PONLY;
+    int rc = nt ? launch_tiled<R, 32, 8, OP_FORWARD, true, F1>(g, un, uc, up, kap, slabs, 4, st, &po, nullptr, -1, 16)
+                : launch_tiled<R, 32, 8, OP_FORWARD, true, F0>(g, un, uc, up, kap, slabs, 4, st, &po, nullptr, -1, 16);
+    if (rc != RTM_OK) return rc;
+    if (fc && nx >= 2 * R && ny > 2 * R && nz > 2 * R) {
+        const long long n = 2ll * (ny - 2 * R) * (nz - 2 * R);
+        hipLaunchKernelGGL(k_xface, dim3(blocks_for(n)), dim3(kThreads), 0, st, g, uc, fc, fp, fk, po.recv[0], po.recv[1],
+                           po.faces, po.off[0], po.off[1]);
+        return launch_status();
+    }
+    return nt ? launch_tiled<R, 2, 32, OP_FORWARD, true, F1>(g, un, uc, up, kap, cols, 2, st, &po, nullptr, -1, 32)
+              : launch_tiled<R, 2, 32, OP_FORWARD, true, F0>(g, un, uc, up, kap, cols, 2, st, &po, nullptr, -1, 32);
 }
 
 template <int R, int OP = OP_FORWARD>
@@ -1664,6 +1786,19 @@ int launch_adjoint(const Geo &g, float *mu_out, const float *mu_a, const float *
     if (var == 4 || var == 5) var = 0;
     return launch_tiled_variant<R, OP_ADJOINT>(var, g, mu_out, mu_a, mu_a, mu_b, boxes, 1, st, nullptr, kappa, false,
                                                remap);
+}
+
+// Every owned cell in one launch with the ghosts of u_cur read from po.recv (radius 4): the one-launch
+// call's tiles and settings, except that the 128-register tiles (32 x 16, 16 x 32), which the slot
+// addressing would spill, take 32 x 8.
+int launch_whole_slots(const Geo &g, float *un, const float *uc, const float *up, const float *kap, const PackOut &po,
+                       hipStream_t st)
+{
+    const int boxes[1][6] = {{0, g.nx, 0, g.ny, 0, g.nz}};
+    int var, remap;
+    whole_settings(g, 4, var, remap);
+    if (var == 4 || var == 5) var = 1;
+    return launch_tiled_variant<4, OP_FORWARD>(var, g, un, uc, up, kap, boxes, 1, st, &po, nullptr, true, remap);
 }
 
 bool faces_vec(const Geo &g, const float *u)
@@ -2043,6 +2178,70 @@ int rtm_step_halo_pack_slots(const rtm_grid *grid, float *u_nxt, const float *u_
         po.recv[f] = recv[f];
     }
     return launch_halo_pack(g, u_nxt, u_cur, u_prv, kappa, po, stream, true);
+}
+
+int rtm_step_shell_pack(const rtm_grid *grid, const float *u_cur, const float *u_prv, const float *kappa,
+                        const float *faces_cur, const float *faces_prv, const float *faces_kappa,
+                        const float *const recv[6], float *faces, hipStream_t stream)
+{
+    const Marker mark("rtm_step_shell_pack");
+    int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (!u_cur || !u_prv || !kappa || !faces || !recv) return RTM_EINVAL;
+    for (int f = 0; f < 6; ++f)
+        if (!recv[f] || !aligned16(recv[f])) return RTM_EINVAL;
+    const bool dense = faces_cur != nullptr;
+    if (dense != (faces_prv != nullptr) || dense != (faces_kappa != nullptr)) return RTM_EINVAL;
+    if (dense && !(aligned16(faces_cur) && aligned16(faces_prv) && aligned16(faces_kappa))) return RTM_EINVAL;
+    long long off[7];
+    fill_face_offsets(grid, off);
+    const long long tot = padded_total(grid);
+    if (ranges_overlap(faces, off[6], u_cur, tot) || ranges_overlap(faces, off[6], u_prv, tot) ||
+        ranges_overlap(faces, off[6], kappa, tot))
+        return RTM_EALIAS;
+    for (int f = 0; f < 6; ++f)   // what this call writes must not be what it reads
+        if (ranges_overlap(recv[f], off[f + 1] - off[f], faces, off[6])) return RTM_EALIAS;
+    if (dense && (ranges_overlap(faces_cur, off[6], faces, off[6]) || ranges_overlap(faces_prv, off[6], faces, off[6]) ||
+                  ranges_overlap(faces_kappa, off[6], faces, off[6])))
+        return RTM_EALIAS;
+    const Geo g = make_geo(grid);
+    if (!(g.R == 4 && vector_path(g, const_cast<float *>(u_cur), u_cur, u_prv, kappa) && faces_vec(g, u_cur) &&
+          aligned16(faces)))
+        return RTM_EINVAL;
+    st = check_device();
+    if (st != RTM_OK) return st;
+    PackOut po;
+    po.faces = faces;
+    for (int f = 0; f < 6; ++f) {
+        po.off[f] = off[f];
+        po.recv[f] = recv[f];
+    }
+    return launch_shell_pack(g, u_cur, u_prv, kappa, faces_cur, faces_prv, faces_kappa, po, stream);
+}
+
+int rtm_step_whole_slots(const rtm_grid *grid, float *u_nxt, const float *u_cur, const float *u_prv,
+                         const float *kappa, const float *const recv[6], hipStream_t stream)
+{
+    const Marker mark("rtm_step_whole_slots");
+    int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (!recv) return RTM_EINVAL;
+    for (int f = 0; f < 6; ++f)
+        if (!recv[f] || !aligned16(recv[f])) return RTM_EINVAL;
+    long long off[7];
+    fill_face_offsets(grid, off);
+    const long long tot = padded_total(grid);
+    if (!u_nxt || !u_cur || !u_prv || !kappa) return RTM_EINVAL;
+    for (int f = 0; f < 6; ++f)   // what this call writes must not be what it reads
+        if (ranges_overlap(recv[f], off[f + 1] - off[f], u_nxt, tot)) return RTM_EALIAS;
+    const Geo g = make_geo(grid);
+    if (!(g.R == 4 && vector_path(g, u_nxt, u_cur, u_prv, kappa) && faces_vec(g, u_nxt))) return RTM_EINVAL;
+    st = step_common(grid, u_nxt, u_cur, u_prv, kappa);
+    if (st != RTM_OK) return st;
+    PackOut po;
+    std::memset(&po, 0, sizeof(po));
+    for (int f = 0; f < 6; ++f) po.recv[f] = recv[f];
+    return launch_whole_slots(g, u_nxt, u_cur, u_prv, kappa, po, stream);
 }
 
 int rtm_pack_cells(const rtm_grid *grid, const float *u, const int64_t *idx, int32_t n, float *faces,

@@ -6,8 +6,12 @@
       Run it under `rocprofv3 --pmc FETCH_SIZE` and, separately, `rocprofv3 --pmc WRITE_SIZE`.
 
   python3 -m paper_1603_03971_amd.profile halo [--n 512] [--launches 10]
-      the same for the halo call as the serial schedule runs it (rtm_step_halo_pack: the z slabs,
+      the same for the halo call of the halo-region form (rtm_step_halo_pack_slots: the z slabs,
       y strips and x strips of the halo region, also writing the six faces), for its counters.
+
+  python3 -m paper_1603_03971_amd.profile whole-slots [--n 512] [--launches 10]
+      the same for the benchmark's dominant call (the shell form's rtm_step_whole_slots: every
+      owned cell, the ghosts read from zero-filled receive slots).
 
   python3 -m paper_1603_03971_amd.profile conv [--n 384] [--launches 10]
       runs the corrector network's forward pass (three 3x3x3 convolutions, 16 channels, BF16 MFMA)
@@ -82,7 +86,9 @@ def run_interior(n: int, launches: int, call: str = "interior"):
     for _ in range(launches):
         if call == "interior":
             _abi.rtm_step_interior(g.c, up, u, up, kap, s)
-        else:                                  # the benchmark's halo call: ghosts from the slots, packs
+        elif call == "whole_slots":            # the shell form's call over every owned cell
+            _abi.rtm_step_whole_slots(g.c, up, u, up, kap, slots, s)
+        else:                                  # the halo-region form's halo call: ghosts from the slots, packs
             _abi.rtm_step_halo_pack_slots(g.c, up, u, up, kap, slots, faces, s)
     a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
@@ -90,7 +96,8 @@ def run_interior(n: int, launches: int, call: str = "interior"):
     torch.cuda.synchronize()
     wx, hy, R = _abi.rtm_halo_region(g.c)
     interior = (n - 2 * wx) * (n - 2 * hy) * (n - 2 * R)
-    print(json.dumps({f"{call}_points": interior if call == "interior" else n**3 - interior, "copy_bytes": COPY_BYTES}))
+    points = {"interior": interior, "whole_slots": n**3}.get(call, n**3 - interior)
+    print(json.dumps({f"{call}_points": points, "copy_bytes": COPY_BYTES}))
 
 
 # The hot kernels of the forward, RTM and gradient paths, each launched `launches` times on the n^3
@@ -107,12 +114,19 @@ def kernel_table(n: int):
     interior = interior_cells(n)
     halo = cells - interior
     faces = 6 * 4 * n * n
+    slab_cells = 2 * 4 * n * n + 2 * 4 * n * (n - 8)        # the shell's z slabs and y strips
+    xface_cells = 2 * 4 * (n - 8) * (n - 8)                # the shell's x strips
     return {
         "interior": ("k_tiled<4, 16, 8, 0, false", 16 * interior, "16 B per interior cell"),
         "halo_pack": ("k_tiled<4, 16, 16, 0, true, 1>", 16 * halo + 4 * faces, "16 B per halo cell + 4 B per face cell"),
         "halo_pack_slots": ("k_tiled<4, 16, 16, 0, true, 5>", 16 * halo + 8 * faces,
                             "16 B per halo cell + 4 B per face cell out + 4 B per ghost cell in"),
-        "whole": ("k_tiled<4, 32, 8, 0, false", 16 * cells, "16 B per cell (also the scaled adjoint step)"),
+        "shell_slabs": ("k_tiled<4, 32, 8, 0, true, 13>", 16 * slab_cells,
+                        "16 B per shell cell of the z slabs and y strips (12 B in, 4 B to the face buffer)"),
+        "shell_xfaces": ("k_xface", 16 * xface_cells,
+                         "16 B per shell cell of the x strips (12 B in, 4 B to the face buffer)"),
+        "whole_slots": ("k_tiled<4, 32, 8, 0, false, 5>", 16 * cells, "16 B per cell"),
+        "whole": ("k_tiled<4, 32, 8, 0, false, 1>", 16 * cells, "16 B per cell (also the scaled adjoint step)"),
         "adjoint_direct": ("k_tiled<4, 32, 8, 1, false", 16 * cells, "16 B per cell: mu_a, kappa, mu_b in, mu out"),
         "gradient": ("k_tiled<4, 32, 8, 2, false", 16 * cells, "16 B per cell: u, mu, grad in, grad out"),
         "gradient_scaled": ("k_tiled<4, 32, 8, 3, false", 16 * cells, "16 B per cell: u, w, grad in, grad out"),
@@ -144,6 +158,9 @@ def run_kernels(n: int, launches: int):
     s = torch.cuda.current_stream()
     send, recv = g.faces(), g.faces()
     slots = g.face_slots(recv)
+    dense = (g.faces(), g.faces(), g.faces())
+    for src, dst in zip((a, b, kap), dense):
+        _abi.rtm_pack_halo(g.c, src, dst, s)
     work = g.field()
     codes = torch.empty(n ** 3, dtype=torch.int16, device="cuda")
     scales = torch.empty(n, dtype=torch.float32, device="cuda")
@@ -151,6 +168,8 @@ def run_kernels(n: int, launches: int):
         "interior": lambda: _abi.rtm_step_interior(g.c, c, a, b, kap, s),
         "halo_pack": lambda: _abi.rtm_step_halo_pack(g.c, c, a, b, kap, send, s),
         "halo_pack_slots": lambda: _abi.rtm_step_halo_pack_slots(g.c, c, a, b, kap, slots, send, s),
+        "shell": lambda: _abi.rtm_step_shell_pack(g.c, a, b, kap, slots, send, s, dense=dense),
+        "whole_slots": lambda: _abi.rtm_step_whole_slots(g.c, c, a, b, kap, slots, s),
         "whole": lambda: _abi.rtm_step_whole(g.c, c, a, b, kap, s),
         "adjoint_direct": lambda: _abi.rtm_adjoint_step(g.c, c, a, b, kap, work, s),
         "gradient": lambda: _abi.rtm_gradient_accumulate(g.c, c, a, b, s),
@@ -250,11 +269,16 @@ def run_corrected(n: int, steps: int, every: int):
     print(json.dumps({"coarse_cells": coarse.points, "steps": steps, "corrections": corr.applied}))
 
 
-# The radius-4 tiled kernels under the default options: the interior call's (16 x 8-thread tiles),
-# the halo call's (16 x 16) and the one-launch whole step's (32 x 8).
-# (name prefixes: the demangled names go on with the kernel's last template argument, e.g. ", false>")
+# The radius-4 kernels of the forward step under the default options at 512^3 (prefixes of the
+# demangled names): the interior call's tiles (16 x 8 threads), the halo-region call's (16 x 16), the
+# shell call's z slabs and y strips (32 x 8, faces only) and x strips, the whole-block call with the
+# ghosts from the slots (32 x 8) and the one-launch step's (32 x 8).
 INTERIOR_KERNEL = "k_tiled<4, 16, 8, 0, false"
 HALO_KERNEL = "k_tiled<4, 16, 16, 0, true"
+SHELL_KERNEL = "k_tiled<4, 32, 8, 0, true, 13>"
+XFACE_KERNEL = "k_xface"
+WHOLE_SLOTS_KERNEL = "k_tiled<4, 32, 8, 0, false, 5>"
+WHOLE_KERNEL = "k_tiled<4, 32, 8, 0, false, 1>"
 TILED_R4 = "k_tiled<4, "
 
 
@@ -438,7 +462,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def summarize(stats_dir, fetch_dir, write_dir, out, n, commands):
+def summarize(stats_dir, fetch_dir, write_dir, out, n, commands, kernel="whole_slots"):
+    """Kernel statistics of a benchmark run, the stencil launches by call, and the counter traffic of
+    the dominant call (`kernel`: "whole_slots" for the shell form, "interior" for the halo-region
+    form); writes the summary and the traffic record that bench.py reads."""
     stats = _csv(stats_dir, "*kernel_stats.csv")
     lines = ["# rocprofv3 summary: 512^3 layered forward workload", ""]
     lines += ["Commands:"] + [f"    {c}" for c in commands] + [""]
@@ -448,49 +475,47 @@ def summarize(stats_dir, fetch_dir, write_dir, out, n, commands):
         name = r["Name"].replace("(anonymous namespace)::", "")[:60]
         avg = float(r["AverageNs"]) / 1e3
         lines.append(f"    {name:60s} {r['Calls']:>6s} {avg:10.2f} {float(r['Percentage']):8.2f}")
-    # In the halo-first sequence the interior call is the first radius-4 tiled dispatch after a halo
-    # call (injections may come between them); the other radius-4 tiled dispatches that are not halo
-    # calls are one-launch whole steps.
-    trace = sorted(_csv(stats_dir, "*kernel_trace.csv"), key=lambda r: int(r["Start_Timestamp"]))
-    calls = {"rtm_step_interior": [], "rtm_step_whole (fused schedule)": []}
-    grids = {}
-    prev = ""                                  # the last radius-4 tiled dispatch
+    # the radius-4 stencil dispatches of the run by call, from their kernel names
+    kinds = [(WHOLE_SLOTS_KERNEL, "rtm_step_whole_slots"), (INTERIOR_KERNEL, "rtm_step_interior"),
+             (WHOLE_KERNEL, "rtm_step_whole (fused schedule)"), (SHELL_KERNEL, "rtm_step_shell_pack (slabs)"),
+             (XFACE_KERNEL, "rtm_step_shell_pack (x strips)"), (HALO_KERNEL, "rtm_step_halo_pack_slots")]
+    trace = _csv(stats_dir, "*kernel_trace.csv")
+    calls, grids = {}, {}
     for r in trace:
-        name = r["Kernel_Name"]
-        if TILED_R4 in name and HALO_KERNEL not in name:
-            what = "rtm_step_interior" if HALO_KERNEL in prev else "rtm_step_whole (fused schedule)"
-            calls[what].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
-            grids.setdefault(what, set()).add(int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"]))
-        if TILED_R4 in name:
-            prev = name
-    interior_avg_us = None
-    if any(calls.values()):
-        lines += ["", "Radius-4 tiled launches other than the halo call (kernel trace):",
-                  f"    {'call':32s} {'workgroups':>10s} {'calls':>6s} {'avg us':>10s}"]
-        for what, d in calls.items():
+        for sub, what in kinds:
+            if sub in r["Kernel_Name"]:
+                calls.setdefault(what, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+                grids.setdefault(what, set()).add(int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"]))
+                break
+    if calls:
+        lines += ["", "Radius-4 stencil launches by call (kernel trace):",
+                  f"    {'call':34s} {'workgroups':>10s} {'calls':>6s} {'avg us':>10s}"]
+        for _, what in kinds:
+            d = calls.get(what)
             if d:
                 wg = ",".join(str(x) for x in sorted(grids[what]))
-                lines.append(f"    {what:32s} {wg:>10s} {len(d):6d} {sum(d) / len(d):10.2f}")
-        d = calls["rtm_step_interior"]
-        interior_avg_us = sum(d) / len(d) if d else None
-    record = {"n": n, "kernel_source_sha256_16": kernel_source_hash(), "interior_avg_us_kernel_trace": interior_avg_us}
+                lines.append(f"    {what:34s} {wg:>10s} {len(d):6d} {sum(d) / len(d):10.2f}")
+    sub, name, pts = ((WHOLE_SLOTS_KERNEL, "rtm_step_whole_slots", n ** 3) if kernel == "whole_slots"
+                      else (INTERIOR_KERNEL, "rtm_step_interior", interior_cells(n)))
+    d = calls.get(name, [])
+    avg_us = sum(d) / len(d) if d else None
+    record = {"n": n, "kernel_source_sha256_16": kernel_source_hash(), "kernel": name, "avg_us_kernel_trace": avg_us}
     if fetch_dir and write_dir:
         fr, wr = _csv(fetch_dir, "*counter_collection.csv"), _csv(write_dir, "*counter_collection.csv")
-        f_int, nf = _counter(fr, INTERIOR_KERNEL, "FETCH_SIZE")
-        w_int, nw = _counter(wr, INTERIOR_KERNEL, "WRITE_SIZE")
+        f_k, nf = _counter(fr, sub, "FETCH_SIZE")
+        w_k, nw = _counter(wr, sub, "WRITE_SIZE")
         # the 1 GiB copy is the largest copy dispatch of the run
         f_cp, _ = _counter(fr, "opy", "FETCH_SIZE", largest=True)
         w_cp, _ = _counter(wr, "opy", "WRITE_SIZE", largest=True)
         kf = COPY_BYTES / (f_cp * 1024.0)
         kw = COPY_BYTES / (w_cp * 1024.0)
-        traffic = f_int * 1024.0 * kf + w_int * 1024.0 * kw
-        pts = interior_cells(n)
-        lines += ["", "HBM traffic of the interior stencil launch (counters, KiB per dispatch):",
-                  f"    FETCH_SIZE {f_int:.0f} KiB ({nf} dispatches), WRITE_SIZE {w_int:.0f} KiB ({nw} dispatches)",
+        traffic = f_k * 1024.0 * kf + w_k * 1024.0 * kw
+        lines += ["", f"HBM traffic of the {name} launch (counters, KiB per dispatch):",
+                  f"    FETCH_SIZE {f_k:.0f} KiB ({nf} dispatches), WRITE_SIZE {w_k:.0f} KiB ({nw} dispatches)",
                   f"    calibration with a plain 1 GiB device copy: FETCH x {kf:.3f}, WRITE x {kw:.3f}",
                   f"    traffic per launch {traffic / 1e6:.1f} MB; algorithmic 16 B x {pts} cells = {16 * pts / 1e6:.1f} MB"
                   f" (ratio {traffic / (16 * pts):.3f})"]
-        record.update({"fetch_kib": f_int, "write_kib": w_int, "fetch_factor": kf, "write_factor": kw,
+        record.update({"fetch_kib": f_k, "write_kib": w_k, "fetch_factor": kf, "write_factor": kw,
                        "hbm_bytes_per_launch": traffic, "algorithmic_bytes_per_launch": 16 * pts})
     text = "\n".join(lines) + "\n"
     with open(out, "w") as f:
@@ -517,8 +542,8 @@ def summarize_halo(fetch_dir, write_dir, out, n, commands, stats_dir=None):
     alg_w = 4 * (pts + fc)
     lines = [f"# rocprofv3 summary: HBM traffic of the halo call, {n}^3 layered forward workload", "",
              "Commands:"] + [f"    {c}" for c in commands] + [""]
-    lines += ["Halo call as the benchmark's serial schedule runs it (rtm_step_halo_pack_slots: two 4-plane z",
-              "slabs, two 8-row y strips, two 64-column x strips; the ghosts read from six receive slots,",
+    lines += ["Halo call of the halo-region form (bench.py --halo region; rtm_step_halo_pack_slots: two 4-plane",
+              "z slabs, two 8-row y strips, two 64-column x strips; the ghosts read from six receive slots,",
               "the six 4-wide faces written to the face buffer):",
               f"    cells {pts} (the interior call's box is the rest), face cells {fc} (as many ghost cells)",
               f"    FETCH_SIZE {f_h:.0f} KiB ({nf} dispatches), WRITE_SIZE {w_h:.0f} KiB ({nw} dispatches)",
@@ -532,7 +557,7 @@ def summarize_halo(fetch_dir, write_dir, out, n, commands, stats_dir=None):
         for r in _csv(stats_dir, "*kernel_stats.csv"):
             if HALO_KERNEL in r["Name"]:
                 us = float(r["AverageNs"]) / 1e3
-                lines.append(f"    kernel trace of the benchmark run: {us:.1f} us per launch -> "
+                lines.append(f"    kernel trace (--stats run): {us:.1f} us per launch -> "
                              f"{(alg_r + alg_w) / us / 1e6:.2f} TB/s algorithmic, "
                              f"{(rd + wt) / us / 1e6:.2f} TB/s moved")
                 break
@@ -548,7 +573,9 @@ def summarize_markers(trace_dir, out, commands):
     launched, from the first kernel after the step's first call to the last before the next step."""
     marks = sorted(_csv(trace_dir, "*marker_api_trace.csv"), key=lambda r: int(r["Start_Timestamp"]))
     kern = sorted(_csv(trace_dir, "*kernel_trace.csv"), key=lambda r: int(r["Start_Timestamp"]))
-    first = "rtm_step_halo_pack_slots"
+    names = {r["Function"] for r in marks}
+    first = "rtm_step_shell_pack" if "rtm_step_shell_pack" in names else "rtm_step_halo_pack_slots"
+    step_kernel = SHELL_KERNEL if first == "rtm_step_shell_pack" else HALO_KERNEL
     starts = [i for i, r in enumerate(marks) if r["Function"] == first]
     lines = ["# rocprofv3 summary: phase markers of the 512^3 halo-first benchmark step", "", "Commands:"]
     lines += [f"    {c}" for c in commands] + [""]
@@ -566,7 +593,7 @@ def summarize_markers(trace_dir, out, commands):
             lines.append(f"    {name:30s} {len(d):6d} {sum(d) / len(d):17.1f}")
         # the GPU side from the kernel trace alone: a step's kernels run from its halo call's kernel
         # to the next step's (the host enqueues ahead, so host and GPU times do not line up)
-        halo = [i for i, k in enumerate(kern) if HALO_KERNEL in k["Kernel_Name"]]
+        halo = [i for i, k in enumerate(kern) if step_kernel in k["Kernel_Name"]]
         per, rows = [], {}
         for a, b in zip(halo[:-1], halo[1:]):
             per.append((int(kern[b]["Start_Timestamp"]) - int(kern[a]["Start_Timestamp"])) / 1e3)
@@ -671,6 +698,9 @@ def main(argv=None):
     hl = sub.add_parser("halo")
     hl.add_argument("--n", type=int, default=512)
     hl.add_argument("--launches", type=int, default=10)
+    ws = sub.add_parser("whole-slots")
+    ws.add_argument("--n", type=int, default=512)
+    ws.add_argument("--launches", type=int, default=10)
     bh = sub.add_parser("summarize-halo")
     bh.add_argument("--fetch", required=True)
     bh.add_argument("--write", required=True)
@@ -721,6 +751,7 @@ def main(argv=None):
     b.add_argument("--write")
     b.add_argument("--out", required=True)
     b.add_argument("--n", type=int, default=512)
+    b.add_argument("--kernel", default="whole_slots", choices=["whole_slots", "interior"])
     b.add_argument("--command", action="append", default=[])
     bc = sub.add_parser("summarize-corrected")
     bc.add_argument("--stats", required=True)
@@ -739,6 +770,8 @@ def main(argv=None):
         run_interior(args.n, args.launches)
     elif args.cmd == "halo":
         run_interior(args.n, args.launches, call="halo")
+    elif args.cmd == "whole-slots":
+        run_interior(args.n, args.launches, call="whole_slots")
     elif args.cmd == "summarize-halo":
         summarize_halo(args.fetch, args.write, args.out, args.n, args.command, args.stats)
     elif args.cmd == "kernels":
@@ -760,7 +793,7 @@ def main(argv=None):
     elif args.cmd == "summarize-corrected":
         summarize_corrected(args.stats, args.out, args.n, args.steps, args.every, args.command)
     else:
-        summarize(args.stats, args.fetch, args.write, args.out, args.n, args.command)
+        summarize(args.stats, args.fetch, args.write, args.out, args.n, args.command, args.kernel)
 
 
 if __name__ == "__main__":

@@ -23,7 +23,15 @@ the ghosts of level n stay in the receive slots that the exchange filled, and st
 them there (rtm_step_halo_pack_slots); the interior call reads no ghost cell.  The level buffers'
 ghost rings are then not kept (fill_ghosts() writes the newest level's from its slots), and the face
 buffer alternates between two buffers, since step n + 1 packs while a periodic exchange still has
-step n's faces in use as its receive slots.  Same bits as ghosts="ring".  The
+step n's faces in use as its receive slots.  Same bits as ghosts="ring".
+
+With ghosts="slots" and halo="shell" the halo call only produces the faces: rtm_step_shell_pack
+computes the owned cells within R of a face into the send buffer (reading the x faces of u^n, u^{n-1}
+and kappa densely from the face buffers of the last two steps and a packed copy of kappa's faces),
+and rtm_step_whole_slots then updates every owned cell in one launch of full-width tiles, the shell
+again included (about 5% of the cells at 512^3), on the interior stream; the sources are injected
+after it and those in face cells re-copied into the send buffer.  The face buffers rotate over three
+(step n writes the faces of u^{n+1} while those of u^n and u^{n-1} are read).  Same bits.  The
 "fused" schedule, for one subdomain with nothing to overlap, updates every owned cell in one launch
 (rtm_step_whole) instead of the halo and interior calls, then injects, refreshes the ghosts and
 records on one stream; it too is bitwise identical.  With no face received (the physical boundary),
@@ -129,12 +137,16 @@ def tune_grid(grid: Grid, reps: int = 3):
 class Propagator:
     def __init__(self, grid: Grid, kappa: torch.Tensor, *, sources: Sources | list | None = None,
                  receivers=None, boundary: str = "zero", schedule: str = "overlap", debug: bool = False,
-                 check_every: int = 0, unpack_aside: bool = False, ghosts: str = "ring"):
+                 check_every: int = 0, unpack_aside: bool = False, ghosts: str = "ring", halo: str = "region"):
         """ghosts: "ring" (default) keeps every level's ghost ring current with an unpack pass after
         each step; "slots" (serial and overlap schedules, radius 4, nx % 4 == 0) leaves the ghosts of
         each level in the receive slots, where the next halo call reads them (rtm_step_halo_pack_slots),
         so a step has no unpack pass and the level buffers' rings are not kept (fill_ghosts() writes
         the newest level's).
+
+        halo (ghosts="slots"): "region" (default) updates the halo region in the halo call and the
+        rest in the interior call; "shell" computes only the faces in the halo call
+        (rtm_step_shell_pack) and every owned cell in the second call (rtm_step_whole_slots).
 
         unpack_aside (serial schedule): the unpack runs on a second stream as soon as the halo call
         and the shell sources are done, concurrently with the interior call (it writes ghost cells
@@ -177,15 +189,26 @@ class Propagator:
         self.pool: list[torch.Tensor] = []
         if ghosts not in ("ring", "slots"):
             raise ValueError(ghosts)
+        if halo not in ("region", "shell"):
+            raise ValueError(halo)
+        if halo == "shell" and ghosts != "slots":
+            raise ValueError("halo='shell' reads the ghosts from the receive slots (ghosts='slots')")
         self.ghosts = ghosts
+        self.halo = halo
         if ghosts == "slots":
             if schedule == "fused" or unpack_aside:
                 raise ValueError("ghosts='slots' is for the serial and overlap schedules (no unpack pass)")
             if grid.radius != 4 or grid.nx % 4:
                 raise ValueError("ghosts='slots' needs radius 4 and nx % 4 == 0")
         self.send = grid.faces()
-        # ghosts="slots": step n packs into send_bufs[n % 2]
-        self.send_bufs = [self.send, grid.faces()] if ghosts == "slots" else [self.send]
+        # ghosts="slots": step n packs into send_bufs[n % len(send_bufs)]: two buffers, three with
+        # halo="shell" (whose shell call reads the faces of u^n and u^{n-1} from the last two)
+        nbuf = 1 if ghosts != "slots" else (3 if halo == "shell" else 2)
+        self.send_bufs = [self.send] + [grid.faces() for _ in range(nbuf - 1)]
+        self.kappa_faces = None
+        if halo == "shell":
+            self.kappa_faces = grid.faces()
+            _abi.rtm_pack_halo(grid.c, kappa, self.kappa_faces, torch.cuda.current_stream())
         slots = grid.face_slots(self.send)
         # what face f of each new level receives: NULL slots for the physical boundary (the unpack
         # writes zero ghosts and reads nothing); "zero_faces": the same zeros received through six
@@ -203,7 +226,7 @@ class Propagator:
         else:
             self.recv = [slots[OPPOSITE[f]] for f in range(6)]
         # ghosts="slots", periodic: the receive slots of a level made by a step that packed into
-        # send_bufs[b] (a pointer swap, as above)
+        # send_bufs[b] (a pointer swap, as above), for level m in buffer (m - 1) % len(send_bufs)
         self._recv_periodic = [[self.grid.face_slots(b)[OPPOSITE[f]].data_ptr() for f in range(6)]
                                for b in self.send_bufs]
         self.n = 0
@@ -241,7 +264,10 @@ class Propagator:
         call reads them, and its ghost ring is written from there too."""
         st = stream if stream is not None else torch.cuda.current_stream()
         if self.ghosts == "slots":
-            _abi.rtm_pack_halo(self.grid.c, u, self.send_bufs[(self.n - 1) % 2], st)
+            nb = len(self.send_bufs)
+            _abi.rtm_pack_halo(self.grid.c, u, self.send_bufs[(self.n - 1) % nb], st)
+            if self.halo == "shell":        # the shell call reads u^{n-1}'s faces too
+                _abi.rtm_pack_halo(self.grid.c, self.u_prv, self.send_bufs[(self.n - 2) % nb], st)
             _abi.rtm_unpack_halo(self.grid.c, u, self._recv_for(self.n), st)
             return
         _abi.rtm_pack_halo(self.grid.c, u, self.send, st)
@@ -254,7 +280,7 @@ class Propagator:
         the step that made level m, or by exchange_ghosts)."""
         if self.boundary != "periodic":
             return self.recv
-        return self._recv_periodic[(m - 1) % 2]
+        return self._recv_periodic[(m - 1) % len(self.send_bufs)]
 
     def fill_ghosts(self, stream=None):
         """Write the newest level's ghost ring (kept in the receive slots with ghosts="slots", for code
@@ -288,9 +314,13 @@ class Propagator:
         self.sync()
         self._zero_ghosts.pop(u_prv.data_ptr(), None)     # its ghosts are the caller's: refreshed on reuse
         self.u_cur, self.u_prv, self.n = u_cur, u_prv, n
-        if self.ghosts == "slots" and self.boundary == "periodic":
-            # the next halo call reads u^n's ghosts from the slots: the faces they are copies of
-            _abi.rtm_pack_halo(self.grid.c, u_cur, self.send_bufs[(n - 1) % 2], torch.cuda.current_stream())
+        nb, st = len(self.send_bufs), torch.cuda.current_stream()
+        if self.ghosts == "slots" and (self.boundary == "periodic" or self.halo == "shell"):
+            # the next halo call reads u^n's ghosts from the slots (periodic: the faces they are copies
+            # of) and, with halo="shell", the faces of u^n and u^{n-1}
+            _abi.rtm_pack_halo(self.grid.c, u_cur, self.send_bufs[(n - 1) % nb], st)
+        if self.halo == "shell":
+            _abi.rtm_pack_halo(self.grid.c, u_prv, self.send_bufs[(n - 2) % nb], st)
 
     def unpin(self, t: torch.Tensor, recycle: bool = True):
         self.pinned.discard(t.data_ptr())
@@ -323,8 +353,13 @@ class Propagator:
         u_cur, u_prv, kap = self.u_cur, self.u_prv, self.kappa
         n = self.n
         slots = self.ghosts == "slots"
+        shell = self.halo == "shell"
+        dense = None
         if slots:
-            self.send = self.send_bufs[n % 2]
+            nb = len(self.send_bufs)
+            self.send = self.send_bufs[n % nb]
+            # halo="shell": the face buffers of u^n and u^{n-1}, and kappa's
+            dense = (self.send_bufs[(n - 1) % nb], self.send_bufs[(n - 2) % nb], self.kappa_faces) if shell else None
         tr_ptr = None if traces is None or self.nrec == 0 else traces.data_ptr() + 4 * n * self.nrec
         if self.schedule == "fused":
             st = torch.cuda.current_stream()
@@ -341,6 +376,11 @@ class Propagator:
                 self._mark_zero_ghosts(u_nxt)
             if tr_ptr is not None:
                 _abi.rtm_record(c, u_nxt, self.rec_idx, tr_ptr, self.nrec, st)
+        elif self.schedule == "serial" and shell:
+            for s in self.sources:
+                s.ensure_split(g)
+            st = torch.cuda.current_stream()
+            self._shell_step(u_nxt, u_cur, u_prv, n, dense, tr_ptr, st, st)
         elif self.schedule == "serial":
             for s in self.sources:
                 s.ensure_split(g)
@@ -366,14 +406,7 @@ class Propagator:
                 _abi.rtm_unpack_halo(c, u_nxt, self.recv, self.sH)
                 self._ev_unpack = torch.cuda.Event()
                 self._ev_unpack.record(self.sH)
-            if self.interior_events is not None and n % self.interior_event_every == 0:
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(st)
-                _abi.rtm_step_interior(c, u_nxt, u_cur, u_prv, kap, st)
-                e1.record(st)
-                self.interior_events.append((e0, e1))
-            else:
-                _abi.rtm_step_interior(c, u_nxt, u_cur, u_prv, kap, st)
+            self._interior(u_nxt, u_cur, u_prv, n, st)
             for s in self.sources:
                 s.inject(g, u_nxt, n, 1, st)
             if not self.unpack_aside and not slots:
@@ -389,30 +422,26 @@ class Propagator:
             else:
                 sH.wait_stream(torch.cuda.current_stream())
                 sI.wait_stream(torch.cuda.current_stream())
-            if slots:
-                _abi.rtm_step_halo_pack_slots(c, u_nxt, u_cur, u_prv, kap, self._recv_for(n), self.send, sH)
+            if shell:
+                self._shell_step(u_nxt, u_cur, u_prv, n, dense, tr_ptr, sH, sI)
             else:
-                _abi.rtm_step_halo_pack(c, u_nxt, u_cur, u_prv, kap, self.send, sH)
-            for s in self.sources:
-                s.inject(g, u_nxt, n, 0, sH)
-                s.repack(g, u_nxt, n, self.send, sH)
-            ev_halo = torch.cuda.Event()
-            ev_halo.record(sH)
-            if not slots:
-                _abi.rtm_unpack_halo(c, u_nxt, self.recv, sH)
-            if self.interior_events is not None and n % self.interior_event_every == 0:
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(sI)
-                _abi.rtm_step_interior(c, u_nxt, u_cur, u_prv, kap, sI)
-                e1.record(sI)
-                self.interior_events.append((e0, e1))
-            else:
-                _abi.rtm_step_interior(c, u_nxt, u_cur, u_prv, kap, sI)
-            for s in self.sources:
-                s.inject(g, u_nxt, n, 1, sI)
-            sI.wait_event(ev_halo)
-            if tr_ptr is not None:
-                _abi.rtm_record(c, u_nxt, self.rec_idx, tr_ptr, self.nrec, sI)
+                if slots:
+                    _abi.rtm_step_halo_pack_slots(c, u_nxt, u_cur, u_prv, kap, self._recv_for(n), self.send, sH)
+                else:
+                    _abi.rtm_step_halo_pack(c, u_nxt, u_cur, u_prv, kap, self.send, sH)
+                for s in self.sources:
+                    s.inject(g, u_nxt, n, 0, sH)
+                    s.repack(g, u_nxt, n, self.send, sH)
+                ev_halo = torch.cuda.Event()
+                ev_halo.record(sH)
+                if not slots:
+                    _abi.rtm_unpack_halo(c, u_nxt, self.recv, sH)
+                self._interior(u_nxt, u_cur, u_prv, n, sI)
+                for s in self.sources:
+                    s.inject(g, u_nxt, n, 1, sI)
+                sI.wait_event(ev_halo)
+                if tr_ptr is not None:
+                    _abi.rtm_record(c, u_nxt, self.rec_idx, tr_ptr, self.nrec, sI)
             ev_int = torch.cuda.Event()
             ev_int.record(sI)
             self._ev_int = ev_int
@@ -422,6 +451,46 @@ class Propagator:
             self._check_finite(u_nxt)
         if self.check_every and self.n % self.check_every == 0:
             self._health_check(u_nxt)
+
+    def _interior(self, u_nxt, u_cur, u_prv, n, st):
+        """The interior call, bracketed by timing events on every interior_event_every-th step when
+        interior_events is a list."""
+        c = self.grid.c
+        if self.interior_events is not None and n % self.interior_event_every == 0:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            _abi.rtm_step_interior(c, u_nxt, u_cur, u_prv, self.kappa, st)
+            e1.record(st)
+            self.interior_events.append((e0, e1))
+        else:
+            _abi.rtm_step_interior(c, u_nxt, u_cur, u_prv, self.kappa, st)
+
+    def _shell_step(self, u_nxt, u_cur, u_prv, n, dense, tr_ptr, sH, sI):
+        """halo="shell": the shell call on sH (faces of u^{n+1} into the send buffer), then on sI,
+        once it is done (u_nxt may be u_prv, which the shell call reads), the call over every owned
+        cell (timed like the interior call), the sources, the re-copy of those in face cells into the
+        send buffer, and the record.  The exchange of a multi-GPU run would start on sH after the
+        shell call, and wait for the re-copy when a source sits in a face cell."""
+        g, c, kap = self.grid, self.grid.c, self.kappa
+        recv = self._recv_for(n)
+        _abi.rtm_step_shell_pack(c, u_cur, u_prv, kap, recv, self.send, sH, dense=dense)
+        if sI is not sH:
+            ev = torch.cuda.Event()
+            ev.record(sH)
+            sI.wait_event(ev)
+        if self.interior_events is not None and n % self.interior_event_every == 0:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(sI)
+            _abi.rtm_step_whole_slots(c, u_nxt, u_cur, u_prv, kap, recv, sI)
+            e1.record(sI)
+            self.interior_events.append((e0, e1))
+        else:
+            _abi.rtm_step_whole_slots(c, u_nxt, u_cur, u_prv, kap, recv, sI)
+        for s in self.sources:
+            s.inject(g, u_nxt, n, 2, sI)
+            s.repack(g, u_nxt, n, self.send, sI)
+        if tr_ptr is not None:
+            _abi.rtm_record(c, u_nxt, self.rec_idx, tr_ptr, self.nrec, sI)
 
     def _health_check(self, u: torch.Tensor):
         st = self.level_stream

@@ -38,7 +38,7 @@ def oracle_forward_problem(v, h, nsteps, src_ijk, fpeak=15.0, rec_ijk=None, spon
 
 
 def gpu_forward_problem(v, h, nsteps, src_ijk, fpeak=15.0, rec_ijk=None, sponge_width=16, alpha=0.015,
-                        schedule="overlap", radius=4, x_align=32, return_prop=False, ghosts="ring"):
+                        schedule="overlap", radius=4, x_align=32, return_prop=False, ghosts="ring", halo="region"):
     """The same problem on the HIP path."""
     import torch
 
@@ -54,7 +54,7 @@ def gpu_forward_problem(v, h, nsteps, src_ijk, fpeak=15.0, rec_ijk=None, sponge_
     wav = g.ricker(nsteps, fpeak)
     amp = np.repeat(wav[:, None], len(src_ijk), axis=1)
     src = Sources(g, src_ijk, g.injection_weights(vs), amp)
-    prop = Propagator(g, kap, sources=src, receivers=rec_ijk, schedule=schedule, ghosts=ghosts)
+    prop = Propagator(g, kap, sources=src, receivers=rec_ijk, schedule=schedule, ghosts=ghosts, halo=halo)
     traces = prop.new_traces(nsteps)
     prop.run(nsteps, traces)
     torch.cuda.synchronize()

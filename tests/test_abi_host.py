@@ -94,6 +94,25 @@ def test_validation_before_device(abi):
     assert hps(gp, 4096, 1 << 36, 1 << 37, 1 << 38, slots, 4096 + 64, None) == abi.RTM_EALIAS   # faces over u_nxt
     g2 = _grid(abi, radius=2)
     assert hps(ctypes.byref(g2), 4096, 1 << 36, 1 << 37, 1 << 38, slots, 1 << 39, None) == abi.RTM_EINVAL
+    # the shell call (faces only, optional dense face copies) and the whole-block call with slots
+    shp, wsl = L.rtm_step_shell_pack, L.rtm_step_whole_slots
+    F = 1 << 39
+    assert shp(gp, 1 << 36, 1 << 37, 1 << 38, None, None, None, slots, None, None) == abi.RTM_EINVAL      # no faces
+    assert shp(gp, None, 1 << 37, 1 << 38, None, None, None, slots, F, None) == abi.RTM_EINVAL           # no u_cur
+    assert shp(gp, 1 << 36, 1 << 37, 1 << 38, None, None, None, one_null, F, None) == abi.RTM_EINVAL
+    assert shp(gp, 1 << 36, 1 << 37, 1 << 38, F + (1 << 30), None, None, slots, F, None) == abi.RTM_EINVAL  # 1 of 3
+    assert shp(gp, 1 << 36, 1 << 37, 1 << 38, F + 8 + (1 << 30), F + (2 << 30), F + (3 << 30), slots, F,
+               None) == abi.RTM_EINVAL                                                                # misaligned copy
+    assert shp(gp, 1 << 36, 1 << 37, 1 << 38, F + 64, F + (2 << 30), F + (3 << 30), slots, F,
+               None) == abi.RTM_EALIAS                                                                # copy over faces
+    assert shp(gp, 1 << 36, 1 << 37, 1 << 38, None, None, None, slots, (1 << 40) + 8192, None) == abi.RTM_EALIAS
+    assert shp(gp, 1 << 36, 1 << 37, 1 << 38, None, None, None, slots, (1 << 36) + 64, None) == abi.RTM_EALIAS
+    assert shp(ctypes.byref(g2), 1 << 36, 1 << 37, 1 << 38, None, None, None, slots, F, None) == abi.RTM_EINVAL
+    assert wsl(gp, 4096, 1 << 36, 1 << 37, 1 << 38, None, None) == abi.RTM_EINVAL
+    assert wsl(gp, 4096, 1 << 36, 1 << 37, 1 << 38, one_null, None) == abi.RTM_EINVAL
+    assert wsl(gp, None, 1 << 36, 1 << 37, 1 << 38, slots, None) == abi.RTM_EINVAL
+    assert wsl(gp, (1 << 40) + 4096 * 5, 1 << 36, 1 << 37, 1 << 38, slots, None) == abi.RTM_EALIAS   # slot in u_nxt
+    assert wsl(ctypes.byref(g2), 4096, 1 << 36, 1 << 37, 1 << 38, slots, None) == abi.RTM_EINVAL
     # the tuning call: reps in 1..1000, and u_nxt is scratch, never u_prv
     assert L.rtm_tune_step(gp, 4096, 1 << 36, 1 << 37, 1 << 38, 0, None, None) == abi.RTM_EINVAL
     assert L.rtm_tune_step(gp, 4096, 1 << 36, 1 << 37, 1 << 38, 1001, None, None) == abi.RTM_EINVAL
@@ -101,6 +120,8 @@ def test_validation_before_device(abi):
     assert L.rtm_tune_step(None, 4096, 1 << 36, 1 << 37, 1 << 38, 3, None, None) == abi.RTM_EINVAL
     g3 = _grid(abi, nx=18, pitch_y=28)                                                  # nx % 4 != 0
     assert hps(ctypes.byref(g3), 4096, 1 << 36, 1 << 37, 1 << 38, slots, 1 << 39, None) == abi.RTM_EINVAL
+    assert shp(ctypes.byref(g3), 1 << 36, 1 << 37, 1 << 38, None, None, None, slots, F, None) == abi.RTM_EINVAL
+    assert wsl(ctypes.byref(g3), 4096, 1 << 36, 1 << 37, 1 << 38, slots, None) == abi.RTM_EINVAL
     assert L.rtm_pack_cells(gp, 4096, 64, -1, 1 << 39, None) == abi.RTM_EINVAL
     assert L.rtm_pack_cells(gp, 4096, 64, 0, 1 << 39, None) == abi.RTM_OK             # nothing to do
     assert L.rtm_pack_cells(gp, 4096, 64, 3, None, None) == abi.RTM_EINVAL

@@ -28,7 +28,7 @@ def layered():
     return prof
 
 
-def _gpu_run(prof, nsteps, u0=None, um=None, schedule="overlap", ghosts="ring"):
+def _gpu_run(prof, nsteps, u0=None, um=None, schedule="overlap", ghosts="ring", halo="region"):
     import torch
 
     from paper_1603_03971_amd.grid import Grid
@@ -40,7 +40,7 @@ def _gpu_run(prof, nsteps, u0=None, um=None, schedule="overlap", ghosts="ring"):
     kap = g.kappa_from_velocity(v.cuda())
     c = N // 2
     src = Sources(g, [(c, c, c)], g.injection_weights([prof[c]]), g.ricker(nsteps, 15.0)[:, None])
-    prop = Propagator(g, kap, sources=src, schedule=schedule, ghosts=ghosts)
+    prop = Propagator(g, kap, sources=src, schedule=schedule, ghosts=ghosts, halo=halo)
     if u0 is not None:
         prop.set_state(u0, um)
     prop.run(nsteps)
@@ -54,7 +54,7 @@ def test_fullsize_sampled_cells_match_oracle(layered):
     u0 = synth.random_field((N, N, N), seed=101)
     um = synth.random_field((N, N, N), seed=102)
     _say("fullsize: gpu 512^3 x 20 steps from a seeded random state")
-    g, prop, dt_gpu = _gpu_run(prof, nsteps, u0, um, schedule="serial", ghosts="slots")   # the benchmark's
+    g, prop, dt_gpu = _gpu_run(prof, nsteps, u0, um, schedule="serial", ghosts="slots", halo="shell")  # the benchmark's
     u_gpu = g.owned(prop.u_cur)
     c = N // 2
     # cells in every region of the split: source, x strips and their edges, y strips, z slabs, corners
@@ -120,7 +120,8 @@ def test_c2_final_field_matches_oracle_after_1000_steps(layered, capsys):
     kap = g.kappa_from_velocity(v.cuda())
     del v
     src = Sources(g, [(c, c, c)], g.injection_weights([prof[c]]), g.ricker(nsteps, 15.0)[:, None])
-    prop = Propagator(g, kap, sources=src, receivers=rec, schedule="serial", boundary="zero_faces", ghosts="slots")
+    prop = Propagator(g, kap, sources=src, receivers=rec, schedule="serial", boundary="zero_faces", ghosts="slots",
+                      halo="shell")
     traces = prop.new_traces(nsteps)
     prop.run(nsteps, traces)
     torch.cuda.synchronize()
@@ -189,14 +190,17 @@ def test_fullsize_mirror_symmetry_after_1000_steps(layered):
 
 
 def test_fullsize_schedules_bitwise(layered):
-    """Halo-first on one and two streams and the one-launch step (its own z chunking, the ghost ring
-    written once per buffer) give the same bits at the benchmark's size."""
+    """Halo-first on one and two streams, with the ghosts from the receive slots in the halo-region and
+    the shell form, and the one-launch step (its own z chunking, the ghost ring written once per
+    buffer) give the same bits at the benchmark's size."""
     import torch
 
     a = _gpu_run(layered, 60, schedule="serial")
     ua = a[0].owned(a[1].u_cur).clone()
     del a
-    for schedule in ("overlap", "fused"):
-        b = _gpu_run(layered, 60, schedule=schedule)
-        assert bool(torch.equal(ua, b[0].owned(b[1].u_cur))), schedule
+    for schedule, ghosts, halo in (("overlap", "ring", "region"), ("fused", "ring", "region"),
+                                   ("serial", "slots", "region"), ("serial", "slots", "shell"),
+                                   ("overlap", "slots", "shell")):
+        b = _gpu_run(layered, 60, schedule=schedule, ghosts=ghosts, halo=halo)
+        assert bool(torch.equal(ua, b[0].owned(b[1].u_cur))), (schedule, ghosts, halo)
         del b

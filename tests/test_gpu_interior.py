@@ -14,6 +14,12 @@ from tests import problems
 pytestmark = pytest.mark.gpu
 
 
+def _parse(schedule):
+    """"sched[-ghosts[-halo]]" -> (sched, ghosts, halo), with "ring" and "region" by default."""
+    parts = schedule.split("-")
+    return parts[0], parts[1] if len(parts) > 1 else "ring", parts[2] if len(parts) > 2 else "region"
+
+
 def _say(msg):
     print(msg, flush=True)
 
@@ -57,13 +63,15 @@ def test_wide_box_exercises_full_interior_tiles(wide_case):
     assert inner >= 0.3 * np.max(np.abs(ref))       # the wavefield is really there
 
 
-@pytest.mark.parametrize("schedule", ["serial", "overlap", "fused", "serial-slots", "overlap-slots"])
+@pytest.mark.parametrize("schedule", ["serial", "overlap", "fused", "serial-slots", "overlap-slots",
+                                      "serial-slots-shell", "overlap-slots-shell"])
 def test_wide_box_parity(wide_case, schedule):
-    """-slots: the steps with no unpack pass, whose halo calls read the ghosts from the receive slots."""
+    """-slots: the steps with no unpack pass, whose halo calls read the ghosts from the receive slots;
+    -shell: the halo call computes only the faces, the second call every owned cell."""
     v, src, rec, nsteps, ref = wide_case
     _say(f"wide {schedule}: gpu")
-    sched, _, ghosts = schedule.partition("-")
-    gpu = problems.gpu_forward_problem(v, 10.0, nsteps, src, rec_ijk=rec, schedule=sched, ghosts=ghosts or "ring")
+    sched, ghosts, halo = _parse(schedule)
+    gpu = problems.gpu_forward_problem(v, 10.0, nsteps, src, rec_ijk=rec, schedule=sched, ghosts=ghosts, halo=halo)
     e_u = problems.rel_l2(gpu["u_cur"], ref["u_cur"])
     e_p = problems.rel_l2(gpu["u_prv"], ref["u_prv"])
     e_t = problems.rel_l2(gpu["traces"], ref["traces"])

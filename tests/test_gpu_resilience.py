@@ -13,6 +13,12 @@ from paper_1603_03971_amd import synth
 pytestmark = pytest.mark.gpu
 
 
+def _parse(schedule):
+    """"sched[-ghosts[-halo]]" -> (sched, ghosts, halo), with "ring" and "region" by default."""
+    parts = schedule.split("-")
+    return parts[0], parts[1] if len(parts) > 1 else "ring", parts[2] if len(parts) > 2 else "region"
+
+
 def _say(msg):
     print(msg, flush=True)
 
@@ -59,9 +65,10 @@ def test_stable_run_is_not_flagged():
     assert prop.n == 800
 
 
-@pytest.mark.parametrize("schedule", ["serial", "fused", "serial-slots"])
+@pytest.mark.parametrize("schedule", ["serial", "fused", "serial-slots", "serial-slots-shell"])
 def test_kill_and_resume_is_bitwise(tmp_path, schedule):
-    """-slots: ghosts read from the receive slots; the resumed run primes them from the saved level."""
+    """-slots: ghosts read from the receive slots; the resumed run primes them from the saved level.
+    -shell: the shell form of the halo call, which also reads the faces of the two saved levels."""
     import torch
 
     from paper_1603_03971_amd.grid import Grid
@@ -79,9 +86,9 @@ def test_kill_and_resume_is_bitwise(tmp_path, schedule):
     rec = [(10, 10, 3), (70, 35, 39)]
 
     def fresh():
-        sched, _, ghosts = schedule.partition("-")
+        sched, ghosts, halo = _parse(schedule)
         return Propagator(g, kap, sources=Sources(g, src_ijk, w, amp), receivers=rec, schedule=sched,
-                          ghosts=ghosts or "ring")
+                          ghosts=ghosts, halo=halo)
 
     ref = fresh()
     tr_ref = ref.new_traces(nsteps)

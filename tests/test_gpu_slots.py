@@ -99,7 +99,7 @@ def _problem(shape, seed=21):
     return v, src, rec
 
 
-def _run(v, src, rec, nsteps, schedule, boundary, ghosts, poison=False, pin_at=None):
+def _run(v, src, rec, nsteps, schedule, boundary, ghosts, poison=False, pin_at=None, halo="region"):
     import torch
 
     from paper_1603_03971_amd.grid import Grid
@@ -112,7 +112,7 @@ def _run(v, src, rec, nsteps, schedule, boundary, ghosts, poison=False, pin_at=N
     amp = np.repeat(g.ricker(nsteps, 25.0)[:, None], len(src), axis=1)
     s = Sources(g, src, g.injection_weights(vs), amp)
     prop = Propagator(g, kap, sources=s, receivers=rec, schedule=schedule, boundary=boundary, ghosts=ghosts,
-                      debug=poison)
+                      debug=poison, halo=halo)
     prop.set_state(synth.random_field(v.shape, seed=31, scale=1e-3), synth.random_field(v.shape, seed=32, scale=1e-3))
     if poison:
         torch.cuda.synchronize()
@@ -129,15 +129,17 @@ def _run(v, src, rec, nsteps, schedule, boundary, ghosts, poison=False, pin_at=N
     return prop, g, traces.cpu().numpy()
 
 
+@pytest.mark.parametrize("halo", ["region", "shell"])
 @pytest.mark.parametrize("boundary", ["zero", "zero_faces", "periodic"])
 @pytest.mark.parametrize("schedule", ["serial", "overlap"])
-def test_slots_steps_bitwise(torch_cuda, schedule, boundary):
+def test_slots_steps_bitwise(torch_cuda, schedule, boundary, halo):
     """40 steps with ghosts="slots" (the level buffers' ghost rings NaN throughout, and a level pinned
-    half-way so that later levels land in fresh NaN buffers) against ghosts="ring": the same bits."""
+    half-way so that later levels land in fresh NaN buffers), with the halo region or the shell form of
+    the halo call, against ghosts="ring": the same bits."""
     v, src, rec = _problem((44, 40, 200))
-    _say(f"slots {schedule} {boundary}")
+    _say(f"slots {schedule} {boundary} {halo}")
     pr, g, tr = _run(v, src, rec, 40, schedule, boundary, "ring", pin_at=20)
-    ps, _, ts = _run(v, src, rec, 40, schedule, boundary, "slots", poison=True, pin_at=20)
+    ps, _, ts = _run(v, src, rec, 40, schedule, boundary, "slots", poison=True, pin_at=20, halo=halo)
     a_cur, a_prv = g.download(pr.u_cur), g.download(pr.u_prv)
     b_cur, b_prv = g.download(ps.u_cur), g.download(ps.u_prv)
     assert np.all(np.isfinite(b_cur)) and np.abs(a_cur).max() > 0

@@ -291,6 +291,15 @@ int rtm_unpack_halo(const rtm_grid *grid, float *u, const float *const faces[6],
 int rtm_inject(const rtm_grid *grid, float *u, const int64_t *idx, const float *w, const float *amp,
                int32_t n, hipStream_t stream);
 
+/* rtm_inject(u, src_idx, w, amp, nsrc) followed by rtm_record(u, rec_idx, out, nrec), with the same
+ * results (a receiver on a source cell records the injected value): the injection and recording that
+ * end a step.  When nsrc + nrec <= 4096 both run in one workgroup of one launch (adds, fence,
+ * barrier, gathers), which for short lists costs about one launch instead of two; longer lists take
+ * the two launches.  Argument meaning, layout and errors as for the two calls; either count may be
+ * zero (its pointers may then be NULL). */
+int rtm_inject_record(const rtm_grid *grid, float *u, const int64_t *src_idx, const float *w, const float *amp,
+                      int32_t nsrc, const int64_t *rec_idx, float *out, int32_t nrec, hipStream_t stream);
+
 /* Receiver recording: out[r] = u[idx[r]] for r < n (an index outside the padded block gives 0). */
 int rtm_record(const rtm_grid *grid, const float *u, const int64_t *idx, float *out, int32_t n,
                hipStream_t stream);

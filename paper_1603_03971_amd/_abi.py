@@ -64,6 +64,7 @@ def _load():
         "rtm_pack_halo": ([gp, vp, vp, vp], ctypes.c_int),
         "rtm_step_halo_pack": ([gp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "rtm_step_halo_pack_slots": ([gp, vp, vp, vp, vp, ctypes.POINTER(vp), vp, vp], ctypes.c_int),
+        "rtm_inject_record": ([gp, vp, vp, vp, vp, ctypes.c_int32, vp, vp, ctypes.c_int32, vp], ctypes.c_int),
         "rtm_step_shell_pack": ([gp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp), vp, vp], ctypes.c_int),
         "rtm_step_whole_slots": ([gp, vp, vp, vp, vp, ctypes.POINTER(vp), vp], ctypes.c_int),
         "rtm_pack_cells": ([gp, vp, vp, i32, vp, vp], ctypes.c_int),
@@ -253,6 +254,11 @@ def rtm_step_halo_pack_slots(grid, u_nxt, u_cur, u_prv, kappa, recv, faces, stre
     arr = (ctypes.c_void_p * 6)(*[_p(f) for f in recv])
     _check(_lib.rtm_step_halo_pack_slots(ctypes.byref(grid), _p(u_nxt), _p(u_cur), _p(u_prv), _p(kappa), arr,
                                          _p(faces), _s(stream)), "rtm_step_halo_pack_slots")
+
+
+def rtm_inject_record(grid, u, src_idx, w, amp, nsrc, rec_idx, out, nrec, stream=None):
+    _check(_lib.rtm_inject_record(ctypes.byref(grid), _p(u), _p(src_idx), _p(w), _p(amp), int(nsrc), _p(rec_idx),
+                                  _p(out), int(nrec), _s(stream)), "rtm_inject_record")
 
 
 def rtm_step_shell_pack(grid, u_cur, u_prv, kappa, recv, faces, stream=None, dense=None):

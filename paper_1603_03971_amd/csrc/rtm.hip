@@ -235,10 +235,18 @@ __device__ __forceinline__ float4 weight4(float4 mu, float4 kp, const float (&gx
     return w;
 }
 
-template <int R, int BX, int BY, int OP, bool PACK = false, int FL = 0>
-__global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(BX * BY >= 512 ? 4 : 1)))
-void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, const float *kap, BoxList bl,
-             PackOut po, const float *__restrict__ rk)
+// LDS of one tile: R + 2 planes of (BY + 2R) rows of BX + 2 float4s.
+template <int R, int BX, int BY>
+struct TileLds {
+    static constexpr int S = R + 2, LH = BY + 2 * R, LW4 = BX + 2, N = S * LH * LW4;
+};
+
+// One workgroup of the tiled kernel: block `bid` of the box list, its LDS at `lds_raw`
+// (TileLds<R, BX, BY>::N float4s).  The structs come by value, as kernel arguments do.
+template <int R, int BX, int BY, int OP, bool PACK, int FL>
+__device__ __forceinline__ void tiled_body(int bid, float4 *lds_raw, const Geo g, float *un,
+                                           const float *__restrict__ uc, const float *up, const float *kap,
+                                           const BoxList bl, const PackOut po, const float *__restrict__ rk)
 {
     constexpr bool STREAM = (FL & FL_NT) != 0;
     constexpr bool XS = (FL & FL_XSHUF) != 0;
@@ -260,9 +268,10 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
     constexpr int HPT = (NH + NT - 1) / NT;
     constexpr int QR = 2 * R + 2;          // register ring: the 2R+1 planes in use plus the one in flight
     constexpr int S = R + 2;               // LDS ring: planes k-1 .. k+R
-    __shared__ float4 lds[S][LH][LW4];
+    static_assert(TileLds<R, BX, BY>::N == S * LH * LW4, "LDS size");
+    auto &lds = *reinterpret_cast<float4 (*)[S][LH][LW4]>(lds_raw);
 
-    int lb = bl.remap ? xcd_remap(blockIdx.x, bl.nblk) : (int)blockIdx.x;
+    int lb = bl.remap ? xcd_remap(bid, bl.nblk) : bid;
     Box bx = bl.b[0];
 #pragma unroll
     for (int i = 1; i < kMaxBoxes; ++i) {
@@ -620,6 +629,15 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
     for (k0_ = zs; k0_ < ze; k0_ += QR) unroll_seq(plane, std::make_integer_sequence<int, QR>{});
 }
 
+template <int R, int BX, int BY, int OP, bool PACK = false, int FL = 0>
+__global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(BX * BY >= 512 ? 4 : 1)))
+void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, const float *kap, BoxList bl,
+             PackOut po, const float *__restrict__ rk)
+{
+    __shared__ float4 lds[TileLds<R, BX, BY>::N];
+    tiled_body<R, BX, BY, OP, PACK, FL>((int)blockIdx.x, lds, g, un, uc, up, kap, bl, po, rk);
+}
+
 
 // The shell call's x strips (radius 4: the float4 at x = 0 or x = nx - 4 of the rows y in [4, ny - 4),
 // z in [4, nz - 4)) from dense face copies: one thread per row and side.  u^n at the strip and its y and
@@ -627,17 +645,18 @@ void k_tiled(Geo g, float *un, const float *__restrict__ uc, const float *up, co
 // the face slots 0 and 1 at off0 and off1), the x ghosts from gl / gr (the receive slots 0 and 1), and
 // only the float4 on the inside (x = 4 or nx - 8) from the field uc.  The result goes to the face
 // buffer `faces` only.  Same arithmetic, in the same order, as k_tiled.
-__global__ __launch_bounds__(kThreads) void k_xface(Geo g, const float *__restrict__ uc, const float *__restrict__ fc,
-                                                    const float *__restrict__ fp, const float *__restrict__ fk,
-                                                    const float *__restrict__ gl, const float *__restrict__ gr,
-                                                    float *__restrict__ faces, long long off0, long long off1)
+__device__ __forceinline__ void xface_rows(long long t0, long long tstride, const Geo g,
+                                           const float *__restrict__ uc, const float *__restrict__ fc,
+                                           const float *__restrict__ fp, const float *__restrict__ fk,
+                                           const float *__restrict__ gl, const float *__restrict__ gr,
+                                           float *__restrict__ faces, long long off0, long long off1)
 {
     constexpr int R = 4;
     const long long ny = g.ny, wy = g.ny - 2 * R, per = wy * (g.nz - 2 * R);
     float c[5];
 #pragma unroll
     for (int m = 0; m < 5; ++m) c[m] = g.c[m];
-    for (long long t = first_item(); t < 2 * per; t += item_stride()) {
+    for (long long t = t0; t < 2 * per; t += tstride) {
         const int side = t >= per ? 1 : 0;
         const long long r = t - side * per;
         const int y = R + (int)(r % wy), z = R + (int)(r / wy);
@@ -670,6 +689,28 @@ __global__ __launch_bounds__(kThreads) void k_xface(Geo g, const float *__restri
             out[e] = point_op<R, OP_FORWARD>(xs[4 + e], sm, el(pv, e), el(kv, e), gxy * gz, c);
         }
         st4(faces + at(y, z), make_float4(out[0], out[1], out[2], out[3]));
+    }
+}
+
+// The shell call in one launch: the first xblocks workgroups walk the x-strip rows (xface_rows, a
+// stride over those blocks), the rest are 32x8-thread tiles of the z slabs and y strips (faces only,
+// FL has FL_PONLY).  Both parts are latency-bound and overlap in one launch (512^3: 45 us, against
+// 24 + 30 us as two launches).
+constexpr int kShellLds = 6 * 16 * 34;     // TileLds<4, 32, 8>::N
+template <int FL>
+__global__ __launch_bounds__(256) void k_shell(Geo g, const float *__restrict__ uc, const float *up, const float *kap,
+                                               BoxList slabs, PackOut po, const float *__restrict__ fc,
+                                               const float *__restrict__ fp, const float *__restrict__ fk,
+                                               int xblocks)
+{
+    __shared__ float4 lds[kShellLds];
+    const int b = (int)blockIdx.x;
+    if (b < xblocks) {
+        xface_rows((long long)b * 256 + threadIdx.x, (long long)xblocks * 256, g, uc, fc, fp, fk, po.recv[0],
+                   po.recv[1], po.faces, po.off[0], po.off[1]);
+    } else {
+        tiled_body<4, 32, 8, OP_FORWARD, true, FL>(b - xblocks, lds, g, const_cast<float *>(uc), uc, up, kap, slabs,
+                                                   po, nullptr);
     }
 }
 
@@ -868,6 +909,26 @@ __global__ __launch_bounds__(kThreads) void k_record(const float *__restrict__ u
 {
     for (long long r = first_item(); r < n; r += item_stride()) {
         const long long p = idx[r];
+        out[r] = (p >= 0 && p < total) ? u[p] : 0.0f;
+    }
+}
+
+// k_inject then k_record in one workgroup: the adds, a device-scope fence (they are complete and no
+// stale line of u is read), a barrier, then the gathers, so a receiver on a source cell records the
+// injected value.  For short lists, where each launch is mostly its own start-up.
+__global__ __launch_bounds__(kThreads) void k_inject_record(float *u, long long total, const int64_t *__restrict__ sidx,
+                                                            const float *__restrict__ w, const float *__restrict__ amp,
+                                                            int ns, const int64_t *__restrict__ ridx,
+                                                            float *__restrict__ out, int nr)
+{
+    for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+        const long long p = sidx[s];
+        if (p >= 0 && p < total) atomicAdd(u + p, w[s] * amp[s]);
+    }
+    __threadfence();
+    __syncthreads();
+    for (int r = threadIdx.x; r < nr; r += blockDim.x) {
+        const long long p = ridx[r];
         out[r] = (p >= 0 && p < total) ? u[p] : 0.0f;
     }
 }
@@ -1360,6 +1421,8 @@ int launch_status()
 
 // Workgroups for n items of an elementwise kernel (which strides by the grid beyond the cap).
 constexpr long long kMaxBlocks = 1ll << 20;
+// rtm_inject_record: at most this many sources plus receivers go to one workgroup
+constexpr long long kInjectRecordOneGroup = 4096;
 unsigned blocks_for(long long n) { return (unsigned)std::min((n + kThreads - 1) / kThreads, kMaxBlocks); }
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
@@ -1662,15 +1725,25 @@ int launch_shell_pack(const Geo &g, const float *uc, const float *up, const floa
     float *un = const_cast<float *>(uc);
     const bool nt = (g_opt.tile_flags.load(std::memory_order_relaxed) & FL_NT) != 0;
     constexpr int F1 = FL_NT | FL_SLOTS | FL_PONLY, F0 = FL_SLOTS | FL_PONLY;
+    if (fc && nx >= 2 * R && ny > 2 * R && nz > 2 * R) {
+        BoxList bs;
+        const int rc = make_boxlist<R, 32, 8>(g, slabs, 4, -1, 16, bs);
+        if (rc != RTM_OK) return rc;
+        const long long rows = 2ll * (ny - 2 * R) * (nz - 2 * R);
+        const int xblocks = (int)((rows + 255) / 256);      // one row per thread (45 us at 512^3)
+        const long long nb = (long long)xblocks + bs.nblk;
+        if (nb >= (1ll << 31)) return RTM_EINVAL;
+        if (nt)
+            hipLaunchKernelGGL((k_shell<F1>), dim3((unsigned)nb), dim3(256), 0, st, g, uc, up, kap, bs, po, fc, fp, fk,
+                               xblocks);
+        else
+            hipLaunchKernelGGL((k_shell<F0>), dim3((unsigned)nb), dim3(256), 0, st, g, uc, up, kap, bs, po, fc, fp, fk,
+                               xblocks);
+        return launch_status();
+    }
     int rc = nt ? launch_tiled<R, 32, 8, OP_FORWARD, true, F1>(g, un, uc, up, kap, slabs, 4, st, &po, nullptr, -1, 16)
                 : launch_tiled<R, 32, 8, OP_FORWARD, true, F0>(g, un, uc, up, kap, slabs, 4, st, &po, nullptr, -1, 16);
     if (rc != RTM_OK) return rc;
-    if (fc && nx >= 2 * R && ny > 2 * R && nz > 2 * R) {
-        const long long n = 2ll * (ny - 2 * R) * (nz - 2 * R);
-        hipLaunchKernelGGL(k_xface, dim3(blocks_for(n)), dim3(kThreads), 0, st, g, uc, fc, fp, fk, po.recv[0], po.recv[1],
-                           po.faces, po.off[0], po.off[1]);
-        return launch_status();
-    }
     return nt ? launch_tiled<R, 2, 32, OP_FORWARD, true, F1>(g, un, uc, up, kap, cols, 2, st, &po, nullptr, -1, 32)
               : launch_tiled<R, 2, 32, OP_FORWARD, true, F0>(g, un, uc, up, kap, cols, 2, st, &po, nullptr, -1, 32);
 }
@@ -2325,6 +2398,37 @@ int rtm_inject(const rtm_grid *grid, float *u, const int64_t *idx, const float *
     hipLaunchKernelGGL(k_inject, dim3(blocks_for(n)), dim3(kThreads), 0, stream, u, padded_total(grid), idx, w, amp,
                        (int)n);
     return launch_status();
+}
+
+int rtm_inject_record(const rtm_grid *grid, float *u, const int64_t *src_idx, const float *w, const float *amp,
+                      int32_t nsrc, const int64_t *rec_idx, float *out, int32_t nrec, hipStream_t stream)
+{
+    const Marker mark("rtm_inject_record");
+    int st = check_grid(grid);
+    if (st != RTM_OK) return st;
+    if (nsrc < 0 || nrec < 0) return RTM_EINVAL;
+    if ((nsrc > 0 && (!u || !src_idx || !w || !amp)) || (nrec > 0 && (!u || !rec_idx || !out))) return RTM_EINVAL;
+    if (nsrc == 0 && nrec == 0) return RTM_OK;
+    st = check_device();
+    if (st != RTM_OK) return st;
+    const long long total = padded_total(grid);
+    if ((long long)nsrc + nrec <= kInjectRecordOneGroup) {
+        hipLaunchKernelGGL(k_inject_record, dim3(1), dim3(kThreads), 0, stream, u, total, src_idx, w, amp, (int)nsrc,
+                           rec_idx, out, (int)nrec);
+        return launch_status();
+    }
+    if (nsrc > 0) {
+        hipLaunchKernelGGL(k_inject, dim3(blocks_for(nsrc)), dim3(kThreads), 0, stream, u, total, src_idx, w, amp,
+                           (int)nsrc);
+        st = launch_status();
+        if (st != RTM_OK) return st;
+    }
+    if (nrec > 0) {
+        hipLaunchKernelGGL(k_record, dim3(blocks_for(nrec)), dim3(kThreads), 0, stream, u, total, rec_idx, out,
+                           (int)nrec);
+        st = launch_status();
+    }
+    return st;
 }
 
 int rtm_record(const rtm_grid *grid, const float *u, const int64_t *idx, float *out, int32_t n, hipStream_t stream)

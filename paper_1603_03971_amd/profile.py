@@ -114,17 +114,14 @@ def kernel_table(n: int):
     interior = interior_cells(n)
     halo = cells - interior
     faces = 6 * 4 * n * n
-    slab_cells = 2 * 4 * n * n + 2 * 4 * n * (n - 8)        # the shell's z slabs and y strips
-    xface_cells = 2 * 4 * (n - 8) * (n - 8)                # the shell's x strips
+    shell_cells = n ** 3 - (n - 8) ** 3                    # the owned cells within 4 of a face
     return {
         "interior": ("k_tiled<4, 16, 8, 0, false", 16 * interior, "16 B per interior cell"),
         "halo_pack": ("k_tiled<4, 16, 16, 0, true, 1>", 16 * halo + 4 * faces, "16 B per halo cell + 4 B per face cell"),
         "halo_pack_slots": ("k_tiled<4, 16, 16, 0, true, 5>", 16 * halo + 8 * faces,
                             "16 B per halo cell + 4 B per face cell out + 4 B per ghost cell in"),
-        "shell_slabs": ("k_tiled<4, 32, 8, 0, true, 13>", 16 * slab_cells,
-                        "16 B per shell cell of the z slabs and y strips (12 B in, 4 B to the face buffer)"),
-        "shell_xfaces": ("k_xface", 16 * xface_cells,
-                         "16 B per shell cell of the x strips (12 B in, 4 B to the face buffer)"),
+        "shell": ("k_shell<13>", 16 * shell_cells + 4 * faces,
+                  "16 B per shell cell (12 B in, 4 B to the face buffer) + 4 B per ghost cell in"),
         "whole_slots": ("k_tiled<4, 32, 8, 0, false, 5>", 16 * cells, "16 B per cell"),
         "whole": ("k_tiled<4, 32, 8, 0, false, 1>", 16 * cells, "16 B per cell (also the scaled adjoint step)"),
         "adjoint_direct": ("k_tiled<4, 32, 8, 1, false", 16 * cells, "16 B per cell: mu_a, kappa, mu_b in, mu out"),
@@ -271,12 +268,11 @@ def run_corrected(n: int, steps: int, every: int):
 
 # The radius-4 kernels of the forward step under the default options at 512^3 (prefixes of the
 # demangled names): the interior call's tiles (16 x 8 threads), the halo-region call's (16 x 16), the
-# shell call's z slabs and y strips (32 x 8, faces only) and x strips, the whole-block call with the
-# ghosts from the slots (32 x 8) and the one-launch step's (32 x 8).
+# shell call (one launch: x-strip rows and 32 x 8 tiles of the z slabs and y strips, faces only),
+# the whole-block call with the ghosts from the slots (32 x 8) and the one-launch step's (32 x 8).
 INTERIOR_KERNEL = "k_tiled<4, 16, 8, 0, false"
 HALO_KERNEL = "k_tiled<4, 16, 16, 0, true"
-SHELL_KERNEL = "k_tiled<4, 32, 8, 0, true, 13>"
-XFACE_KERNEL = "k_xface"
+SHELL_KERNEL = "k_shell<"
 WHOLE_SLOTS_KERNEL = "k_tiled<4, 32, 8, 0, false, 5>"
 WHOLE_KERNEL = "k_tiled<4, 32, 8, 0, false, 1>"
 TILED_R4 = "k_tiled<4, "
@@ -477,8 +473,8 @@ def summarize(stats_dir, fetch_dir, write_dir, out, n, commands, kernel="whole_s
         lines.append(f"    {name:60s} {r['Calls']:>6s} {avg:10.2f} {float(r['Percentage']):8.2f}")
     # the radius-4 stencil dispatches of the run by call, from their kernel names
     kinds = [(WHOLE_SLOTS_KERNEL, "rtm_step_whole_slots"), (INTERIOR_KERNEL, "rtm_step_interior"),
-             (WHOLE_KERNEL, "rtm_step_whole (fused schedule)"), (SHELL_KERNEL, "rtm_step_shell_pack (slabs)"),
-             (XFACE_KERNEL, "rtm_step_shell_pack (x strips)"), (HALO_KERNEL, "rtm_step_halo_pack_slots")]
+             (WHOLE_KERNEL, "rtm_step_whole (fused schedule)"), (SHELL_KERNEL, "rtm_step_shell_pack"),
+             (HALO_KERNEL, "rtm_step_halo_pack_slots")]
     trace = _csv(stats_dir, "*kernel_trace.csv")
     calls, grids = {}, {}
     for r in trace:

@@ -108,13 +108,20 @@ class Sources:
             torch.cuda.synchronize(grid.device)
             self._split(grid)
 
-    def inject(self, grid: Grid, u: torch.Tensor, n: int, which: int, stream):
-        """Add row n of the amplitude table at set `which`: 0 = halo region, 1 = the rest, 2 = all."""
+    def inject_args(self, n: int, which: int):
+        """(index, weight and amplitude addresses, count) of row n at set `which` (0 = halo region,
+        1 = the rest, 2 = all), or None when there is nothing to add."""
         off, cnt = self.ranges[which]
         if cnt == 0 or n >= self.nsteps:
-            return
-        _abi.rtm_inject(grid.c, u, self.idx.data_ptr() + 8 * off, self.w.data_ptr() + 4 * off,
-                        self.amp.data_ptr() + 4 * (n * self.count + off), cnt, stream)
+            return None
+        return (self.idx.data_ptr() + 8 * off, self.w.data_ptr() + 4 * off,
+                self.amp.data_ptr() + 4 * (n * self.count + off), cnt)
+
+    def inject(self, grid: Grid, u: torch.Tensor, n: int, which: int, stream):
+        """Add row n of the amplitude table at set `which`: 0 = halo region, 1 = the rest, 2 = all."""
+        a = self.inject_args(n, which)
+        if a is not None:
+            _abi.rtm_inject(grid.c, u, *a, stream)
 
     def repack(self, grid: Grid, u: torch.Tensor, n: int, faces: torch.Tensor, stream):
         """After the halo-region injection of row n: copy the injected face cells into `faces`."""
@@ -407,12 +414,15 @@ class Propagator:
                 self._ev_unpack = torch.cuda.Event()
                 self._ev_unpack.record(self.sH)
             self._interior(u_nxt, u_cur, u_prv, n, st)
-            for s in self.sources:
-                s.inject(g, u_nxt, n, 1, st)
-            if not self.unpack_aside and not slots:
-                _abi.rtm_unpack_halo(c, u_nxt, self.recv, st)
-            if tr_ptr is not None:
-                _abi.rtm_record(c, u_nxt, self.rec_idx, tr_ptr, self.nrec, st)
+            if slots:
+                self._inject_and_record(u_nxt, n, 1, tr_ptr, st)
+            else:
+                for s in self.sources:
+                    s.inject(g, u_nxt, n, 1, st)
+                if not self.unpack_aside:
+                    _abi.rtm_unpack_halo(c, u_nxt, self.recv, st)
+                if tr_ptr is not None:
+                    _abi.rtm_record(c, u_nxt, self.rec_idx, tr_ptr, self.nrec, st)
         else:
             for s in self.sources:
                 s.ensure_split(g)
@@ -486,11 +496,24 @@ class Propagator:
             self.interior_events.append((e0, e1))
         else:
             _abi.rtm_step_whole_slots(c, u_nxt, u_cur, u_prv, kap, recv, sI)
+        self._inject_and_record(u_nxt, n, 2, tr_ptr, sI)
+
+    def _inject_and_record(self, u_nxt, n, which, tr_ptr, st):
+        """Sources of set `which`, their face cells re-copied into the send buffer, then the record; one
+        launch for both when a single source table has no face cell (rtm_inject_record)."""
+        g, c = self.grid, self.grid.c
+        if len(self.sources) == 1 and self.sources[0].face_idx is None:
+            a = self.sources[0].inject_args(n, which)
+            if a is not None or tr_ptr is not None:
+                a = a if a is not None else (None, None, None, 0)
+                _abi.rtm_inject_record(c, u_nxt, *a, self.rec_idx, tr_ptr, self.nrec if tr_ptr is not None else 0, st)
+            return
         for s in self.sources:
-            s.inject(g, u_nxt, n, 2, sI)
-            s.repack(g, u_nxt, n, self.send, sI)
+            s.inject(g, u_nxt, n, which, st)
+            if which != 1:
+                s.repack(g, u_nxt, n, self.send, st)
         if tr_ptr is not None:
-            _abi.rtm_record(c, u_nxt, self.rec_idx, tr_ptr, self.nrec, sI)
+            _abi.rtm_record(c, u_nxt, self.rec_idx, tr_ptr, self.nrec, st)
 
     def _health_check(self, u: torch.Tensor):
         st = self.level_stream

@@ -129,6 +129,15 @@ def test_validation_before_device(abi):
     assert L.rtm_inject(gp, 4096, 64, 64, 64, -1, None) == abi.RTM_EINVAL
     assert L.rtm_inject(gp, 4096, 64, 64, 64, 0, None) == abi.RTM_OK                # nothing to do
     assert L.rtm_record(gp, 4096, 64, 64, -5, None) == abi.RTM_EINVAL
+    # injection and recording in one call
+    ir = L.rtm_inject_record
+    assert ir(gp, 4096, 64, 64, 64, -1, 64, 64, 1, None) == abi.RTM_EINVAL
+    assert ir(gp, 4096, 64, 64, 64, 1, 64, 64, -1, None) == abi.RTM_EINVAL
+    assert ir(gp, 4096, None, 64, 64, 1, 64, 64, 1, None) == abi.RTM_EINVAL
+    assert ir(gp, 4096, 64, 64, 64, 1, None, 64, 1, None) == abi.RTM_EINVAL
+    assert ir(gp, 4096, 64, 64, 64, 1, 64, None, 1, None) == abi.RTM_EINVAL
+    assert ir(gp, None, None, None, None, 0, None, None, 0, None) == abi.RTM_OK       # nothing to do
+    assert ir(None, 4096, 64, 64, 64, 1, 64, 64, 1, None) == abi.RTM_EINVAL
     assert L.rtm_record(gp, None, None, None, 0, None) == abi.RTM_OK               # nothing to do
     assert L.rtm_misfit_residual_chunks(64, 128, 256, 10, 512, 0, 1024, None) == abi.RTM_EINVAL   # no chunks
     assert L.rtm_misfit_residual_chunks(64, 128, 256, 10, None, 4, 1024, None) == abi.RTM_EINVAL  # no partials

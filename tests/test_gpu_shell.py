@@ -202,3 +202,54 @@ def test_two_subdomain_split_shell_bitwise(torch_cuda):
     prv = np.concatenate([h_[1] for h_ in halves], axis=2)
     assert np.abs(ref_cur).max() > 0 and np.all(np.isfinite(cur))
     assert np.array_equal(cur, ref_cur) and np.array_equal(prv, ref_prv)
+
+
+@pytest.mark.parametrize("nsrc,nrec", [(1, 1024), (5, 0), (0, 300), (3, 4093), (40, 5000)])
+def test_inject_record_matches_the_two_calls(torch_cuda, nsrc, nrec):
+    """rtm_inject_record against rtm_inject then rtm_record: the same field and samples, bit for bit,
+    with a receiver on a source cell, a source given twice and indices outside the block; up to 4096
+    items in one workgroup, more in the two launches."""
+    torch = torch_cuda
+    from paper_1603_03971_amd import _abi
+    from paper_1603_03971_amd.grid import Grid
+
+    g = Grid(40, 36, 30, 10.0, 1e-3)
+    rng = np.random.default_rng(nsrc * 1000 + nrec)
+    u0 = g.upload(synth.random_field((30, 36, 40), seed=5))
+    total = int(g.total)
+    sidx = rng.integers(0, total, size=nsrc).astype(np.int64)
+    if nsrc >= 3:
+        sidx[1] = sidx[0]                                   # twice: two adds
+        sidx[2] = total + 7                                 # outside: ignored
+    ridx = rng.integers(0, total, size=nrec).astype(np.int64)
+    if nrec >= 2 and nsrc >= 1:
+        ridx[0] = sidx[0]                                   # on a source cell: records the injected value
+        ridx[1] = -3                                        # outside: 0
+    w = rng.uniform(0.5, 2.0, nsrc).astype(np.float32)
+    amp = rng.standard_normal(nsrc).astype(np.float32)
+    dev = lambda a: torch.from_numpy(a).cuda() if a.size else None
+    si, ri, wd, ad = dev(sidx), dev(ridx), dev(w), dev(amp)
+    st = torch.cuda.current_stream()
+    ua, ub = u0.clone(), u0.clone()
+    oa = torch.full((max(nrec, 1),), float("nan"), device="cuda")
+    ob = oa.clone()
+    if nsrc:
+        _abi.rtm_inject(g.c, ua, si, wd, ad, nsrc, st)
+    if nrec:
+        _abi.rtm_record(g.c, ua, ri, oa, nrec, st)
+    _abi.rtm_inject_record(g.c, ub, si, wd, ad, nsrc, ri, ob if nrec else None, nrec, st)
+    torch.cuda.synchronize()
+    if nsrc >= 3:
+        # the cell given twice takes two atomic adds, whose order is not fixed: equal up to rounding
+        d = int(sidx[0])
+        assert torch.allclose(ua[d], ub[d], rtol=1e-6, atol=0.0)
+        ua[d] = ub[d] = 0.0
+        if nrec >= 1:
+            assert torch.allclose(oa[0], ob[0], rtol=1e-6, atol=0.0)
+            oa[0] = ob[0] = 0.0
+    assert torch.equal(ua, ub)
+    if nrec:
+        assert not torch.isnan(ob).any()                   # every sample written
+        assert torch.equal(oa, ob)
+    if nsrc >= 3 and nrec >= 2:
+        assert ob[1].item() == 0.0 and ub[int(ridx[2])].item() == ob[2].item()

@@ -913,10 +913,11 @@ __global__ __launch_bounds__(kThreads) void k_record(const float *__restrict__ u
     }
 }
 
-// k_inject then k_record in one workgroup: the adds, a device-scope fence (they are complete and no
-// stale line of u is read), a barrier, then the gathers, so a receiver on a source cell records the
-// injected value.  For short lists, where each launch is mostly its own start-up.
-__global__ __launch_bounds__(kThreads) void k_inject_record(float *u, long long total, const int64_t *__restrict__ sidx,
+// k_inject then k_record in one workgroup of 1024 threads: the adds, a device-scope fence (they are
+// complete and no stale line of u is read), a barrier, then the gathers, so a receiver on a source cell
+// records the injected value.  For short lists, where each launch is mostly its own start-up.
+constexpr int kInjectRecordThreads = 1024;
+__global__ __launch_bounds__(kInjectRecordThreads) void k_inject_record(float *u, long long total, const int64_t *__restrict__ sidx,
                                                             const float *__restrict__ w, const float *__restrict__ amp,
                                                             int ns, const int64_t *__restrict__ ridx,
                                                             float *__restrict__ out, int nr)
@@ -2413,8 +2414,8 @@ int rtm_inject_record(const rtm_grid *grid, float *u, const int64_t *src_idx, co
     if (st != RTM_OK) return st;
     const long long total = padded_total(grid);
     if ((long long)nsrc + nrec <= kInjectRecordOneGroup) {
-        hipLaunchKernelGGL(k_inject_record, dim3(1), dim3(kThreads), 0, stream, u, total, src_idx, w, amp, (int)nsrc,
-                           rec_idx, out, (int)nrec);
+        hipLaunchKernelGGL(k_inject_record, dim3(1), dim3(kInjectRecordThreads), 0, stream, u, total, src_idx, w, amp,
+                           (int)nsrc, rec_idx, out, (int)nrec);
         return launch_status();
     }
     if (nsrc > 0) {

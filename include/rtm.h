@@ -7,7 +7,11 @@
  * phases: stencil on the halo region, pack of the halo points into messages, non-blocking
  * exchange, stencil on the rest of the block while the messages are in flight, wait, unpack.  The
  * calls below are those phases for one subdomain, plus the source injection, receiver recording
- * and zero-lag imaging that reverse time migration wraps around them.
+ * and zero-lag imaging that reverse time migration wraps around them.  The halo-first step comes in
+ * two forms: the halo region and the rest (rtm_step_halo or rtm_step_halo_pack[_slots], then
+ * rtm_step_interior), and the shell form (rtm_step_shell_pack, which computes the cells within R of
+ * a face into the face buffer only, then rtm_step_whole_slots over every owned cell); both give the
+ * same bits as the one-launch rtm_step_whole.
  *
  * Scheme (3-D isotropic acoustic wave equation, radius-R star stencil, second-order leapfrog,
  * Cerjan sponge on both time levels):

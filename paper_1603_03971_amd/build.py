@@ -1,8 +1,9 @@
-"""Build librtm.so (HIP, gfx950) in-tree with hipcc.
+"""Build librtm.so (HIP, gfx950) in-tree with hipcc, and the stand-alone bandwidth probe.
 
 Flags: FP contraction off (the kernels spell out every FMA, so halo and interior agree bitwise),
 packed-FP32 instructions off, fast hardware float atomics for injection.  The two sources compile
-in parallel to objects under _build/, which are then linked into the shared library.
+in parallel to objects under _build/, which are then linked into the shared library.  The probe
+(csrc/stream_probe.hip, a program of its own that the library does not use) is built beside it.
 """
 import os
 import subprocess
@@ -12,6 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = [os.path.join(HERE, "csrc", "rtm.hip"), os.path.join(HERE, "csrc", "cnn.hip")]
 LIB = os.path.join(HERE, "librtm.so")
+PROBE_SRC = os.path.join(HERE, "csrc", "stream_probe.hip")
+PROBE = os.path.join(HERE, "stream_probe")
 OBJDIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("RTM_OFFLOAD_ARCH", "gfx950")
 
@@ -33,9 +36,13 @@ def build(verbose: bool = False, extra=()) -> str:
             print(" ".join(cmd), flush=True)
         procs.append((cmd, subprocess.Popen(cmd)))
         objs.append(obj)
+    probe_cmd = ["hipcc", "-O3", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
+                 "-packed-fp32-ops", "-o", PROBE + ".tmp", PROBE_SRC]
+    procs.append((probe_cmd, subprocess.Popen(probe_cmd)))
     for cmd, p in procs:
         if p.wait() != 0:
             raise subprocess.CalledProcessError(p.returncode, cmd)
+    os.replace(PROBE + ".tmp", PROBE)
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs, "-ldl"]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -45,6 +45,11 @@
       the halo call's HBM traffic from the counter runs of `halo` (and its kernel-trace time from the
       benchmark's kernel statistics, if given).
 
+  python3 -m paper_1603_03971_amd.profile summarize-stream --dir DIR --out FILE
+      the bandwidth reference from a kernel trace of the stand-alone probe
+      (paper_1603_03971_amd/stream_probe, built by build.py: three arrays of 512^3 floats read and one
+      written per element, a copy and three reads alone, at several grid sizes), per kernel and grid.
+
   python3 -m paper_1603_03971_amd.profile summarize-conv --stats DIR --out FILE [--n 384]
   python3 -m paper_1603_03971_amd.profile summarize-corrected --stats DIR --out FILE [--n 384 ...]
       the same for kernel traces of the `conv` and `corrected` runs (per-launch rates; per-step and
@@ -563,6 +568,39 @@ def summarize_halo(fetch_dir, write_dir, out, n, commands, stats_dir=None):
     print(text)
 
 
+STREAM_ARRAYS = {"triad_range": 4, "triad": 4, "copy": 2, "read3": 3}   # arrays of 512^3 floats per launch
+
+
+def summarize_stream(trace_dir, out, commands):
+    """Average duration and bytes per second of each probe kernel at each grid size."""
+    rows = _csv(trace_dir, "*kernel_trace.csv")
+    groups = {}
+    for r in rows:
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "").strip()
+        if name not in STREAM_ARRAYS:
+            continue
+        wg = int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"])
+        groups.setdefault((name, wg), []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    lines = ["# rocprofv3 summary: streaming bandwidth reference on one MI355X (arrays of 512^3 floats)", "",
+             "Commands:"] + [f"    {c}" for c in commands] + [""]
+    lines += ["triad: out = a + b c (3 reads + 1 write, the stencil's mix; streaming hints on b, c, out),",
+              "grid-stride; triad_range: the same, one contiguous range per workgroup; copy: 1 read + 1 write;",
+              "read3: 3 reads.  Kernel trace, 21 launches per case (the first is a warm-up):", "",
+              f"    {'kernel':12s} {'workgroups':>10s} {'launches':>8s} {'avg us':>9s} {'TB/s':>6s}"]
+    best = {}
+    for (name, wg), d in sorted(groups.items(), key=lambda kv: (list(STREAM_ARRAYS).index(kv[0][0]), kv[0][1])):
+        d = d[1:] if len(d) > 1 else d
+        us = sum(d) / len(d)
+        tbs = STREAM_ARRAYS[name] * 512 ** 3 * 4 / us / 1e6
+        best[name] = max(best.get(name, 0.0), tbs)
+        lines.append(f"    {name:12s} {wg:10d} {len(d):8d} {us:9.1f} {tbs:6.2f}")
+    lines += ["", "Best per kernel: " + ", ".join(f"{k} {v:.2f} TB/s" for k, v in best.items())]
+    text = "\n".join(lines) + "\n"
+    with open(out, "w") as f:
+        f.write(text)
+    print(text)
+
+
 def summarize_markers(trace_dir, out, commands):
     """Phase sequence of the benchmark's steps from a marker trace (RTM_OPT_MARKERS): the calls of
     one halo-first step in order, host time per call, and the GPU time of the kernels each step
@@ -707,6 +745,10 @@ def main(argv=None):
     kn = sub.add_parser("kernels")
     kn.add_argument("--n", type=int, default=512)
     kn.add_argument("--launches", type=int, default=10)
+    ss = sub.add_parser("summarize-stream")
+    ss.add_argument("--dir", required=True)
+    ss.add_argument("--out", required=True)
+    ss.add_argument("--command", action="append", default=[])
     sm = sub.add_parser("summarize-markers")
     sm.add_argument("--dir", required=True)
     sm.add_argument("--out", required=True)
@@ -772,6 +814,8 @@ def main(argv=None):
         summarize_halo(args.fetch, args.write, args.out, args.n, args.command, args.stats)
     elif args.cmd == "kernels":
         run_kernels(args.n, args.launches)
+    elif args.cmd == "summarize-stream":
+        summarize_stream(args.dir, args.out, args.command)
     elif args.cmd == "summarize-markers":
         summarize_markers(args.dir, args.out, args.command)
     elif args.cmd == "summarize-kernels":

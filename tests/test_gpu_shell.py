@@ -204,7 +204,7 @@ def test_two_subdomain_split_shell_bitwise(torch_cuda):
     assert np.array_equal(cur, ref_cur) and np.array_equal(prv, ref_prv)
 
 
-@pytest.mark.parametrize("nsrc,nrec", [(1, 1024), (5, 0), (0, 300), (3, 4093), (40, 5000)])
+@pytest.mark.parametrize("nsrc,nrec", [(1, 1024), (5, 0), (0, 300), (3, 4093), (40, 1000), (40, 5000)])
 def test_inject_record_matches_the_two_calls(torch_cuda, nsrc, nrec):
     """rtm_inject_record against rtm_inject then rtm_record: the same field and samples, bit for bit,
     with a receiver on a source cell, a source given twice and indices outside the block; up to 4096

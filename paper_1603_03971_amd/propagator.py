@@ -153,7 +153,9 @@ class Propagator:
 
         halo (ghosts="slots"): "region" (default) updates the halo region in the halo call and the
         rest in the interior call; "shell" computes only the faces in the halo call
-        (rtm_step_shell_pack) and every owned cell in the second call (rtm_step_whole_slots).
+        (rtm_step_shell_pack) and every owned cell in the second call (rtm_step_whole_slots).  The
+        shell call reads kappa's faces from a copy packed here: after changing kappa in place, call
+        refresh_kappa().
 
         unpack_aside (serial schedule): the unpack runs on a second stream as soon as the halo call
         and the shell sources are done, concurrently with the interior call (it writes ghost cells
@@ -297,6 +299,13 @@ class Propagator:
         self.sync()
         st = stream if stream is not None else torch.cuda.current_stream()
         _abi.rtm_unpack_halo(self.grid.c, self.u_cur, self._recv_for(self.n), st)
+
+    def refresh_kappa(self):
+        """halo="shell": re-pack kappa's faces after kappa was changed in place (the shell call reads
+        the x strips' kappa from that copy); a no-op otherwise."""
+        if self.kappa_faces is not None:
+            self.sync()
+            _abi.rtm_pack_halo(self.grid.c, self.kappa, self.kappa_faces, torch.cuda.current_stream())
 
     def _mark_zero_ghosts(self, u: torch.Tensor):
         self._zero_ghosts[u.data_ptr()] = weakref.ref(u)

@@ -253,3 +253,29 @@ def test_inject_record_matches_the_two_calls(torch_cuda, nsrc, nrec):
         assert torch.equal(oa, ob)
     if nsrc >= 3 and nrec >= 2:
         assert ob[1].item() == 0.0 and ub[int(ridx[2])].item() == ob[2].item()
+
+
+def test_refresh_kappa_after_in_place_change(torch_cuda):
+    """A medium changed in place half-way (kappa scaled in a block touching the -x face): with
+    refresh_kappa() the shell form stays bitwise the halo-region form, which reads kappa itself."""
+    torch = torch_cuda
+    from paper_1603_03971_amd.grid import Grid
+    from paper_1603_03971_amd.propagator import Propagator, Sources
+
+    shape = (36, 40, 96)
+    nz, ny, nx = shape
+    v = np.array(synth.layered_velocity(shape, 10.0, seed=8))
+    g = Grid(nx, ny, nz, 10.0, Grid.stable_dt(4, 10.0, float(v.max()) * 1.1), sponge_width=6)
+    runs = []
+    for halo in ("region", "shell"):
+        kap = g.kappa_from_velocity(v)
+        src = Sources(g, [(30, 20, 18)], g.injection_weights([v[18, 20, 30]]), g.ricker(60, 20.0)[:, None])
+        p = Propagator(g, kap, sources=src, schedule="serial", boundary="zero_faces", ghosts="slots", halo=halo)
+        p.run(30)
+        p.sync()
+        g.owned(kap)[4:20, 5:30, 0:12] *= 1.2          # in place, x from 0: the shell call's x strips
+        p.refresh_kappa()
+        p.run(30)
+        torch.cuda.synchronize()
+        runs.append(g.download(p.u_cur))
+    assert np.abs(runs[0]).max() > 0 and np.array_equal(runs[0], runs[1])

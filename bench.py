@@ -33,9 +33,9 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_POINT = 16          # read u^n, u^{n-1}, kappa; write u^{n+1} (FP32)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "forward_512_layered_traffic.txt")
 # the dominant call (the whole-block call, or the interior call with --halo region) is timed with HIP
-# events on every EVENT_EVERY-th timed step (100 launches of 1000):
-# each event pair makes the step it brackets about 11 us longer (an event waits for the kernel before
-# it and writes back the caches), which the other steps then do not pay
+# events on every EVENT_EVERY-th timed step counted from the first (100 launches of 1000; at least one
+# in any run): each event pair makes the step it brackets about 11 us longer (an event waits for the
+# kernel before it and writes back the caches), which the other steps then do not pay
 EVENT_EVERY = 10
 
 
@@ -168,6 +168,7 @@ def main():
 
     prop.interior_events = []
     prop.interior_event_every = EVENT_EVERY
+    prop.interior_event_start = prop.n
     t0 = time.perf_counter()
     for _ in range(args.steps):
         prop.step(traces)
@@ -186,7 +187,8 @@ def main():
         step_text = ("halo-first with 6 x 4-wide faces packed to a send buffer and read by the next halo call "
                      "from zero-filled receive slots (no unpack pass)")
     else:
-        step_text = "halo-first with 6 x 4-wide faces packed to a send buffer and unpacked from zero-filled receive slots"
+        step_text = ("halo-first with 6 x 4-wide faces packed to a send buffer and unpacked from zero-filled "
+                     "receive slots")
     result = {
         "metric": "Gpoint-updates/s", "value": round(value, 3), "unit": "Gpts/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 4),

@@ -242,10 +242,13 @@ class Propagator:
         self.sH = torch.cuda.Stream(device=grid.device)
         self.sI = torch.cuda.Stream(device=grid.device)
         self._ev_int = None
-        self.interior_events = None   # list of (start, end) timing events around rtm_step_interior
+        # list of (start, end) timing events around the dominant call (rtm_step_interior; with
+        # halo="shell", rtm_step_whole_slots), or None
+        self.interior_events = None
         # time the interior call on every k-th step only: an event pair costs the step it brackets
         # about 11 us at 512^3 (each event waits for the kernel before it and writes back the caches)
         self.interior_event_every = 1
+        self.interior_event_start = 0       # timed steps: n - start a multiple of interior_event_every
         self.debug = bool(debug)
         if check_every < 0:
             raise ValueError("check_every must be >= 0")
@@ -475,7 +478,8 @@ class Propagator:
         """The interior call, bracketed by timing events on every interior_event_every-th step when
         interior_events is a list."""
         c = self.grid.c
-        if self.interior_events is not None and n % self.interior_event_every == 0:
+        if self.interior_events is not None and \
+                (n - self.interior_event_start) % self.interior_event_every == 0:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(st)
             _abi.rtm_step_interior(c, u_nxt, u_cur, u_prv, self.kappa, st)
@@ -497,7 +501,8 @@ class Propagator:
             ev = torch.cuda.Event()
             ev.record(sH)
             sI.wait_event(ev)
-        if self.interior_events is not None and n % self.interior_event_every == 0:
+        if self.interior_events is not None and \
+                (n - self.interior_event_start) % self.interior_event_every == 0:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(sI)
             _abi.rtm_step_whole_slots(c, u_nxt, u_cur, u_prv, kap, recv, sI)

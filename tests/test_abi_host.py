@@ -280,3 +280,16 @@ def test_time_at_error_reads_the_plain_frontier():
     assert abs(t - (0.25 + w * 0.01)) < 1e-12
     assert time_at_error(pts, 0.01) == 3.2            # only the fine solve reaches it
     assert time_at_error([(0.2, 0.3), (0.4, 0.1)], 0.05) is None
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU: --gpus 2 exits with status 2 and says so, before touching a device."""
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+

@@ -696,7 +696,7 @@ __device__ __forceinline__ void xface_rows(long long t0, long long tstride, cons
 // stride over those blocks), the rest are 32x8-thread tiles of the z slabs and y strips (faces only,
 // FL has FL_PONLY).  Both parts are latency-bound and overlap in one launch (512^3: 45 us, against
 // 24 + 30 us as two launches).
-constexpr int kShellLds = 6 * 16 * 34;     // TileLds<4, 32, 8>::N
+constexpr int kShellLds = TileLds<4, 32, 8>::N;
 template <int FL>
 __global__ __launch_bounds__(256) void k_shell(Geo g, const float *__restrict__ uc, const float *up, const float *kap,
                                                BoxList slabs, PackOut po, const float *__restrict__ fc,
@@ -1700,12 +1700,13 @@ int launch_halo_pack(const Geo &g, float *un, const float *uc, const float *up, 
 }
 
 // The shell call (radius 4, ghosts from po.recv): the owned cells within R of a face, written to the
-// face buffer only.  The two z slabs and the two y strips between them: one launch of 32x8-thread
-// tiles in 16-plane z chunks (27 us at 512^3).  The two 4-column x strips between those: with dense
-// face copies of u_cur, u_prv and kappa (fc, fp, fk), k_xface, which reads one float4 per row from the
-// field; otherwise 2x32-thread tiles (8 columns: the centre float4 and its inside neighbour) in
-// 32-plane chunks, which read three float4s of separate lines per row and plane from the fields
-// (38 us at 512^3).
+// face buffer only.  With dense face copies of u_cur, u_prv and kappa (fc, fp, fk): one launch of
+// k_shell, the two 4-column x strips as one thread per row (xface_rows, one float4 per row read from
+// the field) and the two z slabs and the two y strips between them as 32x8-thread tiles in 16-plane
+// z chunks (44-49 us at 512^3).  Without them, or on grids too small for the row walk: the slabs and
+// strips in one launch of those tiles, then the x strips in 2x32-thread tiles (8 columns: the centre
+// float4 and its inside neighbour) in 32-plane chunks, which read three float4s of separate lines per
+// row and plane from the fields (68-70 us at 512^3).
 int launch_shell_pack(const Geo &g, const float *uc, const float *up, const float *kap, const float *fc,
                       const float *fp, const float *fk, const PackOut &po, hipStream_t st)
 {
